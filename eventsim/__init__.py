@@ -1,0 +1,226 @@
+"""Seeded synthetic event streams with ground truth (input generator only).
+
+This module produces the inputs that both the oracle and the GPU library are
+fed: events (x uint16, y uint16, polarity uint8, t uint64 ns), ground-truth
+log-intensity frames, and the push/readout schedule a harness follows.  It
+holds none of the reconstruction method's arithmetic.
+
+The event model is the paper's (Notation section, Eq. (1)-(3)): an event is
+emitted whenever a pixel's log intensity crosses its ON/OFF contrast
+threshold.  The recorded datasets the paper measures on are not available, so
+these seeded scenes stand in for them (see `preset`).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "eventsim.c")
+_LIB = os.path.join(_HERE, "libeventsim.so")
+
+
+def build(force: bool = False) -> str:
+    """Compile the simulator with gcc (no GPU code involved)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class SimParams(ctypes.Structure):
+    _fields_ = [
+        ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+        ("n_events", ctypes.c_uint64), ("seed", ctypes.c_uint64),
+        ("n_blobs", ctypes.c_int32),
+        ("amp_lo", ctypes.c_double), ("amp_hi", ctypes.c_double),
+        ("sig_lo", ctypes.c_double), ("sig_hi", ctypes.c_double),
+        ("checker_cell", ctypes.c_double), ("checker_contrast", ctypes.c_double),
+        ("speed_px_s", ctypes.c_double), ("rot_rad_s", ctypes.c_double),
+        ("thr_on", ctypes.c_double), ("thr_off", ctypes.c_double),
+        ("thr_jitter", ctypes.c_double), ("noise_frac", ctypes.c_double),
+        ("step_px", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(build())
+        lib.sim_generate.restype = ctypes.c_int64
+        lib.sim_generate.argtypes = [ctypes.POINTER(SimParams), ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                     ctypes.POINTER(ctypes.c_uint64)]
+        lib.sim_render_frames.restype = ctypes.c_int
+        lib.sim_render_frames.argtypes = [ctypes.POINTER(SimParams), ctypes.c_void_p,
+                                          ctypes.c_size_t, ctypes.c_void_p]
+        lib.sim_step_seconds.restype = ctypes.c_double
+        lib.sim_step_seconds.argtypes = [ctypes.POINTER(SimParams)]
+        lib.sim_philox4x32_10.restype = None
+        lib.sim_philox4x32_10.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        _lib = lib
+    return _lib
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 block function (exposed for its known-answer test)."""
+    c = np.asarray(ctr, dtype=np.uint32).copy()
+    k = np.asarray(key, dtype=np.uint32).copy()
+    o = np.zeros(4, dtype=np.uint32)
+    _load().sim_philox4x32_10(c.ctypes.data, k.ctypes.data, o.ctypes.data)
+    return o
+
+
+@dataclass
+class Scene:
+    width: int
+    height: int
+    n_events: int
+    seed: int
+    n_blobs: int = 32
+    amp: tuple = (-1.0, 1.0)
+    sigma: tuple = (2.0, 8.0)
+    checker_cell: float = 0.0
+    checker_contrast: float = 0.0
+    speed_px_s: float = 30.0
+    rot_rad_s: float = 0.0
+    thr_on: float = 0.2
+    thr_off: float = 0.2
+    thr_jitter: float = 0.0
+    noise_frac: float = 0.01
+    step_px: float = 0.25
+
+    def c_params(self) -> SimParams:
+        return SimParams(self.width, self.height, self.n_events, self.seed, self.n_blobs,
+                         self.amp[0], self.amp[1], self.sigma[0], self.sigma[1],
+                         self.checker_cell, self.checker_contrast, self.speed_px_s,
+                         self.rot_rad_s, self.thr_on, self.thr_off, self.thr_jitter,
+                         self.noise_frac, self.step_px)
+
+
+@dataclass
+class Events:
+    x: np.ndarray
+    y: np.ndarray
+    p: np.ndarray
+    t: np.ndarray
+    steps: int = 0
+
+    def __len__(self):
+        return int(self.x.shape[0])
+
+    def slice(self, a: int, b: int) -> "Events":
+        return Events(self.x[a:b], self.y[a:b], self.p[a:b], self.t[a:b])
+
+
+def generate(scene: Scene, max_steps: int = 1 << 40) -> Events:
+    n = int(scene.n_events)
+    x = np.empty(n, np.uint16)
+    y = np.empty(n, np.uint16)
+    p = np.empty(n, np.uint8)
+    t = np.empty(n, np.uint64)
+    steps = ctypes.c_uint64(0)
+    prm = scene.c_params()
+    got = _load().sim_generate(ctypes.byref(prm), x.ctypes.data, y.ctypes.data, p.ctypes.data,
+                               t.ctypes.data, max_steps, ctypes.byref(steps))
+    if got < 0:
+        raise MemoryError("event simulator failed")
+    return Events(x[:got], y[:got], p[:got], t[:got], int(steps.value))
+
+
+def render_frames(scene: Scene, t_ns) -> np.ndarray:
+    """Ground-truth log intensity, shape (len(t_ns), H, W), float32."""
+    t = np.ascontiguousarray(np.asarray(t_ns, dtype=np.uint64).reshape(-1))
+    out = np.empty((t.shape[0], scene.height, scene.width), np.float32)
+    prm = scene.c_params()
+    if _load().sim_render_frames(ctypes.byref(prm), t.ctypes.data, t.shape[0], out.ctypes.data) != 0:
+        raise MemoryError("render failed")
+    return out
+
+
+# --------------------------------------------------------------------------
+# Workload presets.  Each stands in for a recorded dataset of the paper's
+# kind (moving camera, 640x480 sensor in the paper's runtime section); the
+# numbers below are the workload definitions, not measurements.
+# --------------------------------------------------------------------------
+@dataclass
+class Workload:
+    name: str
+    scene: Scene
+    packet: int
+    readouts: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int64))
+
+
+def preset(name: str, n_events: int | None = None, seed: int | None = None) -> Workload:
+    """Named synthetic workloads.
+
+    sensor64x48  : 64x48, 32 blobs, 30 px/s, C=0.2, 1% noise, 1024-event
+                   packets, readout every 10 000 events (200 000 events).
+    vga          : 640x480, 512 blobs + 16 px checkerboard (contrast 0.5),
+                   200 px/s, C = 0.2 +- 0.02 per pixel, 1% noise, 8192-event
+                   packets, readout every 50 000 events (20 M events).
+    hd720        : 1280x720, 2048 blobs, 0.5 rad/s rotation + 300 px/s,
+                   C=0.15, 2% noise, 16384-event packets, readouts at random
+                   indices with mean spacing 100 000 (100 M events).  Time
+                   steps of at most 1 texel of motion keep generation of the
+                   100 M-event stream to well under a minute.
+    """
+    if name == "sensor64x48":
+        n = 200_000 if n_events is None else n_events
+        sc = Scene(64, 48, n, 1 if seed is None else seed, n_blobs=32, speed_px_s=30.0,
+                   thr_on=0.2, thr_off=0.2, noise_frac=0.01)
+        ro = np.arange(10_000, n + 1, 10_000, dtype=np.int64)
+        return Workload(name, sc, 1024, ro)
+    if name == "vga":
+        n = 20_000_000 if n_events is None else n_events
+        sc = Scene(640, 480, n, 2 if seed is None else seed, n_blobs=512, checker_cell=16.0,
+                   checker_contrast=0.5, speed_px_s=200.0, thr_on=0.2, thr_off=0.2,
+                   thr_jitter=0.02, noise_frac=0.01)
+        ro = np.arange(50_000, n + 1, 50_000, dtype=np.int64)
+        return Workload(name, sc, 8192, ro)
+    if name == "hd720":
+        n = 100_000_000 if n_events is None else n_events
+        sd = 3 if seed is None else seed
+        sc = Scene(1280, 720, n, sd, n_blobs=2048, speed_px_s=300.0, rot_rad_s=0.5,
+                   thr_on=0.15, thr_off=0.15, noise_frac=0.02, step_px=1.0)
+        nro = max(1, n // 100_000)
+        rng = np.random.default_rng(1000 + sd)
+        ro = np.sort(rng.choice(np.arange(1, n, dtype=np.int64), size=min(nro, n - 1),
+                                replace=False)) if n > 1 else np.zeros(0, np.int64)
+        return Workload(name, sc, 16384, ro)
+    raise KeyError(name)
+
+
+def schedule(n_events: int, packet: int, readouts) -> list:
+    """Push/readout schedule: a list of ("push", a, b) and ("read", k) items.
+
+    Packets are consecutive runs of `packet` events; a readout index r (the
+    number of events applied before the readout) that falls inside a packet
+    splits that packet in two, so every consumer sees the same pushes.
+    """
+    ro = sorted(set(int(r) for r in readouts if 0 < int(r) <= n_events))
+    out = []
+    ri = 0
+    a = 0
+    while a < n_events:
+        b = min(a + packet, n_events)
+        while ri < len(ro) and ro[ri] <= b:
+            r = ro[ri]
+            if r > a:
+                out.append(("push", a, r))
+                a = r
+            out.append(("read", r))
+            ri += 1
+        if b > a:
+            out.append(("push", a, b))
+        a = b
+    return out
