@@ -1,0 +1,235 @@
+/*
+ * fibar.h -- C ABI of libfibar, an MI355X (gfx950) implementation of the
+ * FIBAR event-camera image reconstruction hot path (Pfrommer, "Filter-Based
+ * Reconstruction of Images from Events", arXiv 2510.20071).
+ *
+ * The paper's problem statement (Introduction): events arrive
+ * asynchronously, grouped into packets by the transport; every event updates
+ * the brightness image at its own pixel; the image can be read out at any
+ * time with no final processing.  The library keeps the whole reconstruction
+ * state in device memory and runs every step in its own HIP kernels:
+ *
+ *   - temporal filter per event (Method, Eq. (6), (7), (10); coefficients
+ *     from the cutoff period by Eq. (17), (18));
+ *   - active-event window and 2x2 active-tile bookkeeping with the queue
+ *     target regulated by Eq. (19), (20) (Method, "Spatial filtering");
+ *   - one-time 3x3 Gaussian blur of pixels that go stale.
+ *
+ * Regulation granularity: the library regulates once per pushed packet
+ * (all events of the packet are applied, then old events leave the window,
+ * every pixel that went stale in that step is blurred from the same pre-blur
+ * image, then the target length is updated).  A packet of one event is the
+ * paper's per-event step.
+ *
+ * Threading: a context is not thread-safe; calls on one context must be
+ * serialised by the caller.  All device work of a context is ordered on the
+ * stream given at creation.
+ */
+#ifndef FIBAR_H
+#define FIBAR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fibar_ctx fibar_ctx;  /* opaque; owns all device state */
+
+typedef enum {
+    FIBAR_OK = 0,
+    FIBAR_E_INVALID_ARG = -1,   /* NULL pointer, bad size or parameter        */
+    FIBAR_E_RANGE = -2,         /* an event has x >= width or y >= height     */
+    FIBAR_E_POLARITY = -3,      /* a polarity byte is neither 0 nor 1         */
+    FIBAR_E_TIME = -4,          /* readout time earlier than a previous one   */
+    FIBAR_E_NOMEM = -5,         /* device or host allocation failed           */
+    FIBAR_E_DEVICE = -6,        /* a HIP call failed                          */
+    FIBAR_E_UNSUPPORTED = -7    /* output not maintained in this mode         */
+} fibar_status;
+
+typedef enum {
+    FIBAR_REG_PACKET = 0        /* regulate once per pushed packet            */
+} fibar_regulation;
+
+/*
+ * Parameters.  fibar_default_params() fills the paper's settings.
+ *   t_cut          cutoff period in events, > 4 (Eq. (16)-(18); the paper
+ *                  uses 40).  alpha and beta are derived on the host in
+ *                  double precision and rounded once to float.
+ *   fill_num/den   target fill ratio r_fill = num/den of Eq. (19), with
+ *                  0 < num <= den <= 65535 (the paper uses 1/2).
+ *   q_min, q_max   clamp of the target queue length; q_min >= 1 (the paper
+ *                  only asks for a lower bound; default 64); q_max = 0 means
+ *                  width*height (the paper's queue limit).
+ *   spatial_filter 1 = FIBAR (stale detection + blur), 0 = FIBAR-NSF
+ *                  (temporal filter only).
+ *   regulation     FIBAR_REG_PACKET.
+ *   max_packet     largest packet accepted by fibar_push_events (events),
+ *                  1 .. 1048576; sizes device buffers.  Default 65536.
+ *   stream         hipStream_t all work is ordered on; NULL = the null stream.
+ */
+typedef struct {
+    double   t_cut;
+    uint32_t fill_num, fill_den;
+    uint32_t q_min;
+    uint32_t q_max;
+    uint32_t spatial_filter;
+    uint32_t regulation;
+    uint32_t max_packet;
+    void*    stream;
+} fibar_params;
+
+void fibar_default_params(fibar_params* p);
+
+/*
+ * Create a context for a width x height sensor (1..65535 each).  Allocates
+ * all device state (zero brightness, no events seen).  On success *out
+ * receives the context; on failure *out is NULL and the status says why
+ * (FIBAR_E_INVALID_ARG for bad sizes or parameters, FIBAR_E_NOMEM if device
+ * memory is short, FIBAR_E_DEVICE for other HIP errors).
+ */
+int fibar_create(uint32_t width, uint32_t height, const fibar_params* p, fibar_ctx** out);
+
+/*
+ * One packet of n events, in arrival (time) order, as structure-of-arrays:
+ *   x[n], y[n]  pixel coordinates (uint16),
+ *   p[n]        polarity byte: 1 = ON (+1), 0 = OFF (-1),
+ *   t[n]        time stamps (uint64); may be NULL.  The method never uses
+ *               them (paper, Introduction and Method: each pixel runs on
+ *               event time); for host packets t[n-1] is remembered for the
+ *               readout-order check.
+ *   on_device   0: the arrays are host memory, read before the call returns.
+ *               1: the arrays are device memory, read in stream order; the
+ *               caller keeps them alive until the stream has passed this
+ *               call.
+ */
+typedef struct {
+    const uint16_t* x;
+    const uint16_t* y;
+    const uint8_t*  p;
+    const uint64_t* t;
+    size_t          n;
+    int             on_device;
+} fibar_packet;
+
+/*
+ * Apply a packet: every event updates its pixel (temporal filter), enters
+ * the active-event window, and then the window is regulated once (spatial
+ * filter on).  n == 0 is a no-op.  n > max_packet -> FIBAR_E_INVALID_ARG.
+ *
+ * Validation is all-or-nothing: a packet with any event out of range
+ * (FIBAR_E_RANGE, checked first) or any polarity byte other than 0/1
+ * (FIBAR_E_POLARITY) changes no state.  Host packets are checked before
+ * the call returns.  Device packets are checked on the device; a rejected
+ * device packet is skipped by every kernel and its status is reported by
+ * the next fibar_synchronize / fibar_get_stats / host readout (then
+ * cleared).
+ */
+int fibar_push_events(fibar_ctx* c, const fibar_packet* pkt);
+
+/*
+ * Output buffers of a readout, width*height elements each, row-major
+ * (index y*width + x).  Any pointer but `brightness` may be NULL.
+ *   brightness    L, the reconstructed brightness (float).
+ *   pbar          the per-pixel polarity average of Eq. (7) (float).
+ *   stale_mask    1 where the pixel has had events but none is left in the
+ *                 window, else 0.                        [spatial filter]
+ *   active_count  events of that pixel inside the window. [spatial filter]
+ *   last_index    global index (0-based) of the pixel's newest event, -1 if
+ *                 none.
+ *   log_age       log(1 + k - last_index), k = index of the newest event
+ *                 overall (float); never-seen pixels use last_index = -1.
+ *   tile_count    active pixels per 2x2 tile, ((width+1)/2)*((height+1)/2)
+ *                 elements, tile (tx, ty) at ty*((width+1)/2)+tx.
+ *                                                          [spatial filter]
+ *   on_device     0: host memory (the call synchronises the stream);
+ *                 1: device memory, written in stream order.
+ * Outputs marked [spatial filter] return FIBAR_E_UNSUPPORTED when the
+ * context was created with spatial_filter = 0 and the pointer is non-NULL.
+ */
+typedef struct {
+    float*    brightness;
+    float*    pbar;
+    uint8_t*  stale_mask;
+    uint32_t* active_count;
+    int64_t*  last_index;
+    float*    log_age;
+    uint32_t* tile_count;
+    int       on_device;
+} fibar_readout_buf;
+
+/*
+ * Read the state after all pushed events (paper, Introduction: no final
+ * processing is needed at read-out).  t is the readout time; it is not used
+ * by the method, but it may not be earlier than a previous readout time or
+ * the newest host-packet time stamp (FIBAR_E_TIME otherwise).
+ */
+int fibar_readout(fibar_ctx* c, uint64_t t, const fibar_readout_buf* out);
+
+/*
+ * A list of operations executed in order, with the same results as calling
+ * fibar_push_events / fibar_readout one by one.  Executing them together lets
+ * the library group and compose the events of many packets in one parallel
+ * pass before applying them in order.  Host readouts inside a list do not
+ * report pending device-side packet errors (the next fibar_synchronize does).
+ * Execution stops at the first error the host detects, which is returned;
+ * the operations before it have been carried out.
+ */
+typedef enum { FIBAR_OP_PUSH = 0, FIBAR_OP_READOUT = 1 } fibar_op_kind;
+
+typedef struct {
+    int               kind;     /* fibar_op_kind                   */
+    fibar_packet      packet;   /* FIBAR_OP_PUSH                   */
+    uint64_t          t;        /* FIBAR_OP_READOUT: readout time  */
+    fibar_readout_buf readout;  /* FIBAR_OP_READOUT: outputs       */
+} fibar_op;
+
+int fibar_submit(fibar_ctx* c, const fibar_op* ops, size_t n_ops);
+
+/* Free all resources.  NULL-safe.  Waits for the context's stream. */
+void fibar_destroy(fibar_ctx* c);
+
+/*
+ * Window statistics after the last regulation step (synchronises):
+ *   k  index of the newest event (-1 before any), h index of the oldest
+ *   event in the window, q = k - h + 1, Q the target length, P active
+ *   pixels, T active tiles, n_regulations steps so far, last_stale pixels
+ *   blurred in the last step, total_stale blurred so far.
+ */
+typedef struct {
+    int64_t  k;
+    uint64_t h, q, Q, P, T;
+    uint64_t n_regulations, last_stale, total_stale;
+} fibar_stats;
+
+int fibar_get_stats(fibar_ctx* c, fibar_stats* s);
+
+/*
+ * Return the context to its initial state (no events seen, zero images,
+ * target length q_max), keeping its allocations.  Stream ordered.
+ */
+int fibar_reset(fibar_ctx* c);
+
+/*
+ * Optional per-kernel timing with HIP events recorded around every launch of
+ * the kernels selected by `kernel_mask` (bit i = kernel i below; 0 turns
+ * timing off).  fibar_kernel_time() synchronises, returns the summed device
+ * time (ms) and the launch count of kernel `kernel` since the last call, and
+ * clears them.  Kernels: 0 group+compose (bulk), 1 apply, 2 window pop +
+ * stale blur values, 3 blur write, 4 readout.
+ */
+int fibar_set_kernel_timing(fibar_ctx* c, uint32_t kernel_mask);
+int fibar_kernel_time(fibar_ctx* c, int kernel, double* total_ms, uint64_t* launches);
+
+/* Wait for all queued work; returns a pending device-side packet error. */
+int fibar_synchronize(fibar_ctx* c);
+
+/* Short English description of a status code (static string). */
+const char* fibar_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FIBAR_H */

@@ -1,0 +1,292 @@
+"""Python binding of libfibar (FIBAR event-camera reconstruction on MI355X).
+
+Argument marshalling only: every step of the reconstruction runs in the HIP
+kernels of ``libfibar.so`` behind the C ABI of ``include/fibar.h``.  The
+functions below carry the C names.  Device buffers are passed as raw
+pointers (for example ``tensor.data_ptr()`` of a torch tensor on the GPU);
+host buffers as numpy arrays.
+
+Importing this package does not need a GPU.  Using it does: if the library
+has not been built, ``load()`` raises instead of falling back to anything.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfibar.so")
+
+FIBAR_OK = 0
+FIBAR_E_INVALID_ARG = -1
+FIBAR_E_RANGE = -2
+FIBAR_E_POLARITY = -3
+FIBAR_E_TIME = -4
+FIBAR_E_NOMEM = -5
+FIBAR_E_DEVICE = -6
+FIBAR_E_UNSUPPORTED = -7
+FIBAR_REG_PACKET = 0
+FIBAR_OP_PUSH = 0
+FIBAR_OP_READOUT = 1
+
+
+class FibarError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__("%s: %s (%d)" % (what or "fibar", _status_text(status), status))
+
+
+class fibar_params(ctypes.Structure):
+    _fields_ = [("t_cut", ctypes.c_double), ("fill_num", ctypes.c_uint32),
+                ("fill_den", ctypes.c_uint32), ("q_min", ctypes.c_uint32),
+                ("q_max", ctypes.c_uint32), ("spatial_filter", ctypes.c_uint32),
+                ("regulation", ctypes.c_uint32), ("max_packet", ctypes.c_uint32),
+                ("stream", ctypes.c_void_p)]
+
+
+class fibar_packet(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("p", ctypes.c_void_p),
+                ("t", ctypes.c_void_p), ("n", ctypes.c_size_t), ("on_device", ctypes.c_int)]
+
+
+class fibar_readout_buf(ctypes.Structure):
+    _fields_ = [("brightness", ctypes.c_void_p), ("pbar", ctypes.c_void_p),
+                ("stale_mask", ctypes.c_void_p), ("active_count", ctypes.c_void_p),
+                ("last_index", ctypes.c_void_p), ("log_age", ctypes.c_void_p),
+                ("tile_count", ctypes.c_void_p), ("on_device", ctypes.c_int)]
+
+
+class fibar_op(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("packet", fibar_packet), ("t", ctypes.c_uint64),
+                ("readout", fibar_readout_buf)]
+
+
+class fibar_stats(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int64), ("h", ctypes.c_uint64), ("q", ctypes.c_uint64),
+                ("Q", ctypes.c_uint64), ("P", ctypes.c_uint64), ("T", ctypes.c_uint64),
+                ("n_regulations", ctypes.c_uint64), ("last_stale", ctypes.c_uint64),
+                ("total_stale", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+# name -> (restype, argtypes); every function declared in include/fibar.h
+_SIGNATURES = {
+    "fibar_default_params": (None, [ctypes.POINTER(fibar_params)]),
+    "fibar_create": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.POINTER(fibar_params),
+                                    ctypes.POINTER(ctypes.c_void_p)]),
+    "fibar_push_events": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(fibar_packet)]),
+    "fibar_readout": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64,
+                                     ctypes.POINTER(fibar_readout_buf)]),
+    "fibar_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(fibar_op), ctypes.c_size_t]),
+    "fibar_destroy": (None, [ctypes.c_void_p]),
+    "fibar_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(fibar_stats)]),
+    "fibar_synchronize": (ctypes.c_int, [ctypes.c_void_p]),
+    "fibar_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "fibar_reset": (ctypes.c_int, [ctypes.c_void_p]),
+    "fibar_set_kernel_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
+    "fibar_kernel_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_uint64)]),
+}
+
+KERNEL_NAMES = ("group_compose", "apply", "pop_blur", "blur_write", "readout")
+
+_lib = None
+
+
+def load():
+    """Load libfibar.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libfibar.so is not built (run __graft_entry__.build() or "
+                              "python -m paper_2510_20071_amd.build)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _status_text(status: int) -> str:
+    try:
+        return load().fibar_status_string(int(status)).decode()
+    except Exception:
+        return "status"
+
+
+# ---- same-name wrappers of the C ABI ---------------------------------------
+def fibar_default_params() -> fibar_params:
+    p = fibar_params()
+    load().fibar_default_params(ctypes.byref(p))
+    return p
+
+
+def fibar_create(width: int, height: int, params: fibar_params | None = None):
+    """Returns (status, handle)."""
+    h = ctypes.c_void_p()
+    rc = load().fibar_create(int(width), int(height),
+                             None if params is None else ctypes.byref(params), ctypes.byref(h))
+    return rc, h
+
+
+def fibar_push_events(handle, packet: fibar_packet) -> int:
+    return load().fibar_push_events(handle, ctypes.byref(packet))
+
+
+def fibar_readout(handle, t: int, buf: fibar_readout_buf) -> int:
+    return load().fibar_readout(handle, int(t), ctypes.byref(buf))
+
+
+def fibar_submit(handle, ops) -> int:
+    arr = (fibar_op * len(ops))(*ops)
+    return load().fibar_submit(handle, arr, len(ops))
+
+
+def fibar_destroy(handle) -> None:
+    load().fibar_destroy(handle)
+
+
+def fibar_get_stats(handle):
+    """Returns (status, stats dict)."""
+    s = fibar_stats()
+    rc = load().fibar_get_stats(handle, ctypes.byref(s))
+    return rc, s.as_dict()
+
+
+def fibar_synchronize(handle) -> int:
+    return load().fibar_synchronize(handle)
+
+
+def fibar_status_string(status: int) -> str:
+    return _status_text(status)
+
+
+def fibar_reset(handle) -> int:
+    return load().fibar_reset(handle)
+
+
+def fibar_set_kernel_timing(handle, kernel_mask: int) -> int:
+    return load().fibar_set_kernel_timing(handle, int(kernel_mask))
+
+
+def fibar_kernel_time(handle, kernel: int):
+    """Returns (status, total_ms, launches)."""
+    ms = ctypes.c_double()
+    n = ctypes.c_uint64()
+    rc = load().fibar_kernel_time(handle, int(kernel), ctypes.byref(ms), ctypes.byref(n))
+    return rc, ms.value, int(n.value)
+
+
+# ---- convenience layer used by the tests and the benchmark -----------------
+def _addr(a):
+    """Pointer of a numpy array or a torch tensor (None -> NULL)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return int(a.data_ptr())
+
+
+def make_packet(x, y, p, t=None, on_device=None) -> fibar_packet:
+    n = int(x.shape[0])
+    if on_device is None:
+        on_device = 0 if isinstance(x, np.ndarray) else 1
+    return fibar_packet(_addr(x), _addr(y), _addr(p), _addr(t), n, int(on_device))
+
+
+class Context:
+    """One reconstruction context (owns its device state)."""
+
+    def __init__(self, width, height, t_cut=40.0, fill=(1, 2), q_min=64, q_max=0,
+                 spatial_filter=True, max_packet=65536, stream=None):
+        prm = fibar_default_params()
+        prm.t_cut = float(t_cut)
+        prm.fill_num, prm.fill_den = int(fill[0]), int(fill[1])
+        prm.q_min = int(q_min)
+        prm.q_max = int(q_max)
+        prm.spatial_filter = 1 if spatial_filter else 0
+        prm.max_packet = int(max_packet)
+        prm.stream = stream
+        rc, h = fibar_create(width, height, prm)
+        if rc != FIBAR_OK:
+            raise FibarError(rc, "fibar_create")
+        self.handle = h
+        self.width, self.height = int(width), int(height)
+        self.tiles = ((self.width + 1) // 2) * ((self.height + 1) // 2)
+        self.spatial_filter = bool(spatial_filter)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            fibar_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def push(self, x, y, p, t=None) -> int:
+        return fibar_push_events(self.handle, make_packet(x, y, p, t))
+
+    def readout_host(self, t=0, spatial_outputs=None):
+        """Read everything into numpy arrays (synchronises); returns dict or status."""
+        npx = self.width * self.height
+        sp = self.spatial_filter if spatial_outputs is None else spatial_outputs
+        out = {"L": np.empty(npx, np.float32), "pbar": np.empty(npx, np.float32),
+               "last": np.empty(npx, np.int64), "log_age": np.empty(npx, np.float32)}
+        if sp:
+            out.update(stale=np.empty(npx, np.uint8), cnt=np.empty(npx, np.uint32),
+                       tcnt=np.empty(self.tiles, np.uint32))
+        buf = fibar_readout_buf(_addr(out["L"]), _addr(out["pbar"]), _addr(out.get("stale")),
+                                _addr(out.get("cnt")), _addr(out["last"]),
+                                _addr(out["log_age"]), _addr(out.get("tcnt")), 0)
+        rc = fibar_readout(self.handle, t, buf)
+        if rc != FIBAR_OK:
+            return rc
+        return out
+
+    def readout_device(self, t, L, pbar=None, stale=None, cnt=None, last=None, log_age=None,
+                       tcnt=None) -> int:
+        buf = fibar_readout_buf(_addr(L), _addr(pbar), _addr(stale), _addr(cnt), _addr(last),
+                                _addr(log_age), _addr(tcnt), 1)
+        return fibar_readout(self.handle, t, buf)
+
+    def stats(self):
+        rc, s = fibar_get_stats(self.handle)
+        if rc != FIBAR_OK:
+            raise FibarError(rc, "fibar_get_stats")
+        return s
+
+    def synchronize(self) -> int:
+        return fibar_synchronize(self.handle)
+
+    def submit(self, ops) -> int:
+        return fibar_submit(self.handle, ops)
+
+    def reset(self) -> int:
+        return fibar_reset(self.handle)
+
+
+def push_op(x, y, p, t=None, on_device=None) -> fibar_op:
+    op = fibar_op()
+    op.kind = FIBAR_OP_PUSH
+    op.packet = make_packet(x, y, p, t, on_device)
+    return op
+
+
+def readout_op(t, L, pbar=None, stale=None, cnt=None, last=None, log_age=None, tcnt=None,
+               on_device=1) -> fibar_op:
+    op = fibar_op()
+    op.kind = FIBAR_OP_READOUT
+    op.t = int(t)
+    op.readout = fibar_readout_buf(_addr(L), _addr(pbar), _addr(stale), _addr(cnt), _addr(last),
+                                   _addr(log_age), _addr(tcnt), int(on_device))
+    return op

@@ -1,0 +1,596 @@
+// Host runtime and C ABI of libfibar (see include/fibar.h).
+//
+// Every public call is turned into a list of operations (pushes and
+// readouts) executed in batches:
+//   1. one bulk launch groups and composes the events of every packet of the
+//      batch (state independent, all packets in parallel);
+//   2. the packets are then applied in order: compositions -> state, window
+//      pops / stale detection / blur values, blur write; readouts run at
+//      their place in the sequence.
+// All work is ordered on the context's stream.
+#include "fibar.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "fibar_internal.h"
+
+using namespace fibar;
+
+namespace {
+
+constexpr uint32_t kMaxBatchChunks = 256;   // chunks sorted per bulk launch
+constexpr uint32_t kMaxPacket = 1u << 20;
+
+// Eq. (17) and Eq. (18), evaluated in double precision.
+void filter_coefficients(double t_cut, double* alpha, double* beta)
+{
+    const double w = 2.0 * M_PI / t_cut;
+    *alpha = (1.0 - sin(w)) / cos(w);
+    const double a = 2.0 - cos(w);
+    *beta = a - sqrt(a * a - 1.0);
+}
+
+}  // namespace
+
+struct fibar_ctx {
+    uint32_t W = 0, H = 0, TW = 0, TH = 0;
+    uint64_t npx = 0, ntiles = 0;
+    fibar_params prm{};
+    Coef coef{};
+    int key_bits = 4;
+    hipStream_t st = nullptr;
+    State s{};
+    // batch resources
+    ChunkDesc* d_chunks = nullptr;
+    ChunkDesc* h_chunks = nullptr;      // pinned
+    hipEvent_t chunks_free = nullptr;   // h_chunks may be rewritten once this fired
+    SegRec* seg = nullptr;
+    uint32_t* seg_count = nullptr;
+    StepScratch* scratch = nullptr;
+    uint16_t* stg_x = nullptr;          // device staging for host packets
+    uint16_t* stg_y = nullptr;
+    uint8_t* stg_p = nullptr;
+    size_t stg_cap = 0;
+    DevScalars* h_sc = nullptr;         // pinned copy for stats
+    uint64_t t_hi = 0;
+    // optional per-kernel timing
+    uint32_t time_mask = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[5];
+    std::vector<hipEvent_t> event_pool;
+};
+
+namespace {
+
+int map_err(hipError_t e)
+{
+    if (e == hipSuccess) return FIBAR_OK;
+    if (e == hipErrorOutOfMemory) return FIBAR_E_NOMEM;
+    return FIBAR_E_DEVICE;
+}
+
+#define HIP_TRY(expr)                            \
+    do {                                         \
+        hipError_t e_ = (expr);                  \
+        if (e_ != hipSuccess) return map_err(e_); \
+    } while (0)
+
+hipEvent_t pooled_event(fibar_ctx* c)
+{
+    if (!c->event_pool.empty()) {
+        hipEvent_t ev = c->event_pool.back();
+        c->event_pool.pop_back();
+        return ev;
+    }
+    hipEvent_t ev = nullptr;
+    if (hipEventCreate(&ev) != hipSuccess) return nullptr;
+    return ev;
+}
+
+// Launch through `fn`, bracketed by timing events when kernel `kind` is timed.
+template <class F>
+hipError_t timed_launch(fibar_ctx* c, int kind, F&& fn)
+{
+    if (!(c->time_mask & (1u << kind))) return fn();
+    hipEvent_t a = pooled_event(c), b = pooled_event(c);
+    if (!a || !b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, c->st);
+    if (e == hipSuccess) e = fn();
+    if (e == hipSuccess) e = hipEventRecord(b, c->st);
+    c->timed[kind].emplace_back(a, b);
+    return e;
+}
+
+void free_ctx(fibar_ctx* c)
+{
+    if (!c) return;
+    if (c->st) hipStreamSynchronize(c->st);
+    else hipDeviceSynchronize();
+    hipFree(c->s.pbar);
+    hipFree(c->s.L);
+    hipFree(c->s.last);
+    hipFree(c->s.cnt);
+    hipFree(c->s.tcnt);
+    hipFree(c->s.ring);
+    hipFree(c->s.sc);
+    hipFree(c->s.S);
+    hipFree(c->s.Sval);
+    hipFree(c->d_chunks);
+    hipFree(c->seg);
+    hipFree(c->seg_count);
+    hipFree(c->scratch);
+    hipFree(c->stg_x);
+    hipFree(c->stg_y);
+    hipFree(c->stg_p);
+    if (c->h_chunks) hipHostFree(c->h_chunks);
+    if (c->h_sc) hipHostFree(c->h_sc);
+    if (c->chunks_free) (void)hipEventDestroy(c->chunks_free);
+    for (auto& v : c->timed)
+        for (auto& pr : v) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+    for (hipEvent_t ev : c->event_pool) (void)hipEventDestroy(ev);
+    delete c;
+}
+
+// One operation of an execution list.
+struct Op {
+    int kind;  // 0 push, 1 readout
+    const uint16_t* x;
+    const uint16_t* y;
+    const uint8_t* p;
+    uint32_t n;
+    fibar_readout_buf ro;
+};
+
+int host_validate(const fibar_ctx* c, const fibar_packet* pk)
+{
+    for (size_t e = 0; e < pk->n; ++e)
+        if (pk->x[e] >= c->W || pk->y[e] >= c->H) return FIBAR_E_RANGE;
+    for (size_t e = 0; e < pk->n; ++e)
+        if (pk->p[e] > 1) return FIBAR_E_POLARITY;
+    return FIBAR_OK;
+}
+
+int do_readout_kernel(fibar_ctx* c, const fibar_readout_buf& ro)
+{
+    const int sp = (int)c->prm.spatial_filter;
+    if (ro.on_device) {
+        HIP_TRY(timed_launch(c, 4, [&] {
+            return launch_readout(c->s, sp, ro.brightness, ro.pbar, ro.stale_mask,
+                                  ro.active_count, ro.last_index, ro.log_age, ro.tile_count, c->st);
+        }));
+        return FIBAR_OK;
+    }
+    // host outputs: stage on the device, copy back, synchronise
+    const size_t npx = c->npx;
+    size_t bytes = npx * 4;                       // brightness
+    if (ro.pbar) bytes += npx * 4;
+    if (ro.stale_mask) bytes += (npx + 255) & ~size_t(255);
+    if (ro.active_count) bytes += npx * 4;
+    if (ro.last_index) bytes += npx * 8;
+    if (ro.log_age) bytes += npx * 4;
+    if (ro.tile_count) bytes += c->ntiles * 4;
+    bytes += 8 * 256;
+    uint8_t* stage = nullptr;
+    HIP_TRY(hipMallocAsync((void**)&stage, bytes, c->st));
+    uint8_t* cur = stage;
+    auto take = [&](size_t n) { uint8_t* r = cur; cur += (n + 255) & ~size_t(255); return r; };
+    float* dL = (float*)take(npx * 4);
+    float* dP = ro.pbar ? (float*)take(npx * 4) : nullptr;
+    uint8_t* dS = ro.stale_mask ? take(npx) : nullptr;
+    uint32_t* dC = ro.active_count ? (uint32_t*)take(npx * 4) : nullptr;
+    int64_t* dLi = ro.last_index ? (int64_t*)take(npx * 8) : nullptr;
+    float* dA = ro.log_age ? (float*)take(npx * 4) : nullptr;
+    uint32_t* dT = ro.tile_count ? (uint32_t*)take(c->ntiles * 4) : nullptr;
+    hipError_t e = launch_readout(c->s, sp, dL, dP, dS, dC, dLi, dA, dT, c->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(ro.brightness, dL, npx * 4, hipMemcpyDeviceToHost, c->st);
+    if (e == hipSuccess && dP) e = hipMemcpyAsync(ro.pbar, dP, npx * 4, hipMemcpyDeviceToHost, c->st);
+    if (e == hipSuccess && dS) e = hipMemcpyAsync(ro.stale_mask, dS, npx, hipMemcpyDeviceToHost, c->st);
+    if (e == hipSuccess && dC) e = hipMemcpyAsync(ro.active_count, dC, npx * 4, hipMemcpyDeviceToHost, c->st);
+    if (e == hipSuccess && dLi) e = hipMemcpyAsync(ro.last_index, dLi, npx * 8, hipMemcpyDeviceToHost, c->st);
+    if (e == hipSuccess && dA) e = hipMemcpyAsync(ro.log_age, dA, npx * 4, hipMemcpyDeviceToHost, c->st);
+    if (e == hipSuccess && dT) e = hipMemcpyAsync(ro.tile_count, dT, c->ntiles * 4, hipMemcpyDeviceToHost, c->st);
+    hipError_t e2 = hipFreeAsync(stage, c->st);
+    hipError_t e3 = hipStreamSynchronize(c->st);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = e3;
+    return map_err(e);
+}
+
+// Execute ops[0..n): bulk sort for all pushes, then the in-order steps.
+int run_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, uint32_t n_steps)
+{
+    if (n_chunks > 0) {
+        // the pinned descriptor buffer may still feed a previous copy
+        HIP_TRY(hipEventSynchronize(c->chunks_free));
+        uint32_t ci = 0, step = 0;
+        for (size_t i = 0; i < n; ++i) {
+            if (ops[i].kind != 0) continue;
+            for (uint32_t off = 0; off < ops[i].n; off += kChunk) {
+                ChunkDesc& d = c->h_chunks[ci++];
+                const uint32_t m = ops[i].n - off < (uint32_t)kChunk ? ops[i].n - off : (uint32_t)kChunk;
+                d.x = ops[i].x + off;
+                d.y = ops[i].y + off;
+                d.p = ops[i].p + off;
+                d.n = m;
+                d.pkt = step;
+            }
+            ++step;
+        }
+        HIP_TRY(hipMemcpyAsync(c->d_chunks, c->h_chunks, (size_t)n_chunks * sizeof(ChunkDesc),
+                               hipMemcpyHostToDevice, c->st));
+        HIP_TRY(hipEventRecord(c->chunks_free, c->st));
+        HIP_TRY(hipMemsetAsync(c->scratch, 0, (size_t)n_steps * sizeof(StepScratch), c->st));
+        HIP_TRY(timed_launch(c, 0, [&] {
+            return launch_sort_compose(c->d_chunks, n_chunks, c->seg, c->seg_count, c->scratch,
+                                       c->W, c->H, c->key_bits, c->coef, c->st);
+        }));
+    }
+    uint32_t ci = 0, step = 0;
+    const int sp = (int)c->prm.spatial_filter;
+    for (size_t i = 0; i < n; ++i) {
+        if (ops[i].kind == 1) {
+            int rc = do_readout_kernel(c, ops[i].ro);
+            if (rc) return rc;
+            continue;
+        }
+        StepScratch* stp = c->scratch + step;
+        const uint32_t nev = ops[i].n;
+        for (uint32_t off = 0; off < nev; off += kChunk) {
+            const uint32_t m = nev - off < (uint32_t)kChunk ? nev - off : (uint32_t)kChunk;
+            const int finalize = (!sp && off + kChunk >= nev) ? 1 : 0;
+            HIP_TRY(timed_launch(c, 1, [&] {
+                return launch_apply(c->s, &c->h_chunks[ci], c->seg + (size_t)ci * kChunk,
+                                    c->seg_count + ci, m, off, nev, stp, sp, finalize, c->st);
+            }));
+            ++ci;
+        }
+        if (sp) {
+            HIP_TRY(timed_launch(c, 2, [&] { return launch_pop_blur(c->s, nev, stp, c->st); }));
+            HIP_TRY(timed_launch(c, 3, [&] { return launch_blur_write(c->s, stp, c->st); }));
+        }
+        ++step;
+    }
+    return FIBAR_OK;
+}
+
+// Check, stage and execute a list of public ops.
+int execute(fibar_ctx* c, const fibar_op* ops, size_t n_ops)
+{
+    std::vector<Op> batch;
+    batch.reserve(n_ops < 4096 ? n_ops : 4096);
+    uint32_t n_chunks = 0, n_steps = 0;
+    size_t stg_used = 0;
+    for (size_t i = 0; i < n_ops; ++i) {
+        const fibar_op& op = ops[i];
+        if (op.kind == FIBAR_OP_PUSH) {
+            const fibar_packet& pk = op.packet;
+            if (pk.n == 0) continue;
+            if (pk.n > c->prm.max_packet || !pk.x || !pk.y || !pk.p) {
+                int rc = run_batch(c, batch.data(), batch.size(), n_chunks, n_steps);
+                return rc ? rc : FIBAR_E_INVALID_ARG;
+            }
+            const uint32_t need = (uint32_t)((pk.n + kChunk - 1) / kChunk);
+            const bool host = !pk.on_device;
+            if (n_chunks + need > kMaxBatchChunks || (host && stg_used + pk.n > c->stg_cap)) {
+                int rc = run_batch(c, batch.data(), batch.size(), n_chunks, n_steps);
+                if (rc) return rc;
+                batch.clear();
+                n_chunks = n_steps = 0;
+                stg_used = 0;
+            }
+            Op o{};
+            o.kind = 0;
+            o.n = (uint32_t)pk.n;
+            if (host) {
+                int rc = host_validate(c, &pk);
+                if (rc) {
+                    int rc2 = run_batch(c, batch.data(), batch.size(), n_chunks, n_steps);
+                    return rc2 ? rc2 : rc;
+                }
+                // the staging area is reused by the next batch: copy synchronously
+                HIP_TRY(hipStreamSynchronize(c->st));
+                HIP_TRY(hipMemcpy(c->stg_x + stg_used, pk.x, pk.n * 2, hipMemcpyHostToDevice));
+                HIP_TRY(hipMemcpy(c->stg_y + stg_used, pk.y, pk.n * 2, hipMemcpyHostToDevice));
+                HIP_TRY(hipMemcpy(c->stg_p + stg_used, pk.p, pk.n, hipMemcpyHostToDevice));
+                o.x = c->stg_x + stg_used;
+                o.y = c->stg_y + stg_used;
+                o.p = c->stg_p + stg_used;
+                stg_used += pk.n;
+                if (pk.t && pk.t[pk.n - 1] > c->t_hi) c->t_hi = pk.t[pk.n - 1];
+            } else {
+                o.x = pk.x;
+                o.y = pk.y;
+                o.p = pk.p;
+            }
+            batch.push_back(o);
+            n_chunks += need;
+            n_steps += 1;
+        } else if (op.kind == FIBAR_OP_READOUT) {
+            const fibar_readout_buf& ro = op.readout;
+            int rc = FIBAR_OK;
+            if (!ro.brightness) rc = FIBAR_E_INVALID_ARG;
+            else if (!c->prm.spatial_filter &&
+                     (ro.stale_mask || ro.active_count || ro.tile_count)) rc = FIBAR_E_UNSUPPORTED;
+            else if (op.t < c->t_hi) rc = FIBAR_E_TIME;
+            if (rc) {
+                int rc2 = run_batch(c, batch.data(), batch.size(), n_chunks, n_steps);
+                return rc2 ? rc2 : rc;
+            }
+            c->t_hi = op.t;
+            Op o{};
+            o.kind = 1;
+            o.ro = ro;
+            batch.push_back(o);
+        } else {
+            int rc2 = run_batch(c, batch.data(), batch.size(), n_chunks, n_steps);
+            return rc2 ? rc2 : FIBAR_E_INVALID_ARG;
+        }
+    }
+    return run_batch(c, batch.data(), batch.size(), n_chunks, n_steps);
+}
+
+// Initial state: zero images, no events seen, target length q_max.
+hipError_t init_state(fibar_ctx* c)
+{
+    c->h_sc->k = -1;
+    c->h_sc->h = 0;
+    c->h_sc->Q = c->prm.q_max;
+    c->h_sc->P = c->h_sc->T = 0;
+    c->h_sc->n_reg = c->h_sc->last_stale = c->h_sc->total_stale = 0;
+    c->h_sc->err = 0;
+    c->h_sc->pad = 0;
+    hipError_t e = hipMemsetAsync(c->s.pbar, 0, c->npx * 4, c->st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->s.L, 0, c->npx * 4, c->st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->s.last, 0xff, c->npx * 8, c->st);   // -1
+    if (e == hipSuccess) e = hipMemsetAsync(c->s.cnt, 0, c->npx * 4, c->st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->s.tcnt, 0, c->ntiles * 4, c->st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->s.sc, c->h_sc, sizeof(DevScalars), hipMemcpyHostToDevice, c->st);
+    // the pinned source must not change before the copy has run
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    c->t_hi = 0;
+    return e;
+}
+
+int fetch_scalars(fibar_ctx* c)
+{
+    HIP_TRY(hipMemcpyAsync(c->h_sc, c->s.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, c->st));
+    HIP_TRY(hipStreamSynchronize(c->st));
+    return FIBAR_OK;
+}
+
+// Report and clear a device-side packet error.
+int take_device_error(fibar_ctx* c)
+{
+    const int err = c->h_sc->err;
+    if (err) {
+        const int32_t zero = 0;
+        HIP_TRY(hipMemcpyAsync(&c->s.sc->err, &zero, sizeof(zero), hipMemcpyHostToDevice, c->st));
+        HIP_TRY(hipStreamSynchronize(c->st));
+    }
+    return err;
+}
+
+}  // namespace
+
+extern "C" {
+
+void fibar_default_params(fibar_params* p)
+{
+    if (!p) return;
+    p->t_cut = 40.0;
+    p->fill_num = 1;
+    p->fill_den = 2;
+    p->q_min = 64;
+    p->q_max = 0;
+    p->spatial_filter = 1;
+    p->regulation = FIBAR_REG_PACKET;
+    p->max_packet = 65536;
+    p->stream = nullptr;
+}
+
+int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar_ctx** out)
+{
+    if (!out) return FIBAR_E_INVALID_ARG;
+    *out = nullptr;
+    fibar_params p;
+    if (prm) p = *prm;
+    else fibar_default_params(&p);
+    if (width == 0 || height == 0 || width > 65535 || height > 65535) return FIBAR_E_INVALID_ARG;
+    if (!(p.t_cut > 4.0) || !isfinite(p.t_cut)) return FIBAR_E_INVALID_ARG;
+    if (p.fill_num == 0 || p.fill_den == 0 || p.fill_num > p.fill_den || p.fill_den > 65535)
+        return FIBAR_E_INVALID_ARG;
+    if (p.spatial_filter > 1 || p.regulation != FIBAR_REG_PACKET) return FIBAR_E_INVALID_ARG;
+    if (p.max_packet == 0 || p.max_packet > kMaxPacket) return FIBAR_E_INVALID_ARG;
+    const uint64_t npx = (uint64_t)width * height;
+    if (p.q_max == 0) p.q_max = (uint32_t)npx;
+    if (p.q_min == 0 || p.q_min > p.q_max) return FIBAR_E_INVALID_ARG;
+
+    fibar_ctx* c = new (std::nothrow) fibar_ctx();
+    if (!c) return FIBAR_E_NOMEM;
+    c->W = width;
+    c->H = height;
+    c->TW = (width + 1) / 2;
+    c->TH = (height + 1) / 2;
+    c->npx = npx;
+    c->ntiles = (uint64_t)c->TW * c->TH;
+    c->prm = p;
+    c->st = (hipStream_t)p.stream;
+    double a, b;
+    filter_coefficients(p.t_cut, &a, &b);
+    c->coef.alpha = (float)a;
+    c->coef.one_m_alpha = (float)(1.0 - a);
+    c->coef.beta = (float)b;
+    c->coef.c_alpha = (float)(0.5 * (1.0 + b) * a);
+    int kb = 1;
+    while (kb < 32 && (1ull << kb) < npx) ++kb;
+    c->key_bits = kb;
+
+    uint64_t ring = 1;
+    while (ring < (uint64_t)p.q_max + p.max_packet) ring <<= 1;
+    const uint64_t stg = (uint64_t)kMaxBatchChunks * kChunk;
+
+    hipError_t e = hipSuccess;
+    auto alloc = [&](void** ptr, size_t bytes) {
+        if (e == hipSuccess) e = hipMalloc(ptr, bytes);
+    };
+    alloc((void**)&c->s.pbar, npx * 4);
+    alloc((void**)&c->s.L, npx * 4);
+    alloc((void**)&c->s.last, npx * 8);
+    alloc((void**)&c->s.cnt, npx * 4);
+    alloc((void**)&c->s.tcnt, c->ntiles * 4);
+    alloc((void**)&c->s.ring, ring * 4);
+    alloc((void**)&c->s.sc, sizeof(DevScalars));
+    alloc((void**)&c->s.S, npx * 4);
+    alloc((void**)&c->s.Sval, npx * 4);
+    alloc((void**)&c->d_chunks, kMaxBatchChunks * sizeof(ChunkDesc));
+    alloc((void**)&c->seg, (size_t)kMaxBatchChunks * kChunk * sizeof(SegRec));
+    alloc((void**)&c->seg_count, kMaxBatchChunks * 4);
+    alloc((void**)&c->scratch, kMaxBatchChunks * sizeof(StepScratch));
+    alloc((void**)&c->stg_x, stg * 2);
+    alloc((void**)&c->stg_y, stg * 2);
+    alloc((void**)&c->stg_p, stg);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_chunks, kMaxBatchChunks * sizeof(ChunkDesc), 0);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_sc, sizeof(DevScalars), 0);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->chunks_free, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        int rc = map_err(e);
+        free_ctx(c);
+        return rc;
+    }
+    c->stg_cap = stg;
+    c->s.ring_mask = ring - 1;
+    c->s.W = width;
+    c->s.H = height;
+    c->s.TW = c->TW;
+    c->s.fill_num = p.fill_num;
+    c->s.fill_den = p.fill_den;
+    c->s.q_min = p.q_min;
+    c->s.q_max = p.q_max;
+
+    e = init_state(c);
+    if (e == hipSuccess) e = hipEventRecord(c->chunks_free, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (e != hipSuccess) {
+        int rc = map_err(e);
+        free_ctx(c);
+        return rc;
+    }
+    *out = c;
+    return FIBAR_OK;
+}
+
+int fibar_push_events(fibar_ctx* c, const fibar_packet* pkt)
+{
+    if (!c || !pkt) return FIBAR_E_INVALID_ARG;
+    fibar_op op{};
+    op.kind = FIBAR_OP_PUSH;
+    op.packet = *pkt;
+    return execute(c, &op, 1);
+}
+
+int fibar_readout(fibar_ctx* c, uint64_t t, const fibar_readout_buf* out)
+{
+    if (!c || !out) return FIBAR_E_INVALID_ARG;
+    fibar_op op{};
+    op.kind = FIBAR_OP_READOUT;
+    op.t = t;
+    op.readout = *out;
+    int rc = execute(c, &op, 1);
+    if (rc) return rc;
+    if (!out->on_device) {
+        rc = fetch_scalars(c);
+        if (rc) return rc;
+        return take_device_error(c);
+    }
+    return FIBAR_OK;
+}
+
+int fibar_submit(fibar_ctx* c, const fibar_op* ops, size_t n_ops)
+{
+    if (!c || (!ops && n_ops)) return FIBAR_E_INVALID_ARG;
+    return execute(c, ops, n_ops);
+}
+
+void fibar_destroy(fibar_ctx* c) { free_ctx(c); }
+
+int fibar_get_stats(fibar_ctx* c, fibar_stats* s)
+{
+    if (!c || !s) return FIBAR_E_INVALID_ARG;
+    int rc = fetch_scalars(c);
+    if (rc) return rc;
+    const DevScalars& d = *c->h_sc;
+    s->k = d.k;
+    s->h = d.h;
+    s->q = (uint64_t)(d.k + 1) - d.h;
+    s->Q = d.Q;
+    s->P = d.P;
+    s->T = d.T;
+    s->n_regulations = d.n_reg;
+    s->last_stale = d.last_stale;
+    s->total_stale = d.total_stale;
+    return take_device_error(c);
+}
+
+int fibar_synchronize(fibar_ctx* c)
+{
+    if (!c) return FIBAR_E_INVALID_ARG;
+    int rc = fetch_scalars(c);
+    if (rc) return rc;
+    return take_device_error(c);
+}
+
+int fibar_reset(fibar_ctx* c)
+{
+    if (!c) return FIBAR_E_INVALID_ARG;
+    return map_err(init_state(c));
+}
+
+int fibar_set_kernel_timing(fibar_ctx* c, uint32_t kernel_mask)
+{
+    if (!c || kernel_mask >= (1u << 5)) return FIBAR_E_INVALID_ARG;
+    c->time_mask = kernel_mask;
+    return FIBAR_OK;
+}
+
+int fibar_kernel_time(fibar_ctx* c, int kernel, double* total_ms, uint64_t* launches)
+{
+    if (!c || kernel < 0 || kernel >= 5 || !total_ms || !launches) return FIBAR_E_INVALID_ARG;
+    HIP_TRY(hipStreamSynchronize(c->st));
+    double sum = 0.0;
+    for (auto& pr : c->timed[kernel]) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+        sum += ms;
+        c->event_pool.push_back(pr.first);
+        c->event_pool.push_back(pr.second);
+    }
+    *launches = c->timed[kernel].size();
+    *total_ms = sum;
+    c->timed[kernel].clear();
+    return FIBAR_OK;
+}
+
+const char* fibar_status_string(int status)
+{
+    switch (status) {
+    case FIBAR_OK: return "ok";
+    case FIBAR_E_INVALID_ARG: return "invalid argument";
+    case FIBAR_E_RANGE: return "event coordinate out of range";
+    case FIBAR_E_POLARITY: return "polarity byte not 0 or 1";
+    case FIBAR_E_TIME: return "readout time earlier than a previous time";
+    case FIBAR_E_NOMEM: return "out of memory";
+    case FIBAR_E_DEVICE: return "device error";
+    case FIBAR_E_UNSUPPORTED: return "output not maintained in this mode";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

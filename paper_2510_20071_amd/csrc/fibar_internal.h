@@ -1,0 +1,105 @@
+// Internal declarations shared by the host runtime and the kernels of
+// libfibar.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fibar {
+
+// One LDS sort tile: 1024 threads x 16 events.  A packet larger than this is
+// cut into consecutive chunks that are applied in order.
+constexpr int kSortThreads = 1024;
+constexpr int kSortItems = 16;
+constexpr int kChunk = kSortThreads * kSortItems;
+
+// Filter constants, derived on the host in double precision and rounded once.
+//   one event of polarity p maps the state s = (pbar, L) to
+//   [[alpha, 0], [-c*alpha, beta]] s + [(1-alpha) p, c*alpha p],
+//   c = (1 + beta) / 2  -- Eq. (7), then Eq. (6) and Eq. (10) substituted.
+struct Coef {
+    float alpha;
+    float one_m_alpha;
+    float beta;
+    float c_alpha;
+};
+
+// The composition of all events of one pixel inside one chunk:
+//   s -> [[a, 0], [g, b]] s + [u1, u2]
+// n_last packs the event count (high 16 bits) and the chunk-local index of
+// the pixel's newest event (low 16 bits).
+struct alignas(32) SegRec {
+    uint32_t pix;
+    uint32_t n_last;
+    float a, g, b, u1, u2;
+    uint32_t pad;
+};
+
+// Per-chunk work item of the bulk sort kernel.
+struct ChunkDesc {
+    const uint16_t* x;
+    const uint16_t* y;
+    const uint8_t* p;
+    uint32_t n;        // events in this chunk (<= kChunk)
+    uint32_t pkt;      // packet slot in the current batch
+};
+
+// Window scalars of one context (device resident).
+struct DevScalars {
+    int64_t k;             // index of the newest applied event (-1: none)
+    uint64_t h;            // index of the oldest event in the window
+    uint64_t Q;            // target window length
+    uint64_t P;            // active pixels
+    uint64_t T;            // active 2x2 tiles
+    uint64_t n_reg;        // regulation steps so far
+    uint64_t last_stale;   // pixels blurred in the last step
+    uint64_t total_stale;  // pixels blurred so far
+    int32_t err;           // first device-side packet error (0: none)
+    int32_t pad;
+};
+
+// Per-packet scratch of one batch (zeroed at the start of the batch).
+struct StepScratch {
+    uint32_t status;   // validation bits: 1 = coordinate range, 2 = polarity
+    uint32_t ticket;   // finished blocks of the step's last kernel
+    uint32_t n_stale;  // pixels that went stale in this step
+    uint32_t pad;
+};
+
+// Device pointers of one context's state.
+struct State {
+    float* pbar;
+    float* L;
+    int64_t* last;
+    uint32_t* cnt;
+    uint32_t* tcnt;
+    uint32_t* ring;
+    uint64_t ring_mask;
+    DevScalars* sc;
+    uint32_t* S;      // pixels that went stale in the current step
+    float* Sval;      // their blurred values
+    uint32_t W, H, TW;
+    uint32_t fill_num, fill_den;
+    uint64_t q_min, q_max;
+};
+
+// ---- launchers (fibar_kernels.hip) ---------------------------------------
+hipError_t launch_sort_compose(const ChunkDesc* d_chunks, uint32_t n_chunks, SegRec* seg,
+                               uint32_t* seg_count, StepScratch* scratch, uint32_t W,
+                               uint32_t H, int key_bits, Coef coef, hipStream_t st);
+
+hipError_t launch_apply(const State& s, const ChunkDesc* d_chunk, const SegRec* seg,
+                        const uint32_t* seg_count, uint32_t chunk_events,
+                        uint32_t chunk_offset, uint32_t pkt_events, StepScratch* step,
+                        int spatial, int finalize, hipStream_t st);
+
+hipError_t launch_pop_blur(const State& s, uint32_t pkt_events, StepScratch* step,
+                           hipStream_t st);
+
+hipError_t launch_blur_write(const State& s, StepScratch* step, hipStream_t st);
+
+hipError_t launch_readout(const State& s, int spatial, float* L, float* pbar, uint8_t* stale,
+                          uint32_t* cnt, int64_t* last, float* log_age, uint32_t* tcnt,
+                          hipStream_t st);
+
+}  // namespace fibar

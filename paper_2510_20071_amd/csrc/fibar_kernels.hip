@@ -1,0 +1,609 @@
+// HIP kernels of libfibar for gfx950 (MI355X).
+//
+// Per pushed packet the work splits into a part that does not depend on the
+// reconstruction state (grouping the packet's events by pixel and composing
+// each pixel's temporal-filter updates) and an in-order part (applying the
+// compositions to the state, moving the active-event window, detecting and
+// blurring stale pixels).  The first part runs for many packets in one bulk
+// launch (k_sort_compose, one 1024-thread workgroup per <=16384-event chunk);
+// the second runs packet by packet (k_apply, k_pop_blur, k_blur_write).
+//
+// Paper references: temporal filter Eq. (6), (7), (10); active event queue
+// and its regulation Eq. (19), (20) (Method, "Spatial filtering"); one-time
+// 3x3 Gaussian blur of stale pixels (same section).
+#include "fibar_internal.h"
+
+namespace fibar {
+namespace {
+
+constexpr int kWaves = kSortThreads / 64;
+
+// ---------------------------------------------------------------------------
+// Affine maps of the 2-vector state s = (pbar, L):  s -> [[a,0],[g,b]] s + u
+// ---------------------------------------------------------------------------
+struct Aff {
+    float a, g, b, u1, u2;
+    uint32_t n;
+};
+
+__device__ __forceinline__ Aff aff_identity()
+{
+    Aff r;
+    r.a = 1.f; r.g = 0.f; r.b = 1.f; r.u1 = 0.f; r.u2 = 0.f; r.n = 0u;
+    return r;
+}
+
+// One event of polarity byte `pol` (1 -> +1, 0 -> -1):
+//   pbar' = alpha pbar + (1 - alpha) p                       Eq. (7)
+//   L'    = beta L + c (p - pbar') = beta L - c alpha pbar + c alpha p
+//                                                           Eq. (6), (10)
+__device__ __forceinline__ Aff aff_event(const Coef& c, uint32_t pol)
+{
+    const float p = pol ? 1.f : -1.f;
+    Aff r;
+    r.a = c.alpha;
+    r.g = -c.c_alpha;
+    r.b = c.beta;
+    r.u1 = c.one_m_alpha * p;
+    r.u2 = c.c_alpha * p;
+    r.n = 1u;
+    return r;
+}
+
+// Apply `f` first, then `s`.
+__device__ __forceinline__ Aff aff_then(const Aff& f, const Aff& s)
+{
+    Aff r;
+    r.a = s.a * f.a;
+    r.g = fmaf(s.g, f.a, s.b * f.g);
+    r.b = s.b * f.b;
+    r.u1 = fmaf(s.a, f.u1, s.u1);
+    r.u2 = fmaf(s.g, f.u1, fmaf(s.b, f.u2, s.u2));
+    r.n = f.n + s.n;
+    return r;
+}
+
+// Segmented-scan element: `flag` = a segment starts inside this span.
+struct SegPair {
+    uint32_t flag;
+    Aff v;
+};
+
+// x precedes y.
+__device__ __forceinline__ SegPair seg_combine(const SegPair& x, const SegPair& y)
+{
+    SegPair r;
+    r.flag = x.flag | y.flag;
+    r.v = y.flag ? y.v : aff_then(x.v, y.v);
+    return r;
+}
+
+__device__ __forceinline__ SegPair shfl_up_pair(const SegPair& v, int off)
+{
+    SegPair r;
+    r.flag = __shfl_up(v.flag, off, 64);
+    r.v.a = __shfl_up(v.v.a, off, 64);
+    r.v.g = __shfl_up(v.v.g, off, 64);
+    r.v.b = __shfl_up(v.v.b, off, 64);
+    r.v.u1 = __shfl_up(v.v.u1, off, 64);
+    r.v.u2 = __shfl_up(v.v.u2, off, 64);
+    r.v.n = __shfl_up(v.v.n, off, 64);
+    return r;
+}
+
+// Exclusive segmented scan over the workgroup (thread order).
+__device__ SegPair block_exscan_pair(const SegPair& x, SegPair* lds)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    SegPair inc = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        SegPair o = shfl_up_pair(inc, off);
+        if (lane >= off) inc = seg_combine(o, inc);
+    }
+    if (lane == 63) lds[wave] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        SegPair run;
+        run.flag = 0u;
+        run.v = aff_identity();
+        for (int w = 0; w < kWaves; ++w) {
+            SegPair t = lds[w];
+            lds[w] = run;
+            run = seg_combine(run, t);
+        }
+    }
+    __syncthreads();
+    SegPair ex = shfl_up_pair(inc, 1);
+    if (lane == 0) {
+        ex.flag = 0u;
+        ex.v = aff_identity();
+    }
+    SegPair res = seg_combine(lds[wave], ex);
+    __syncthreads();
+    return res;
+}
+
+// Exclusive sum over the workgroup; *total receives the sum of all threads.
+__device__ uint32_t block_exscan_u32(uint32_t x, uint32_t* lds, uint32_t* total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t o = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += o;
+    }
+    if (lane == 63) lds[wave] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            uint32_t t = lds[w];
+            lds[w] = run;
+            run += t;
+        }
+        lds[kWaves] = run;
+    }
+    __syncthreads();
+    uint32_t res = lds[wave] + inc - x;
+    *total = lds[kWaves];
+    __syncthreads();
+    return res;
+}
+
+// ---------------------------------------------------------------------------
+// Radix digit counters: 16 bins of 16 bits packed into four 64-bit words.
+// A bin never exceeds 16384 (the chunk size), so fields never overflow and
+// packed vectors can be added and scanned as plain integers.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t dig_field(const uint64_t v[4], uint32_t d)
+{
+    const uint32_t q = d >> 2;
+    const uint64_t w = q == 0 ? v[0] : q == 1 ? v[1] : q == 2 ? v[2] : v[3];
+    return (uint32_t)(w >> ((d & 3u) * 16u)) & 0xffffu;
+}
+
+__device__ __forceinline__ void dig_add(uint64_t v[4], uint32_t d)
+{
+    const uint64_t inc = 1ull << ((d & 3u) * 16u);
+    const uint32_t q = d >> 2;
+    v[0] += q == 0 ? inc : 0ull;
+    v[1] += q == 1 ? inc : 0ull;
+    v[2] += q == 2 ? inc : 0ull;
+    v[3] += q == 3 ? inc : 0ull;
+}
+
+__device__ void block_exscan4(const uint64_t x[4], uint64_t ex[4], uint64_t tot[4],
+                              uint64_t (*lds)[4])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint64_t inc[4] = {x[0], x[1], x[2], x[3]};
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint64_t o = __shfl_up(inc[q], off, 64);
+            if (lane >= off) inc[q] += o;
+        }
+    }
+    if (lane == 63) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) lds[wave][q] = inc[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int q = threadIdx.x;
+        uint64_t run = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            uint64_t t = lds[w][q];
+            lds[w][q] = run;
+            run += t;
+        }
+        lds[kWaves][q] = run;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        ex[q] = lds[wave][q] + inc[q] - x[q];
+        tot[q] = lds[kWaves][q];
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Bulk kernel: validate, stable LDS radix sort by pixel, segmented scan of
+// the per-event affine maps.  One workgroup per chunk.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kSortThreads) void k_sort_compose(
+    const ChunkDesc* __restrict__ chunks, SegRec* __restrict__ seg, uint32_t* __restrict__ seg_count,
+    StepScratch* __restrict__ scratch, uint32_t W, uint32_t H, int key_bits, Coef coef)
+{
+    __shared__ uint32_t keypol[kChunk];                 // (pixel << 1) | polarity, arrival order
+    __shared__ __align__(16) uint16_t idxA[kChunk];     // permutation ping
+    __shared__ __align__(16) uint16_t idxB[kChunk];     // permutation pong
+    __shared__ uint64_t scan4[kWaves + 1][4];
+    __shared__ SegPair scanp[kWaves];
+    __shared__ uint32_t scan1[kWaves + 1];
+    __shared__ uint32_t bad_sh;
+
+    const ChunkDesc cd = chunks[blockIdx.x];
+    const uint32_t cn = cd.n;
+    const int tid = threadIdx.x;
+    if (tid == 0) bad_sh = 0u;
+    __syncthreads();
+
+    uint32_t bad = 0u;
+    for (uint32_t e = tid; e < cn; e += kSortThreads) {
+        const uint32_t x = cd.x[e], y = cd.y[e], p = cd.p[e];
+        const bool inr = x < W && y < H;
+        bad |= inr ? 0u : 1u;
+        bad |= p > 1u ? 2u : 0u;
+        keypol[e] = ((inr ? y * W + x : 0u) << 1) | (p & 1u);
+        idxA[e] = (uint16_t)e;
+    }
+    if (bad) atomicOr(&bad_sh, bad);
+    __syncthreads();
+    if (tid == 0 && bad_sh) atomicOr(&scratch[cd.pkt].status, bad_sh);
+
+    // --- stable LSD radix sort of the permutation, 4 bits per pass --------
+    uint16_t* src = idxA;
+    uint16_t* dst = idxB;
+    const uint32_t beg = (uint32_t)tid * kSortItems;
+    for (int shift = 0; shift < key_bits; shift += 4) {
+        uint16_t id[kSortItems];
+        uint32_t dg[kSortItems];
+        {
+            const uint4 v0 = *reinterpret_cast<const uint4*>(src + beg);
+            const uint4 v1 = *reinterpret_cast<const uint4*>(src + beg + 8);
+            const uint32_t w[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                id[2 * j] = (uint16_t)(w[j] & 0xffffu);
+                id[2 * j + 1] = (uint16_t)(w[j] >> 16);
+            }
+        }
+        uint64_t c[4] = {0ull, 0ull, 0ull, 0ull};
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            dg[j] = 0u;
+            if (beg + j < cn) {
+                dg[j] = (keypol[id[j]] >> (1 + shift)) & 15u;
+                dig_add(c, dg[j]);
+            }
+        }
+        uint64_t ex[4], tot[4];
+        block_exscan4(c, ex, tot, scan4);
+        // exclusive prefix over bins, packed the same way (<= 16384 fits)
+        uint64_t sum[4] = {ex[0], ex[1], ex[2], ex[3]};
+        {
+            uint32_t acc = 0u;
+#pragma unroll
+            for (int d = 0; d < 16; ++d) {
+                sum[d >> 2] += (uint64_t)acc << ((d & 3) * 16);
+                acc += dig_field(tot, (uint32_t)d);
+            }
+        }
+        uint64_t run[4] = {0ull, 0ull, 0ull, 0ull};
+#pragma unroll
+        for (int j = 0; j < kSortItems; ++j) {
+            if (beg + j < cn) {
+                const uint32_t pos = dig_field(sum, dg[j]) + dig_field(run, dg[j]);
+                dst[pos] = id[j];
+                dig_add(run, dg[j]);
+            }
+        }
+        __syncthreads();
+        uint16_t* t = src;
+        src = dst;
+        dst = t;
+    }
+
+    // --- segmented scan of the affine maps in sorted (pixel, time) order ----
+    uint32_t key[kSortItems], pol[kSortItems], oid[kSortItems];
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+        key[j] = 0xffffffffu;
+        pol[j] = 0u;
+        oid[j] = 0u;
+        if (beg + j < cn) {
+            oid[j] = src[beg + j];
+            const uint32_t kp = keypol[oid[j]];
+            key[j] = kp >> 1;
+            pol[j] = kp & 1u;
+        }
+    }
+    const uint32_t prevkey = (beg > 0 && beg - 1 < cn) ? (keypol[src[beg - 1]] >> 1) : 0xffffffffu;
+    const uint32_t nextkey = (beg + kSortItems < cn) ? (keypol[src[beg + kSortItems]] >> 1) : 0xffffffffu;
+
+    SegPair agg;
+    agg.flag = 0u;
+    agg.v = aff_identity();
+    uint32_t ntail = 0u;
+    uint32_t headm = 0u, tailm = 0u;
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+        if (beg + j < cn) {
+            const uint32_t pk = j == 0 ? prevkey : key[j - 1];
+            const bool head = (beg + j == 0) || key[j] != pk;
+            const uint32_t nk = j == kSortItems - 1 ? nextkey : key[j + 1];
+            const bool tail = (beg + j == cn - 1) || key[j] != nk;
+            headm |= head ? (1u << j) : 0u;
+            tailm |= tail ? (1u << j) : 0u;
+            const Aff e = aff_event(coef, pol[j]);
+            if (head) {
+                agg.flag = 1u;
+                agg.v = e;
+            } else {
+                agg.v = aff_then(agg.v, e);
+            }
+            ntail += tail ? 1u : 0u;
+        }
+    }
+    const SegPair carry = block_exscan_pair(agg, scanp);
+    uint32_t total;
+    uint32_t outpos = block_exscan_u32(ntail, scan1, &total);
+    SegRec* out = seg + (size_t)blockIdx.x * kChunk;
+    Aff acc = carry.v;
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+        if (beg + j < cn) {
+            const Aff e = aff_event(coef, pol[j]);
+            acc = (headm >> j) & 1u ? e : aff_then(acc, e);
+            if ((tailm >> j) & 1u) {
+                SegRec r;
+                r.pix = key[j];
+                r.n_last = (acc.n << 16) | oid[j];
+                r.a = acc.a;
+                r.g = acc.g;
+                r.b = acc.b;
+                r.u1 = acc.u1;
+                r.u2 = acc.u2;
+                r.pad = 0u;
+                out[outpos++] = r;
+            }
+        }
+    }
+    if (tid == 0) seg_count[blockIdx.x] = total;
+}
+
+__device__ __forceinline__ void record_error(DevScalars* sc, uint32_t status)
+{
+    if (sc->err == 0) sc->err = (status & 1u) ? -2 : -3;  // FIBAR_E_RANGE / FIBAR_E_POLARITY
+}
+
+__device__ __forceinline__ uint32_t tile_of(const State& s, uint32_t pix)
+{
+    const uint32_t y = pix / s.W, x = pix - y * s.W;
+    return (y >> 1) * s.TW + (x >> 1);
+}
+
+// Returns true in exactly one thread of the grid: the last to finish.
+__device__ __forceinline__ bool last_block_done(uint32_t* ticket)
+{
+    __shared__ uint32_t is_last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t t = atomicAdd(ticket, 1u);
+        is_last = (t == gridDim.x - 1) ? 1u : 0u;
+    }
+    __syncthreads();
+    return is_last && threadIdx.x == 0;
+}
+
+// ---------------------------------------------------------------------------
+// In-order kernels
+// ---------------------------------------------------------------------------
+
+// Apply one chunk's compositions to the state; push the chunk's events to
+// the back of the window (spatial filter); count activations.
+__global__ __launch_bounds__(256) void k_apply(State s, ChunkDesc cd, const SegRec* __restrict__ seg,
+                                               const uint32_t* __restrict__ seg_count,
+                                               uint32_t chunk_offset, uint32_t pkt_events,
+                                               StepScratch* step, int spatial, int finalize)
+{
+    const uint32_t status = step->status;
+    if (status) {
+        if (finalize && blockIdx.x == 0 && threadIdx.x == 0) record_error(s.sc, status);
+        return;
+    }
+    const int64_t k0 = s.sc->k;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t first = (uint64_t)(k0 + 1) + chunk_offset;
+    if (spatial && i < cd.n) {
+        const uint32_t x = cd.x[i], y = cd.y[i];
+        s.ring[(first + i) & s.ring_mask] = y * s.W + x;
+    }
+    uint32_t dP = 0u, dT = 0u;
+    if (i < *seg_count) {
+        const SegRec r = seg[i];
+        const uint32_t pix = r.pix;
+        const float pb = s.pbar[pix], l = s.L[pix];
+        s.pbar[pix] = fmaf(r.a, pb, r.u1);
+        s.L[pix] = fmaf(r.g, pb, fmaf(r.b, l, r.u2));
+        s.last[pix] = (int64_t)(first + (r.n_last & 0xffffu));
+        if (spatial) {
+            const uint32_t old = s.cnt[pix];
+            s.cnt[pix] = old + (r.n_last >> 16);
+            if (old == 0u) {
+                dP = 1u;
+                if (atomicAdd(&s.tcnt[tile_of(s, pix)], 1u) == 0u) dT = 1u;
+            }
+        }
+    }
+    if (spatial) {
+        dP = wave_sum(dP);
+        dT = wave_sum(dT);
+        if ((threadIdx.x & 63) == 0) {
+            if (dP) atomicAdd((unsigned long long*)&s.sc->P, (unsigned long long)dP);
+            if (dT) atomicAdd((unsigned long long*)&s.sc->T, (unsigned long long)dT);
+        }
+    }
+    if (finalize && last_block_done(&step->ticket)) s.sc->k = k0 + (int64_t)pkt_events;
+}
+
+// 3x3 binomial blur of L at `pix`, clamp-to-edge, fixed summation order.
+__device__ __forceinline__ float blur_at(const State& s, uint32_t pix)
+{
+    const uint32_t y = pix / s.W, x = pix - y * s.W;
+    const uint32_t xm = x > 0 ? x - 1 : 0, xp = x + 1 < s.W ? x + 1 : s.W - 1;
+    const uint32_t ym = y > 0 ? y - 1 : 0, yp = y + 1 < s.H ? y + 1 : s.H - 1;
+    const float* r0 = s.L + (size_t)ym * s.W;
+    const float* r1 = s.L + (size_t)y * s.W;
+    const float* r2 = s.L + (size_t)yp * s.W;
+    const float h0 = r0[xm] + 2.f * r0[x] + r0[xp];
+    const float h1 = r1[xm] + 2.f * r1[x] + r1[xp];
+    const float h2 = r2[xm] + 2.f * r2[x] + r2[xp];
+    return (h0 + 2.f * h1 + h2) * 0.0625f;
+}
+
+// Move the window head, detect pixels whose last queued event leaves the
+// window, compute their blurred values from the unmodified image, and (last
+// block) update the window scalars and the target length, Eq. (20).
+__global__ __launch_bounds__(256) void k_pop_blur(State s, uint32_t pkt_events, StepScratch* step)
+{
+    const uint32_t status = step->status;
+    if (status) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) record_error(s.sc, status);
+        return;
+    }
+    const int64_t k0 = s.sc->k;
+    const uint64_t k_end = (uint64_t)(k0 + (int64_t)pkt_events);
+    const uint64_t h_old = s.sc->h, Q = s.sc->Q;
+    uint64_t h_new = h_old;
+    if (k_end + 1 > Q && k_end + 1 - Q > h_old) h_new = k_end + 1 - Q;
+
+    uint32_t dP = 0u, dT = 0u;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t j = h_old + blockIdx.x * blockDim.x + threadIdx.x; j < h_new; j += stride) {
+        const uint32_t pix = s.ring[j & s.ring_mask];
+        if (atomicSub(&s.cnt[pix], 1u) == 1u) {
+            ++dP;
+            if (atomicSub(&s.tcnt[tile_of(s, pix)], 1u) == 1u) ++dT;
+            const uint32_t slot = atomicAdd(&step->n_stale, 1u);
+            s.S[slot] = pix;
+            s.Sval[slot] = blur_at(s, pix);
+        }
+    }
+    dP = wave_sum(dP);
+    dT = wave_sum(dT);
+    if ((threadIdx.x & 63) == 0) {
+        if (dP) atomicAdd((unsigned long long*)&s.sc->P, (unsigned long long)(-(int64_t)dP));
+        if (dT) atomicAdd((unsigned long long*)&s.sc->T, (unsigned long long)(-(int64_t)dT));
+    }
+    if (last_block_done(&step->ticket)) {
+        __threadfence();
+        const uint64_t P = atomicAdd((unsigned long long*)&s.sc->P, 0ull);
+        const uint64_t T = atomicAdd((unsigned long long*)&s.sc->T, 0ull);
+        const uint32_t ns = atomicAdd(&step->n_stale, 0u);
+        const uint64_t q = k_end + 1 - h_new;
+        if (P > 0) {
+            const unsigned __int128 num = (unsigned __int128)q * s.fill_num * 4u * T;
+            const unsigned __int128 den = (unsigned __int128)s.fill_den * P;
+            const unsigned __int128 v = num / den;
+            uint64_t Qn = v > s.q_max ? s.q_max : (uint64_t)v;
+            if (Qn < s.q_min) Qn = s.q_min;
+            s.sc->Q = Qn;
+        }
+        s.sc->h = h_new;
+        s.sc->k = (int64_t)k_end;
+        s.sc->n_reg += 1;
+        s.sc->last_stale = ns;
+        s.sc->total_stale += ns;
+    }
+}
+
+// Write the blurred values of the step (after every one of them was read).
+__global__ __launch_bounds__(256) void k_blur_write(State s, StepScratch* step)
+{
+    if (step->status) return;
+    const uint32_t n = step->n_stale;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        s.L[s.S[i]] = s.Sval[i];
+}
+
+__global__ __launch_bounds__(256) void k_readout(State s, int spatial, float* L, float* pbar,
+                                                 uint8_t* stale, uint32_t* cnt, int64_t* last,
+                                                 float* log_age, uint32_t* tcnt)
+{
+    const uint64_t npx = (uint64_t)s.W * s.H;
+    const int64_t k = s.sc->k;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < npx; i += stride) {
+        L[i] = s.L[i];
+        if (pbar) pbar[i] = s.pbar[i];
+        int64_t li = 0;
+        if (last || log_age || stale) li = s.last[i];
+        if (last) last[i] = li;
+        if (log_age) log_age[i] = log1pf((float)(k - li));
+        if (spatial) {
+            const uint32_t c = s.cnt[i];
+            if (cnt) cnt[i] = c;
+            if (stale) stale[i] = (li >= 0 && c == 0u) ? 1u : 0u;
+        }
+    }
+    if (spatial && tcnt) {
+        const uint64_t nt = (uint64_t)s.TW * ((s.H + 1) / 2);
+        for (uint64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += stride) tcnt[i] = s.tcnt[i];
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_sort_compose(const ChunkDesc* d_chunks, uint32_t n_chunks, SegRec* seg,
+                               uint32_t* seg_count, StepScratch* scratch, uint32_t W,
+                               uint32_t H, int key_bits, Coef coef, hipStream_t st)
+{
+    if (n_chunks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sort_compose, dim3(n_chunks), dim3(kSortThreads), 0, st, d_chunks, seg,
+                       seg_count, scratch, W, H, key_bits, coef);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply(const State& s, const ChunkDesc* d_chunk, const SegRec* seg,
+                        const uint32_t* seg_count, uint32_t chunk_events, uint32_t chunk_offset,
+                        uint32_t pkt_events, StepScratch* step, int spatial, int finalize,
+                        hipStream_t st)
+{
+    const uint32_t blocks = (chunk_events + 255) / 256;
+    hipLaunchKernelGGL(k_apply, dim3(blocks ? blocks : 1), dim3(256), 0, st, s, *d_chunk, seg,
+                       seg_count, chunk_offset, pkt_events, step, spatial, finalize);
+    return hipGetLastError();
+}
+
+hipError_t launch_pop_blur(const State& s, uint32_t pkt_events, StepScratch* step, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pop_blur, dim3(256), dim3(256), 0, st, s, pkt_events, step);
+    return hipGetLastError();
+}
+
+hipError_t launch_blur_write(const State& s, StepScratch* step, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_blur_write, dim3(256), dim3(256), 0, st, s, step);
+    return hipGetLastError();
+}
+
+hipError_t launch_readout(const State& s, int spatial, float* L, float* pbar, uint8_t* stale,
+                          uint32_t* cnt, int64_t* last, float* log_age, uint32_t* tcnt,
+                          hipStream_t st)
+{
+    const uint64_t npx = (uint64_t)s.W * s.H;
+    uint64_t blocks = (npx + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_readout, dim3((uint32_t)blocks), dim3(256), 0, st, s, spatial, L, pbar,
+                       stale, cnt, last, log_age, tcnt);
+    return hipGetLastError();
+}
+
+}  // namespace fibar

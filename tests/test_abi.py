@@ -1,0 +1,72 @@
+"""The C-ABI library: it is built, loads, and exports every declared symbol.
+
+No compute call is made here (no GPU in this environment)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2510_20071_amd as fb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if not fn.endswith(".h"):
+            continue
+        src = open(os.path.join(inc, fn)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w \*]*?\b(fibar_\w+)\s*\(", src, flags=re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("fibar_create", "fibar_push_events", "fibar_readout", "fibar_destroy"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(fb.LIB_PATH):
+        pytest.fail("libfibar.so is not built")
+    lib = ctypes.CDLL(fb.LIB_PATH)
+    for name in sorted(declared_functions()):
+        assert hasattr(lib, name), name
+    # and the binding wraps every one of them under the same name
+    for name in declared_functions():
+        assert name in fb._SIGNATURES, name
+        assert callable(getattr(fb, name)), name
+
+
+def test_binding_structs_match_header_sizes():
+    # x86-64 SysV layout of the public structs
+    assert ctypes.sizeof(fb.fibar_params) == 8 + 7 * 4 + 4 + 8
+    assert ctypes.sizeof(fb.fibar_packet) == 4 * 8 + 8 + 8
+    assert ctypes.sizeof(fb.fibar_readout_buf) == 7 * 8 + 8
+    assert ctypes.sizeof(fb.fibar_stats) == 9 * 8
+
+
+def test_status_strings_and_defaults_without_gpu():
+    lib = fb.load()
+    assert fb.fibar_status_string(fb.FIBAR_E_RANGE).startswith("event coordinate")
+    p = fb.fibar_default_params()
+    assert p.t_cut == 40.0 and (p.fill_num, p.fill_den) == (1, 2)
+    assert p.spatial_filter == 1 and p.q_min == 64 and p.q_max == 0
+    # argument validation happens before any device call
+    assert fb.fibar_create(0, 10, p)[0] == fb.FIBAR_E_INVALID_ARG
+    bad = fb.fibar_default_params()
+    bad.t_cut = 4.0
+    assert fb.fibar_create(10, 10, bad)[0] == fb.FIBAR_E_INVALID_ARG
+    bad = fb.fibar_default_params()
+    bad.fill_num, bad.fill_den = 3, 2
+    assert fb.fibar_create(10, 10, bad)[0] == fb.FIBAR_E_INVALID_ARG
+    bad = fb.fibar_default_params()
+    bad.q_min = 1000
+    assert fb.fibar_create(10, 10, bad)[0] == fb.FIBAR_E_INVALID_ARG
+    assert lib.fibar_push_events(None, None) == fb.FIBAR_E_INVALID_ARG
+    lib.fibar_destroy(None)

@@ -1,0 +1,260 @@
+"""GPU parity: libfibar (HIP, through the C ABI) against the FP64 oracle.
+
+Integer state (active counts, last-update indices, stale masks, active
+tiles, window scalars) must match bit for bit; brightness and the polarity
+average within 1e-5 relative (per pixel, with a floor of one event's step).
+"""
+import numpy as np
+import pytest
+
+import eventsim
+import oracle
+import paper_2510_20071_amd as fb
+from _harness import (REL, compare_state, compare_stats, make_ctx, run_pair, to_device,
+                      torch_dev)
+
+pytestmark = pytest.mark.gpu
+
+
+def flush(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("spatial", [True, False])
+def test_sensor64x48_full_stream(spatial):
+    w = eventsim.preset("sensor64x48")
+    ev = eventsim.generate(w.scene)
+    flush("sensor64x48 200k events, spatial=%s" % spatial)
+    sched = eventsim.schedule(len(ev), w.packet, w.readouts)
+    run_pair(ev, 64, 48, sched, spatial_filter=spatial)
+
+
+def test_ragged_packets_spanning_chunks():
+    w = eventsim.preset("sensor64x48", n_events=150000, seed=7)
+    ev = eventsim.generate(w.scene)
+    sizes = [1, 2, 3, 17, 1023, 1024, 1025, 16383, 16384, 16385, 40000, 5, 7, 33000]
+    sched, a = [], 0
+    i = 0
+    while a < len(ev):
+        b = min(len(ev), a + sizes[i % len(sizes)])
+        sched.append(("push", a, b))
+        sched.append(("read", b))
+        a = b
+        i += 1
+    flush("ragged packets on 64x48 (%d pushes)" % (len(sched) // 2))
+    run_pair(ev, 64, 48, sched, q_min=8)
+
+
+@pytest.mark.parametrize("W,H", [(1, 1), (2, 2), (4, 2), (3, 3), (5, 4)])
+def test_tiny_sensors(W, H):
+    rng = np.random.default_rng(W * 10 + H)
+    n = 3000
+    pix = np.empty(n, np.int64)
+    cur = 0
+    for e in range(n):
+        if rng.random() < 0.35:
+            cur = int(rng.integers(0, W * H))
+        pix[e] = cur
+    ev = eventsim.Events((pix % W).astype(np.uint16), (pix // W).astype(np.uint16),
+                         (rng.random(n) < 0.5).astype(np.uint8), np.arange(n, dtype=np.uint64))
+    sched, a = [], 0
+    while a < n:
+        b = min(n, a + int(rng.integers(1, 9)))
+        sched.append(("push", a, b))
+        sched.append(("read", b))
+        a = b
+    flush("tiny sensor %dx%d" % (W, H))
+    run_pair(ev, W, H, sched, q_min=1)
+
+
+def test_single_pixel_long_segments_closed_form():
+    W, H = 16, 8
+    n = 50000
+    ev = eventsim.Events(np.full(n, 5, np.uint16), np.full(n, 3, np.uint16),
+                         np.ones(n, np.uint8), np.arange(n, dtype=np.uint64))
+    sched = [("push", 0, 20000), ("read", 20000), ("push", 20000, 20001), ("read", 20001),
+             ("push", 20001, 50000), ("read", 50000)]
+    flush("single pixel, segments of 20000 and 29999 events")
+    g, r = run_pair(ev, W, H, sched, q_min=1, max_packet=1 << 20)
+    a, b = oracle.coefficients(40.0)
+    i = 3 * W + 5
+    assert abs(g["pbar"][i] - (1.0 - a ** n)) <= REL
+    assert abs(g["L"][i]) <= REL   # decayed to zero after 50000 identical events
+
+
+def test_polarity_flip_is_exact_negation():
+    w = eventsim.preset("sensor64x48", n_events=60000, seed=3)
+    ev = eventsim.generate(w.scene)
+    flip = eventsim.Events(ev.x, ev.y, (1 - ev.p).astype(np.uint8), ev.t)
+    outs = []
+    for e in (ev, flip):
+        ctx = make_ctx(64, 48, q_min=16)
+        gx, gy, gp = to_device(e)
+        for a in range(0, len(e), 1024):
+            assert ctx.push(gx[a:a + 1024], gy[a:a + 1024], gp[a:a + 1024]) == 0
+        outs.append(ctx.readout_host(0))
+        ctx.close()
+    assert np.array_equal(outs[0]["L"], -outs[1]["L"])
+    assert np.array_equal(outs[0]["pbar"], -outs[1]["pbar"])
+    for key in ("cnt", "stale", "last", "tcnt"):
+        assert np.array_equal(outs[0][key], outs[1][key])
+
+
+def test_same_input_twice_is_bit_identical():
+    w = eventsim.preset("vga", n_events=400000, seed=12)
+    ev = eventsim.generate(w.scene)
+    outs = []
+    for _ in range(2):
+        ctx = make_ctx(640, 480)
+        gx, gy, gp = to_device(ev)
+        for a in range(0, len(ev), 8192):
+            assert ctx.push(gx[a:a + 8192], gy[a:a + 8192], gp[a:a + 8192]) == 0
+        outs.append(ctx.readout_host(0))
+        ctx.close()
+    for key in outs[0]:
+        assert np.array_equal(outs[0][key], outs[1][key]), key
+
+
+@pytest.mark.parametrize("spatial", [True, False])
+def test_vga_two_million_events(spatial):
+    w = eventsim.preset("vga", n_events=2_000_000)
+    ev = eventsim.generate(w.scene)
+    sched = eventsim.schedule(len(ev), w.packet, w.readouts)
+    flush("vga 2M events, spatial=%s" % spatial)
+    run_pair(ev, 640, 480, sched, check_every_read=8, spatial_filter=spatial)
+
+
+def test_hd720_twenty_million_events():
+    w = eventsim.preset("hd720", n_events=20_000_000)
+    ev = eventsim.generate(w.scene)
+    sched = eventsim.schedule(len(ev), w.packet, w.readouts)
+    flush("hd720 20M events, blur on, %d readouts" % len(w.readouts))
+    run_pair(ev, 1280, 720, sched, check_every_read=25)
+
+
+def test_empty_push_and_repeated_readout_change_nothing():
+    w = eventsim.preset("sensor64x48", n_events=30000)
+    ev = eventsim.generate(w.scene)
+    ctx = make_ctx(64, 48)
+    gx, gy, gp = to_device(ev)
+    for a in range(0, len(ev), 1024):
+        assert ctx.push(gx[a:a + 1024], gy[a:a + 1024], gp[a:a + 1024]) == 0
+    r1 = ctx.readout_host(0)
+    s1 = ctx.stats()
+    assert ctx.push(gx[:0], gy[:0], gp[:0]) == 0
+    r2 = ctx.readout_host(0)
+    assert ctx.stats() == s1
+    for key in r1:
+        assert np.array_equal(r1[key], r2[key])
+    ctx.close()
+
+
+def test_device_packet_rejection_changes_nothing():
+    torch, dev = torch_dev()
+    w = eventsim.preset("sensor64x48", n_events=20000)
+    ev = eventsim.generate(w.scene)
+    ctx = make_ctx(64, 48)
+    orc = oracle.Oracle(64, 48)
+    gx, gy, gp = to_device(ev)
+    assert ctx.push(gx[:5000], gy[:5000], gp[:5000]) == 0
+    orc.push(ev.x[:5000], ev.y[:5000], ev.p[:5000])
+    before = ctx.readout_host(0)
+    bx = gx[5000:6000].clone()
+    bx[17] = 64                       # x == width
+    assert ctx.push(bx, gy[5000:6000], gp[5000:6000]) == 0   # checked on the device
+    assert ctx.synchronize() == fb.FIBAR_E_RANGE
+    assert ctx.synchronize() == 0     # reported once
+    bp = gp[5000:6000].clone()
+    bp[3] = 2
+    assert ctx.push(gx[5000:6000], gy[5000:6000], bp) == 0
+    assert ctx.synchronize() == fb.FIBAR_E_POLARITY
+    after = ctx.readout_host(0)
+    for key in before:
+        assert np.array_equal(before[key], after[key]), key
+    # the stream continues normally
+    assert ctx.push(gx[5000:], gy[5000:], gp[5000:]) == 0
+    orc.push(ev.x[5000:], ev.y[5000:], ev.p[5000:])
+    compare_state(ctx.readout_host(0), orc.readout(0), True, "after rejection")
+    compare_stats(ctx.stats(), orc.stats())
+    ctx.close()
+
+
+def test_host_packets_and_errors():
+    w = eventsim.preset("sensor64x48", n_events=20000)
+    ev = eventsim.generate(w.scene)
+    ctx = make_ctx(64, 48)
+    orc = oracle.Oracle(64, 48)
+    for a in range(0, len(ev), 3000):
+        sl = slice(a, a + 3000)
+        assert ctx.push(ev.x[sl], ev.y[sl], ev.p[sl], ev.t[sl]) == 0
+        orc.push(ev.x[sl], ev.y[sl], ev.p[sl], ev.t[sl])
+    x = ev.x[:10].copy()
+    x[2] = 999
+    assert ctx.push(x, ev.y[:10], ev.p[:10]) == fb.FIBAR_E_RANGE
+    p = ev.p[:10].copy()
+    p[0] = 7
+    assert ctx.push(ev.x[:10], ev.y[:10], p) == fb.FIBAR_E_POLARITY
+    assert ctx.readout_host(int(ev.t[-1]) - 1) == fb.FIBAR_E_TIME
+    compare_state(ctx.readout_host(int(ev.t[-1])), orc.readout(int(ev.t[-1])), True)
+    big = np.zeros(70000, np.uint16)
+    assert ctx.push(big, big, big.astype(np.uint8)) == fb.FIBAR_E_INVALID_ARG
+    ctx.close()
+
+
+def test_submit_equals_single_calls_and_device_readouts():
+    torch, dev = torch_dev()
+    w = eventsim.preset("vga", n_events=600000, seed=4)
+    ev = eventsim.generate(w.scene)
+    gx, gy, gp = to_device(ev)
+    ro = [100000, 250001, 400000, 600000]
+    sched = eventsim.schedule(len(ev), w.packet, ro)
+    # one call per op
+    c1 = make_ctx(640, 480)
+    res1 = []
+    for it in sched:
+        if it[0] == "push":
+            assert c1.push(gx[it[1]:it[2]], gy[it[1]:it[2]], gp[it[1]:it[2]]) == 0
+        else:
+            res1.append(c1.readout_host(0))
+    # one submit of the whole schedule, readouts into device buffers
+    c2 = make_ctx(640, 480)
+    npx = 640 * 480
+    bufs = []
+    ops = []
+    for it in sched:
+        if it[0] == "push":
+            ops.append(fb.push_op(gx[it[1]:it[2]], gy[it[1]:it[2]], gp[it[1]:it[2]]))
+        else:
+            b = dict(L=torch.empty(npx, dtype=torch.float32, device=dev),
+                     stale=torch.empty(npx, dtype=torch.uint8, device=dev),
+                     cnt=torch.empty(npx, dtype=torch.int32, device=dev),
+                     last=torch.empty(npx, dtype=torch.int64, device=dev),
+                     log_age=torch.empty(npx, dtype=torch.float32, device=dev))
+            bufs.append(b)
+            ops.append(fb.readout_op(0, b["L"], stale=b["stale"], cnt=b["cnt"], last=b["last"],
+                                     log_age=b["log_age"]))
+    assert c2.submit(ops) == 0
+    torch.cuda.synchronize()
+    for r, b in zip(res1, bufs):
+        assert np.array_equal(r["L"], b["L"].cpu().numpy())
+        assert np.array_equal(r["stale"], b["stale"].cpu().numpy())
+        assert np.array_equal(r["cnt"].view(np.int32), b["cnt"].cpu().numpy())
+        assert np.array_equal(r["last"], b["last"].cpu().numpy())
+        assert np.array_equal(r["log_age"], b["log_age"].cpu().numpy())
+    # log age definition
+    k = len(ev) - 1
+    last = bufs[-1]["last"].cpu().numpy()
+    want = np.log1p((k - last).astype(np.float64))
+    assert np.allclose(bufs[-1]["log_age"].cpu().numpy(), want, rtol=1e-6, atol=1e-6)
+    c1.close()
+    c2.close()
+
+
+def test_nsf_rejects_spatial_outputs():
+    ctx = make_ctx(32, 16, spatial_filter=False, q_min=1)
+    npx = 32 * 16
+    L = np.empty(npx, np.float32)
+    st = np.empty(npx, np.uint8)
+    buf = fb.fibar_readout_buf(L.ctypes.data, None, st.ctypes.data, None, None, None, None, 0)
+    assert fb.fibar_readout(ctx.handle, 0, buf) == fb.FIBAR_E_UNSUPPORTED
+    ctx.close()
