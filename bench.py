@@ -1,0 +1,259 @@
+#!/usr/bin/env python3
+"""Throughput of the FIBAR hot path on one MI355X.
+
+Workload (hd720): a 1280x720 sensor, 100 M events from the seeded simulator
+(2048 blobs, rotation 0.5 rad/s + translation 300 px/s, threshold 0.15, 2 %
+noise), pushed in 16384-event packets, with readouts of the brightness image
+at ~1000 random event indices (mean spacing 100 000; a readout inside a
+packet splits it).  Events are resident in device memory before timing.
+
+One step = the whole stream from a freshly reset context: every packet
+pushed (temporal filter, window bookkeeping, stale blur) and every readout
+written to its own device buffer, submitted through the C ABI.  The JSON
+line reports Mev/s with the spatial filter on (FIBAR) and, as extra fields,
+with it off (FIBAR-NSF).
+
+Extra legs: the FP64 CPU oracle timed on this host over a bounded sample of
+the same stream (cpu_baseline), and a parity check of the GPU's final state
+against the oracle's.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic bytes per unit of work of each kernel (see the design notes):
+#   apply      : per distinct (pixel, packet): pbar, L read+write (16 B), last
+#                write (8 B), active count read+write (8 B); per event: x, y
+#                read (4 B) and window ring write (4 B).
+#   pop_blur   : per popped event: ring read (4 B) + active count read+write
+#                (8 B); per stale pixel: 9 brightness reads (36 B) + blurred
+#                value written (4 B) + tile count read+write (8 B).
+#   group      : per event: x, y, p read (5 B); per distinct (pixel, chunk):
+#                one 32-B composed-map record written.
+KERNELS = ("group_compose", "apply", "pop_blur", "blur_write", "readout")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def distinct_per_packet(x, y, W, packet, sample_every=16):
+    """Mean number of distinct pixels per packet, over every 16th packet."""
+    n = x.shape[0]
+    tot_d, tot_e = 0, 0
+    for a in range(0, n, packet * sample_every):
+        b = min(n, a + packet)
+        pix = y[a:b].astype(np.int64) * W + x[a:b]
+        tot_d += np.unique(pix).size
+        tot_e += b - a
+    return tot_d / max(tot_e, 1)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--events", type=int, default=100_000_000)
+    ap.add_argument("--cpu-sample-events", type=int, default=100_000_000,
+                    help="events of the stream the oracle is timed on")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-nsf", action="store_true", help="skip the blur-off measurement")
+    ap.add_argument("--roofline-kernel", default="pop_blur", choices=KERNELS)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the FIBAR path keeps one global window per "
+              "stream and this build has no multi-GPU path (see the design notes for how it "
+              "would shard). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import eventsim
+    import paper_2510_20071_amd as fb
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    fb.load()
+
+    wl = eventsim.preset("hd720", n_events=args.events)
+    W, H = wl.scene.width, wl.scene.height
+    npx = W * H
+    t0 = time.time()
+    ev = eventsim.generate(wl.scene)
+    n = len(ev)
+    log("generated %d events in %.1f s" % (n, time.time() - t0))
+    sched = eventsim.schedule(n, wl.packet, wl.readouts)
+    n_push = sum(1 for it in sched if it[0] == "push")
+    n_read = sum(1 for it in sched if it[0] == "read")
+
+    gx = torch.from_numpy(ev.x.view(np.int16)).to(dev)
+    gy = torch.from_numpy(ev.y.view(np.int16)).to(dev)
+    gp = torch.from_numpy(ev.p).to(dev)
+    frames = torch.empty((n_read, npx), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    bx, by, bp = gx.data_ptr(), gy.data_ptr(), gp.data_ptr()
+    fptr = frames.data_ptr()
+
+    def build_ops():
+        ops = []
+        r = 0
+        for it in sched:
+            if it[0] == "push":
+                a, b = it[1], it[2]
+                op = fb.fibar_op()
+                op.kind = fb.FIBAR_OP_PUSH
+                op.packet = fb.fibar_packet(bx + 2 * a, by + 2 * a, bp + a, None, b - a, 1)
+                ops.append(op)
+            else:
+                op = fb.fibar_op()
+                op.kind = fb.FIBAR_OP_READOUT
+                op.t = int(ev.t[it[1] - 1])
+                op.readout = fb.fibar_readout_buf(fptr + 4 * npx * r, None, None, None, None,
+                                                  None, None, 1)
+                ops.append(op)
+                r += 1
+        return (fb.fibar_op * len(ops))(*ops), len(ops)
+
+    ops, n_ops = build_ops()
+    lib = fb.load()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+
+    def run_mode(spatial, steps, warmup, time_kernel=None):
+        ctx = fb.Context(W, H, spatial_filter=spatial, stream=stream)
+        for _ in range(warmup):
+            assert ctx.reset() == 0
+            assert lib.fibar_submit(ctx.handle, ops, n_ops) == 0
+        torch.cuda.synchronize()
+        if time_kernel is not None:
+            fb.fibar_set_kernel_timing(ctx.handle, 1 << KERNELS.index(time_kernel))
+            fb.fibar_kernel_time(ctx.handle, KERNELS.index(time_kernel))  # clear
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for _ in range(steps):
+            assert ctx.reset() == 0
+            assert lib.fibar_submit(ctx.handle, ops, n_ops) == 0
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        kt = None
+        if time_kernel is not None:
+            rc, ms, launches = fb.fibar_kernel_time(ctx.handle, KERNELS.index(time_kernel))
+            kt = (ms, launches)
+            fb.fibar_set_kernel_timing(ctx.handle, 0)
+        assert ctx.synchronize() == 0
+        st = ctx.stats() if spatial else None
+        final = ctx.readout_host(int(ev.t[-1]))
+        ctx.close()
+        return elapsed, kt, st, final
+
+    el_on, kt, st_on, final_on = run_mode(True, args.steps, args.warmup, args.roofline_kernel)
+    mev_on = n * args.steps / el_on / 1e6
+    log("blur on : %.1f ms/step, %.1f Mev/s" % (1e3 * el_on / args.steps, mev_on))
+    mev_off = None
+    if not args.no_nsf:
+        el_off, _, _, final_off = run_mode(False, args.steps, args.warmup)
+        mev_off = n * args.steps / el_off / 1e6
+        log("blur off: %.1f ms/step, %.1f Mev/s" % (1e3 * el_off / args.steps, mev_off))
+
+    # ---- roofline of the timed kernel ------------------------------------
+    u = distinct_per_packet(ev.x, ev.y, W, wl.packet)          # distinct pixels / event
+    s_per_ev = st_on["total_stale"] / n                         # stale pixels / event
+    pops_per_ev = (st_on["h"]) / n                              # popped events / event
+    ms, launches = kt
+    avg_s = ms / 1e3 / max(launches, 1)
+    if args.roofline_kernel == "pop_blur":
+        per_launch = (12.0 * pops_per_ev + 48.0 * s_per_ev) * n / n_push
+    elif args.roofline_kernel == "apply":
+        per_launch = (32.0 * u + 8.0) * n / n_push
+    elif args.roofline_kernel == "group_compose":
+        per_launch = (5.0 + 32.0 * u) * n / max(launches, 1)
+    elif args.roofline_kernel == "readout":
+        per_launch = 8.0 * npx
+    else:
+        per_launch = 8.0 * s_per_ev * n / n_push
+    achieved = per_launch / avg_s / 1e9
+    roofline = {"bound": "hbm", "kernel": args.roofline_kernel, "achieved": round(achieved, 2),
+                "peak": 8000.0, "unit": "GB/s", "frac": round(achieved / 8000.0, 5),
+                "traffic": None, "avg_launch_us": round(avg_s * 1e6, 3), "launches": launches,
+                "bytes_per_launch": round(per_launch, 1)}
+
+    # ---- CPU baseline (the FP64 oracle) and parity -------------------------
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        import ctypes
+
+        import oracle
+        m = min(args.cpu_sample_events, n)
+        orc = oracle.Oracle(W, H)
+        lo = oracle._load()
+        Lbuf = np.empty(npx, np.float64)
+        sub = [it for it in sched if (it[0] == "push" and it[2] <= m) or
+               (it[0] == "read" and it[1] <= m)]
+        t0 = time.perf_counter()
+        for it in sub:
+            if it[0] == "push":
+                a, b = it[1], it[2]
+                lo.fibar_ref_push_events(orc._h, ev.x[a:b].ctypes.data, ev.y[a:b].ctypes.data,
+                                         ev.p[a:b].ctypes.data, None, b - a)
+            else:
+                lo.fibar_ref_readout(orc._h, int(ev.t[it[1] - 1]), Lbuf.ctypes.data, None, None,
+                                     None, None, None, None)
+        cpu_s = time.perf_counter() - t0
+        cpu = {"value": round(m / cpu_s / 1e6, 3), "unit": "Mev/s", "cores": 1, "kind": "oracle",
+               "sample": "first %d events of the hd720 stream with their readouts, blur on, "
+                         "FP64, one thread" % m}
+        log("oracle: %d events in %.1f s (%.2f Mev/s)" % (m, cpu_s, m / cpu_s / 1e6))
+        if m == n:
+            r = orc.readout(int(ev.t[-1]))
+            ints = all(np.array_equal(final_on[k].astype(np.int64), r[k].astype(np.int64))
+                       for k in ("cnt", "last", "stale", "tcnt"))
+            d = np.abs(final_on["L"].astype(np.float64) - r["L"])
+            rel = float((d / np.maximum(np.abs(r["L"]), 1.0)).max())
+            parity = {"integer_state_bit_exact": bool(ints), "max_rel_err_L": rel,
+                      "window_scalars_equal": all(st_on[f] == orc.stats()[f]
+                                                  for f in ("k", "h", "Q", "P", "T"))}
+            log("parity: %s" % parity)
+
+    out = {
+        "metric": "Mev/s reconstructed at 1280x720 (blur on)",
+        "value": round(mev_on, 2),
+        "unit": "Mev/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * el_on / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "hd720: 1280x720 sensor, %d events, %d-event packets, %d readouts "
+                               "(random indices), T_cut=40, r_fill=1/2, spatial filter on"
+                               % (n, wl.packet, n_read),
+                   "events": n, "packets": n_push, "readouts": n_read},
+        "blur_off_mev_s": None if mev_off is None else round(mev_off, 2),
+        "workload_stats": {"distinct_pixels_per_event": round(u, 4),
+                           "stale_pixels_per_event": round(s_per_ev, 5),
+                           "final_queue_length": st_on["q"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity": parity,
+        "paper_cpu_context_mev_s": {"blur_on": 42, "blur_off": 140},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

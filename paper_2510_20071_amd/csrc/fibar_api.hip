@@ -57,6 +57,7 @@ struct fibar_ctx {
     uint8_t* stg_p = nullptr;
     size_t stg_cap = 0;
     DevScalars* h_sc = nullptr;         // pinned copy for stats
+    int cur_slot = 0;                   // scalar slot holding the committed state
     uint64_t t_hi = 0;
     // optional per-kernel timing
     uint32_t time_mask = 0;
@@ -111,14 +112,12 @@ void free_ctx(fibar_ctx* c)
     if (c->st) hipStreamSynchronize(c->st);
     else hipDeviceSynchronize();
     hipFree(c->s.pbar);
-    hipFree(c->s.L);
+    hipFree(c->s.Lp);
     hipFree(c->s.last);
     hipFree(c->s.cnt);
     hipFree(c->s.tcnt);
     hipFree(c->s.ring);
     hipFree(c->s.sc);
-    hipFree(c->s.S);
-    hipFree(c->s.Sval);
     hipFree(c->d_chunks);
     hipFree(c->seg);
     hipFree(c->seg_count);
@@ -157,13 +156,16 @@ int host_validate(const fibar_ctx* c, const fibar_packet* pk)
     return FIBAR_OK;
 }
 
-int do_readout_kernel(fibar_ctx* c, const fibar_readout_buf& ro)
+int do_readout_kernel(fibar_ctx* c, const fibar_readout_buf& ro, const StepScratch* pend,
+                      uint32_t pend_n)
 {
     const int sp = (int)c->prm.spatial_filter;
+    const int slot = c->cur_slot;
     if (ro.on_device) {
         HIP_TRY(timed_launch(c, 4, [&] {
-            return launch_readout(c->s, sp, ro.brightness, ro.pbar, ro.stale_mask,
-                                  ro.active_count, ro.last_index, ro.log_age, ro.tile_count, c->st);
+            return launch_readout(c->s, sp, pend, pend_n, slot, ro.brightness, ro.pbar,
+                                  ro.stale_mask, ro.active_count, ro.last_index, ro.log_age,
+                                  ro.tile_count, c->st);
         }));
         return FIBAR_OK;
     }
@@ -188,7 +190,7 @@ int do_readout_kernel(fibar_ctx* c, const fibar_readout_buf& ro)
     int64_t* dLi = ro.last_index ? (int64_t*)take(npx * 8) : nullptr;
     float* dA = ro.log_age ? (float*)take(npx * 4) : nullptr;
     uint32_t* dT = ro.tile_count ? (uint32_t*)take(c->ntiles * 4) : nullptr;
-    hipError_t e = launch_readout(c->s, sp, dL, dP, dS, dC, dLi, dA, dT, c->st);
+    hipError_t e = launch_readout(c->s, sp, pend, pend_n, slot, dL, dP, dS, dC, dLi, dA, dT, c->st);
     if (e == hipSuccess) e = hipMemcpyAsync(ro.brightness, dL, npx * 4, hipMemcpyDeviceToHost, c->st);
     if (e == hipSuccess && dP) e = hipMemcpyAsync(ro.pbar, dP, npx * 4, hipMemcpyDeviceToHost, c->st);
     if (e == hipSuccess && dS) e = hipMemcpyAsync(ro.stale_mask, dS, npx, hipMemcpyDeviceToHost, c->st);
@@ -234,28 +236,39 @@ int run_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, uint32_t
     }
     uint32_t ci = 0, step = 0;
     const int sp = (int)c->prm.spatial_filter;
+    const StepScratch* pend = nullptr;   // step applied but not yet committed
+    uint32_t pend_n = 0;
     for (size_t i = 0; i < n; ++i) {
         if (ops[i].kind == 1) {
-            int rc = do_readout_kernel(c, ops[i].ro);
+            int rc = do_readout_kernel(c, ops[i].ro, pend, pend_n);
             if (rc) return rc;
             continue;
         }
         StepScratch* stp = c->scratch + step;
         const uint32_t nev = ops[i].n;
+        const int slot_in = c->cur_slot;
+        const int slot_out = pend ? (slot_in ^ 1) : -1;
         for (uint32_t off = 0; off < nev; off += kChunk) {
             const uint32_t m = nev - off < (uint32_t)kChunk ? nev - off : (uint32_t)kChunk;
-            const int finalize = (!sp && off + kChunk >= nev) ? 1 : 0;
             HIP_TRY(timed_launch(c, 1, [&] {
                 return launch_apply(c->s, &c->h_chunks[ci], c->seg + (size_t)ci * kChunk,
-                                    c->seg_count + ci, m, off, nev, stp, sp, finalize, c->st);
+                                    c->seg_count + ci, m, off, stp, pend, pend_n, slot_in,
+                                    slot_out, sp, c->st);
             }));
             ++ci;
         }
+        if (pend) c->cur_slot ^= 1;
         if (sp) {
-            HIP_TRY(timed_launch(c, 2, [&] { return launch_pop_blur(c->s, nev, stp, c->st); }));
-            HIP_TRY(timed_launch(c, 3, [&] { return launch_blur_write(c->s, stp, c->st); }));
+            const int slot = c->cur_slot;
+            HIP_TRY(timed_launch(c, 2, [&] { return launch_pop_blur(c->s, nev, stp, slot, c->st); }));
         }
+        pend = stp;
+        pend_n = nev;
         ++step;
+    }
+    if (pend) {
+        HIP_TRY(launch_commit(c->s, pend, pend_n, c->cur_slot, c->cur_slot ^ 1, sp, c->st));
+        c->cur_slot ^= 1;
     }
     return FIBAR_OK;
 }
@@ -346,13 +359,15 @@ hipError_t init_state(fibar_ctx* c)
     c->h_sc->n_reg = c->h_sc->last_stale = c->h_sc->total_stale = 0;
     c->h_sc->err = 0;
     c->h_sc->pad = 0;
+    c->cur_slot = 0;
     hipError_t e = hipMemsetAsync(c->s.pbar, 0, c->npx * 4, c->st);
-    if (e == hipSuccess) e = hipMemsetAsync(c->s.L, 0, c->npx * 4, c->st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->s.Lp, 0, c->npx * 8, c->st);
     if (e == hipSuccess) e = hipMemsetAsync(c->s.last, 0xff, c->npx * 8, c->st);   // -1
     if (e == hipSuccess) e = hipMemsetAsync(c->s.cnt, 0, c->npx * 4, c->st);
     if (e == hipSuccess) e = hipMemsetAsync(c->s.tcnt, 0, c->ntiles * 4, c->st);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(c->s.sc, c->h_sc, sizeof(DevScalars), hipMemcpyHostToDevice, c->st);
+        e = hipMemcpyAsync(c->s.sc + c->cur_slot, c->h_sc, sizeof(DevScalars), hipMemcpyHostToDevice,
+                           c->st);
     // the pinned source must not change before the copy has run
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
     c->t_hi = 0;
@@ -361,7 +376,8 @@ hipError_t init_state(fibar_ctx* c)
 
 int fetch_scalars(fibar_ctx* c)
 {
-    HIP_TRY(hipMemcpyAsync(c->h_sc, c->s.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, c->st));
+    HIP_TRY(hipMemcpyAsync(c->h_sc, c->s.sc + c->cur_slot, sizeof(DevScalars),
+                           hipMemcpyDeviceToHost, c->st));
     HIP_TRY(hipStreamSynchronize(c->st));
     return FIBAR_OK;
 }
@@ -372,7 +388,8 @@ int take_device_error(fibar_ctx* c)
     const int err = c->h_sc->err;
     if (err) {
         const int32_t zero = 0;
-        HIP_TRY(hipMemcpyAsync(&c->s.sc->err, &zero, sizeof(zero), hipMemcpyHostToDevice, c->st));
+        HIP_TRY(hipMemcpyAsync(&c->s.sc[c->cur_slot].err, &zero, sizeof(zero),
+                               hipMemcpyHostToDevice, c->st));
         HIP_TRY(hipStreamSynchronize(c->st));
     }
     return err;
@@ -442,14 +459,12 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
         if (e == hipSuccess) e = hipMalloc(ptr, bytes);
     };
     alloc((void**)&c->s.pbar, npx * 4);
-    alloc((void**)&c->s.L, npx * 4);
+    alloc((void**)&c->s.Lp, npx * 8);
     alloc((void**)&c->s.last, npx * 8);
     alloc((void**)&c->s.cnt, npx * 4);
     alloc((void**)&c->s.tcnt, c->ntiles * 4);
     alloc((void**)&c->s.ring, ring * 4);
-    alloc((void**)&c->s.sc, sizeof(DevScalars));
-    alloc((void**)&c->s.S, npx * 4);
-    alloc((void**)&c->s.Sval, npx * 4);
+    alloc((void**)&c->s.sc, 2 * sizeof(DevScalars));
     alloc((void**)&c->d_chunks, kMaxBatchChunks * sizeof(ChunkDesc));
     alloc((void**)&c->seg, (size_t)kMaxBatchChunks * kChunk * sizeof(SegRec));
     alloc((void**)&c->seg_count, kMaxBatchChunks * 4);

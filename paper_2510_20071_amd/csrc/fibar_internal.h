@@ -44,7 +44,7 @@ struct ChunkDesc {
     uint32_t pkt;      // packet slot in the current batch
 };
 
-// Window scalars of one context (device resident).
+// Window scalars of one context after a regulation step (device resident).
 struct DevScalars {
     int64_t k;             // index of the newest applied event (-1: none)
     uint64_t h;            // index of the oldest event in the window
@@ -59,25 +59,27 @@ struct DevScalars {
 };
 
 // Per-packet scratch of one batch (zeroed at the start of the batch).
+// Counters are spread over kSpread addresses (picked by workgroup index) so
+// that atomics of different workgroups rarely meet on one address.
+constexpr int kSpread = 8;
 struct StepScratch {
-    uint32_t status;   // validation bits: 1 = coordinate range, 2 = polarity
-    uint32_t ticket;   // finished blocks of the step's last kernel
-    uint32_t n_stale;  // pixels that went stale in this step
-    uint32_t pad;
+    uint32_t status;                 // validation bits: 1 = range, 2 = polarity
+    uint32_t pad[3];
+    uint32_t part[kSpread][4];       // activated pixels, activated tiles,
+                                     // stale pixels, deactivated tiles
 };
 
 // Device pointers of one context's state.
 struct State {
     float* pbar;
-    float* L;
+    float2* Lp;       // .x: brightness of active / never-seen pixels,
+                      // .y: brightness of stale pixels (their one-time blur)
     int64_t* last;
     uint32_t* cnt;
     uint32_t* tcnt;
     uint32_t* ring;
     uint64_t ring_mask;
-    DevScalars* sc;
-    uint32_t* S;      // pixels that went stale in the current step
-    float* Sval;      // their blurred values
+    DevScalars* sc;   // two slots; see the commit scheme in fibar_kernels.hip
     uint32_t W, H, TW;
     uint32_t fill_num, fill_den;
     uint64_t q_min, q_max;
@@ -88,18 +90,24 @@ hipError_t launch_sort_compose(const ChunkDesc* d_chunks, uint32_t n_chunks, Seg
                                uint32_t* seg_count, StepScratch* scratch, uint32_t W,
                                uint32_t H, int key_bits, Coef coef, hipStream_t st);
 
+// In-order launches.  `slot_in` holds the last committed scalars; when
+// `prev` is not null the step it describes (with `prev_events` events) is
+// committed on top of them, and the result is written to `slot_out`.
 hipError_t launch_apply(const State& s, const ChunkDesc* d_chunk, const SegRec* seg,
                         const uint32_t* seg_count, uint32_t chunk_events,
-                        uint32_t chunk_offset, uint32_t pkt_events, StepScratch* step,
-                        int spatial, int finalize, hipStream_t st);
+                        uint32_t chunk_offset, StepScratch* step, const StepScratch* prev,
+                        uint32_t prev_events, int slot_in, int slot_out, int spatial,
+                        hipStream_t st);
 
-hipError_t launch_pop_blur(const State& s, uint32_t pkt_events, StepScratch* step,
+hipError_t launch_pop_blur(const State& s, uint32_t pkt_events, StepScratch* step, int slot,
                            hipStream_t st);
 
-hipError_t launch_blur_write(const State& s, StepScratch* step, hipStream_t st);
+hipError_t launch_commit(const State& s, const StepScratch* prev, uint32_t prev_events,
+                         int slot_in, int slot_out, int spatial, hipStream_t st);
 
-hipError_t launch_readout(const State& s, int spatial, float* L, float* pbar, uint8_t* stale,
-                          uint32_t* cnt, int64_t* last, float* log_age, uint32_t* tcnt,
-                          hipStream_t st);
+hipError_t launch_readout(const State& s, int spatial, const StepScratch* prev,
+                          uint32_t prev_events, int slot, float* L, float* pbar,
+                          uint8_t* stale, uint32_t* cnt, int64_t* last, float* log_age,
+                          uint32_t* tcnt, hipStream_t st);
 
 }  // namespace fibar
