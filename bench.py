@@ -66,6 +66,8 @@ def main():
                     help="events of the stream the oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-nsf", action="store_true", help="skip the blur-off measurement")
+    ap.add_argument("--only-nsf", action="store_true",
+                    help="measure only the blur-off mode (for profiling)")
     ap.add_argument("--roofline-kernel", default="pop_blur", choices=KERNELS)
     args = ap.parse_args()
 
@@ -157,6 +159,11 @@ def main():
         ctx.close()
         return elapsed, kt, st, final
 
+    if args.only_nsf:
+        el_off, _, _, _ = run_mode(False, args.steps, args.warmup)
+        log("blur off: %.1f ms/step, %.1f Mev/s" % (1e3 * el_off / args.steps,
+                                                     n * args.steps / el_off / 1e6))
+        return
     el_on, kt, st_on, final_on = run_mode(True, args.steps, args.warmup, args.roofline_kernel)
     mev_on = n * args.steps / el_on / 1e6
     log("blur on : %.1f ms/step, %.1f Mev/s" % (1e3 * el_on / args.steps, mev_on))

@@ -23,7 +23,6 @@ using namespace fibar;
 
 namespace {
 
-constexpr uint32_t kMaxBatchChunks = 256;   // chunks sorted per bulk launch
 constexpr uint32_t kMaxPacket = 1u << 20;
 
 // Eq. (17) and Eq. (18), evaluated in double precision.
@@ -59,6 +58,11 @@ struct fibar_ctx {
     DevScalars* h_sc = nullptr;         // pinned copy for stats
     int cur_slot = 0;                   // scalar slot holding the committed state
     uint64_t t_hi = 0;
+    // blur-off batch path
+    bool region_path = false;
+    RegionBuffers rb{};
+    RegionReadout* h_ro = nullptr;      // pinned
+    hipEvent_t ro_free = nullptr;
     // optional per-kernel timing
     uint32_t time_mask = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[5];
@@ -125,6 +129,14 @@ void free_ctx(fibar_ctx* c)
     hipFree(c->stg_x);
     hipFree(c->stg_y);
     hipFree(c->stg_p);
+    hipFree(c->rb.cnt);
+    hipFree(c->rb.base);
+    hipFree(c->rb.total);
+    hipFree(c->rb.chunk_k);
+    hipFree(c->rb.payload);
+    hipFree(c->rb.ro);
+    if (c->h_ro) hipHostFree(c->h_ro);
+    if (c->ro_free) (void)hipEventDestroy(c->ro_free);
     if (c->h_chunks) hipHostFree(c->h_chunks);
     if (c->h_sc) hipHostFree(c->h_sc);
     if (c->chunks_free) (void)hipEventDestroy(c->chunks_free);
@@ -205,9 +217,55 @@ int do_readout_kernel(fibar_ctx* c, const fibar_readout_buf& ro, const StepScrat
     return map_err(e);
 }
 
+// Blur-off batch: pushes and device readouts in one region-path pass.
+int run_region_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, uint32_t n_steps)
+{
+    HIP_TRY(hipEventSynchronize(c->chunks_free));
+    HIP_TRY(hipEventSynchronize(c->ro_free));
+    uint32_t ci = 0, step = 0, nr = 0;
+    for (size_t i = 0; i < n; ++i) {
+        if (ops[i].kind == 1) {
+            RegionReadout& d = c->h_ro[nr++];
+            d.chunk_end = ci;
+            d.pad = 0;
+            d.L = ops[i].ro.brightness;
+            d.pbar = ops[i].ro.pbar;
+            d.last = ops[i].ro.last_index;
+            d.log_age = ops[i].ro.log_age;
+            continue;
+        }
+        for (uint32_t off = 0; off < ops[i].n; off += kChunk) {
+            ChunkDesc& d = c->h_chunks[ci++];
+            const uint32_t m = ops[i].n - off < (uint32_t)kChunk ? ops[i].n - off : (uint32_t)kChunk;
+            d.x = ops[i].x + off;
+            d.y = ops[i].y + off;
+            d.p = ops[i].p + off;
+            d.n = m;
+            d.pkt = step;
+        }
+        ++step;
+    }
+    if (n_chunks)
+        HIP_TRY(hipMemcpyAsync(c->d_chunks, c->h_chunks, (size_t)n_chunks * sizeof(ChunkDesc),
+                               hipMemcpyHostToDevice, c->st));
+    HIP_TRY(hipEventRecord(c->chunks_free, c->st));
+    if (nr)
+        HIP_TRY(hipMemcpyAsync(c->rb.ro, c->h_ro, (size_t)nr * sizeof(RegionReadout),
+                               hipMemcpyHostToDevice, c->st));
+    HIP_TRY(hipEventRecord(c->ro_free, c->st));
+    if (n_steps) HIP_TRY(hipMemsetAsync(c->scratch, 0, (size_t)n_steps * sizeof(StepScratch), c->st));
+    HIP_TRY(timed_launch(c, 0, [&] {
+        return launch_region_batch(c->s, c->cur_slot, c->d_chunks, n_chunks, c->scratch, c->rb, nr,
+                                   c->key_bits, c->coef, c->st);
+    }));
+    return FIBAR_OK;
+}
+
 // Execute ops[0..n): bulk sort for all pushes, then the in-order steps.
 int run_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, uint32_t n_steps)
 {
+    if (n == 0) return FIBAR_OK;
+    if (c->region_path) return run_region_batch(c, ops, n, n_chunks, n_steps);
     if (n_chunks > 0) {
         // the pinned descriptor buffer may still feed a previous copy
         HIP_TRY(hipEventSynchronize(c->chunks_free));
@@ -278,7 +336,7 @@ int execute(fibar_ctx* c, const fibar_op* ops, size_t n_ops)
 {
     std::vector<Op> batch;
     batch.reserve(n_ops < 4096 ? n_ops : 4096);
-    uint32_t n_chunks = 0, n_steps = 0;
+    uint32_t n_chunks = 0, n_steps = 0, n_readouts = 0;
     size_t stg_used = 0;
     for (size_t i = 0; i < n_ops; ++i) {
         const fibar_op& op = ops[i];
@@ -297,6 +355,7 @@ int execute(fibar_ctx* c, const fibar_op* ops, size_t n_ops)
                 batch.clear();
                 n_chunks = n_steps = 0;
                 stg_used = 0;
+                n_readouts = 0;
             }
             Op o{};
             o.kind = 0;
@@ -340,6 +399,28 @@ int execute(fibar_ctx* c, const fibar_op* ops, size_t n_ops)
             Op o{};
             o.kind = 1;
             o.ro = ro;
+            if (c->region_path) {
+                if (!ro.on_device) {
+                    // host outputs: finish the batch, then read the state
+                    int rc2 = run_batch(c, batch.data(), batch.size(), n_chunks, n_steps);
+                    if (rc2) return rc2;
+                    batch.clear();
+                    n_chunks = n_steps = 0;
+                    stg_used = 0;
+                    rc2 = do_readout_kernel(c, ro, nullptr, 0);
+                    if (rc2) return rc2;
+                    continue;
+                }
+                if (n_readouts == kMaxBatchReadouts) {
+                    int rc2 = run_batch(c, batch.data(), batch.size(), n_chunks, n_steps);
+                    if (rc2) return rc2;
+                    batch.clear();
+                    n_chunks = n_steps = 0;
+                    stg_used = 0;
+                    n_readouts = 0;
+                }
+                ++n_readouts;
+            }
             batch.push_back(o);
         } else {
             int rc2 = run_batch(c, batch.data(), batch.size(), n_chunks, n_steps);
@@ -472,6 +553,19 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
     alloc((void**)&c->stg_x, stg * 2);
     alloc((void**)&c->stg_y, stg * 2);
     alloc((void**)&c->stg_p, stg);
+    const uint64_t n_regions = (npx + kRegion - 1) / kRegion;
+    if (!p.spatial_filter && n_regions <= kMaxRegions) {
+        c->region_path = true;
+        c->rb.n_regions = (uint32_t)n_regions;
+        alloc((void**)&c->rb.cnt, (size_t)kMaxBatchChunks * n_regions * 4);
+        alloc((void**)&c->rb.base, (n_regions + 1) * 8);
+        alloc((void**)&c->rb.total, n_regions * 4);
+        alloc((void**)&c->rb.chunk_k, (kMaxBatchChunks + 1) * 8);
+        alloc((void**)&c->rb.payload, (size_t)kMaxBatchChunks * kChunk * 8);
+        alloc((void**)&c->rb.ro, kMaxBatchReadouts * sizeof(RegionReadout));
+        if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_ro, kMaxBatchReadouts * sizeof(RegionReadout), 0);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ro_free, hipEventDisableTiming);
+    }
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_chunks, kMaxBatchChunks * sizeof(ChunkDesc), 0);
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_sc, sizeof(DevScalars), 0);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->chunks_free, hipEventDisableTiming);
@@ -492,6 +586,7 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
 
     e = init_state(c);
     if (e == hipSuccess) e = hipEventRecord(c->chunks_free, c->st);
+    if (e == hipSuccess && c->ro_free) e = hipEventRecord(c->ro_free, c->st);
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
     if (e != hipSuccess) {
         int rc = map_err(e);

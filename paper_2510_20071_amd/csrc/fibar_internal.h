@@ -13,6 +13,9 @@ constexpr int kSortThreads = 1024;
 constexpr int kSortItems = 16;
 constexpr int kChunk = kSortThreads * kSortItems;
 
+// Chunks grouped and composed per bulk launch (one batch).
+constexpr uint32_t kMaxBatchChunks = 256;
+
 // Filter constants, derived on the host in double precision and rounded once.
 //   one event of polarity p maps the state s = (pbar, L) to
 //   [[alpha, 0], [-c*alpha, beta]] s + [(1-alpha) p, c*alpha p],
@@ -84,6 +87,39 @@ struct State {
     uint32_t fill_num, fill_den;
     uint64_t q_min, q_max;
 };
+
+// ---- blur-off batch path (fibar_region.hip) --------------------------------
+// Pixels are split into regions of kRegion consecutive pixels; a batch's
+// events are bucketed by region (stable), and one workgroup per region
+// applies them in time order with the region's state held in LDS.
+constexpr uint32_t kRegion = 1024;
+constexpr uint32_t kMaxRegions = 16384;
+constexpr uint32_t kMaxBatchReadouts = 1024;
+
+// A readout placed inside a blur-off batch: it sees the events of chunks
+// [0, chunk_end).
+struct RegionReadout {
+    uint32_t chunk_end;
+    uint32_t pad;
+    float* L;
+    float* pbar;
+    int64_t* last;
+    float* log_age;
+};
+
+struct RegionBuffers {
+    uint32_t* cnt;        // [chunks][regions]: counts, then offsets within region
+    uint64_t* base;       // [regions + 1]: first slot of each region
+    uint32_t* total;      // [regions]
+    int64_t* chunk_k;     // [chunks + 1]: global index of each chunk's first event
+    uint64_t* payload;    // bucketed events
+    RegionReadout* ro;    // [kMaxBatchReadouts]
+    uint32_t n_regions;
+};
+
+hipError_t launch_region_batch(const State& s, int slot, const ChunkDesc* d_chunks,
+                               uint32_t n_chunks, StepScratch* scratch, const RegionBuffers& rb,
+                               uint32_t n_readouts, int key_bits, Coef coef, hipStream_t st);
 
 // ---- launchers (fibar_kernels.hip) ---------------------------------------
 hipError_t launch_sort_compose(const ChunkDesc* d_chunks, uint32_t n_chunks, SegRec* seg,

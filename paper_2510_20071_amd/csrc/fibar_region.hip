@@ -1,0 +1,394 @@
+// Blur-off (FIBAR-NSF) batch path of libfibar for gfx950.
+//
+// Without the spatial filter every event only updates its own pixel
+// (temporal filter, Eq. (6), (7), (10)), so packet boundaries do not matter
+// and a whole batch of packets -- with the readouts placed between them --
+// can be processed at once:
+//
+//   k_region_count   per chunk: validate, histogram of events per region
+//   k_region_scan    per region: offsets of each chunk's events in the
+//                    region's slice (exclusive scan over chunks)
+//   k_region_bases   one workgroup: region slice bases, first global event
+//                    index of every chunk (rejected packets do not count),
+//                    new newest-event index
+//   k_region_scatter per chunk: stable LDS sort by region, then every event
+//                    goes to its region's slice (chunk order, then arrival
+//                    order)
+//   k_region_apply   per region, one thread per pixel holding that pixel's
+//                    pbar, L and last index in registers; the slice is
+//                    consumed in tiles (stable LDS sort by pixel), each
+//                    owner applies its pixel's events in time order and
+//                    writes the pixel into every readout of the batch as it
+//                    passes the readout's position.
+//
+// HBM traffic per event: the packet (5 B) is read twice, an 8-byte bucket
+// entry is written and read once; the state is read and written once per
+// batch per region, and each readout writes 4 B per pixel.
+#include "fibar_tile.h"
+
+namespace fibar {
+namespace {
+
+using namespace tile;
+
+constexpr uint64_t kSentinelPix = 0xffffffffull;
+
+// Exclusive max-scan of u32 over a 1024-thread workgroup.
+__device__ uint32_t block_exscan_max(uint32_t x, uint32_t* lds)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(inc, off, 64);
+        if (lane >= off) inc = max(inc, o);
+    }
+    if (lane == 63) lds[wave] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t t = lds[w];
+            lds[w] = run;
+            run = max(run, t);
+        }
+    }
+    __syncthreads();
+    uint32_t ex = __shfl_up(inc, 1, 64);
+    if (lane == 0) ex = 0;
+    const uint32_t res = max(lds[wave], ex);
+    __syncthreads();
+    return res;
+}
+
+// Exclusive sum over a 256-thread workgroup; *total = sum of all.
+__device__ uint32_t block256_exscan(uint32_t x, uint32_t* lds, uint32_t* total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += o;
+    }
+    if (lane == 63) lds[wave] = inc;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t t = lds[w];
+        before += w < wave ? t : 0u;
+        all += t;
+    }
+    *total = all;
+    __syncthreads();
+    return before + inc - x;
+}
+
+__device__ __forceinline__ uint32_t event_key(const ChunkDesc& cd, uint32_t e, uint32_t W,
+                                              uint32_t H, uint32_t* bad, uint32_t* pol)
+{
+    const uint32_t x = cd.x[e], y = cd.y[e], p = cd.p[e];
+    const bool inr = x < W && y < H;
+    *bad |= inr ? 0u : 1u;
+    *bad |= p > 1u ? 2u : 0u;
+    *pol = p & 1u;
+    return inr ? y * W + x : 0u;
+}
+
+__global__ __launch_bounds__(1024) void k_region_count(const ChunkDesc* __restrict__ chunks,
+                                                       uint32_t W, uint32_t H, uint32_t n_regions,
+                                                       uint32_t* __restrict__ cnt,
+                                                       StepScratch* __restrict__ scratch)
+{
+    __shared__ uint32_t hist[kMaxRegions];
+    __shared__ uint32_t bad_sh;
+    const ChunkDesc cd = chunks[blockIdx.x];
+    for (uint32_t r = threadIdx.x; r < n_regions; r += blockDim.x) hist[r] = 0u;
+    if (threadIdx.x == 0) bad_sh = 0u;
+    __syncthreads();
+    uint32_t bad = 0u;
+    for (uint32_t e = threadIdx.x; e < cd.n; e += blockDim.x) {
+        uint32_t pol;
+        const uint32_t key = event_key(cd, e, W, H, &bad, &pol);
+        atomicAdd(&hist[key / kRegion], 1u);
+    }
+    if (bad) atomicOr(&bad_sh, bad);
+    __syncthreads();
+    if (threadIdx.x == 0 && bad_sh) atomicOr(&scratch[cd.pkt].status, bad_sh);
+    uint32_t* row = cnt + (size_t)blockIdx.x * n_regions;
+    for (uint32_t r = threadIdx.x; r < n_regions; r += blockDim.x) row[r] = hist[r];
+}
+
+__global__ __launch_bounds__(256) void k_region_scan(uint32_t* __restrict__ cnt, uint32_t n_chunks,
+                                                     uint32_t n_regions,
+                                                     uint32_t* __restrict__ total)
+{
+    __shared__ uint32_t lds[4];
+    const uint32_t r = blockIdx.x, c = threadIdx.x;
+    const uint32_t v = c < n_chunks ? cnt[(size_t)c * n_regions + r] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block256_exscan(v, lds, &tot);
+    if (c < n_chunks) cnt[(size_t)c * n_regions + r] = ex;
+    if (c == 0) total[r] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_region_bases(State s, int slot,
+                                                       const ChunkDesc* __restrict__ chunks,
+                                                       uint32_t n_chunks,
+                                                       const StepScratch* __restrict__ scratch,
+                                                       RegionBuffers rb)
+{
+    __shared__ uint32_t scan1[kWaves + 1];
+    const uint32_t per = (rb.n_regions + blockDim.x - 1) / blockDim.x;
+    const uint32_t r0 = threadIdx.x * per;
+    uint32_t local = 0;
+    for (uint32_t i = 0; i < per; ++i)
+        if (r0 + i < rb.n_regions) local += rb.total[r0 + i];
+    uint32_t all;
+    uint32_t run = block_exscan_u32(local, scan1, &all);
+    for (uint32_t i = 0; i < per; ++i) {
+        if (r0 + i < rb.n_regions) {
+            rb.base[r0 + i] = run;
+            run += rb.total[r0 + i];
+        }
+    }
+    // first global event index of every chunk: prefix over chunks of the
+    // sizes of chunks whose packet passed validation (<= 256 chunks)
+    const uint32_t ci = threadIdx.x;
+    uint32_t st = 0u, sz = 0u;
+    if (ci < n_chunks) {
+        st = scratch[chunks[ci].pkt].status;
+        sz = st == 0u ? chunks[ci].n : 0u;
+    }
+    uint32_t nvalid;
+    const uint32_t before = block_exscan_u32(sz, scan1, &nvalid);
+    const int64_t k0 = s.sc[slot].k;
+    if (ci < n_chunks) rb.chunk_k[ci] = k0 + 1 + before;
+    // first rejected chunk decides the reported error
+    const uint32_t bad_ci = block_exscan_max(st ? (kMaxBatchChunks - ci) : 0u, scan1);
+    __syncthreads();
+    if (threadIdx.x == blockDim.x - 1) {
+        uint32_t first_bad = max(bad_ci, (ci < n_chunks && st) ? kMaxBatchChunks - ci : 0u);
+        rb.base[rb.n_regions] = all;
+        rb.chunk_k[n_chunks] = k0 + 1 + nvalid;
+        DevScalars& c = s.sc[slot];
+        c.k = k0 + nvalid;
+        if (first_bad && c.err == 0) {
+            const uint32_t st0 = scratch[chunks[kMaxBatchChunks - first_bad].pkt].status;
+            c.err = (st0 & 1u) ? -2 : -3;   // FIBAR_E_RANGE / FIBAR_E_POLARITY
+        }
+    }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_region_scatter(
+    const ChunkDesc* __restrict__ chunks, uint32_t W, uint32_t H, int region_bits,
+    const uint32_t* __restrict__ offs, uint32_t n_regions, const uint64_t* __restrict__ base,
+    const StepScratch* __restrict__ scratch, uint64_t* __restrict__ payload)
+{
+    __shared__ uint32_t keypol[kChunk];
+    __shared__ __align__(16) uint16_t idxA[kChunk];
+    __shared__ __align__(16) uint16_t idxB[kChunk];
+    __shared__ uint64_t scan4[kWaves + 1][4];
+    __shared__ uint32_t scan1[kWaves + 1];
+    const ChunkDesc cd = chunks[blockIdx.x];
+    const uint32_t cn = cd.n;
+    uint32_t bad = 0u;
+    for (uint32_t e = threadIdx.x; e < cn; e += kSortThreads) {
+        uint32_t pol;
+        const uint32_t key = event_key(cd, e, W, H, &bad, &pol);
+        keypol[e] = (key << 1) | pol;
+        idxA[e] = (uint16_t)e;
+    }
+    __syncthreads();
+    // group by region only (stable, so arrival order is kept inside a region)
+    const uint16_t* sorted = tile_sort(keypol, idxA, idxB, cn, region_bits, scan4, 10);
+    const bool valid = scratch[cd.pkt].status == 0u;
+    const uint32_t* off_row = offs + (size_t)blockIdx.x * n_regions;
+
+    // rank of each item among the chunk's items of its region: position
+    // minus the position of the region's first item (last head at or before)
+    const uint32_t beg = threadIdx.x * kSortItems;
+    uint32_t lmax = 0;
+    uint32_t prev_reg = (beg > 0 && beg - 1 < cn) ? (keypol[sorted[beg - 1]] >> 1) / kRegion
+                                                  : 0xffffffffu;
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+        const uint32_t sidx = beg + j;
+        if (sidx < cn) {
+            const uint32_t reg = (keypol[sorted[sidx]] >> 1) / kRegion;
+            if (sidx == 0 || reg != prev_reg) lmax = sidx;
+            prev_reg = reg;
+        }
+    }
+    uint32_t head = block_exscan_max(lmax, scan1);
+    prev_reg = (beg > 0 && beg - 1 < cn) ? (keypol[sorted[beg - 1]] >> 1) / kRegion : 0xffffffffu;
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+        const uint32_t sidx = beg + j;
+        if (sidx < cn) {
+            const uint32_t oid = sorted[sidx];
+            const uint32_t kp = keypol[oid];
+            const uint32_t pix = kp >> 1;
+            const uint32_t reg = pix / kRegion;
+            if (sidx == 0 || reg != prev_reg) head = sidx;
+            prev_reg = reg;
+            const uint64_t dest = base[reg] + off_row[reg] + (sidx - head);
+            const uint64_t pixf = valid ? (uint64_t)pix : kSentinelPix;
+            payload[dest] = (pixf << 32) | ((uint64_t)blockIdx.x << 15) | ((uint64_t)oid << 1) |
+                            (uint64_t)(kp & 1u);
+        }
+    }
+}
+
+// One workgroup per region, thread t owns pixel p0 + t.  The region's slice
+// (chunk order, then arrival order) is consumed
+// in tiles of up to kChunk events: a stable LDS sort by local pixel puts
+// each pixel's events of the tile together, in time order, and the owner
+// thread applies them one by one (Eq. (7), then Eq. (6) and (10)).  The
+// readouts of the batch are visited in order by the whole workgroup: every
+// owner first applies its events that precede the readout, then all write
+// the readout together (coalesced).
+__global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBuffers rb,
+                                                               uint32_t n_chunks,
+                                                               uint32_t n_readouts, Coef coef)
+{
+    // keypol: chunk (bits 24..31) | local pixel, kRegion for rejected
+    // packets (bits 1..11) | polarity (bit 0)
+    __shared__ uint32_t keypol[kChunk];
+    __shared__ __align__(16) uint16_t idxA[kChunk];
+    __shared__ __align__(16) uint16_t idxB[kChunk];
+    __shared__ uint64_t scan4[kWaves + 1][4];
+    __shared__ uint32_t scan1[kWaves + 1];
+    __shared__ uint32_t run_cnt[kRegion + 1];
+    __shared__ uint32_t ro_pos[kMaxBatchReadouts];    // readout position in the slice
+
+    const uint32_t r = blockIdx.x;
+    const uint32_t t = threadIdx.x;
+    const uint64_t npx = (uint64_t)s.W * s.H;
+    const uint64_t p0 = (uint64_t)r * kRegion;
+    const bool own = p0 + t < npx;
+    const uint64_t gp = p0 + t;
+    const float c = 0.5f + 0.5f * coef.beta;
+    float pb = 0.f, l = 0.f;
+    int64_t last = -1;
+    if (own) {
+        pb = s.pbar[gp];
+        l = s.Lp[gp].x;
+        last = s.last[gp];
+    }
+    const uint64_t lo = rb.base[r], hi = rb.base[r + 1];
+    for (uint32_t i = t; i < n_readouts; i += kSortThreads) {
+        const uint32_t ce = rb.ro[i].chunk_end;
+        ro_pos[i] = ce < n_chunks ? rb.cnt[(size_t)ce * rb.n_regions + r] : (uint32_t)(hi - lo);
+    }
+    __syncthreads();
+    uint32_t next_ro = 0;   // first readout not written yet (uniform)
+
+    // own events of the current tile: sorted positions [run_at, run_end)
+    uint32_t run_at = 0, run_end = 0;
+    uint32_t last_pos = 0xffffffffu;   // sorted position of the newest applied event
+    const uint16_t* sorted = idxA;
+    uint64_t tile0 = lo;
+
+    auto resolve_last = [&]() {
+        if (last_pos != 0xffffffffu) {
+            const uint32_t oid = sorted[last_pos];
+            const uint64_t pl = rb.payload[tile0 + oid];
+            last = rb.chunk_k[(uint32_t)(pl >> 15) & 0x1ffffu] + (int64_t)((pl >> 1) & 0x3fffu);
+            last_pos = 0xffffffffu;
+        }
+    };
+    // apply own events of the tile whose chunk is below `chunk_limit`
+    auto advance = [&](uint32_t chunk_limit) {
+        while (run_at < run_end) {
+            const uint32_t kp = keypol[sorted[run_at]];
+            if ((kp >> 24) >= chunk_limit) break;
+            const float p = (kp & 1u) ? 1.f : -1.f;
+            pb = fmaf(coef.alpha, pb, coef.one_m_alpha * p);    // Eq. (7)
+            l = fmaf(coef.beta, l, c * (p - pb));                 // Eq. (6), (10)
+            last_pos = run_at;
+            ++run_at;
+        }
+    };
+    auto write_readout = [&](uint32_t i) {
+        const RegionReadout d = rb.ro[i];
+        if (d.last || d.log_age) resolve_last();
+        if (own) {
+            d.L[gp] = l;
+            if (d.pbar) d.pbar[gp] = pb;
+            if (d.last) d.last[gp] = last;
+            if (d.log_age) d.log_age[gp] = log1pf((float)(rb.chunk_k[d.chunk_end] - 1 - last));
+        }
+    };
+
+    for (uint64_t cursor = lo; cursor < hi;) {
+        const uint32_t cn = (uint32_t)(hi - cursor < kChunk ? hi - cursor : kChunk);
+        const uint32_t rel1 = (uint32_t)(cursor - lo) + cn;
+        for (uint32_t k = t; k <= kRegion; k += kSortThreads) run_cnt[k] = 0u;
+        __syncthreads();
+        for (uint32_t e = t; e < cn; e += kSortThreads) {
+            const uint64_t pl = rb.payload[cursor + e];
+            const uint64_t pix = pl >> 32;
+            const uint32_t lk = pix == kSentinelPix ? kRegion : (uint32_t)(pix - p0);
+            const uint32_t ch = (uint32_t)(pl >> 15) & 0xffu;
+            keypol[e] = (ch << 24) | (lk << 1) | (uint32_t)(pl & 1u);
+            idxA[e] = (uint16_t)e;
+            atomicAdd(&run_cnt[lk], 1u);
+        }
+        __syncthreads();
+        uint32_t total;
+        run_at = block_exscan_u32(run_cnt[t], scan1, &total);
+        run_end = run_at + run_cnt[t];
+        sorted = tile_sort(keypol, idxA, idxB, cn, 11, scan4);
+        tile0 = cursor;
+        if (!own) run_end = run_at;
+        // readouts that fall inside this tile
+        while (next_ro < n_readouts && ro_pos[next_ro] < rel1) {
+            advance(rb.ro[next_ro].chunk_end);
+            write_readout(next_ro);
+            ++next_ro;
+        }
+        advance(0xffffffffu);
+        resolve_last();
+        __syncthreads();
+        cursor += cn;
+    }
+    while (next_ro < n_readouts) write_readout(next_ro++);
+    if (own) {
+        s.pbar[gp] = pb;
+        s.Lp[gp].x = l;
+        s.last[gp] = last;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_region_batch(const State& s, int slot, const ChunkDesc* d_chunks,
+                               uint32_t n_chunks, StepScratch* scratch, const RegionBuffers& rb,
+                               uint32_t n_readouts, int key_bits, Coef coef, hipStream_t st)
+{
+    if (n_chunks > 0) {
+        hipLaunchKernelGGL(k_region_count, dim3(n_chunks), dim3(1024), 0, st, d_chunks, s.W, s.H,
+                           rb.n_regions, rb.cnt, scratch);
+        hipLaunchKernelGGL(k_region_scan, dim3(rb.n_regions), dim3(256), 0, st, rb.cnt, n_chunks,
+                           rb.n_regions, rb.total);
+        hipLaunchKernelGGL(k_region_bases, dim3(1), dim3(1024), 0, st, s, slot, d_chunks, n_chunks,
+                           scratch, rb);
+        int region_bits = 1;
+        while ((1u << region_bits) < rb.n_regions) ++region_bits;
+        hipLaunchKernelGGL(k_region_scatter, dim3(n_chunks), dim3(kSortThreads), 0, st, d_chunks,
+                           s.W, s.H, region_bits, rb.cnt, rb.n_regions, rb.base, scratch,
+                           rb.payload);
+    } else {
+        // readouts only: empty slices
+        hipLaunchKernelGGL(k_region_scan, dim3(rb.n_regions), dim3(256), 0, st, rb.cnt, 0u,
+                           rb.n_regions, rb.total);
+        hipLaunchKernelGGL(k_region_bases, dim3(1), dim3(1024), 0, st, s, slot, d_chunks, 0u,
+                           scratch, rb);
+    }
+    hipLaunchKernelGGL(k_region_apply, dim3(rb.n_regions), dim3(kSortThreads), 0, st, s, rb,
+                       n_chunks, n_readouts, coef);
+    return hipGetLastError();
+}
+
+}  // namespace fibar

@@ -258,3 +258,78 @@ def test_nsf_rejects_spatial_outputs():
     buf = fb.fibar_readout_buf(L.ctypes.data, None, st.ctypes.data, None, None, None, None, 0)
     assert fb.fibar_readout(ctx.handle, 0, buf) == fb.FIBAR_E_UNSUPPORTED
     ctx.close()
+
+
+def _submit_with_device_readouts(ctx, ev, sched, gx, gy, gp, npx, with_extras=True):
+    torch, dev = torch_dev()
+    ops, bufs = [], []
+    for it in sched:
+        if it[0] == "push":
+            ops.append(fb.push_op(gx[it[1]:it[2]], gy[it[1]:it[2]], gp[it[1]:it[2]]))
+        else:
+            b = dict(k=it[1], L=torch.empty(npx, dtype=torch.float32, device=dev))
+            if with_extras:
+                b.update(pbar=torch.empty(npx, dtype=torch.float32, device=dev),
+                         last=torch.empty(npx, dtype=torch.int64, device=dev),
+                         log_age=torch.empty(npx, dtype=torch.float32, device=dev))
+            bufs.append(b)
+            ops.append(fb.readout_op(0, b["L"], pbar=b.get("pbar"), last=b.get("last"),
+                                     log_age=b.get("log_age")))
+    assert ctx.submit(ops) == 0
+    torch.cuda.synchronize()
+    return bufs
+
+
+def test_nsf_batched_readouts_match_oracle():
+    """Blur off: one submit of pushes and device readouts (the batched path
+    writes every readout when its events are applied) against the oracle."""
+    w = eventsim.preset("vga", n_events=900_000, seed=8)
+    ev = eventsim.generate(w.scene)
+    ro = [1, 8191, 8192, 100_000, 123_457, 500_000, 900_000]
+    sched = eventsim.schedule(len(ev), w.packet, ro)
+    gx, gy, gp = to_device(ev)
+    ctx = make_ctx(640, 480, spatial_filter=False)
+    bufs = _submit_with_device_readouts(ctx, ev, sched, gx, gy, gp, 640 * 480)
+    orc = oracle.Oracle(640, 480, spatial_filter=False)
+    done = 0
+    for b in bufs:
+        k = b["k"]
+        orc.push(ev.x[done:k], ev.y[done:k], ev.p[done:k])
+        done = k
+        r = orc.readout(0)
+        g = {"L": b["L"].cpu().numpy(), "pbar": b["pbar"].cpu().numpy(),
+             "last": b["last"].cpu().numpy()}
+        compare_state(g, r, False, "readout at %d" % k)
+        want = np.log1p((k - 1 - r["last"]).astype(np.float64))
+        assert np.allclose(b["log_age"].cpu().numpy(), want, rtol=1e-6, atol=1e-6)
+    assert ctx.stats()["k"] == len(ev) - 1
+    ctx.close()
+
+
+def test_nsf_many_batches_and_host_readouts():
+    """More events than one batch holds, host readouts in between."""
+    w = eventsim.preset("hd720", n_events=9_000_000, seed=5)
+    ev = eventsim.generate(w.scene)
+    sched = eventsim.schedule(len(ev), w.packet, [4_200_000, 8_999_999])
+    flush("hd720 9M events blur off, host readouts")
+    run_pair(ev, 1280, 720, sched, spatial_filter=False)
+
+
+def test_nsf_device_packet_rejection():
+    w = eventsim.preset("sensor64x48", n_events=20000)
+    ev = eventsim.generate(w.scene)
+    ctx = make_ctx(64, 48, spatial_filter=False)
+    orc = oracle.Oracle(64, 48, spatial_filter=False)
+    gx, gy, gp = to_device(ev)
+    bx = gx[5000:6000].clone()
+    bx[999] = 100
+    ops = [fb.push_op(gx[:5000], gy[:5000], gp[:5000]),
+           fb.push_op(bx, gy[5000:6000], gp[5000:6000]),
+           fb.push_op(gx[6000:], gy[6000:], gp[6000:])]
+    assert ctx.submit(ops) == 0
+    assert ctx.synchronize() == fb.FIBAR_E_RANGE
+    orc.push(ev.x[:5000], ev.y[:5000], ev.p[:5000])
+    orc.push(ev.x[6000:], ev.y[6000:], ev.p[6000:])
+    compare_state(ctx.readout_host(0), orc.readout(0), False, "after rejected packet")
+    assert ctx.stats()["k"] == len(ev) - 1000 - 1
+    ctx.close()
