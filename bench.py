@@ -38,6 +38,38 @@ sys.path.insert(0, ROOT)
 #   group      : per event: x, y, p read (5 B); per distinct (pixel, chunk):
 #                one 32-B composed-map record written.
 KERNELS = ("group_compose", "apply", "pop_blur", "blur_write", "readout")
+KERNEL_SOURCES = ("paper_2510_20071_amd/csrc/fibar_kernels.hip",
+                  "paper_2510_20071_amd/csrc/fibar_tile.h",
+                  "paper_2510_20071_amd/csrc/fibar_internal.h")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_hd720.md" % kernel)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(msg):
@@ -69,7 +101,19 @@ def main():
     ap.add_argument("--only-nsf", action="store_true",
                     help="measure only the blur-off mode (for profiling)")
     ap.add_argument("--roofline-kernel", default="pop_blur", choices=KERNELS)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run one plain device-to-device copy of BYTES (for scaling the "
+                         "HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.copy_calibration}))
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -192,7 +236,8 @@ def main():
     achieved = per_launch / avg_s / 1e9
     roofline = {"bound": "hbm", "kernel": args.roofline_kernel, "achieved": round(achieved, 2),
                 "peak": 8000.0, "unit": "GB/s", "frac": round(achieved / 8000.0, 5),
-                "traffic": None, "avg_launch_us": round(avg_s * 1e6, 3), "launches": launches,
+                "traffic": measured_traffic(args.roofline_kernel),
+                "avg_launch_us": round(avg_s * 1e6, 3), "launches": launches,
                 "bytes_per_launch": round(per_launch, 1)}
 
     # ---- CPU baseline (the FP64 oracle) and parity -------------------------
