@@ -39,6 +39,7 @@ sys.path.insert(0, ROOT)
 #                one 32-B composed-map record written.
 KERNELS = ("group_compose", "apply", "pop_blur", "blur_write", "readout")
 KERNEL_SOURCES = ("paper_2510_20071_amd/csrc/fibar_kernels.hip",
+                  "paper_2510_20071_amd/csrc/fibar_step.h",
                   "paper_2510_20071_amd/csrc/fibar_tile.h",
                   "paper_2510_20071_amd/csrc/fibar_internal.h")
 
@@ -88,6 +89,87 @@ def distinct_per_packet(x, y, W, packet, sample_every=16):
     return tot_d / max(tot_e, 1)
 
 
+def run_batched(args, torch, dev, fb, eventsim):
+    """16 streams of uneven resolution and rate, advanced together by one
+    group submission (one step = every stream from a reset state)."""
+    wls = eventsim.batched_streams(16, meta_seed=4, scale=args.multi_scale)
+    t0 = time.time()
+    evs = [eventsim.generate(w.scene) for w in wls]
+    total = sum(len(e) for e in evs)
+    log("batched streams: %d streams, %d events generated in %.1f s"
+        % (len(wls), total, time.time() - t0))
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    keep, op_lists, ctxs = [], [], []
+    for w, ev in zip(wls, evs):
+        W, H = w.scene.width, w.scene.height
+        gx = torch.from_numpy(ev.x.view(np.int16)).to(dev)
+        gy = torch.from_numpy(ev.y.view(np.int16)).to(dev)
+        gp = torch.from_numpy(ev.p).to(dev)
+        n = len(ev)
+        ro = list(range(2_000_000, n, 2_000_000)) + [n]
+        frames = torch.empty((len(ro), W * H), dtype=torch.float32, device=dev)
+        keep.append((gx, gy, gp, frames))
+        ops, r = [], 0
+        for it in eventsim.schedule(n, w.packet, ro):
+            if it[0] == "push":
+                a, bb = it[1], it[2]
+                op = fb.fibar_op()
+                op.kind = fb.FIBAR_OP_PUSH
+                op.packet = fb.fibar_packet(gx.data_ptr() + 2 * a, gy.data_ptr() + 2 * a,
+                                            gp.data_ptr() + a, None, bb - a, 1)
+            else:
+                op = fb.fibar_op()
+                op.kind = fb.FIBAR_OP_READOUT
+                op.t = int(it[1])
+                op.readout = fb.fibar_readout_buf(frames.data_ptr() + 4 * W * H * r, None, None,
+                                                  None, None, None, None, 1)
+                r += 1
+            ops.append(op)
+        op_lists.append(ops)
+        ctxs.append(fb.Context(W, H, max_packet=32768, stream=stream))
+    group = fb.Group(ctxs, stream=stream)
+
+    def reset_all():
+        for c in ctxs:
+            assert c.reset() == 0
+
+    # autotuned launch shape on the warm-up submission
+    assert group.autotune() == 0
+    for _ in range(max(1, args.warmup)):
+        reset_all()
+        assert group.submit(op_lists) == 0
+    torch.cuda.synchronize()
+    shape = group.shape()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        reset_all()
+        assert group.submit(op_lists) == 0
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    # the same streams one after another through single contexts
+    reset_all()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c, ops in zip(ctxs, op_lists):
+        assert c.submit(ops) == 0
+    torch.cuda.synchronize()
+    el_seq = time.perf_counter() - t0
+    for c in ctxs:
+        assert c.synchronize() == 0
+    group.close()
+    for c in ctxs:
+        c.close()
+    res = {"streams": len(wls), "events": total,
+           "resolutions": ["%dx%d" % (w.scene.width, w.scene.height) for w in wls],
+           "packets": [w.packet for w in wls], "mev_s": round(total / el / 1e6, 2),
+           "ms_per_step": round(1e3 * el, 3),
+           "one_stream_at_a_time_mev_s": round(total / el_seq / 1e6, 2),
+           "launch_shape": {"block": shape[0], "grid": shape[1], "autotuned": True}}
+    log("batched streams: %.1f Mev/s together, %.1f Mev/s one at a time"
+        % (res["mev_s"], res["one_stream_at_a_time_mev_s"]))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +183,9 @@ def main():
     ap.add_argument("--only-nsf", action="store_true",
                     help="measure only the blur-off mode (for profiling)")
     ap.add_argument("--roofline-kernel", default="pop_blur", choices=KERNELS)
+    ap.add_argument("--no-multi", action="store_true", help="skip the batched-streams measurement")
+    ap.add_argument("--multi-scale", type=float, default=1.0,
+                    help="scale of the batched streams' lengths (1.0: 5-40M events each)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one plain device-to-device copy of BYTES (for scaling the "
                          "HBM byte counters) and exit")
@@ -278,6 +363,10 @@ def main():
                                                   for f in ("k", "h", "Q", "P", "T"))}
             log("parity: %s" % parity)
 
+    batched = None
+    if not args.no_multi:
+        batched = run_batched(args, torch, dev, fb, eventsim)
+
     out = {
         "metric": "Mev/s reconstructed at 1280x720 (blur on)",
         "value": round(mev_on, 2),
@@ -302,6 +391,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": parity,
+        "batched_streams": batched,
         "paper_cpu_context_mev_s": {"blur_on": 42, "blur_off": 140},
     }
     print(json.dumps(out), flush=True)

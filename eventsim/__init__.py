@@ -224,3 +224,33 @@ def schedule(n_events: int, packet: int, readouts) -> list:
             out.append(("push", a, b))
         a = b
     return out
+
+
+# --------------------------------------------------------------------------
+# Many streams of uneven resolution and rate.
+# --------------------------------------------------------------------------
+RESOLUTIONS = ((346, 260), (640, 480), (1280, 720))
+
+
+def batched_streams(n_streams: int = 16, meta_seed: int = 4, scale: float = 1.0):
+    """Workloads of `n_streams` independent streams (meta seed 4, stream
+    seeds 400 + i): resolution uniform over 346x260 / 640x480 / 1280x720,
+    event rate log-uniform over 1-50 Mev/s, length uniform over 5-40 M
+    events (times `scale`), scene as the vga preset, packet size
+    clamp(nextpow2(rate x 1 ms), 1024, 32768)."""
+    rng = np.random.default_rng(meta_seed)
+    out = []
+    for i in range(n_streams):
+        W, H = RESOLUTIONS[int(rng.integers(0, len(RESOLUTIONS)))]
+        rate = float(np.exp(rng.uniform(np.log(1e6), np.log(50e6))))
+        length = int(rng.integers(5_000_000, 40_000_001) * scale)
+        packet = 1 << int(np.ceil(np.log2(max(rate * 1e-3, 1.0))))
+        packet = int(min(max(packet, 1024), 32768))
+        n_blobs = max(32, int(512 * W * H / (640 * 480)))
+        sc = Scene(W, H, max(length, 1), 400 + i, n_blobs=n_blobs, checker_cell=16.0,
+                   checker_contrast=0.5, speed_px_s=200.0, thr_on=0.2, thr_off=0.2,
+                   thr_jitter=0.02, noise_frac=0.01)
+        out.append(Workload("stream%02d_%dx%d" % (i, W, H), sc, packet,
+                            np.zeros(0, np.int64)))
+        out[-1].rate = rate
+    return out

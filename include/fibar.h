@@ -222,6 +222,39 @@ int fibar_reset(fibar_ctx* c);
 int fibar_set_kernel_timing(fibar_ctx* c, uint32_t kernel_mask);
 int fibar_kernel_time(fibar_ctx* c, int kernel, double* total_ms, uint64_t* launches);
 
+/*
+ * Several independent streams advanced together.  A group holds 1..64
+ * contexts (spatial filter on; the blur-off path already batches well on its
+ * own); fibar_multi_submit takes one op list per context and gives the same
+ * results as fibar_submit on each context separately.  Execution goes in
+ * rounds -- the next packet of every stream -- and every launch of a round
+ * serves all streams: its workgroups walk a device list of (stream, slice)
+ * tasks.  The round's launches form a HIP graph that is replayed per round.
+ * Restrictions: device packets of at most 32768 events, device readouts
+ * without tile counts, and each op list starts with a push.  Contexts stay
+ * owned by the caller and must outlive the group; they may be used alone
+ * between submissions.  The group runs on a stream of its own: a submission
+ * starts after the work already queued on `stream` (hipStream_t, NULL = the
+ * null stream) and on the contexts' streams, and work queued on them after
+ * the call returns waits for it.
+ */
+typedef struct fibar_multi fibar_multi;
+
+int fibar_multi_create(fibar_ctx* const* ctxs, uint32_t n, void* stream, fibar_multi** out);
+int fibar_multi_submit(fibar_multi* m, const fibar_op* const* ops, const size_t* n_ops);
+
+/*
+ * Launch shape of the round kernels (workgroup size x resident workgroups).
+ * It never changes results.  fibar_multi_autotune() makes the next
+ * submission time the candidate shapes on its first rounds and keep the
+ * fastest; fibar_multi_get_shape() reports the one in use;
+ * fibar_multi_set_shape() picks candidate `index` (0..4) directly.
+ */
+int fibar_multi_autotune(fibar_multi* m);
+int fibar_multi_get_shape(fibar_multi* m, uint32_t* block, uint32_t* grid);
+int fibar_multi_set_shape(fibar_multi* m, uint32_t index);
+void fibar_multi_destroy(fibar_multi* m);
+
 /* Wait for all queued work; returns a pending device-side packet error. */
 int fibar_synchronize(fibar_ctx* c);
 

@@ -93,6 +93,18 @@ _SIGNATURES = {
                                          ctypes.POINTER(ctypes.c_uint64)]),
 }
 
+_SIGNATURES.update({
+    "fibar_multi_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32,
+                                          ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "fibar_multi_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.POINTER(fibar_op)),
+                                          ctypes.POINTER(ctypes.c_size_t)]),
+    "fibar_multi_autotune": (ctypes.c_int, [ctypes.c_void_p]),
+    "fibar_multi_get_shape": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32),
+                                             ctypes.POINTER(ctypes.c_uint32)]),
+    "fibar_multi_set_shape": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
+    "fibar_multi_destroy": (None, [ctypes.c_void_p]),
+})
+
 KERNEL_NAMES = ("group_compose", "apply", "pop_blur", "blur_write", "readout")
 
 _lib = None
@@ -182,6 +194,43 @@ def fibar_kernel_time(handle, kernel: int):
     n = ctypes.c_uint64()
     rc = load().fibar_kernel_time(handle, int(kernel), ctypes.byref(ms), ctypes.byref(n))
     return rc, ms.value, int(n.value)
+
+
+def fibar_multi_create(handles, stream=None):
+    """Returns (status, group handle)."""
+    arr = (ctypes.c_void_p * len(handles))(*[h.value if isinstance(h, ctypes.c_void_p) else h
+                                             for h in handles])
+    out = ctypes.c_void_p()
+    rc = load().fibar_multi_create(arr, len(handles), stream, ctypes.byref(out))
+    return rc, out
+
+
+def fibar_multi_submit(group, op_lists) -> int:
+    """op_lists: one list of fibar_op per context of the group."""
+    arrays = [(fibar_op * len(ops))(*ops) for ops in op_lists]
+    ptrs = (ctypes.POINTER(fibar_op) * len(arrays))(
+        *[ctypes.cast(a, ctypes.POINTER(fibar_op)) for a in arrays])
+    sizes = (ctypes.c_size_t * len(arrays))(*[len(ops) for ops in op_lists])
+    return load().fibar_multi_submit(group, ptrs, sizes)
+
+
+def fibar_multi_autotune(group) -> int:
+    return load().fibar_multi_autotune(group)
+
+
+def fibar_multi_get_shape(group):
+    """Returns (status, block, grid)."""
+    b, g = ctypes.c_uint32(), ctypes.c_uint32()
+    rc = load().fibar_multi_get_shape(group, ctypes.byref(b), ctypes.byref(g))
+    return rc, int(b.value), int(g.value)
+
+
+def fibar_multi_set_shape(group, index: int) -> int:
+    return load().fibar_multi_set_shape(group, int(index))
+
+
+def fibar_multi_destroy(group) -> None:
+    load().fibar_multi_destroy(group)
 
 
 # ---- convenience layer used by the tests and the benchmark -----------------
@@ -290,3 +339,38 @@ def readout_op(t, L, pbar=None, stale=None, cnt=None, last=None, log_age=None, t
     op.readout = fibar_readout_buf(_addr(L), _addr(pbar), _addr(stale), _addr(cnt), _addr(last),
                                    _addr(log_age), _addr(tcnt), int(on_device))
     return op
+
+
+class Group:
+    """Several contexts advanced together (fibar_multi_*)."""
+
+    def __init__(self, contexts, stream=None):
+        rc, h = fibar_multi_create([c.handle for c in contexts], stream)
+        if rc != FIBAR_OK:
+            raise FibarError(rc, "fibar_multi_create")
+        self.handle = h
+        self.contexts = list(contexts)
+
+    def submit(self, op_lists) -> int:
+        return fibar_multi_submit(self.handle, op_lists)
+
+    def autotune(self) -> int:
+        return fibar_multi_autotune(self.handle)
+
+    def shape(self):
+        rc, b, g = fibar_multi_get_shape(self.handle)
+        return b, g
+
+    def set_shape(self, index) -> int:
+        return fibar_multi_set_shape(self.handle, index)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            fibar_multi_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

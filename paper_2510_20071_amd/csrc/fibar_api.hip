@@ -17,7 +17,7 @@
 #include <new>
 #include <vector>
 
-#include "fibar_internal.h"
+#include "fibar_ctx.h"
 
 using namespace fibar;
 
@@ -36,53 +36,8 @@ void filter_coefficients(double t_cut, double* alpha, double* beta)
 
 }  // namespace
 
-struct fibar_ctx {
-    uint32_t W = 0, H = 0, TW = 0, TH = 0;
-    uint64_t npx = 0, ntiles = 0;
-    fibar_params prm{};
-    Coef coef{};
-    int key_bits = 4;
-    hipStream_t st = nullptr;
-    State s{};
-    // batch resources
-    ChunkDesc* d_chunks = nullptr;
-    ChunkDesc* h_chunks = nullptr;      // pinned
-    hipEvent_t chunks_free = nullptr;   // h_chunks may be rewritten once this fired
-    SegRec* seg = nullptr;
-    uint32_t* seg_count = nullptr;
-    StepScratch* scratch = nullptr;
-    uint16_t* stg_x = nullptr;          // device staging for host packets
-    uint16_t* stg_y = nullptr;
-    uint8_t* stg_p = nullptr;
-    size_t stg_cap = 0;
-    DevScalars* h_sc = nullptr;         // pinned copy for stats
-    int cur_slot = 0;                   // scalar slot holding the committed state
-    uint64_t t_hi = 0;
-    // blur-off batch path
-    bool region_path = false;
-    RegionBuffers rb{};
-    RegionReadout* h_ro = nullptr;      // pinned
-    hipEvent_t ro_free = nullptr;
-    // optional per-kernel timing
-    uint32_t time_mask = 0;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[5];
-    std::vector<hipEvent_t> event_pool;
-};
-
 namespace {
 
-int map_err(hipError_t e)
-{
-    if (e == hipSuccess) return FIBAR_OK;
-    if (e == hipErrorOutOfMemory) return FIBAR_E_NOMEM;
-    return FIBAR_E_DEVICE;
-}
-
-#define HIP_TRY(expr)                            \
-    do {                                         \
-        hipError_t e_ = (expr);                  \
-        if (e_ != hipSuccess) return map_err(e_); \
-    } while (0)
 
 hipEvent_t pooled_event(fibar_ctx* c)
 {
