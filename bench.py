@@ -128,6 +128,7 @@ def run_batched(args, torch, dev, fb, eventsim):
         op_lists.append(ops)
         ctxs.append(fb.Context(W, H, max_packet=32768, stream=stream))
     group = fb.Group(ctxs, stream=stream)
+    op_lists = fb.OpLists(op_lists)
 
     def reset_all():
         for c in ctxs:
@@ -150,8 +151,9 @@ def run_batched(args, torch, dev, fb, eventsim):
     reset_all()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for c, ops in zip(ctxs, op_lists):
-        assert c.submit(ops) == 0
+    lib = fb.load()
+    for c, arr, n_ops in zip(ctxs, op_lists.arrays, op_lists.sizes):
+        assert lib.fibar_submit(c.handle, arr, n_ops) == 0
     torch.cuda.synchronize()
     el_seq = time.perf_counter() - t0
     for c in ctxs:
@@ -183,7 +185,11 @@ def main():
     ap.add_argument("--only-nsf", action="store_true",
                     help="measure only the blur-off mode (for profiling)")
     ap.add_argument("--roofline-kernel", default="pop_blur", choices=KERNELS)
+    ap.add_argument("--time-every", type=int, default=16,
+                    help="time every n-th launch of the roofline kernel (events on its dispatch)")
     ap.add_argument("--no-multi", action="store_true", help="skip the batched-streams measurement")
+    ap.add_argument("--only-multi", action="store_true",
+                    help="measure only the batched streams (for profiling)")
     ap.add_argument("--multi-scale", type=float, default=1.0,
                     help="scale of the batched streams' lengths (1.0: 5-40M events each)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -217,6 +223,9 @@ def main():
         sys.exit(2)
     dev = torch.device("cuda:0")
     fb.load()
+    if args.only_multi:
+        run_batched(args, torch, dev, fb, eventsim)
+        return
 
     wl = eventsim.preset("hd720", n_events=args.events)
     W, H = wl.scene.width, wl.scene.height
@@ -268,7 +277,8 @@ def main():
             assert lib.fibar_submit(ctx.handle, ops, n_ops) == 0
         torch.cuda.synchronize()
         if time_kernel is not None:
-            fb.fibar_set_kernel_timing(ctx.handle, 1 << KERNELS.index(time_kernel))
+            fb.fibar_set_kernel_timing(ctx.handle, 1 << KERNELS.index(time_kernel),
+                                       args.time_every)
             fb.fibar_kernel_time(ctx.handle, KERNELS.index(time_kernel))  # clear
         torch.cuda.synchronize()
         t_start = time.perf_counter()
@@ -313,7 +323,10 @@ def main():
     elif args.roofline_kernel == "apply":
         per_launch = (32.0 * u + 8.0) * n / n_push
     elif args.roofline_kernel == "group_compose":
-        per_launch = (5.0 + 32.0 * u) * n / max(launches, 1)
+        # one launch per batch of up to 256 chunks of 16384 events
+        chunks = sum(-(-(b - a) // 16384) for it in sched if it[0] == "push"
+                     for a, b in [(it[1], it[2])])
+        per_launch = (5.0 + 32.0 * u) * n / -(-chunks // 256)
     elif args.roofline_kernel == "readout":
         per_launch = 8.0 * npx
     else:
@@ -322,8 +335,8 @@ def main():
     roofline = {"bound": "hbm", "kernel": args.roofline_kernel, "achieved": round(achieved, 2),
                 "peak": 8000.0, "unit": "GB/s", "frac": round(achieved / 8000.0, 5),
                 "traffic": measured_traffic(args.roofline_kernel),
-                "avg_launch_us": round(avg_s * 1e6, 3), "launches": launches,
-                "bytes_per_launch": round(per_launch, 1)}
+                "avg_launch_us": round(avg_s * 1e6, 3), "timed_launches": launches,
+                "timed_every": args.time_every, "bytes_per_launch": round(per_launch, 1)}
 
     # ---- CPU baseline (the FP64 oracle) and parity -------------------------
     cpu = None

@@ -212,14 +212,19 @@ int fibar_get_stats(fibar_ctx* c, fibar_stats* s);
 int fibar_reset(fibar_ctx* c);
 
 /*
- * Optional per-kernel timing with HIP events recorded around every launch of
- * the kernels selected by `kernel_mask` (bit i = kernel i below; 0 turns
- * timing off).  fibar_kernel_time() synchronises, returns the summed device
- * time (ms) and the launch count of kernel `kernel` since the last call, and
- * clears them.  Kernels: 0 group+compose (bulk), 1 apply, 2 window pop +
- * stale blur values, 3 blur write, 4 readout.
+ * Optional per-kernel timing.  Launches of the kernels selected by
+ * `kernel_mask` (bit i = kernel i below; 0 turns timing off) are counted per
+ * kernel, and launch 0, every, 2 every, ... carries a pair of HIP events on
+ * its dispatch (hipExtLaunchKernel), which the runtime stamps with the
+ * dispatch's start and end.  Sampling (every > 1) keeps the event handling
+ * off most launches, so a timed run keeps the pace of an untimed one.
+ * fibar_kernel_time() synchronises the context's stream, returns the summed
+ * duration (ms) and the count of the launches of kernel `kernel` timed since
+ * the last call, and clears them.  Kernels: 0 group+compose (bulk; the whole
+ * blur-off batch in that mode), 1 apply, 2 window pop + stale blur values,
+ * 3 (unused), 4 readout.
  */
-int fibar_set_kernel_timing(fibar_ctx* c, uint32_t kernel_mask);
+int fibar_set_kernel_timing(fibar_ctx* c, uint32_t kernel_mask, uint32_t every);
 int fibar_kernel_time(fibar_ctx* c, int kernel, double* total_ms, uint64_t* launches);
 
 /*
@@ -228,8 +233,9 @@ int fibar_kernel_time(fibar_ctx* c, int kernel, double* total_ms, uint64_t* laun
  * own); fibar_multi_submit takes one op list per context and gives the same
  * results as fibar_submit on each context separately.  Execution goes in
  * rounds -- the next packet of every stream -- and every launch of a round
- * serves all streams: its workgroups walk a device list of (stream, slice)
- * tasks.  The round's launches form a HIP graph that is replayed per round.
+ * serves all streams: its workgroups split the round's (stream, slice)
+ * tasks.  Consecutive rounds are either replayed as one HIP graph or
+ * launched kernel by kernel, whichever the launch configuration says.
  * Restrictions: device packets of at most 32768 events, device readouts
  * without tile counts, and each op list starts with a push.  Contexts stay
  * owned by the caller and must outlive the group; they may be used alone
@@ -244,14 +250,18 @@ int fibar_multi_create(fibar_ctx* const* ctxs, uint32_t n, void* stream, fibar_m
 int fibar_multi_submit(fibar_multi* m, const fibar_op* const* ops, const size_t* n_ops);
 
 /*
- * Launch shape of the round kernels (workgroup size x resident workgroups).
- * It never changes results.  fibar_multi_autotune() makes the next
- * submission time the candidate shapes on its first rounds and keep the
- * fastest; fibar_multi_get_shape() reports the one in use;
- * fibar_multi_set_shape() picks candidate `index` (0..4) directly.
+ * Launch configuration of the round kernels: workgroup size x resident
+ * workgroups, and HIP-graph replay or direct launches.  Candidates 0..9:
+ * index % 5 picks the shape (128x512, 64x1024, 128x1024, 256x256, 256x512),
+ * index / 5 the mode (0 graphs, 1 direct).  It never changes results.
+ * fibar_multi_autotune() makes the next submissions time the candidates on
+ * interleaved groups of rounds and keep the fastest; fibar_multi_get_shape()
+ * reports the shape in use and fibar_multi_get_config() its index;
+ * fibar_multi_set_shape() picks a candidate directly.
  */
 int fibar_multi_autotune(fibar_multi* m);
 int fibar_multi_get_shape(fibar_multi* m, uint32_t* block, uint32_t* grid);
+int fibar_multi_get_config(fibar_multi* m, uint32_t* index);
 int fibar_multi_set_shape(fibar_multi* m, uint32_t index);
 void fibar_multi_destroy(fibar_multi* m);
 

@@ -87,7 +87,7 @@ _SIGNATURES = {
     "fibar_synchronize": (ctypes.c_int, [ctypes.c_void_p]),
     "fibar_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "fibar_reset": (ctypes.c_int, [ctypes.c_void_p]),
-    "fibar_set_kernel_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
+    "fibar_set_kernel_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32]),
     "fibar_kernel_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_uint64)]),
@@ -101,6 +101,7 @@ _SIGNATURES.update({
     "fibar_multi_autotune": (ctypes.c_int, [ctypes.c_void_p]),
     "fibar_multi_get_shape": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32),
                                              ctypes.POINTER(ctypes.c_uint32)]),
+    "fibar_multi_get_config": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)]),
     "fibar_multi_set_shape": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
     "fibar_multi_destroy": (None, [ctypes.c_void_p]),
 })
@@ -184,8 +185,8 @@ def fibar_reset(handle) -> int:
     return load().fibar_reset(handle)
 
 
-def fibar_set_kernel_timing(handle, kernel_mask: int) -> int:
-    return load().fibar_set_kernel_timing(handle, int(kernel_mask))
+def fibar_set_kernel_timing(handle, kernel_mask: int, every: int = 1) -> int:
+    return load().fibar_set_kernel_timing(handle, int(kernel_mask), int(every))
 
 
 def fibar_kernel_time(handle, kernel: int):
@@ -205,13 +206,21 @@ def fibar_multi_create(handles, stream=None):
     return rc, out
 
 
+class OpLists:
+    """Op lists marshalled once for repeated fibar_multi_submit calls."""
+
+    def __init__(self, op_lists):
+        self.arrays = [(fibar_op * len(ops))(*ops) for ops in op_lists]
+        self.ptrs = (ctypes.POINTER(fibar_op) * len(self.arrays))(
+            *[ctypes.cast(a, ctypes.POINTER(fibar_op)) for a in self.arrays])
+        self.sizes = (ctypes.c_size_t * len(self.arrays))(*[len(ops) for ops in op_lists])
+
+
 def fibar_multi_submit(group, op_lists) -> int:
-    """op_lists: one list of fibar_op per context of the group."""
-    arrays = [(fibar_op * len(ops))(*ops) for ops in op_lists]
-    ptrs = (ctypes.POINTER(fibar_op) * len(arrays))(
-        *[ctypes.cast(a, ctypes.POINTER(fibar_op)) for a in arrays])
-    sizes = (ctypes.c_size_t * len(arrays))(*[len(ops) for ops in op_lists])
-    return load().fibar_multi_submit(group, ptrs, sizes)
+    """op_lists: one list of fibar_op per context of the group, or OpLists."""
+    if not isinstance(op_lists, OpLists):
+        op_lists = OpLists(op_lists)
+    return load().fibar_multi_submit(group, op_lists.ptrs, op_lists.sizes)
 
 
 def fibar_multi_autotune(group) -> int:
@@ -223,6 +232,16 @@ def fibar_multi_get_shape(group):
     b, g = ctypes.c_uint32(), ctypes.c_uint32()
     rc = load().fibar_multi_get_shape(group, ctypes.byref(b), ctypes.byref(g))
     return rc, int(b.value), int(g.value)
+
+
+def fibar_multi_get_config(group):
+    """Returns (status, candidate index)."""
+    i = ctypes.c_uint32()
+    rc = load().fibar_multi_get_config(group, ctypes.byref(i))
+    return rc, i.value
+
+
+MULTI_CONFIGS = 10   # launch configurations of a group (see fibar_multi_set_shape)
 
 
 def fibar_multi_set_shape(group, index: int) -> int:
@@ -360,6 +379,10 @@ class Group:
     def shape(self):
         rc, b, g = fibar_multi_get_shape(self.handle)
         return b, g
+
+    def config(self) -> int:
+        rc, i = fibar_multi_get_config(self.handle)
+        return i
 
     def set_shape(self, index) -> int:
         return fibar_multi_set_shape(self.handle, index)

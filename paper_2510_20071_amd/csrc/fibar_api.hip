@@ -14,6 +14,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -51,17 +52,19 @@ hipEvent_t pooled_event(fibar_ctx* c)
     return ev;
 }
 
-// Launch through `fn`, bracketed by timing events when kernel `kind` is timed.
+// Launch through `fn`; every time_every-th launch of a timed kernel kind
+// carries start/stop events on its dispatch.
 template <class F>
 hipError_t timed_launch(fibar_ctx* c, int kind, F&& fn)
 {
-    if (!(c->time_mask & (1u << kind))) return fn();
-    hipEvent_t a = pooled_event(c), b = pooled_event(c);
-    if (!a || !b) return hipErrorOutOfMemory;
-    hipError_t e = hipEventRecord(a, c->st);
-    if (e == hipSuccess) e = fn();
-    if (e == hipSuccess) e = hipEventRecord(b, c->st);
-    c->timed[kind].emplace_back(a, b);
+    if (!(c->time_mask & (1u << kind)) || (c->time_seq[kind]++ % c->time_every) != 0)
+        return fn(LaunchTiming());
+    LaunchTiming tm;
+    tm.start = pooled_event(c);
+    tm.stop = pooled_event(c);
+    if (!tm.start || !tm.stop) return hipErrorOutOfMemory;
+    const hipError_t e = fn(tm);
+    c->timed[kind].emplace_back(tm.start, tm.stop);
     return e;
 }
 
@@ -129,10 +132,10 @@ int do_readout_kernel(fibar_ctx* c, const fibar_readout_buf& ro, const StepScrat
     const int sp = (int)c->prm.spatial_filter;
     const int slot = c->cur_slot;
     if (ro.on_device) {
-        HIP_TRY(timed_launch(c, 4, [&] {
+        HIP_TRY(timed_launch(c, 4, [&](const LaunchTiming& tm) {
             return launch_readout(c->s, sp, pend, pend_n, slot, ro.brightness, ro.pbar,
                                   ro.stale_mask, ro.active_count, ro.last_index, ro.log_age,
-                                  ro.tile_count, c->st);
+                                  ro.tile_count, c->st, tm);
         }));
         return FIBAR_OK;
     }
@@ -209,9 +212,9 @@ int run_region_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, u
                                hipMemcpyHostToDevice, c->st));
     HIP_TRY(hipEventRecord(c->ro_free, c->st));
     if (n_steps) HIP_TRY(hipMemsetAsync(c->scratch, 0, (size_t)n_steps * sizeof(StepScratch), c->st));
-    HIP_TRY(timed_launch(c, 0, [&] {
+    HIP_TRY(timed_launch(c, 0, [&](const LaunchTiming& tm) {
         return launch_region_batch(c->s, c->cur_slot, c->d_chunks, n_chunks, c->scratch, c->rb, nr,
-                                   c->key_bits, c->coef, c->st);
+                                   c->key_bits, c->coef, c->st, tm);
     }));
     return FIBAR_OK;
 }
@@ -242,9 +245,9 @@ int run_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, uint32_t
                                hipMemcpyHostToDevice, c->st));
         HIP_TRY(hipEventRecord(c->chunks_free, c->st));
         HIP_TRY(hipMemsetAsync(c->scratch, 0, (size_t)n_steps * sizeof(StepScratch), c->st));
-        HIP_TRY(timed_launch(c, 0, [&] {
+        HIP_TRY(timed_launch(c, 0, [&](const LaunchTiming& tm) {
             return launch_sort_compose(c->d_chunks, n_chunks, c->seg, c->seg_count, c->scratch,
-                                       c->W, c->H, c->key_bits, c->coef, c->st);
+                                       c->W, c->H, c->key_bits, c->coef, c->st, tm);
         }));
     }
     uint32_t ci = 0, step = 0;
@@ -263,17 +266,19 @@ int run_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, uint32_t
         const int slot_out = pend ? (slot_in ^ 1) : -1;
         for (uint32_t off = 0; off < nev; off += kChunk) {
             const uint32_t m = nev - off < (uint32_t)kChunk ? nev - off : (uint32_t)kChunk;
-            HIP_TRY(timed_launch(c, 1, [&] {
+            HIP_TRY(timed_launch(c, 1, [&](const LaunchTiming& tm) {
                 return launch_apply(c->s, &c->h_chunks[ci], c->seg + (size_t)ci * kChunk,
                                     c->seg_count + ci, m, off, stp, pend, pend_n, slot_in,
-                                    slot_out, sp, c->st);
+                                    slot_out, sp, c->st, tm);
             }));
             ++ci;
         }
         if (pend) c->cur_slot ^= 1;
         if (sp) {
             const int slot = c->cur_slot;
-            HIP_TRY(timed_launch(c, 2, [&] { return launch_pop_blur(c->s, nev, stp, slot, c->st); }));
+            HIP_TRY(timed_launch(c, 2, [&](const LaunchTiming& tm) {
+                return launch_pop_blur(c->s, nev, stp, slot, c->st, tm);
+            }));
         }
         pend = stp;
         pend_n = nev;
@@ -618,10 +623,12 @@ int fibar_reset(fibar_ctx* c)
     return map_err(init_state(c));
 }
 
-int fibar_set_kernel_timing(fibar_ctx* c, uint32_t kernel_mask)
+int fibar_set_kernel_timing(fibar_ctx* c, uint32_t kernel_mask, uint32_t every)
 {
-    if (!c || kernel_mask >= (1u << 5)) return FIBAR_E_INVALID_ARG;
+    if (!c || kernel_mask >= (1u << 5) || every == 0) return FIBAR_E_INVALID_ARG;
     c->time_mask = kernel_mask;
+    c->time_every = every;
+    for (auto& q : c->time_seq) q = 0;
     return FIBAR_OK;
 }
 

@@ -35,8 +35,10 @@ struct fibar_ctx {
     fibar::RegionBuffers rb{};
     fibar::RegionReadout* h_ro = nullptr;      // pinned
     hipEvent_t ro_free = nullptr;
-    // optional per-kernel timing
-    uint32_t time_mask = 0;
+    // optional per-kernel timing: every time_every-th launch of a selected
+    // kind carries a pair of events
+    uint32_t time_mask = 0, time_every = 1;
+    uint64_t time_seq[5] = {};
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[5];
     std::vector<hipEvent_t> event_pool;
 };

@@ -2,6 +2,7 @@
 // libfibar.  Not part of the public ABI.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -88,6 +89,25 @@ struct State {
     uint64_t q_min, q_max;
 };
 
+// Optional HIP events attached to a launch's dispatch (hipExtLaunchKernel):
+// the runtime stamps them with the dispatch's own start and end, as a
+// profiler does.  For a launcher that queues several kernels, `start` goes on
+// the first and `stop` on the last.  Null events: an ordinary launch.
+struct LaunchTiming {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
+template <typename K, typename... A>
+inline hipError_t launch_timed(K kernel, dim3 grid, dim3 block, hipStream_t st,
+                               hipEvent_t start, hipEvent_t stop, A... args)
+{
+    if (start || stop)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, st, start, stop, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+    return hipGetLastError();
+}
+
 // ---- blur-off batch path (fibar_region.hip) --------------------------------
 // Pixels are split into regions of kRegion consecutive pixels; a batch's
 // events are bucketed by region (stable), and one workgroup per region
@@ -119,12 +139,14 @@ struct RegionBuffers {
 
 hipError_t launch_region_batch(const State& s, int slot, const ChunkDesc* d_chunks,
                                uint32_t n_chunks, StepScratch* scratch, const RegionBuffers& rb,
-                               uint32_t n_readouts, int key_bits, Coef coef, hipStream_t st);
+                               uint32_t n_readouts, int key_bits, Coef coef, hipStream_t st,
+                               const LaunchTiming& tm = LaunchTiming());
 
 // ---- launchers (fibar_kernels.hip) ---------------------------------------
 hipError_t launch_sort_compose(const ChunkDesc* d_chunks, uint32_t n_chunks, SegRec* seg,
                                uint32_t* seg_count, StepScratch* scratch, uint32_t W,
-                               uint32_t H, int key_bits, Coef coef, hipStream_t st);
+                               uint32_t H, int key_bits, Coef coef, hipStream_t st,
+                               const LaunchTiming& tm = LaunchTiming());
 
 // In-order launches.  `slot_in` holds the last committed scalars; when
 // `prev` is not null the step it describes (with `prev_events` events) is
@@ -133,10 +155,10 @@ hipError_t launch_apply(const State& s, const ChunkDesc* d_chunk, const SegRec* 
                         const uint32_t* seg_count, uint32_t chunk_events,
                         uint32_t chunk_offset, StepScratch* step, const StepScratch* prev,
                         uint32_t prev_events, int slot_in, int slot_out, int spatial,
-                        hipStream_t st);
+                        hipStream_t st, const LaunchTiming& tm = LaunchTiming());
 
 hipError_t launch_pop_blur(const State& s, uint32_t pkt_events, StepScratch* step, int slot,
-                           hipStream_t st);
+                           hipStream_t st, const LaunchTiming& tm = LaunchTiming());
 
 hipError_t launch_commit(const State& s, const StepScratch* prev, uint32_t prev_events,
                          int slot_in, int slot_out, int spatial, hipStream_t st);
@@ -144,6 +166,7 @@ hipError_t launch_commit(const State& s, const StepScratch* prev, uint32_t prev_
 hipError_t launch_readout(const State& s, int spatial, const StepScratch* prev,
                           uint32_t prev_events, int slot, float* L, float* pbar,
                           uint8_t* stale, uint32_t* cnt, int64_t* last, float* log_age,
-                          uint32_t* tcnt, hipStream_t st);
+                          uint32_t* tcnt, hipStream_t st,
+                          const LaunchTiming& tm = LaunchTiming());
 
 }  // namespace fibar

@@ -99,14 +99,18 @@ __global__ __launch_bounds__(128) void k_apply(State s, ChunkDesc cd, const SegR
             s.sc[slot_out] = commit_step(s.sc[slot_in], prev, prev_events, s, spatial);
         return;
     }
+    // every load that needs only the arguments is issued before any is used
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t status = step->status;
+    const uint32_t nseg = *seg_count;
+    const Item it = load_item(cd, seg, i, spatial);
     int64_t k0;
     uint64_t h0;
     current_head(s, slot_in, prev, prev_events, spatial, &k0, &h0);
-    if (step->status) return;
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (status) return;   // the packet was rejected
     const uint64_t first = (uint64_t)(k0 + 1) + chunk_offset;
     uint32_t dP = 0u, dT = 0u;
-    apply_item(s, cd, seg, *seg_count, i, first, h0, spatial, dP, dT);
+    apply_loaded(s, it, cd.n, nseg, i, first, h0, spatial, dP, dT);
     if (spatial) add_counts(step, 0, dP, dT);
 }
 
@@ -116,9 +120,10 @@ __global__ __launch_bounds__(128) void k_apply(State s, ChunkDesc cd, const SegR
 __global__ __launch_bounds__(128) void k_pop_blur(State s, uint32_t pkt_events, StepScratch* step,
                                                   int slot)
 {
-    if (step->status) return;
+    const uint32_t status = step->status;
     uint64_t h_old, h_new;
     pop_bounds(s.sc[slot], pkt_events, &h_old, &h_new);
+    if (status) return;
     uint32_t dP = 0u, dT = 0u;
     pop_range(s, h_old + blockIdx.x * blockDim.x + threadIdx.x, h_new,
               (uint64_t)gridDim.x * blockDim.x, h_old, dP, dT);
@@ -158,33 +163,33 @@ __global__ __launch_bounds__(256) void k_readout(State s, int spatial, const Ste
 // ---------------------------------------------------------------------------
 hipError_t launch_sort_compose(const ChunkDesc* d_chunks, uint32_t n_chunks, SegRec* seg,
                                uint32_t* seg_count, StepScratch* scratch, uint32_t W,
-                               uint32_t H, int key_bits, Coef coef, hipStream_t st)
+                               uint32_t H, int key_bits, Coef coef, hipStream_t st,
+                               const LaunchTiming& tm)
 {
     if (n_chunks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sort_compose, dim3(n_chunks), dim3(kSortThreads), 0, st, d_chunks, seg,
-                       seg_count, scratch, W, H, key_bits, coef);
-    return hipGetLastError();
+    return launch_timed(k_sort_compose, dim3(n_chunks), dim3(kSortThreads), st, tm.start, tm.stop,
+                        d_chunks, seg, seg_count, scratch, W, H, key_bits, coef);
 }
 
 hipError_t launch_apply(const State& s, const ChunkDesc* d_chunk, const SegRec* seg,
                         const uint32_t* seg_count, uint32_t chunk_events, uint32_t chunk_offset,
                         StepScratch* step, const StepScratch* prev, uint32_t prev_events,
-                        int slot_in, int slot_out, int spatial, hipStream_t st)
+                        int slot_in, int slot_out, int spatial, hipStream_t st,
+                        const LaunchTiming& tm)
 {
     // one extra workgroup commits the previous step's scalars
     const uint32_t blocks = (chunk_events + 127) / 128 + 1;
-    hipLaunchKernelGGL(k_apply, dim3(blocks), dim3(128), 0, st, s, *d_chunk, seg,
-                       seg_count, chunk_offset, step, prev, prev_events, slot_in, slot_out,
-                       spatial);
-    return hipGetLastError();
+    return launch_timed(k_apply, dim3(blocks), dim3(128), st, tm.start, tm.stop, s, *d_chunk, seg,
+                        seg_count, chunk_offset, step, prev, prev_events, slot_in, slot_out,
+                        spatial);
 }
 
 hipError_t launch_pop_blur(const State& s, uint32_t pkt_events, StepScratch* step, int slot,
-                           hipStream_t st)
+                           hipStream_t st, const LaunchTiming& tm)
 {
     // many small workgroups spread the scattered reads over more CUs
-    hipLaunchKernelGGL(k_pop_blur, dim3(128), dim3(128), 0, st, s, pkt_events, step, slot);
-    return hipGetLastError();
+    return launch_timed(k_pop_blur, dim3(128), dim3(128), st, tm.start, tm.stop, s, pkt_events,
+                        step, slot);
 }
 
 hipError_t launch_commit(const State& s, const StepScratch* prev, uint32_t prev_events,
@@ -198,14 +203,14 @@ hipError_t launch_commit(const State& s, const StepScratch* prev, uint32_t prev_
 hipError_t launch_readout(const State& s, int spatial, const StepScratch* prev,
                           uint32_t prev_events, int slot, float* L, float* pbar, uint8_t* stale,
                           uint32_t* cnt, int64_t* last, float* log_age, uint32_t* tcnt,
-                          hipStream_t st)
+                          hipStream_t st, const LaunchTiming& tm)
 {
     const uint64_t npx = (uint64_t)s.W * s.H;
     uint64_t blocks = (npx + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_readout, dim3((uint32_t)blocks), dim3(256), 0, st, s, spatial, prev,
-                       prev_events, slot, L, pbar, stale, cnt, last, log_age, tcnt);
-    return hipGetLastError();
+    return launch_timed(k_readout, dim3((uint32_t)blocks), dim3(256), st, tm.start, tm.stop, s,
+                        spatial, prev, prev_events, slot, L, pbar, stale, cnt, last, log_age,
+                        tcnt);
 }
 
 }  // namespace fibar

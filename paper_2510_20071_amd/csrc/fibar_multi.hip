@@ -3,22 +3,31 @@
 // together, one packet per stream per round.
 //
 // A round is a fixed sequence of launches shared by every stream:
-//   k_multi_apply (sub-round 0, and sub-round 1 when a packet has a second
-//   chunk), k_multi_pop, k_multi_readout, k_multi_advance.
-// Each of them consumes the round's device task list -- (stream, slice)
-// tasks of equal size, planned on the host -- with a fixed number of resident
-// workgroups, workgroup w taking tasks w, w + grid, w + 2 grid, ...  (a
-// shared dequeue counter would serialise: same-address atomics cost ~10 ns
-// each), so streams of different sizes share the GPU without a launch per
-// stream.  Every launch reads the round index from device memory; the round
-// is captured once as a HIP graph and replayed for every round.  Within a
-// stream the order of steps is the single-stream order (apply, pop/blur,
-// lagged commit), so results are identical to running each stream alone.
+//   k_multi_apply (sub-round 0, and sub-round 1 when some packet has a second
+//   chunk), k_multi_pop, and k_multi_readout when some stream reads out.
+// The host plans every round of a batch up front: one self-contained record
+// per stream holds everything its step needs (the stream's state pointers,
+// chunk descriptors, scratch, scalar slots) and, per kind of launch, the
+// cumulative count of workgroup tasks up to that stream.  A workgroup finds
+// the stream owning task t with one ballot over those counts (one stream
+// per lane).  Each launch has a fixed number of resident workgroups,
+// workgroup w taking tasks w, w + grid, ...
+//
+// Up to kUnroll consecutive rounds form one HIP graph (readouts only in its
+// last round, so the launch sequence is fixed).  Its first node copies the
+// records of its rounds from the batch table (at the index of the graph's
+// first round, kept on the device and advanced by the graph's last node)
+// into a fixed ring; the round kernels read ring slot j, an address fixed at
+// capture.  So reaching the per-pixel work takes one dependent load, the
+// stream record -- dependent misses, not bandwidth, bound the small rounds.
+// Within a stream the order of steps is the single-stream order (apply,
+// pop/blur, lagged commit), so results are identical to running each stream
+// alone.
 //
 // The launch shape (workgroup size, number of resident workgroups) does not
 // change any result: only integer atomics are reordered and every float is
 // computed from the same operands.  The autotuner times the candidate shapes
-// on the first rounds of a submission and keeps the fastest.
+// on interleaved groups of rounds of a submission and keeps the fastest.
 #include <math.h>
 #include <string.h>
 
@@ -35,45 +44,48 @@ namespace {
 using namespace tile;
 using namespace step;
 
-constexpr uint32_t kMultiMaxStreams = 64;
-constexpr uint32_t kMultiChunks = 1024;        // chunks grouped per multi batch
+constexpr uint32_t kMultiMaxStreams = 64;       // one wave's lanes
+constexpr uint32_t kMultiChunks = 1024;         // chunks grouped per multi batch
 constexpr uint32_t kMultiMaxRounds = 1024;
 constexpr uint32_t kMultiMaxReadouts = 1024;
-constexpr uint32_t kMultiMaxTasks = 1u << 20;  // per task kind per batch
-constexpr uint32_t kReadoutBlock = 4096;       // pixels per readout task
+constexpr uint32_t kMultiMaxRoTasks = 1u << 20;
+constexpr uint32_t kReadoutBlock = 1024;        // pixels per readout task
+constexpr uint32_t kUnroll = 64;                // rounds per graph replay
+constexpr uint32_t kTuneLen = 4;                // rounds per timed group while tuning
+constexpr uint32_t kTuneGroups = 3;             // timed groups per candidate shape
 constexpr uint32_t kNone = 0xffffffffu;
 
-// One stream's step in one round.
-struct MultiStep {
+// Task kinds of a round: apply sub-round 0 (a stream with a pending step
+// gets one extra task, its first, that commits it), apply sub-round 1, pops.
+constexpr int kKinds = 3;
+
+// One stream's step in one round; read by every workgroup working on it.
+// Records of streams without a step in the round have end[] = the round's
+// totals and own no task.
+struct alignas(16) StreamStep {
+    uint32_t end[kKinds];            // cumulative tasks of records 0..this one
+    uint32_t ro_off, ro_cnt;         // the round's readout tasks (record 0)
+    State s;
     ChunkDesc chunk[2];
-    uint32_t seg_chunk[2];   // chunk slot in the batch's record buffer
-    uint32_t n_chunks;       // 0: the stream has no step in this round
-    uint32_t events;
-    uint32_t step_idx;       // scratch slot of this step
-    uint32_t prev_idx;       // scratch slot of the pending step, or kNone
-    uint32_t prev_events;
-    uint32_t pop_blocks;     // virtual workgroups sharing this step's pops
-    int32_t slot_in, slot_out, pop_slot;
-    uint32_t pad;
+    const SegRec* seg[2];            // the chunks' composed records
+    const uint32_t* nseg[2];         // and their counts
+    StepScratch* step;               // this step's counters and status
+    const StepScratch* prev;         // the pending (uncommitted) step, or null
+    uint32_t events, prev_events;
+    int32_t slot_in;                 // committed scalars before this round
+    int32_t slot_out;                // where the pending step is committed
+    int32_t pop_slot;                // committed scalars the pops start from
+    uint32_t pop_blocks;             // workgroup tasks sharing the pops
 };
 
-struct RoundDesc {
-    uint32_t apply_off[2], apply_cnt[2];
-    uint32_t pop_off, pop_cnt;
-    uint32_t ro_off, ro_cnt;
-    uint32_t step_off;       // MultiStep of stream 0 in this round
+struct RoTask {
+    uint32_t rec;                    // stream record in the round
+    uint32_t ro;                     // readout slot in the batch
+    uint32_t blk;                    // pixel block
     uint32_t pad;
-};
-
-struct Task {
-    uint32_t stream;
-    uint32_t idx;            // apply: item block (kNone = commit); pop: virtual block;
-                             // readout: readout slot in the high bits, pixel block low
 };
 
 struct MultiReadout {
-    uint32_t stream;
-    uint32_t pad;
     float* L;
     float* pbar;
     uint8_t* stale;
@@ -83,115 +95,158 @@ struct MultiReadout {
 };
 
 struct CommitDesc {
-    uint32_t stream;
-    uint32_t prev_idx;
+    State s;
+    const StepScratch* prev;
     uint32_t prev_events;
     int32_t slot_in, slot_out;
 };
 
-struct MultiCtl {
-    const State* states;
-    const MultiStep* steps;
-    const RoundDesc* rounds;
-    const Task* apply_tasks;
-    const Task* pop_tasks;
-    const Task* ro_tasks;
+struct MultiArgs {
+    const RoTask* rot;
     const MultiReadout* ros;
-    const SegRec* seg;
-    const uint32_t* seg_count;
-    StepScratch* scratch;
-    uint32_t* round;
+    uint32_t S;
 };
 
-__global__ __launch_bounds__(256) void k_multi_apply(const MultiCtl* __restrict__ ctl, int sub)
+// Each lane of a wave holds one record's cumulative task count of a kind
+// (lanes >= S: no record); the last record's is the round's total.
+__device__ __forceinline__ uint32_t lane_end(const StreamStep* rec, uint32_t S, int kind,
+                                             uint32_t* total)
 {
-    const uint32_t r = *ctl->round;
-    const RoundDesc rd = ctl->rounds[r];
-    for (uint32_t t = blockIdx.x; t < rd.apply_cnt[sub]; t += gridDim.x) {
-        const Task task = ctl->apply_tasks[rd.apply_off[sub] + t];
-        const MultiStep& st = ctl->steps[rd.step_off + task.stream];
-        const State s = ctl->states[task.stream];
-        const StepScratch* prev = st.prev_idx == kNone ? nullptr : ctl->scratch + st.prev_idx;
-        if (task.idx == kNone) {
-            if (threadIdx.x == 0 && prev && st.slot_out >= 0)
-                s.sc[st.slot_out] = commit_step(s.sc[st.slot_in], prev, st.prev_events, s, 1);
-            continue;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t e = lane < S ? rec[lane].end[kind] : 0xffffffffu;
+    *total = __shfl(e, (int)S - 1);
+    return e;
+}
+
+// Record owning task t: the number of records whose range ends at or before
+// t (wave-uniform).  *start gets the record's first task.
+__device__ __forceinline__ uint32_t owner(uint32_t e, uint32_t t, uint32_t* start)
+{
+    const uint32_t k = (uint32_t)__popcll(__ballot(e <= t));
+    const uint32_t prev_end = __shfl(e, (int)(k > 0 ? k - 1 : 0));
+    *start = k > 0 ? prev_end : 0u;
+    return k;
+}
+
+// Every round kernel gets `rr`, the round's S records.
+__global__ __launch_bounds__(256) void k_multi_apply(MultiArgs a, const StreamStep* rr, int sub)
+{
+    uint32_t total;
+    const uint32_t le = lane_end(rr, a.S, sub, &total);
+    for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+        uint32_t start;
+        const StreamStep* e = rr + owner(le, t, &start);
+        const State s = e->s;
+        const StepScratch* prev = e->prev;
+        uint32_t b = t - start;
+        if (sub == 0 && prev) {
+            if (b == 0) {
+                if (threadIdx.x == 0)
+                    s.sc[e->slot_out] = commit_step(s.sc[e->slot_in], prev, e->prev_events, s, 1);
+                continue;
+            }
+            --b;
         }
-        StepScratch* stp = ctl->scratch + st.step_idx;
-        if (stp->status) continue;
+        StepScratch* stp = e->step;
+        const ChunkDesc cd = e->chunk[sub];
+        // i < kChunk: task counts are ceil(n / block) and every block size
+        // divides kChunk, and a chunk slot holds kChunk records
+        const uint32_t i = b * blockDim.x + threadIdx.x;
+        // every load that only needs the record is issued before any is used
+        const uint32_t status = stp->status;
+        const uint32_t nseg = *e->nseg[sub];
+        const Item it = load_item(cd, e->seg[sub], i, 1);
         int64_t k0;
         uint64_t h0;
-        current_head(s, st.slot_in, prev, st.prev_events, 1, &k0, &h0);
+        current_head(s, e->slot_in, prev, e->prev_events, 1, &k0, &h0);
+        if (status) continue;   // the packet was rejected
         const uint64_t first = (uint64_t)(k0 + 1) + (uint64_t)sub * kChunk;
-        const uint32_t i = task.idx * blockDim.x + threadIdx.x;
-        const uint32_t sc = st.seg_chunk[sub];
         uint32_t dP = 0u, dT = 0u;
-        apply_item(s, st.chunk[sub], ctl->seg + (size_t)sc * kChunk, ctl->seg_count[sc], i, first,
-                   h0, 1, dP, dT);
+        apply_loaded(s, it, cd.n, nseg, i, first, h0, 1, dP, dT);
         add_counts(stp, 0, dP, dT);
     }
 }
 
-__global__ __launch_bounds__(256) void k_multi_pop(const MultiCtl* __restrict__ ctl)
+__global__ __launch_bounds__(256) void k_multi_pop(MultiArgs a, const StreamStep* rr)
 {
-    const uint32_t r = *ctl->round;
-    const RoundDesc rd = ctl->rounds[r];
-    for (uint32_t t = blockIdx.x; t < rd.pop_cnt; t += gridDim.x) {
-        const Task task = ctl->pop_tasks[rd.pop_off + t];
-        const MultiStep& st = ctl->steps[rd.step_off + task.stream];
-        StepScratch* stp = ctl->scratch + st.step_idx;
-        if (stp->status) continue;
-        const State s = ctl->states[task.stream];
+    uint32_t total;
+    const uint32_t le = lane_end(rr, a.S, 2, &total);
+    for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+        uint32_t start;
+        const StreamStep* e = rr + owner(le, t, &start);
+        const State s = e->s;
+        StepScratch* stp = e->step;
+        const uint32_t status = stp->status;
         uint64_t h_old, h_new;
-        pop_bounds(s.sc[st.pop_slot], st.events, &h_old, &h_new);
+        pop_bounds(s.sc[e->pop_slot], e->events, &h_old, &h_new);
+        if (status) continue;
         uint32_t dP = 0u, dT = 0u;
-        pop_range(s, h_old + (uint64_t)task.idx * blockDim.x + threadIdx.x, h_new,
-                  (uint64_t)st.pop_blocks * blockDim.x, h_old, dP, dT);
+        pop_range(s, h_old + (uint64_t)(t - start) * blockDim.x + threadIdx.x, h_new,
+                  (uint64_t)e->pop_blocks * blockDim.x, h_old, dP, dT);
         add_counts(stp, 2, dP, dT);
     }
 }
 
-__global__ __launch_bounds__(256) void k_multi_readout(const MultiCtl* __restrict__ ctl)
+__global__ __launch_bounds__(256) void k_multi_readout(MultiArgs a, const StreamStep* rr)
 {
-    const uint32_t r = *ctl->round;
-    const RoundDesc rd = ctl->rounds[r];
-    for (uint32_t t = blockIdx.x; t < rd.ro_cnt; t += gridDim.x) {
-        const Task task = ctl->ro_tasks[rd.ro_off + t];
-        const MultiReadout ro = ctl->ros[task.idx >> 12];
-        const MultiStep& st = ctl->steps[rd.step_off + ro.stream];
-        const State s = ctl->states[ro.stream];
+    const uint32_t off = rr->ro_off, cnt = rr->ro_cnt;
+    for (uint32_t t = blockIdx.x; t < cnt; t += gridDim.x) {
+        const RoTask task = a.rot[off + t];
+        const MultiReadout ro = a.ros[task.ro];
+        const StreamStep* e = rr + task.rec;
+        const State s = e->s;
         int64_t k;
         uint64_t h;
-        current_head(s, st.pop_slot, ctl->scratch + st.step_idx, st.events, 1, &k, &h);
+        current_head(s, e->pop_slot, e->step, e->events, 1, &k, &h);
         const uint64_t npx = (uint64_t)s.W * s.H;
-        const uint64_t p0 = (uint64_t)(task.idx & 0xfffu) * kReadoutBlock;
+        const uint64_t p0 = (uint64_t)task.blk * kReadoutBlock;
         for (uint64_t i = p0 + threadIdx.x; i < npx && i < p0 + kReadoutBlock; i += blockDim.x)
             readout_pixel(s, 1, k, (int64_t)h, i, ro.L, ro.pbar, ro.stale, ro.cnt, ro.last,
                           ro.log_age);
     }
 }
 
-__global__ void k_multi_advance(const MultiCtl* __restrict__ ctl)
+// Copy the records of the graph's rounds (n16 16-byte words from round
+// *base of the batch table) into the ring.
+__global__ __launch_bounds__(256) void k_multi_stage(const StreamStep* __restrict__ rec,
+                                                     StreamStep* __restrict__ ring,
+                                                     const uint32_t* __restrict__ base,
+                                                     uint32_t S, uint32_t n16)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *ctl->round += 1u;
+    const uint4* src = reinterpret_cast<const uint4*>(rec + (size_t)*base * S);
+    uint4* dst = reinterpret_cast<uint4*>(ring);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += gridDim.x * blockDim.x)
+        dst[i] = src[i];
 }
 
-__global__ void k_multi_commit(const MultiCtl* __restrict__ ctl, const CommitDesc* __restrict__ cd,
-                               uint32_t n)
+__global__ void k_multi_advance(uint32_t* base, uint32_t rounds)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *base += rounds;
+}
+
+__global__ void k_multi_commit(const CommitDesc* __restrict__ cd, uint32_t n)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const CommitDesc c = cd[i];
-    const State s = ctl->states[c.stream];
-    s.sc[c.slot_out] = commit_step(s.sc[c.slot_in], ctl->scratch + c.prev_idx, c.prev_events, s, 1);
+    c.s.sc[c.slot_out] = commit_step(c.s.sc[c.slot_in], c.prev, c.prev_events, c.s, 1);
 }
 
-// Launch shapes the autotuner chooses from: (workgroup size, workgroups).
+// Launch configurations the autotuner chooses from: workgroup size,
+// workgroups, and whether groups of rounds are replayed as HIP graphs or the
+// round kernels are launched one by one.
 struct Shape {
     uint32_t block, grid;
+    int graph;
 };
-constexpr Shape kShapes[] = {{128, 512}, {64, 1024}, {128, 1024}, {256, 256}, {256, 512}};
+constexpr Shape kShapes[] = {{128, 512, 1}, {64, 1024, 1}, {128, 1024, 1}, {256, 256, 1},
+                             {256, 512, 1}, {128, 512, 0}, {64, 1024, 0}, {128, 1024, 0},
+                             {256, 256, 0}, {256, 512, 0}};
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+
+// Launch sequence of a group of rounds: bit 0 = second apply sub-round,
+// bit 1 = readouts after the last round.
+constexpr int kVariants = 4;
 
 }  // namespace
 }  // namespace fibar
@@ -204,37 +259,33 @@ struct fibar_multi {
     hipStream_t user = nullptr;      // the caller's stream
     uint32_t n = 0;
     // device tables
-    State* d_states = nullptr;
-    MultiStep* d_steps = nullptr;
-    RoundDesc* d_rounds = nullptr;
-    Task* d_apply = nullptr;
-    Task* d_pop = nullptr;
-    Task* d_rot = nullptr;
+    StreamStep* d_rec = nullptr;     // the batch's records, round by round
+    StreamStep* d_ring = nullptr;    // the current graph's records
+    RoTask* d_rot = nullptr;
     MultiReadout* d_ros = nullptr;
     CommitDesc* d_commits = nullptr;
     ChunkDesc* d_chunks = nullptr;
     SegRec* seg = nullptr;
     uint32_t* seg_count = nullptr;
     StepScratch* scratch = nullptr;
-    uint32_t* round = nullptr;
-    MultiCtl* d_ctl = nullptr;
+    uint32_t* base = nullptr;
     // host staging (pinned)
-    MultiStep* h_steps = nullptr;
-    RoundDesc* h_rounds = nullptr;
-    Task* h_apply = nullptr;
-    Task* h_pop = nullptr;
-    Task* h_rot = nullptr;
+    StreamStep* h_rec = nullptr;
+    RoTask* h_rot = nullptr;
     MultiReadout* h_ros = nullptr;
     CommitDesc* h_commits = nullptr;
     ChunkDesc* h_chunks = nullptr;
     hipEvent_t staging_free = nullptr;
-    // graphs: [shape][with second apply sub-round]
-    hipGraphExec_t graph[kNumShapes][2] = {};
+    hipEvent_t commits_free = nullptr;
+    // graphs: [shape][rounds - 1][launch sequence]
+    hipGraphExec_t graph[kNumShapes][kUnroll][kVariants] = {};
     // autotuning
     int shape = 0;                 // chosen shape
-    int tune = 0;                  // 1: time the candidates on the next submission
+    int tune = 0;                  // 1: time the candidates on the next submissions
+    uint32_t tune_next = 0;        // shape of the next timed group
     double tune_ms[kNumShapes] = {};
     double tune_events[kNumShapes] = {};
+    uint32_t tune_groups[kNumShapes] = {};
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
 };
 
@@ -244,43 +295,66 @@ void multi_free(fibar_multi* m)
 {
     if (!m) return;
     if (m->st) (void)hipStreamSynchronize(m->st);
-    for (auto& g : m->graph)
-        for (auto& e : g)
-            if (e) (void)hipGraphExecDestroy(e);
-    void* dev[] = {m->d_states, m->d_steps, m->d_rounds, m->d_apply, m->d_pop, m->d_rot,
-                   m->d_ros, m->d_commits, m->d_chunks, m->seg, m->seg_count, m->scratch,
-                   m->round, m->d_ctl};
+    for (auto& a : m->graph)
+        for (auto& b : a)
+            for (auto& g : b)
+                if (g) (void)hipGraphExecDestroy(g);
+    void* dev[] = {m->d_rec, m->d_ring, m->d_rot, m->d_ros, m->d_commits, m->d_chunks,
+                   m->seg, m->seg_count, m->scratch, m->base};
     for (void* p : dev) (void)hipFree(p);
-    void* host[] = {m->h_steps, m->h_rounds, m->h_apply, m->h_pop, m->h_rot, m->h_ros,
-                    m->h_commits, m->h_chunks};
+    void* host[] = {m->h_rec, m->h_rot, m->h_ros, m->h_commits, m->h_chunks};
     for (void* p : host)
         if (p) (void)hipHostFree(p);
     if (m->staging_free) (void)hipEventDestroy(m->staging_free);
+    if (m->commits_free) (void)hipEventDestroy(m->commits_free);
     if (m->ev_a) (void)hipEventDestroy(m->ev_a);
     if (m->ev_b) (void)hipEventDestroy(m->ev_b);
     if (m->st) (void)hipStreamDestroy(m->st);
     delete m;
 }
 
-// Launch one round (not captured) with a given shape.
-hipError_t launch_round(fibar_multi* m, const Shape& sh, bool two)
+MultiArgs multi_args(const fibar_multi* m)
 {
-    hipLaunchKernelGGL(k_multi_apply, dim3(sh.grid), dim3(sh.block), 0, m->st, m->d_ctl, 0);
-    if (two) hipLaunchKernelGGL(k_multi_apply, dim3(sh.grid), dim3(sh.block), 0, m->st, m->d_ctl, 1);
-    hipLaunchKernelGGL(k_multi_pop, dim3(sh.grid), dim3(sh.block), 0, m->st, m->d_ctl);
-    hipLaunchKernelGGL(k_multi_readout, dim3(sh.grid), dim3(sh.block), 0, m->st, m->d_ctl);
-    hipLaunchKernelGGL(k_multi_advance, dim3(1), dim3(64), 0, m->st, m->d_ctl);
+    return MultiArgs{m->d_rot, m->d_ros, m->n};
+}
+
+// Queue the kernels of `rounds` rounds with launch sequence `var` whose
+// records start at `rec` (stride S).
+void launch_round_kernels(fibar_multi* m, const Shape& sh, const StreamStep* rec,
+                          uint32_t rounds, int var)
+{
+    const MultiArgs a = multi_args(m);
+    for (uint32_t j = 0; j < rounds; ++j) {
+        const StreamStep* rr = rec + (size_t)j * m->n;
+        hipLaunchKernelGGL(k_multi_apply, dim3(sh.grid), dim3(sh.block), 0, m->st, a, rr, 0);
+        if (var & 1)
+            hipLaunchKernelGGL(k_multi_apply, dim3(sh.grid), dim3(sh.block), 0, m->st, a, rr, 1);
+        hipLaunchKernelGGL(k_multi_pop, dim3(sh.grid), dim3(sh.block), 0, m->st, a, rr);
+    }
+    if (var & 2)
+        hipLaunchKernelGGL(k_multi_readout, dim3(sh.grid), dim3(sh.block), 0, m->st, a,
+                           rec + (size_t)(rounds - 1) * m->n);
+}
+
+// The launches of a graph: stage the records, the rounds on the ring, advance.
+hipError_t launch_rounds(fibar_multi* m, const Shape& sh, uint32_t rounds, int var)
+{
+    const uint32_t n16 = (uint32_t)(rounds * m->n * sizeof(StreamStep) / 16);
+    hipLaunchKernelGGL(k_multi_stage, dim3(std::min<uint32_t>(64, (n16 + 255) / 256)), dim3(256), 0,
+                       m->st, m->d_rec, m->d_ring, m->base, m->n, n16);
+    launch_round_kernels(m, sh, m->d_ring, rounds, var);
+    hipLaunchKernelGGL(k_multi_advance, dim3(1), dim3(64), 0, m->st, m->base, rounds);
     return hipGetLastError();
 }
 
-hipError_t round_graph(fibar_multi* m, int shape, bool two, hipGraphExec_t* out)
+hipError_t rounds_graph(fibar_multi* m, int shape, uint32_t rounds, int var, hipGraphExec_t* out)
 {
-    hipGraphExec_t& g = m->graph[shape][two ? 1 : 0];
+    hipGraphExec_t& g = m->graph[shape][rounds - 1][var];
     if (!g) {
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamBeginCapture(m->st, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return e;
-        hipError_t le = launch_round(m, kShapes[shape], two);
+        hipError_t le = launch_rounds(m, kShapes[shape], rounds, var);
         e = hipStreamEndCapture(m->st, &graph);
         if (le != hipSuccess) e = le;
         if (e == hipSuccess) e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
@@ -303,13 +377,16 @@ struct StreamPlan {
 // Pending steps at the end of a batch are committed in one launch.
 int commit_pending(fibar_multi* m, std::vector<StreamPlan>& plans)
 {
+    // the staged descriptors of the previous batch's commits must have been
+    // copied before they are overwritten
+    HIP_TRY(hipEventSynchronize(m->commits_free));
     uint32_t nc = 0;
     for (uint32_t i = 0; i < m->n; ++i) {
         StreamPlan& p = plans[i];
         if (p.pend_idx == kNone) continue;
         CommitDesc& c = m->h_commits[nc++];
-        c.stream = i;
-        c.prev_idx = p.pend_idx;
+        c.s = m->ctx[i]->s;
+        c.prev = m->scratch + p.pend_idx;
         c.prev_events = p.pend_events;
         c.slot_in = p.cur_slot;
         c.slot_out = p.cur_slot ^ 1;
@@ -319,7 +396,8 @@ int commit_pending(fibar_multi* m, std::vector<StreamPlan>& plans)
     if (nc) {
         HIP_TRY(hipMemcpyAsync(m->d_commits, m->h_commits, nc * sizeof(CommitDesc),
                                hipMemcpyHostToDevice, m->st));
-        hipLaunchKernelGGL(k_multi_commit, dim3((nc + 63) / 64), dim3(64), 0, m->st, m->d_ctl,
+        HIP_TRY(hipEventRecord(m->commits_free, m->st));
+        hipLaunchKernelGGL(k_multi_commit, dim3((nc + 63) / 64), dim3(64), 0, m->st,
                            m->d_commits, nc);
         HIP_TRY(hipGetLastError());
     }
@@ -332,18 +410,14 @@ int run_multi_batch(fibar_multi* m, std::vector<StreamPlan>& plans, bool* done)
 {
     HIP_TRY(hipEventSynchronize(m->staging_free));
     const uint32_t S = m->n;
-    uint32_t n_chunks = 0, n_steps = 0, n_rounds = 0, n_ro = 0;
-    uint32_t n_apply = 0, n_pop = 0, n_rot = 0;
-    uint64_t events_in_group[kNumShapes] = {};
-    bool any_two = false;
+    uint32_t n_chunks = 0, n_steps = 0, n_rounds = 0, n_ro = 0, n_rot = 0;
     struct PendingChunk {
-        uint32_t round, sub;
+        uint32_t round, rec, sub;
         ChunkDesc d;
     };
     std::vector<std::vector<PendingChunk>> chunks_of(S);
-    std::vector<int> round_shape;
+    std::vector<int> round_var;
     std::vector<uint64_t> round_events;
-    const uint32_t tune_group = 4;   // rounds per candidate shape while tuning
     *done = true;
     for (;;) {
         bool more = false;
@@ -360,101 +434,128 @@ int run_multi_batch(fibar_multi* m, std::vector<StreamPlan>& plans, bool* done)
         }
         if (!more) break;
         if (n_rounds == kMultiMaxRounds || n_chunks + need_chunks > kMultiChunks ||
-            n_ro + need_ro > kMultiMaxReadouts || n_apply + need_chunks * kChunk + S > kMultiMaxTasks ||
-            n_pop + need_chunks * kChunk + S > kMultiMaxTasks || n_rot + need_rot > kMultiMaxTasks) {
+            n_ro + need_ro > kMultiMaxReadouts || n_rot + need_rot > kMultiMaxRoTasks) {
             *done = false;
             break;
         }
-        const int shape = m->tune ? (int)((n_rounds / tune_group) % kNumShapes) : m->shape;
-        const uint32_t B = kShapes[shape].block;
-        RoundDesc& rd = m->h_rounds[n_rounds];
-        memset(&rd, 0, sizeof(rd));
-        rd.step_off = n_rounds * S;
-        rd.apply_off[0] = n_apply;
-        rd.pop_off = n_pop;
-        rd.ro_off = n_rot;
+        const uint32_t ro_off = n_rot;
         uint64_t ev = 0;
-        std::vector<Task> second;
+        int var = 0;
+        uint32_t nrec = 0;
         for (uint32_t i = 0; i < S; ++i) {
             StreamPlan& p = plans[i];
-            MultiStep& st = m->h_steps[n_rounds * S + i];
-            memset(&st, 0, sizeof(st));
-            st.prev_idx = kNone;
-            st.slot_out = -1;
             if (p.next >= p.n_ops) continue;         // this stream is done
             const fibar_packet& pk = p.ops[p.next].packet;
             ++p.next;
+            const uint32_t k = nrec++;
+            StreamStep& e = m->h_rec[(size_t)n_rounds * S + k];
+            memset(&e, 0, sizeof(e));
+            e.s = m->ctx[i]->s;
             const uint32_t nev = (uint32_t)pk.n;
             ev += nev;
-            st.events = nev;
-            st.n_chunks = (nev + kChunk - 1) / kChunk;
-            st.step_idx = n_steps++;
-            for (uint32_t c = 0; c < st.n_chunks; ++c) {
+            e.events = nev;
+            const uint32_t step_idx = n_steps++;
+            e.step = m->scratch + step_idx;
+            const uint32_t nch = (nev + kChunk - 1) / kChunk;
+            for (uint32_t c = 0; c < nch; ++c) {
                 PendingChunk pc;
                 const uint32_t off = c * kChunk;
                 pc.round = n_rounds;
+                pc.rec = k;
                 pc.sub = c;
                 pc.d.x = pk.x + off;
                 pc.d.y = pk.y + off;
                 pc.d.p = pk.p + off;
                 pc.d.n = nev - off < (uint32_t)kChunk ? nev - off : (uint32_t)kChunk;
-                pc.d.pkt = st.step_idx;
-                st.chunk[c] = pc.d;
+                pc.d.pkt = step_idx;
+                e.chunk[c] = pc.d;
                 chunks_of[i].push_back(pc);
                 ++n_chunks;
             }
-            st.prev_idx = p.pend_idx;
-            st.prev_events = p.pend_events;
-            st.slot_in = p.cur_slot;
+            e.prev = p.pend_idx == kNone ? nullptr : m->scratch + p.pend_idx;
+            e.prev_events = p.pend_events;
+            e.slot_in = p.cur_slot;
+            e.slot_out = -1;
             if (p.pend_idx != kNone) {
-                st.slot_out = p.cur_slot ^ 1;
-                m->h_apply[n_apply++] = Task{i, kNone};   // commit of the previous step
-                ++rd.apply_cnt[0];
+                e.slot_out = p.cur_slot ^ 1;
                 p.cur_slot ^= 1;
             }
-            st.pop_slot = p.cur_slot;
-            for (uint32_t b = 0; b * B < st.chunk[0].n; ++b) {
-                m->h_apply[n_apply++] = Task{i, b};
-                ++rd.apply_cnt[0];
-            }
-            if (st.n_chunks == 2) {
-                any_two = true;
-                for (uint32_t b = 0; b * B < st.chunk[1].n; ++b) second.push_back(Task{i, b});
-            }
-            st.pop_blocks = std::max<uint32_t>(1, (nev + B - 1) / B);
-            for (uint32_t v = 0; v < st.pop_blocks; ++v) {
-                m->h_pop[n_pop++] = Task{i, v};
-                ++rd.pop_cnt;
-            }
-            p.pend_idx = st.step_idx;
+            e.pop_slot = p.cur_slot;
+            if (nch == 2) var |= 1;
+            p.pend_idx = step_idx;
             p.pend_events = nev;
             while (p.next < p.n_ops && p.ops[p.next].kind == FIBAR_OP_READOUT) {
                 const fibar_readout_buf& rb = p.ops[p.next].readout;
                 MultiReadout& ro = m->h_ros[n_ro];
-                ro.stream = i;
-                ro.pad = 0;
                 ro.L = rb.brightness;
                 ro.pbar = rb.pbar;
                 ro.stale = rb.stale_mask;
                 ro.cnt = rb.active_count;
                 ro.last = rb.last_index;
                 ro.log_age = rb.log_age;
-                for (uint64_t blk = 0; blk * kReadoutBlock < m->ctx[i]->npx; ++blk) {
-                    m->h_rot[n_rot++] = Task{i, (n_ro << 12) | (uint32_t)blk};
-                    ++rd.ro_cnt;
-                }
+                for (uint64_t blk = 0; blk * kReadoutBlock < m->ctx[i]->npx; ++blk)
+                    m->h_rot[n_rot++] = RoTask{k, n_ro, (uint32_t)blk, 0u};
                 ++n_ro;
                 ++p.next;
+                var |= 2;
             }
         }
-        rd.apply_off[1] = n_apply;
-        for (const Task& t : second) m->h_apply[n_apply++] = t;
-        rd.apply_cnt[1] = (uint32_t)second.size();
-        round_shape.push_back(shape);
+        for (uint32_t k = nrec; k < S; ++k)
+            memset(&m->h_rec[(size_t)n_rounds * S + k], 0, sizeof(StreamStep));
+        m->h_rec[(size_t)n_rounds * S].ro_off = ro_off;
+        m->h_rec[(size_t)n_rounds * S].ro_cnt = n_rot - ro_off;
+        round_var.push_back(var);
         round_events.push_back(ev);
         ++n_rounds;
     }
     if (n_rounds == 0) return FIBAR_OK;
+
+    // Groups of rounds replayed as one graph: at most kUnroll rounds
+    // (kTuneLen while tuning, each group with the next candidate shape) of
+    // the same second-sub-round flag, ending at the first round with
+    // readouts.
+    struct Group {
+        uint32_t r0, len;
+        int shape, var;
+        uint64_t events;
+    };
+    std::vector<Group> groups;
+    for (uint32_t r = 0; r < n_rounds;) {
+        const int two = round_var[r] & 1;
+        const int shape = m->tune ? (int)(m->tune_next++ % kNumShapes) : m->shape;
+        const uint32_t cap = m->tune ? kTuneLen : kUnroll;
+        Group g{r, 0, shape, two, 0};
+        while (r < n_rounds && (round_var[r] & 1) == two && g.len < cap) {
+            g.events += round_events[r];
+            ++g.len;
+            const bool ro = round_var[r] & 2;
+            ++r;
+            if (ro) {
+                g.var |= 2;
+                break;
+            }
+        }
+        groups.push_back(g);
+    }
+
+    // task counts of each round for the workgroup size of its group
+    for (const Group& g : groups) {
+        const uint32_t B = kShapes[g.shape].block;
+        for (uint32_t r = g.r0; r < g.r0 + g.len; ++r) {
+            uint32_t acc[kKinds] = {0, 0, 0};
+            for (uint32_t k = 0; k < S; ++k) {
+                StreamStep& e = m->h_rec[(size_t)r * S + k];
+                if (e.events) {
+                    e.pop_blocks = std::max<uint32_t>(1, (e.events + B - 1) / B);
+                    acc[0] += (e.chunk[0].n + B - 1) / B + (e.prev ? 1u : 0u);
+                    acc[1] += (e.chunk[1].n + B - 1) / B;
+                    acc[2] += e.pop_blocks;
+                }
+                // records without a step come last and get the totals
+                for (int q = 0; q < kKinds; ++q) e.end[q] = acc[q];
+            }
+        }
+    }
 
     // chunk records laid out stream by stream, so that one group+compose
     // launch per stream (its own size and filter constants) covers them
@@ -464,7 +565,9 @@ int run_multi_batch(fibar_multi* m, std::vector<StreamPlan>& plans, bool* done)
         first[i] = slot;
         for (const PendingChunk& pc : chunks_of[i]) {
             m->h_chunks[slot] = pc.d;
-            m->h_steps[pc.round * S + i].seg_chunk[pc.sub] = slot;
+            StreamStep& e = m->h_rec[(size_t)pc.round * S + pc.rec];
+            e.seg[pc.sub] = m->seg + (size_t)slot * kChunk;
+            e.nseg[pc.sub] = m->seg_count + slot;
             ++slot;
         }
     }
@@ -472,21 +575,17 @@ int run_multi_batch(fibar_multi* m, std::vector<StreamPlan>& plans, bool* done)
 
     HIP_TRY(hipMemcpyAsync(m->d_chunks, m->h_chunks, n_chunks * sizeof(ChunkDesc),
                            hipMemcpyHostToDevice, m->st));
-    HIP_TRY(hipMemcpyAsync(m->d_steps, m->h_steps, (size_t)n_rounds * S * sizeof(MultiStep),
+    HIP_TRY(hipMemcpyAsync(m->d_rec, m->h_rec, (size_t)n_rounds * S * sizeof(StreamStep),
                            hipMemcpyHostToDevice, m->st));
-    HIP_TRY(hipMemcpyAsync(m->d_rounds, m->h_rounds, n_rounds * sizeof(RoundDesc),
-                           hipMemcpyHostToDevice, m->st));
-    HIP_TRY(hipMemcpyAsync(m->d_apply, m->h_apply, n_apply * sizeof(Task), hipMemcpyHostToDevice,
-                           m->st));
-    HIP_TRY(hipMemcpyAsync(m->d_pop, m->h_pop, n_pop * sizeof(Task), hipMemcpyHostToDevice, m->st));
     if (n_rot)
-        HIP_TRY(hipMemcpyAsync(m->d_rot, m->h_rot, n_rot * sizeof(Task), hipMemcpyHostToDevice, m->st));
+        HIP_TRY(hipMemcpyAsync(m->d_rot, m->h_rot, n_rot * sizeof(RoTask), hipMemcpyHostToDevice,
+                               m->st));
     if (n_ro)
         HIP_TRY(hipMemcpyAsync(m->d_ros, m->h_ros, n_ro * sizeof(MultiReadout),
                                hipMemcpyHostToDevice, m->st));
     HIP_TRY(hipEventRecord(m->staging_free, m->st));
     HIP_TRY(hipMemsetAsync(m->scratch, 0, n_steps * sizeof(StepScratch), m->st));
-    HIP_TRY(hipMemsetAsync(m->round, 0, sizeof(uint32_t), m->st));
+    HIP_TRY(hipMemsetAsync(m->base, 0, sizeof(uint32_t), m->st));
 
     for (uint32_t i = 0; i < S; ++i) {
         const uint32_t cnt = first[i + 1] - first[i];
@@ -497,40 +596,45 @@ int run_multi_batch(fibar_multi* m, std::vector<StreamPlan>& plans, bool* done)
                                     c->coef, m->st));
     }
 
-    // the rounds: one graph replay each
-    for (uint32_t r = 0; r < n_rounds;) {
-        const int shape = round_shape[r];
-        uint32_t r1 = r;
-        uint64_t ev = 0;
-        while (r1 < n_rounds && round_shape[r1] == shape) ev += round_events[r1++];
-        hipGraphExec_t g = nullptr;
-        HIP_TRY(round_graph(m, shape, any_two, &g));
+    // index of the last group replayed as a graph (the device round index is
+    // only read by graphs)
+    int last_graph = -1;
+    for (size_t q = 0; q < groups.size(); ++q)
+        if (kShapes[groups[q].shape].graph) last_graph = (int)q;
+    for (size_t q = 0; q < groups.size(); ++q) {
+        const Group& g = groups[q];
+        hipGraphExec_t ge = nullptr;
+        if (kShapes[g.shape].graph) HIP_TRY(rounds_graph(m, g.shape, g.len, g.var, &ge));
         if (m->tune) HIP_TRY(hipEventRecord(m->ev_a, m->st));
-        for (uint32_t q = r; q < r1; ++q) HIP_TRY(hipGraphLaunch(g, m->st));
+        if (ge) {
+            HIP_TRY(hipGraphLaunch(ge, m->st));
+        } else {
+            // direct launches; a later graph's first round index moves past
+            // these rounds too
+            launch_round_kernels(m, kShapes[g.shape], m->d_rec + (size_t)g.r0 * S, g.len, g.var);
+            if ((int)q < last_graph)
+                hipLaunchKernelGGL(k_multi_advance, dim3(1), dim3(64), 0, m->st, m->base, g.len);
+            HIP_TRY(hipGetLastError());
+        }
         if (m->tune) {
             HIP_TRY(hipEventRecord(m->ev_b, m->st));
             HIP_TRY(hipEventSynchronize(m->ev_b));
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, m->ev_a, m->ev_b));
-            m->tune_ms[shape] += ms;
-            m->tune_events[shape] += (double)ev;
-            events_in_group[shape] += ev;
+            m->tune_ms[g.shape] += ms;
+            m->tune_events[g.shape] += (double)g.events;
+            ++m->tune_groups[g.shape];
         }
-        r = r1;
     }
     if (m->tune) {
-        // fastest time per event over the rounds each shape ran
-        int best = -1;
-        double best_rate = 0.0;
-        for (int k = 0; k < kNumShapes; ++k) {
-            if (!events_in_group[k]) continue;
-            const double rate = m->tune_ms[k] / m->tune_events[k];
-            if (best < 0 || rate < best_rate) {
-                best = k;
-                best_rate = rate;
-            }
-        }
-        if (best >= 0) {
+        // once every shape has run its groups: the fastest time per event
+        bool enough = true;
+        for (int k = 0; k < kNumShapes; ++k) enough = enough && m->tune_groups[k] >= kTuneGroups;
+        if (enough) {
+            int best = 0;
+            for (int k = 1; k < kNumShapes; ++k)
+                if (m->tune_ms[k] / m->tune_events[k] < m->tune_ms[best] / m->tune_events[best])
+                    best = k;
             m->shape = best;
             m->tune = 0;
         }
@@ -565,44 +669,28 @@ int fibar_multi_create(fibar_ctx* const* ctxs, uint32_t n, void* stream, fibar_m
     auto halloc = [&](void** p, size_t b) {
         if (e == hipSuccess) e = hipHostMalloc(p, b, 0);
     };
-    const size_t steps = (size_t)kMultiMaxRounds * n;
-    dalloc((void**)&m->d_states, n * sizeof(State));
-    dalloc((void**)&m->d_steps, steps * sizeof(MultiStep));
-    dalloc((void**)&m->d_rounds, kMultiMaxRounds * sizeof(RoundDesc));
-    dalloc((void**)&m->d_apply, kMultiMaxTasks * sizeof(Task));
-    dalloc((void**)&m->d_pop, kMultiMaxTasks * sizeof(Task));
-    dalloc((void**)&m->d_rot, kMultiMaxTasks * sizeof(Task));
+    const size_t recs = (size_t)kMultiMaxRounds * n;
+    dalloc((void**)&m->d_rec, recs * sizeof(StreamStep));
+    dalloc((void**)&m->d_ring, (size_t)kUnroll * n * sizeof(StreamStep));
+    dalloc((void**)&m->d_rot, kMultiMaxRoTasks * sizeof(RoTask));
     dalloc((void**)&m->d_ros, kMultiMaxReadouts * sizeof(MultiReadout));
     dalloc((void**)&m->d_commits, kMultiMaxStreams * sizeof(CommitDesc));
     dalloc((void**)&m->d_chunks, kMultiChunks * sizeof(ChunkDesc));
     dalloc((void**)&m->seg, (size_t)kMultiChunks * kChunk * sizeof(SegRec));
     dalloc((void**)&m->seg_count, kMultiChunks * sizeof(uint32_t));
-    dalloc((void**)&m->scratch, steps * sizeof(StepScratch));
-    dalloc((void**)&m->round, sizeof(uint32_t));
-    dalloc((void**)&m->d_ctl, sizeof(MultiCtl));
-    halloc((void**)&m->h_steps, steps * sizeof(MultiStep));
-    halloc((void**)&m->h_rounds, kMultiMaxRounds * sizeof(RoundDesc));
-    halloc((void**)&m->h_apply, kMultiMaxTasks * sizeof(Task));
-    halloc((void**)&m->h_pop, kMultiMaxTasks * sizeof(Task));
-    halloc((void**)&m->h_rot, kMultiMaxTasks * sizeof(Task));
+    dalloc((void**)&m->scratch, recs * sizeof(StepScratch));
+    dalloc((void**)&m->base, sizeof(uint32_t));
+    halloc((void**)&m->h_rec, recs * sizeof(StreamStep));
+    halloc((void**)&m->h_rot, kMultiMaxRoTasks * sizeof(RoTask));
     halloc((void**)&m->h_ros, kMultiMaxReadouts * sizeof(MultiReadout));
     halloc((void**)&m->h_commits, kMultiMaxStreams * sizeof(CommitDesc));
     halloc((void**)&m->h_chunks, kMultiChunks * sizeof(ChunkDesc));
     if (e == hipSuccess) e = hipEventCreateWithFlags(&m->staging_free, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&m->commits_free, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreate(&m->ev_a);
     if (e == hipSuccess) e = hipEventCreate(&m->ev_b);
-    if (e != hipSuccess) {
-        multi_free(m);
-        return map_err(e);
-    }
-    std::vector<State> states(n);
-    for (uint32_t i = 0; i < n; ++i) states[i] = ctxs[i]->s;
-    MultiCtl ctl{m->d_states, m->d_steps, m->d_rounds, m->d_apply, m->d_pop, m->d_rot, m->d_ros,
-                 m->seg, m->seg_count, m->scratch, m->round};
-    e = hipMemcpyAsync(m->d_states, states.data(), n * sizeof(State), hipMemcpyHostToDevice, m->st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(m->d_ctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, m->st);
     if (e == hipSuccess) e = hipEventRecord(m->staging_free, m->st);
+    if (e == hipSuccess) e = hipEventRecord(m->commits_free, m->st);
     if (e == hipSuccess) e = hipStreamSynchronize(m->st);
     if (e != hipSuccess) {
         multi_free(m);
@@ -668,7 +756,11 @@ int fibar_multi_autotune(fibar_multi* m)
 {
     if (!m) return FIBAR_E_INVALID_ARG;
     m->tune = 1;
-    for (int k = 0; k < kNumShapes; ++k) m->tune_ms[k] = m->tune_events[k] = 0.0;
+    m->tune_next = 0;
+    for (int k = 0; k < kNumShapes; ++k) {
+        m->tune_ms[k] = m->tune_events[k] = 0.0;
+        m->tune_groups[k] = 0;
+    }
     return FIBAR_OK;
 }
 
@@ -677,6 +769,13 @@ int fibar_multi_get_shape(fibar_multi* m, uint32_t* block, uint32_t* grid)
     if (!m || !block || !grid) return FIBAR_E_INVALID_ARG;
     *block = kShapes[m->shape].block;
     *grid = kShapes[m->shape].grid;
+    return FIBAR_OK;
+}
+
+int fibar_multi_get_config(fibar_multi* m, uint32_t* index)
+{
+    if (!m || !index) return FIBAR_E_INVALID_ARG;
+    *index = (uint32_t)m->shape;
     return FIBAR_OK;
 }
 

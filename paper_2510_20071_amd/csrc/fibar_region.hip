@@ -365,11 +365,14 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
 
 hipError_t launch_region_batch(const State& s, int slot, const ChunkDesc* d_chunks,
                                uint32_t n_chunks, StepScratch* scratch, const RegionBuffers& rb,
-                               uint32_t n_readouts, int key_bits, Coef coef, hipStream_t st)
+                               uint32_t n_readouts, int key_bits, Coef coef, hipStream_t st,
+                               const LaunchTiming& tm)
 {
     if (n_chunks > 0) {
-        hipLaunchKernelGGL(k_region_count, dim3(n_chunks), dim3(1024), 0, st, d_chunks, s.W, s.H,
-                           rb.n_regions, rb.cnt, scratch);
+        const hipError_t e = launch_timed(k_region_count, dim3(n_chunks), dim3(1024), st,
+                                          tm.start, nullptr, d_chunks, s.W, s.H, rb.n_regions,
+                                          rb.cnt, scratch);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_region_scan, dim3(rb.n_regions), dim3(256), 0, st, rb.cnt, n_chunks,
                            rb.n_regions, rb.total);
         hipLaunchKernelGGL(k_region_bases, dim3(1), dim3(1024), 0, st, s, slot, d_chunks, n_chunks,
@@ -381,14 +384,14 @@ hipError_t launch_region_batch(const State& s, int slot, const ChunkDesc* d_chun
                            rb.payload);
     } else {
         // readouts only: empty slices
-        hipLaunchKernelGGL(k_region_scan, dim3(rb.n_regions), dim3(256), 0, st, rb.cnt, 0u,
-                           rb.n_regions, rb.total);
+        const hipError_t e = launch_timed(k_region_scan, dim3(rb.n_regions), dim3(256), st,
+                                          tm.start, nullptr, rb.cnt, 0u, rb.n_regions, rb.total);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_region_bases, dim3(1), dim3(1024), 0, st, s, slot, d_chunks, 0u,
                            scratch, rb);
     }
-    hipLaunchKernelGGL(k_region_apply, dim3(rb.n_regions), dim3(kSortThreads), 0, st, s, rb,
-                       n_chunks, n_readouts, coef);
-    return hipGetLastError();
+    return launch_timed(k_region_apply, dim3(rb.n_regions), dim3(kSortThreads), st, nullptr,
+                        tm.stop, s, rb, n_chunks, n_readouts, coef);
 }
 
 }  // namespace fibar

@@ -143,27 +143,48 @@ __device__ __forceinline__ void pop_bounds(const DevScalars& c, uint32_t pkt_eve
     if (k_end + 1 > c.Q && k_end + 1 - c.Q > c.h) *h_new = k_end + 1 - c.Q;
 }
 
-// Item i of a chunk's apply: push event i to the back of the window and
-// apply the composed map of segment i (one distinct pixel) to the state;
-// counts activations of pixels and tiles.
-__device__ __forceinline__ void apply_item(const State& s, const ChunkDesc& cd,
-                                           const SegRec* __restrict__ seg, uint32_t nseg,
-                                           uint32_t i, uint64_t first, uint64_t h0, int spatial,
-                                           uint32_t& dP, uint32_t& dT)
+// Item i of a chunk's apply, in two parts so that a kernel can issue the
+// loads that need only the chunk (segment record, event coordinates) before
+// it waits for the window head: load_item, then apply_loaded, which pushes
+// event i to the back of the window and applies the composed map of segment
+// i (one distinct pixel) to the state, counting activations of pixels and
+// tiles.  i < kChunk: a chunk slot always holds kChunk records.
+struct Item {
+    SegRec rec;
+    uint32_t ex, ey;
+};
+
+__device__ __forceinline__ Item load_item(const ChunkDesc& cd, const SegRec* __restrict__ seg,
+                                          uint32_t i, int spatial)
 {
+    Item it;
+    it.rec = seg[i];
+    it.ex = 0u;
+    it.ey = 0u;
     if (spatial && i < cd.n) {
-        const uint32_t x = cd.x[i], y = cd.y[i];
-        s.ring[(first + i) & s.ring_mask] = y * s.W + x;
+        it.ex = cd.x[i];
+        it.ey = cd.y[i];
     }
+    return it;
+}
+
+__device__ __forceinline__ void apply_loaded(const State& s, const Item& it, uint32_t n,
+                                             uint32_t nseg, uint32_t i, uint64_t first,
+                                             uint64_t h0, int spatial, uint32_t& dP, uint32_t& dT)
+{
+    if (spatial && i < n) s.ring[(first + i) & s.ring_mask] = it.ey * s.W + it.ex;
     if (i < nseg) {
-        const SegRec r = seg[i];
+        const SegRec& r = it.rec;
         const uint32_t pix = r.pix;
         const float pb = s.pbar[pix];
         float2 lp = s.Lp[pix];
         float l = lp.x;
+        int64_t last_old = 0;
+        uint32_t old = 0u;
         if (spatial) {
+            last_old = s.last[pix];
+            old = s.cnt[pix];
             // a stale (or never seen) pixel's current value is its blurred one
-            const int64_t last_old = s.last[pix];
             l = last_old < (int64_t)h0 ? lp.y : lp.x;
         }
         s.pbar[pix] = fmaf(r.a, pb, r.u1);
@@ -171,7 +192,6 @@ __device__ __forceinline__ void apply_item(const State& s, const ChunkDesc& cd,
         s.Lp[pix] = lp;
         s.last[pix] = (int64_t)(first + (r.n_last & 0xffffu));
         if (spatial) {
-            const uint32_t old = s.cnt[pix];
             s.cnt[pix] = old + (r.n_last >> 16);
             if (old == 0u) {
                 dP += 1u;
@@ -190,14 +210,15 @@ __device__ __forceinline__ void pop_range(const State& s, uint64_t start, uint64
 {
     for (uint64_t j = start; j < h_new; j += stride) {
         const uint32_t pix = s.ring[j & s.ring_mask];
+        // The neighbourhood is read before the count update returns (most
+        // pops end a pixel's activity, so few of these reads are wasted):
+        // the values do not depend on the update, since a pixel that goes
+        // stale in this step is still read as L.
+        const float b = blur_at(s, pix, (int64_t)h_old);
         if (atomicSub(&s.cnt[pix], 1u) == 1u) {
             ++dP;
-            // the tile update and the neighbourhood reads are independent:
-            // issue both before waiting on either
-            const uint32_t told = atomicSub(&s.tcnt[tile_of(s, pix)], 1u);
-            const float b = blur_at(s, pix, (int64_t)h_old);
+            if (atomicSub(&s.tcnt[tile_of(s, pix)], 1u) == 1u) ++dT;
             s.Lp[pix].y = b;
-            if (told == 1u) ++dT;
         }
     }
 }

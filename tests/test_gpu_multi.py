@@ -107,7 +107,7 @@ def test_group_equals_each_stream_alone_and_oracle():
 def test_launch_shape_never_changes_results():
     streams = make_streams()[:3]
     ref = None
-    for shape in range(5):
+    for shape in range(fb.MULTI_CONFIGS):
         print("shape %d" % shape, flush=True)
         res, finals, stats, used = run_group(streams, shape=shape)
         if ref is None:
@@ -171,4 +171,43 @@ def test_group_argument_checks():
     g = fb.Group([a])
     x = np.zeros(10, np.uint16)
     assert g.submit([[fb.push_op(x, x, x.astype(np.uint8))]]) == fb.FIBAR_E_INVALID_ARG
+    assert g.set_shape(fb.MULTI_CONFIGS) == fb.FIBAR_E_INVALID_ARG
+    assert g.set_shape(7) == 0 and g.config() == 7 and g.shape() == (128, 1024)
     g.close()
+
+
+@pytest.mark.parametrize("config", [0, 5])
+def test_group_spanning_many_batches_equals_streams_alone(config):
+    """More rounds and more chunks than one batch of the group holds: the
+    pending commits and staged descriptors at batch boundaries keep every
+    stream exact (tiny packets give thousands of rounds)."""
+    specs = [((64, 48), 2500 * 64, 64, 11), ((346, 260), 1200 * 512, 512, 12),
+             ((640, 480), 40 * 32768, 32768, 13)]
+    streams = []
+    for (W, H), n, packet, seed in specs:
+        sc = eventsim.Scene(W, H, n, 900 + seed, n_blobs=max(32, W * H // 600),
+                            checker_cell=16.0, checker_contrast=0.5, speed_px_s=200.0,
+                            noise_frac=0.01)
+        ev = eventsim.generate(sc)
+        n = len(ev)
+        ro = list(range(n // 7, n, n // 7)) + [n]
+        streams.append((W, H, ev, eventsim.schedule(n, packet, ro)))
+    print("rounds per stream:", [sum(1 for it in s[3] if it[0] == "push") for s in streams],
+          flush=True)
+    res, finals, stats, _ = run_group(streams, shape=config)
+    for si, (W, H, ev, sched) in enumerate(streams):
+        alone, final, st = run_alone(W, H, ev, sched)
+        assert st == stats[si], si
+        for key in final:
+            assert np.array_equal(final[key], finals[si][key]), (si, key)
+        assert len(alone) == len(res[si])
+        for a, g in zip(alone, res[si]):
+            assert np.array_equal(a["L"], g["L"]), si
+            assert np.array_equal(a["stale"], g["stale"]), si
+            assert np.array_equal(a["last"], g["last"]), si
+        orc = oracle.Oracle(W, H)
+        for it in sched:
+            if it[0] == "push":
+                orc.push(ev.x[it[1]:it[2]], ev.y[it[1]:it[2]], ev.p[it[1]:it[2]])
+        compare_state(finals[si], orc.readout(10 ** 12), True, "stream %d" % si)
+        compare_stats(stats[si], orc.stats(), "stream %d" % si)
