@@ -254,3 +254,51 @@ def batched_streams(n_streams: int = 16, meta_seed: int = 4, scale: float = 1.0)
                             np.zeros(0, np.int64)))
         out[-1].rate = rate
     return out
+
+
+# --------------------------------------------------------------------------
+# Inputs of the learned stale fill: seeded initial parameters, the training
+# target and the quality score.  None of this is the fill's arithmetic (the
+# network lives in the library and in the oracle); these are the random draws
+# and the evaluation protocol both sides are given.
+# --------------------------------------------------------------------------
+FILL_CHANNELS = (3, 16, 16, 16, 1)
+
+
+def fill_init_params(seed: int) -> np.ndarray:
+    """He-normal initial weights (std sqrt(2 / (9 Cin))), zero biases, as one
+    flat FP32 vector in layer order, w in [Cout][Cin][3][3] then b."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for cin, cout in zip(FILL_CHANNELS[:-1], FILL_CHANNELS[1:]):
+        std = np.sqrt(2.0 / (9 * cin))
+        parts.append(rng.normal(0.0, std, size=cout * cin * 9))
+        parts.append(np.zeros(cout))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def fill_target(gt, L, active):
+    """Ground truth in the units of the reconstruction: the least-squares
+    affine map of a frame's ground-truth log intensity onto its brightness L,
+    fitted on the frame's active pixels (there the reconstruction follows the
+    scene), applied to the whole frame.  gt, L: [H, W]; active: bool [H, W]."""
+    g = np.asarray(gt, np.float64)[active]
+    l = np.asarray(L, np.float64)[active]
+    if g.size < 2 or np.var(g) == 0:
+        return np.zeros_like(np.asarray(gt, np.float32))
+    a = np.cov(g, l, bias=True)[0, 1] / np.var(g)
+    b = l.mean() - a * g.mean()
+    return (a * np.asarray(gt, np.float64) + b).astype(np.float32)
+
+
+def fill_psnr(img, target, mask):
+    """PSNR (dB) of img against target over mask; the peak is the target's
+    range over the frame."""
+    m = np.asarray(mask) != 0
+    t = np.asarray(target, np.float64)
+    err = np.asarray(img, np.float64)[m] - t[m]
+    mse = float(np.mean(err * err)) if err.size else 0.0
+    peak = float(t.max() - t.min())
+    if mse == 0.0 or peak == 0.0:
+        return float("inf")
+    return 10.0 * np.log10(peak * peak / mse)
