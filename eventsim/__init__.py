@@ -265,14 +265,20 @@ def batched_streams(n_streams: int = 16, meta_seed: int = 4, scale: float = 1.0)
 FILL_CHANNELS = (3, 16, 16, 16, 1)
 
 
-def fill_init_params(seed: int) -> np.ndarray:
+def fill_init_params(seed: int, zero_last: bool = True) -> np.ndarray:
     """He-normal initial weights (std sqrt(2 / (9 Cin))), zero biases, as one
-    flat FP32 vector in layer order, w in [Cout][Cin][3][3] then b."""
+    flat FP32 vector in layer order, w in [Cout][Cin][3][3] then b.  With
+    zero_last the last layer starts at zero, so the untrained fill is the
+    Gaussian fill itself."""
     rng = np.random.default_rng(seed)
     parts = []
-    for cin, cout in zip(FILL_CHANNELS[:-1], FILL_CHANNELS[1:]):
+    layers = list(zip(FILL_CHANNELS[:-1], FILL_CHANNELS[1:]))
+    for k, (cin, cout) in enumerate(layers):
         std = np.sqrt(2.0 / (9 * cin))
-        parts.append(rng.normal(0.0, std, size=cout * cin * 9))
+        w = rng.normal(0.0, std, size=cout * cin * 9)
+        if zero_last and k == len(layers) - 1:
+            w[:] = 0.0
+        parts.append(w)
         parts.append(np.zeros(cout))
     return np.concatenate(parts).astype(np.float32)
 

@@ -15,6 +15,9 @@ state.  Definitions followed here:
   after each of the first three.  Cross-correlation (no kernel flip):
   y[o, i, j] = b[o] + sum_{c, dy, dx} w[o, c, dy, dx] x[c, i + dy - 1, j + dx - 1]
   with x = 0 outside the image.
+* Prediction = L + the last layer's output: the network learns a correction
+  of the brightness the reconstruction shows (its Gaussian fill at stale
+  pixels), so zero last-layer parameters give back L exactly.
 * Loss: the mean of (prediction - target)^2 over the stale pixels of the batch.
 * Optimiser: Adam (Kingma and Ba, 2015, Algorithm 1) with bias correction.
 
@@ -83,14 +86,15 @@ def conv3x3_backward(x, w, gy):
 
 
 def forward(params, x):
-    """Prediction [N, H, W] and the per-layer inputs / pre-activations."""
+    """Prediction [N, H, W] (input channel 0 plus the network's output) and
+    the per-layer inputs / pre-activations."""
     cache = []
     a = x
     for l, (w, b) in enumerate(params):
         z = conv3x3(a, w, b)
         cache.append((a, z))
         a = np.maximum(z, 0.0) if l < N_LAYERS - 1 else z
-    return a[:, 0], cache
+    return x[:, 0] + a[:, 0], cache
 
 
 def backward(params, cache, gpred):

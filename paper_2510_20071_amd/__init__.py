@@ -106,6 +106,30 @@ _SIGNATURES.update({
     "fibar_multi_destroy": (None, [ctypes.c_void_p]),
 })
 
+# include/fibar_fill.h
+FILL_PARAMS = 5233
+_FP = ctypes.POINTER(ctypes.c_float)
+_SIGNATURES.update({
+    "fibar_fill_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "fibar_fill_set_params": (ctypes.c_int, [ctypes.c_void_p, _FP]),
+    "fibar_fill_get_params": (ctypes.c_int, [ctypes.c_void_p, _FP]),
+    "fibar_fill_predict": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                          ctypes.c_uint32, ctypes.c_void_p]),
+    "fibar_fill_loss_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                            ctypes.c_uint32, ctypes.c_uint32, _FP, _FP]),
+    "fibar_fill_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                             ctypes.c_uint32, ctypes.c_uint32, ctypes.c_float,
+                                             _FP]),
+    "fibar_fill_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                        ctypes.c_uint32, ctypes.c_float, ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_uint32)]),
+    "fibar_fill_destroy": (None, [ctypes.c_void_p]),
+})
+
 KERNEL_NAMES = ("group_compose", "apply", "pop_blur", "blur_write", "readout")
 
 _lib = None
@@ -390,6 +414,117 @@ class Group:
     def close(self):
         if getattr(self, "handle", None):
             fibar_multi_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fibar_fill_create(stream=None):
+    """Returns (status, handle)."""
+    h = ctypes.c_void_p()
+    rc = load().fibar_fill_create(stream, ctypes.byref(h))
+    return rc, h
+
+
+def fibar_fill_set_params(handle, params) -> int:
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    return load().fibar_fill_set_params(handle, a.ctypes.data_as(_FP))
+
+
+def fibar_fill_get_params(handle):
+    """Returns (status, params)."""
+    a = np.empty(FILL_PARAMS, np.float32)
+    rc = load().fibar_fill_get_params(handle, a.ctypes.data_as(_FP))
+    return rc, a
+
+
+def fibar_fill_predict(handle, L, stale, log_age, n, H, W, pred) -> int:
+    return load().fibar_fill_predict(handle, _addr(L), _addr(stale), _addr(log_age), n, H, W,
+                                     _addr(pred))
+
+
+def fibar_fill_loss_grad(handle, L, stale, log_age, target, n, H, W, want_grad=True):
+    """Returns (status, loss, grad or None)."""
+    loss = ctypes.c_float()
+    g = np.empty(FILL_PARAMS, np.float32) if want_grad else None
+    rc = load().fibar_fill_loss_grad(handle, _addr(L), _addr(stale), _addr(log_age),
+                                     _addr(target), n, H, W, ctypes.byref(loss),
+                                     g.ctypes.data_as(_FP) if g is not None else None)
+    return rc, float(loss.value), g
+
+
+def fibar_fill_train_step(handle, L, stale, log_age, target, n, H, W, lr, want_loss=True):
+    """Returns (status, loss before the step or None)."""
+    loss = ctypes.c_float()
+    rc = load().fibar_fill_train_step(handle, _addr(L), _addr(stale), _addr(log_age),
+                                      _addr(target), n, H, W, float(lr),
+                                      ctypes.byref(loss) if want_loss else None)
+    return rc, (float(loss.value) if want_loss else None)
+
+
+def fibar_fill_apply(handle, L, stale, log_age, H, W, tile, tau, out):
+    """Returns (status, tiles that fell back)."""
+    fb = ctypes.c_uint32()
+    rc = load().fibar_fill_apply(handle, _addr(L), _addr(stale), _addr(log_age), H, W, int(tile),
+                                 float(tau), _addr(out), ctypes.byref(fb))
+    return rc, int(fb.value)
+
+
+def fibar_fill_destroy(handle) -> None:
+    load().fibar_fill_destroy(handle)
+
+
+class Fill:
+    """Learned stale fill (fibar_fill_*).  Image arguments are device tensors
+    of [n,] H x W (float32 L, log_age, target and outputs; uint8 stale)."""
+
+    def __init__(self, params=None, stream=None):
+        rc, h = fibar_fill_create(stream)
+        if rc != FIBAR_OK:
+            raise FibarError(rc, "fibar_fill_create")
+        self.handle = h
+        if params is not None:
+            rc = self.set_params(params)
+            if rc != FIBAR_OK:
+                raise FibarError(rc, "fibar_fill_set_params")
+
+    def set_params(self, params) -> int:
+        assert np.asarray(params).shape == (FILL_PARAMS,)
+        return fibar_fill_set_params(self.handle, params)
+
+    def get_params(self):
+        rc, a = fibar_fill_get_params(self.handle)
+        if rc != FIBAR_OK:
+            raise FibarError(rc, "fibar_fill_get_params")
+        return a
+
+    @staticmethod
+    def _dims(L):
+        shp = tuple(L.shape)
+        return (1,) + shp if len(shp) == 2 else shp
+
+    def predict(self, L, stale, log_age, out) -> int:
+        return fibar_fill_predict(self.handle, L, stale, log_age, *self._dims(L), out)
+
+    def loss_grad(self, L, stale, log_age, target, want_grad=True):
+        return fibar_fill_loss_grad(self.handle, L, stale, log_age, target, *self._dims(L),
+                                    want_grad=want_grad)
+
+    def train_step(self, L, stale, log_age, target, lr, want_loss=True):
+        return fibar_fill_train_step(self.handle, L, stale, log_age, target, *self._dims(L), lr,
+                                     want_loss=want_loss)
+
+    def apply(self, L, stale, log_age, out, tile=16, tau=4.0):
+        _, H, W = self._dims(L)
+        return fibar_fill_apply(self.handle, L, stale, log_age, H, W, tile, tau, out)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            fibar_fill_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

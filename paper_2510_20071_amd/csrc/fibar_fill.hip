@@ -1,0 +1,651 @@
+// Learned stale fill on gfx950 (C ABI in include/fibar_fill.h).
+//
+// Activations are NHWC with 16 BF16 channels per pixel (32 bytes; the 3 input
+// channels are zero-padded to 16, the 1 output channel is channel 0 of 16).
+// A 3x3 layer is an implicit GEMM per 16-pixel row segment: for each of the 9
+// taps one v_mfma_f32_16x16x16_bf16 multiplies the segment's shifted input
+// (16 pixels x 16 input channels) by the tap's weights (16 x 16), FP32
+// accumulation.  Operand lane layout (checked on the device): lane l holds
+// A[l % 16][4 (l / 16) + j], B[4 (l / 16) + j][l % 16] and D[4 (l / 16) + j][l % 16],
+// j = 0..3.  The weights of every tap are stored per lane in that order, so
+// a lane loads its B operand with one 8-byte read.
+//
+// The input gradient of a layer is the same kernel with the tap-flipped,
+// channel-transposed weights; the weight gradient is a GEMM over pixels
+// (gradient^T x shifted input) per tap, summed per workgroup and then over
+// workgroups in a fixed order, so training is deterministic.
+#include "fibar.h"
+#include "fibar_fill.h"
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+namespace {
+
+constexpr int kC = 16;                          // channels of every activation
+constexpr int kLayers = 4;
+constexpr int kTaps = 9;
+constexpr int kGradBlocks = 256;                // workgroups of a weight gradient
+constexpr int kWgEntries = kTaps * kC * kC + kC;   // one layer's (w, b) gradient, padded
+constexpr int kLossBlocks = 256;
+
+__host__ __device__ constexpr int cin_of(int l) { return l == 0 ? 3 : 16; }
+__host__ __device__ constexpr int cout_of(int l) { return l == 3 ? 1 : 16; }
+__host__ __device__ constexpr int w_off(int l)
+{
+    return l == 0 ? 0 : l == 1 ? 448 : l == 2 ? 2768 : 5088;
+}
+__host__ __device__ constexpr int b_off(int l) { return w_off(l) + cout_of(l) * cin_of(l) * kTaps; }
+static_assert(b_off(3) + 1 == FIBAR_FILL_PARAMS, "parameter layout");
+
+typedef short bf16x4 __attribute__((__vector_size__(4 * sizeof(short))));
+typedef float f32x4 __attribute__((__vector_size__(4 * sizeof(float))));
+
+// FP32 -> BF16 bits, round to nearest even (inputs are finite).
+__device__ __forceinline__ uint16_t to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// ---------------------------------------------------------------------------
+// Weights: FP32 master parameters -> per-lane BF16 MFMA operands.
+// wf[l][t][lane] = w[o = lane % 16][c = 4 (lane / 16) + j][t]        (forward)
+// wb[l][t][lane] = w[o = 4 (lane / 16) + j][c = lane % 16][8 - t]   (input gradient)
+// bias[l][o], zero beyond the layer's channels.  Grid: (4 layers x 9 taps), 64 threads.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_fill_pack_weights(const float* __restrict__ prm,
+                                                          bf16x4* __restrict__ wf,
+                                                          bf16x4* __restrict__ wb,
+                                                          float* __restrict__ bias)
+{
+    const int l = blockIdx.x / kTaps, t = blockIdx.x % kTaps, lane = threadIdx.x;
+    const int ci = cin_of(l), co = cout_of(l);
+    const float* w = prm + w_off(l);
+    bf16x4 f, b;
+    for (int j = 0; j < 4; ++j) {
+        const int fo = lane & 15, fc = 4 * (lane >> 4) + j;
+        f[j] = (short)((fo < co && fc < ci) ? to_bf16(w[(fo * ci + fc) * kTaps + t]) : 0);
+        const int bo = 4 * (lane >> 4) + j, bc = lane & 15;
+        b[j] = (short)((bo < co && bc < ci) ? to_bf16(w[(bo * ci + bc) * kTaps + (kTaps - 1 - t)])
+                                            : 0);
+    }
+    wf[(l * kTaps + t) * 64 + lane] = f;
+    wb[(l * kTaps + t) * 64 + lane] = b;
+    if (t == 0 && lane < kC) bias[l * kC + lane] = lane < co ? prm[b_off(l) + lane] : 0.f;
+}
+
+// Network input from readout planes: channels (L, stale, log(1 + age), 0 ...).
+__global__ __launch_bounds__(256) void k_fill_pack_input(const float* __restrict__ L,
+                                                         const uint8_t* __restrict__ stale,
+                                                         const float* __restrict__ log_age,
+                                                         size_t P, uint16_t* __restrict__ x)
+{
+    const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    uint4 lo, hi = make_uint4(0u, 0u, 0u, 0u);
+    lo.x = (uint32_t)to_bf16(L[p]) | ((uint32_t)(stale[p] ? to_bf16(1.f) : 0u) << 16);
+    lo.y = (uint32_t)to_bf16(log_age[p]);
+    lo.z = 0u;
+    lo.w = 0u;
+    uint4* dst = reinterpret_cast<uint4*>(x + p * kC);
+    dst[0] = lo;
+    dst[1] = hi;
+}
+
+// ---------------------------------------------------------------------------
+// One 3x3 layer (or its input gradient), one wave per 16-pixel row segment.
+// out[p][o] = bias[o] + sum_t sum_c in[p + off(t)][c] w_t[c][o], then ReLU if
+// `relu`, then zero where gate[p][o] == 0 if `gate` (the ReLU of the layer
+// below, for gradients).  Writes BF16 (out16) and/or channel 0 plus skip[p]
+// as FP32 (out32: the prediction, L plus the network's correction).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_fill_conv(const uint16_t* __restrict__ in,
+                                                   const bf16x4* __restrict__ w,
+                                                   const float* __restrict__ bias, int relu,
+                                                   const uint16_t* __restrict__ gate,
+                                                   uint16_t* __restrict__ out16,
+                                                   float* __restrict__ out32,
+                                                   const float* __restrict__ skip, uint32_t n,
+                                                   uint32_t H, uint32_t W)
+{
+    const uint32_t sw = (W + 15) / 16;
+    const size_t seg = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (seg >= (size_t)n * H * sw) return;   // whole wave; no barriers below
+    const uint32_t lane = threadIdx.x & 63;
+    const size_t row = seg / sw;             // img * H + y
+    const uint32_t y = (uint32_t)(row % H);
+    const size_t img0 = row - y;             // img * H
+    const uint32_t x0 = (uint32_t)(seg % sw) * 16;
+    const int px = (int)(x0 + (lane & 15));
+    const uint32_t cq = (lane >> 4) * 4;
+
+    // every tap's operands are loaded before the products
+    bf16x4 a[kTaps], b[kTaps];
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) {
+        const int yy = (int)y + t / 3 - 1, xx = px + t % 3 - 1;
+        bf16x4 v = {0, 0, 0, 0};
+        if (yy >= 0 && yy < (int)H && xx >= 0 && xx < (int)W)
+            v = *reinterpret_cast<const bf16x4*>(in + ((img0 + yy) * W + xx) * kC + cq);
+        a[t] = v;
+        b[t] = w[t * 64 + lane];
+    }
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t)
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[t], b[t], acc, 0, 0, 0);
+
+    const uint32_t o = lane & 15;
+    const float bo = bias ? bias[o] : 0.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t xo = x0 + (lane >> 4) * 4 + j;
+        if (xo >= W) continue;
+        const size_t p = (row * W + xo);
+        float v = acc[j] + bo;
+        if (relu) v = v > 0.f ? v : 0.f;
+        if (gate && (gate[p * kC + o] & 0x7fff) == 0) v = 0.f;
+        if (out16) out16[p * kC + o] = to_bf16(v);
+        if (out32 && o == 0) out32[p] = v + skip[p];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient of one layer: g[t][o][c] = sum_p gz[p][o] in[p + off(t)][c]
+// and gb[o] = sum_p gz[p][o], as one partial sum per workgroup.  Each wave
+// takes 16-pixel segments; per segment and tap one MFMA with A = gz^T
+// (16 channels x 16 pixels) and B = the shifted input (16 pixels x 16
+// channels).  Grid: kGradBlocks x 256 threads.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_fill_wgrad(const uint16_t* __restrict__ in,
+                                                    const uint16_t* __restrict__ gz, uint32_t n,
+                                                    uint32_t H, uint32_t W,
+                                                    float* __restrict__ partial)
+{
+    __shared__ float red[4][kWgEntries];
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t sw = (W + 15) / 16;
+    const size_t nseg = (size_t)n * H * sw;
+    const uint32_t ch = lane & 15, kq = (lane >> 4) * 4;
+    f32x4 acc[kTaps];
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;
+    for (size_t seg = (size_t)blockIdx.x * 4 + wv; seg < nseg; seg += (size_t)gridDim.x * 4) {
+        const size_t row = seg / sw;
+        const uint32_t y = (uint32_t)(row % H);
+        const size_t img0 = row - y;
+        const uint32_t x0 = (uint32_t)(seg % sw) * 16;
+        bf16x4 ga;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t xo = x0 + kq + j;
+            const uint16_t g = xo < W ? gz[(row * W + xo) * kC + ch] : (uint16_t)0;
+            ga[j] = (short)g;
+            bsum += from_bf16(g);
+        }
+        bf16x4 bb[kTaps];
+#pragma unroll
+        for (int t = 0; t < kTaps; ++t) {
+            const int yy = (int)y + t / 3 - 1;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int xx = (int)(x0 + kq + j) + t % 3 - 1;
+                uint16_t v = 0;
+                if (yy >= 0 && yy < (int)H && xx >= 0 && xx < (int)W && x0 + kq + j < W)
+                    v = in[((img0 + yy) * W + xx) * kC + ch];
+                bb[t][j] = (short)v;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < kTaps; ++t)
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ga, bb[t], acc[t], 0, 0, 0);
+    }
+    // D[m = o][n = c]: lane holds o = 4 (lane / 16) + j, c = lane % 16
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) red[wv][t * kC * kC + (kq + j) * kC + ch] = acc[t][j];
+    // bias: the four lane groups of a channel, then the waves
+    bsum += __shfl_xor(bsum, 16);
+    bsum += __shfl_xor(bsum, 32);
+    if (lane < 16) red[wv][kTaps * kC * kC + lane] = bsum;
+    __syncthreads();
+    for (int e = threadIdx.x; e < kWgEntries; e += blockDim.x)
+        partial[(size_t)blockIdx.x * kWgEntries + e] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+}
+
+// Sum the partials of layer l in workgroup order into the canonical gradient.
+__global__ __launch_bounds__(256) void k_fill_wgrad_reduce(const float* __restrict__ partial,
+                                                           uint32_t blocks, int l,
+                                                           float* __restrict__ grad)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= kWgEntries) return;
+    float s = 0.f;
+    for (uint32_t b = 0; b < blocks; ++b) s += partial[(size_t)b * kWgEntries + e];
+    const int ci = cin_of(l), co = cout_of(l);
+    if (e < kTaps * kC * kC) {
+        const int t = e / (kC * kC), o = (e / kC) % kC, c = e % kC;
+        if (o < co && c < ci) grad[w_off(l) + (o * ci + c) * kTaps + t] = s;
+    } else {
+        const int o = e - kTaps * kC * kC;
+        if (o < co) grad[b_off(l) + o] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Loss: mean of (pred - target)^2 over stale pixels.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float2 block_sum_f2(float2 v, float2* sh)
+{
+    for (int m = 32; m > 0; m >>= 1) {
+        v.x += __shfl_xor(v.x, m);
+        v.y += __shfl_xor(v.y, m);
+    }
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    float2 r = make_float2(0.f, 0.f);
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+        r.x += sh[w].x;
+        r.y += sh[w].y;
+    }
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_fill_loss_partial(const float* __restrict__ pred,
+                                                           const float* __restrict__ target,
+                                                           const uint8_t* __restrict__ stale, size_t P,
+                                                           float2* __restrict__ part)
+{
+    __shared__ float2 sh[4];
+    float2 v = make_float2(0.f, 0.f);
+    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < P;
+         p += (size_t)gridDim.x * blockDim.x)
+        if (stale[p]) {
+            const float d = pred[p] - target[p];
+            v.x += d * d;
+            v.y += 1.f;
+        }
+    v = block_sum_f2(v, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+// loss2 = (loss, stale pixel count), summed in workgroup order.
+__global__ void k_fill_loss_final(const float2* __restrict__ part, uint32_t blocks,
+                                  float* __restrict__ loss2)
+{
+    if (threadIdx.x != 0) return;
+    double s = 0.0, c = 0.0;
+    for (uint32_t b = 0; b < blocks; ++b) {
+        s += part[b].x;
+        c += part[b].y;
+    }
+    loss2[0] = c > 0 ? (float)(s / c) : 0.f;
+    loss2[1] = (float)c;
+}
+
+// Gradient of the loss in the prediction, as channel 0 of a BF16 activation.
+__global__ __launch_bounds__(256) void k_fill_loss_grad(const float* __restrict__ pred,
+                                                        const float* __restrict__ target,
+                                                        const uint8_t* __restrict__ stale, size_t P,
+                                                        const float* __restrict__ loss2,
+                                                        uint16_t* __restrict__ g)
+{
+    const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const float cnt = loss2[1];
+    const float v = (stale[p] && cnt > 0.f) ? 2.f * (pred[p] - target[p]) / cnt : 0.f;
+    uint4 lo = make_uint4((uint32_t)to_bf16(v), 0u, 0u, 0u), hi = make_uint4(0u, 0u, 0u, 0u);
+    uint4* dst = reinterpret_cast<uint4*>(g + p * kC);
+    dst[0] = lo;
+    dst[1] = hi;
+}
+
+// Adam with bias correction; bc1 = 1 - beta1^t, bc2 = 1 - beta2^t.
+__global__ __launch_bounds__(256) void k_fill_adam(float* __restrict__ prm, const float* __restrict__ g,
+                                                   float* __restrict__ m, float* __restrict__ v,
+                                                   int n, float lr, float b1, float b2, float eps,
+                                                   float bc1, float bc2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    prm[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// Filled image with per-tile fallback; one workgroup per tile.
+__global__ __launch_bounds__(256) void k_fill_apply(const float* __restrict__ L,
+                                                    const uint8_t* __restrict__ stale,
+                                                    const float* __restrict__ pred, uint32_t H,
+                                                    uint32_t W, uint32_t tile, float tau,
+                                                    float* __restrict__ out,
+                                                    uint32_t* __restrict__ fallbacks)
+{
+    __shared__ float sh[4];
+    const uint32_t tw = (W + tile - 1) / tile;
+    const uint32_t ty0 = (blockIdx.x / tw) * tile, tx0 = (blockIdx.x % tw) * tile;
+    const uint32_t th = min(tile, H - ty0), twd = min(tile, W - tx0);
+    float dev = 0.f;
+    for (uint32_t k = threadIdx.x; k < th * twd; k += blockDim.x) {
+        const size_t p = (size_t)(ty0 + k / twd) * W + tx0 + k % twd;
+        if (stale[p]) dev = fmaxf(dev, fabsf(pred[p] - L[p]));
+    }
+    for (int m = 32; m > 0; m >>= 1) dev = fmaxf(dev, __shfl_xor(dev, m));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = dev;
+    __syncthreads();
+    dev = fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
+    const bool fb = dev > tau;
+    if (fb && threadIdx.x == 0) atomicAdd(fallbacks, 1u);
+    for (uint32_t k = threadIdx.x; k < th * twd; k += blockDim.x) {
+        const size_t p = (size_t)(ty0 + k / twd) * W + tx0 + k % twd;
+        out[p] = (stale[p] && !fb) ? pred[p] : L[p];
+    }
+}
+
+}  // namespace
+
+struct fibar_fill {
+    hipStream_t st = nullptr;
+    float* prm = nullptr;        // FP32 master parameters
+    float* m = nullptr;          // Adam moments
+    float* v = nullptr;
+    float* grad = nullptr;       // canonical gradient
+    bf16x4* wf = nullptr;        // [4][9][64]
+    bf16x4* wb = nullptr;
+    float* bias = nullptr;       // [4][16]
+    float* partial = nullptr;    // [kGradBlocks][kWgEntries]
+    float2* lpart = nullptr;     // [kLossBlocks]
+    float* loss2 = nullptr;      // loss, stale count
+    uint32_t* fallbacks = nullptr;
+    int step = 0;                // Adam steps since the parameters were set
+    // workspace for up to cap pixels
+    size_t cap = 0;
+    uint16_t* act[4] = {};       // x0, a1, a2, a3 (BF16 x 16 channels)
+    uint16_t* g[3] = {};         // gradient of the prediction, two ping-pong buffers
+    float* pred = nullptr;
+};
+
+namespace {
+
+int map_hip(hipError_t e)
+{
+    if (e == hipSuccess) return FIBAR_OK;
+    if (e == hipErrorOutOfMemory) return FIBAR_E_NOMEM;
+    return FIBAR_E_DEVICE;
+}
+
+#define FILL_TRY(x)                                  \
+    do {                                             \
+        const hipError_t e_ = (x);                   \
+        if (e_ != hipSuccess) return map_hip(e_);    \
+    } while (0)
+
+void free_ws(fibar_fill* f)
+{
+    for (auto& a : f->act) (void)hipFree(a), a = nullptr;
+    for (auto& a : f->g) (void)hipFree(a), a = nullptr;
+    (void)hipFree(f->pred);
+    f->pred = nullptr;
+    f->cap = 0;
+}
+
+int ensure_ws(fibar_fill* f, size_t P)
+{
+    if (P <= f->cap) return FIBAR_OK;
+    FILL_TRY(hipStreamSynchronize(f->st));
+    free_ws(f);
+    hipError_t e = hipSuccess;
+    for (auto& a : f->act)
+        if (e == hipSuccess) e = hipMalloc((void**)&a, P * kC * sizeof(uint16_t));
+    for (auto& a : f->g)
+        if (e == hipSuccess) e = hipMalloc((void**)&a, P * kC * sizeof(uint16_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&f->pred, P * sizeof(float));
+    if (e != hipSuccess) {
+        free_ws(f);
+        return map_hip(e);
+    }
+    f->cap = P;
+    return FIBAR_OK;
+}
+
+int check_images(const fibar_fill* f, const void* L, const void* stale, const void* age,
+                 uint32_t n, uint32_t H, uint32_t W)
+{
+    if (!f || !L || !stale || !age || n == 0 || H == 0 || W == 0) return FIBAR_E_INVALID_ARG;
+    return FIBAR_OK;
+}
+
+hipError_t launch_conv(fibar_fill* f, const uint16_t* in, const bf16x4* w, const float* bias,
+                       int relu, const uint16_t* gate, uint16_t* out16, float* out32,
+                       const float* skip, uint32_t n, uint32_t H, uint32_t W)
+{
+    const size_t nseg = (size_t)n * H * ((W + 15) / 16);
+    hipLaunchKernelGGL(k_fill_conv, dim3((uint32_t)((nseg + 3) / 4)), dim3(256), 0, f->st, in, w,
+                       bias, relu, gate, out16, out32, skip, n, H, W);
+    return hipGetLastError();
+}
+
+// Pack the input and run the four layers; the prediction lands in f->pred.
+int forward(fibar_fill* f, const float* L, const uint8_t* stale, const float* age, uint32_t n,
+            uint32_t H, uint32_t W)
+{
+    const size_t P = (size_t)n * H * W;
+    int rc = ensure_ws(f, P);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_fill_pack_input, dim3((uint32_t)((P + 255) / 256)), dim3(256), 0, f->st, L,
+                       stale, age, P, f->act[0]);
+    FILL_TRY(hipGetLastError());
+    for (int l = 0; l < kLayers; ++l) {
+        const bool last = l == kLayers - 1;
+        FILL_TRY(launch_conv(f, f->act[l], f->wf + l * kTaps * 64, f->bias + l * kC, last ? 0 : 1,
+                             nullptr, last ? nullptr : f->act[l + 1], last ? f->pred : nullptr,
+                             last ? L : nullptr, n, H, W));
+    }
+    return FIBAR_OK;
+}
+
+// Loss and full gradient of a batch into f->loss2 and f->grad (device).
+int loss_grad(fibar_fill* f, const float* L, const uint8_t* stale, const float* age,
+              const float* target, uint32_t n, uint32_t H, uint32_t W)
+{
+    int rc = forward(f, L, stale, age, n, H, W);
+    if (rc) return rc;
+    const size_t P = (size_t)n * H * W;
+    hipLaunchKernelGGL(k_fill_loss_partial, dim3(kLossBlocks), dim3(256), 0, f->st, f->pred, target,
+                       stale, P, f->lpart);
+    hipLaunchKernelGGL(k_fill_loss_final, dim3(1), dim3(64), 0, f->st, f->lpart, (uint32_t)kLossBlocks,
+                       f->loss2);
+    hipLaunchKernelGGL(k_fill_loss_grad, dim3((uint32_t)((P + 255) / 256)), dim3(256), 0, f->st,
+                       f->pred, target, stale, P, f->loss2, f->g[0]);
+    FILL_TRY(hipGetLastError());
+    // layer by layer from the top: weight gradient, then the input gradient
+    // gated by the ReLU of the layer below
+    int cur = 0;
+    for (int l = kLayers - 1; l >= 0; --l) {
+        hipLaunchKernelGGL(k_fill_wgrad, dim3(kGradBlocks), dim3(256), 0, f->st, f->act[l], f->g[cur],
+                           n, H, W, f->partial);
+        hipLaunchKernelGGL(k_fill_wgrad_reduce, dim3((kWgEntries + 255) / 256), dim3(256), 0, f->st,
+                           f->partial, (uint32_t)kGradBlocks, l, f->grad);
+        FILL_TRY(hipGetLastError());
+        if (l > 0) {
+            const int nxt = cur == 1 ? 2 : 1;
+            FILL_TRY(launch_conv(f, f->g[cur], f->wb + l * kTaps * 64, nullptr, 0, f->act[l],
+                                 f->g[nxt], nullptr, nullptr, n, H, W));
+            cur = nxt;
+        }
+    }
+    return FIBAR_OK;
+}
+
+hipError_t pack_weights(fibar_fill* f)
+{
+    hipLaunchKernelGGL(k_fill_pack_weights, dim3(kLayers * kTaps), dim3(64), 0, f->st, f->prm, f->wf,
+                       f->wb, f->bias);
+    return hipGetLastError();
+}
+
+void free_fill(fibar_fill* f)
+{
+    if (!f) return;
+    if (f->st) (void)hipStreamSynchronize(f->st);
+    free_ws(f);
+    void* p[] = {f->prm, f->m, f->v, f->grad, f->wf, f->wb, f->bias, f->partial, f->lpart,
+                 f->loss2, f->fallbacks};
+    for (void* q : p) (void)hipFree(q);
+    delete f;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fibar_fill_create(void* stream, fibar_fill** out)
+{
+    if (!out) return FIBAR_E_INVALID_ARG;
+    *out = nullptr;
+    fibar_fill* f = new (std::nothrow) fibar_fill();
+    if (!f) return FIBAR_E_NOMEM;
+    f->st = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    auto alloc = [&](void** p, size_t b) {
+        if (e == hipSuccess) e = hipMalloc(p, b);
+        if (e == hipSuccess) e = hipMemsetAsync(*p, 0, b, f->st);
+    };
+    alloc((void**)&f->prm, FIBAR_FILL_PARAMS * sizeof(float));
+    alloc((void**)&f->m, FIBAR_FILL_PARAMS * sizeof(float));
+    alloc((void**)&f->v, FIBAR_FILL_PARAMS * sizeof(float));
+    alloc((void**)&f->grad, FIBAR_FILL_PARAMS * sizeof(float));
+    alloc((void**)&f->wf, kLayers * kTaps * 64 * sizeof(bf16x4));
+    alloc((void**)&f->wb, kLayers * kTaps * 64 * sizeof(bf16x4));
+    alloc((void**)&f->bias, kLayers * kC * sizeof(float));
+    alloc((void**)&f->partial, (size_t)kGradBlocks * kWgEntries * sizeof(float));
+    alloc((void**)&f->lpart, kLossBlocks * sizeof(float2));
+    alloc((void**)&f->loss2, 2 * sizeof(float));
+    alloc((void**)&f->fallbacks, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipStreamSynchronize(f->st);
+    if (e != hipSuccess) {
+        free_fill(f);
+        return map_hip(e);
+    }
+    *out = f;
+    return FIBAR_OK;
+}
+
+int fibar_fill_set_params(fibar_fill* f, const float* params)
+{
+    if (!f || !params) return FIBAR_E_INVALID_ARG;
+    FILL_TRY(hipMemcpyAsync(f->prm, params, FIBAR_FILL_PARAMS * sizeof(float),
+                            hipMemcpyHostToDevice, f->st));
+    FILL_TRY(hipMemsetAsync(f->m, 0, FIBAR_FILL_PARAMS * sizeof(float), f->st));
+    FILL_TRY(hipMemsetAsync(f->v, 0, FIBAR_FILL_PARAMS * sizeof(float), f->st));
+    FILL_TRY(pack_weights(f));
+    FILL_TRY(hipStreamSynchronize(f->st));
+    f->step = 0;
+    return FIBAR_OK;
+}
+
+int fibar_fill_get_params(fibar_fill* f, float* params)
+{
+    if (!f || !params) return FIBAR_E_INVALID_ARG;
+    FILL_TRY(hipMemcpyAsync(params, f->prm, FIBAR_FILL_PARAMS * sizeof(float),
+                            hipMemcpyDeviceToHost, f->st));
+    FILL_TRY(hipStreamSynchronize(f->st));
+    return FIBAR_OK;
+}
+
+int fibar_fill_predict(fibar_fill* f, const float* L, const uint8_t* stale, const float* log_age,
+                       uint32_t n, uint32_t H, uint32_t W, float* pred)
+{
+    int rc = check_images(f, L, stale, log_age, n, H, W);
+    if (rc) return rc;
+    if (!pred) return FIBAR_E_INVALID_ARG;
+    rc = forward(f, L, stale, log_age, n, H, W);
+    if (rc) return rc;
+    FILL_TRY(hipMemcpyAsync(pred, f->pred, (size_t)n * H * W * sizeof(float),
+                            hipMemcpyDeviceToDevice, f->st));
+    return FIBAR_OK;
+}
+
+int fibar_fill_loss_grad(fibar_fill* f, const float* L, const uint8_t* stale, const float* log_age,
+                         const float* target, uint32_t n, uint32_t H, uint32_t W, float* loss,
+                         float* grad)
+{
+    int rc = check_images(f, L, stale, log_age, n, H, W);
+    if (rc) return rc;
+    if (!target || !loss) return FIBAR_E_INVALID_ARG;
+    rc = loss_grad(f, L, stale, log_age, target, n, H, W);
+    if (rc) return rc;
+    float l2[2];
+    FILL_TRY(hipMemcpyAsync(l2, f->loss2, sizeof(l2), hipMemcpyDeviceToHost, f->st));
+    if (grad)
+        FILL_TRY(hipMemcpyAsync(grad, f->grad, FIBAR_FILL_PARAMS * sizeof(float),
+                                hipMemcpyDeviceToHost, f->st));
+    FILL_TRY(hipStreamSynchronize(f->st));
+    *loss = l2[0];
+    return FIBAR_OK;
+}
+
+int fibar_fill_train_step(fibar_fill* f, const float* L, const uint8_t* stale,
+                          const float* log_age, const float* target, uint32_t n, uint32_t H,
+                          uint32_t W, float lr, float* loss)
+{
+    int rc = check_images(f, L, stale, log_age, n, H, W);
+    if (rc) return rc;
+    if (!target || !(lr >= 0.f)) return FIBAR_E_INVALID_ARG;
+    rc = loss_grad(f, L, stale, log_age, target, n, H, W);
+    if (rc) return rc;
+    const int t = ++f->step;
+    const double b1 = 0.9, b2 = 0.999;
+    const float bc1 = (float)(1.0 - pow(b1, t)), bc2 = (float)(1.0 - pow(b2, t));
+    hipLaunchKernelGGL(k_fill_adam, dim3((FIBAR_FILL_PARAMS + 255) / 256), dim3(256), 0, f->st, f->prm,
+                       f->grad, f->m, f->v, (int)FIBAR_FILL_PARAMS, lr, (float)b1, (float)b2,
+                       1e-8f, bc1, bc2);
+    FILL_TRY(hipGetLastError());
+    FILL_TRY(pack_weights(f));
+    if (loss) {
+        float l2[2];
+        FILL_TRY(hipMemcpyAsync(l2, f->loss2, sizeof(l2), hipMemcpyDeviceToHost, f->st));
+        FILL_TRY(hipStreamSynchronize(f->st));
+        *loss = l2[0];
+    }
+    return FIBAR_OK;
+}
+
+int fibar_fill_apply(fibar_fill* f, const float* L, const uint8_t* stale, const float* log_age,
+                     uint32_t H, uint32_t W, uint32_t tile, float tau, float* out,
+                     uint32_t* fallback_tiles)
+{
+    int rc = check_images(f, L, stale, log_age, 1, H, W);
+    if (rc) return rc;
+    if (!out || tile < 4 || tile > 64 || !(tau >= 0.f)) return FIBAR_E_INVALID_ARG;
+    rc = forward(f, L, stale, log_age, 1, H, W);
+    if (rc) return rc;
+    const uint32_t tiles = ((H + tile - 1) / tile) * ((W + tile - 1) / tile);
+    FILL_TRY(hipMemsetAsync(f->fallbacks, 0, sizeof(uint32_t), f->st));
+    hipLaunchKernelGGL(k_fill_apply, dim3(tiles), dim3(256), 0, f->st, L, stale, f->pred, H, W,
+                       tile, tau, out, f->fallbacks);
+    FILL_TRY(hipGetLastError());
+    if (fallback_tiles) {
+        FILL_TRY(hipMemcpyAsync(fallback_tiles, f->fallbacks, sizeof(uint32_t),
+                                hipMemcpyDeviceToHost, f->st));
+        FILL_TRY(hipStreamSynchronize(f->st));
+    }
+    return FIBAR_OK;
+}
+
+void fibar_fill_destroy(fibar_fill* f) { free_fill(f); }
+
+}  // extern "C"

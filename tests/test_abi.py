@@ -70,3 +70,15 @@ def test_status_strings_and_defaults_without_gpu():
     assert fb.fibar_create(10, 10, bad)[0] == fb.FIBAR_E_INVALID_ARG
     assert lib.fibar_push_events(None, None) == fb.FIBAR_E_INVALID_ARG
     lib.fibar_destroy(None)
+
+
+def test_fill_entry_points_reject_null_handles_without_gpu():
+    lib = fb.load()
+    assert lib.fibar_fill_create(None, None) == fb.FIBAR_E_INVALID_ARG
+    assert lib.fibar_fill_set_params(None, None) == fb.FIBAR_E_INVALID_ARG
+    assert lib.fibar_fill_get_params(None, None) == fb.FIBAR_E_INVALID_ARG
+    assert lib.fibar_fill_predict(None, None, None, None, 1, 1, 1, None) == fb.FIBAR_E_INVALID_ARG
+    assert lib.fibar_fill_apply(None, None, None, None, 1, 1, 16, 1.0, None, None) == \
+        fb.FIBAR_E_INVALID_ARG
+    lib.fibar_fill_destroy(None)
+    assert fb.FILL_PARAMS == 5233

@@ -12,7 +12,7 @@ from oracle import fill
 
 
 def rand_params(seed, scale=1.0):
-    p = eventsim.fill_init_params(seed).astype(np.float64)
+    p = eventsim.fill_init_params(seed, zero_last=False).astype(np.float64)
     rng = np.random.default_rng(seed + 100)
     # non-zero biases, so that the bias terms are exercised too
     k = 0
@@ -165,3 +165,13 @@ def test_fill_target_and_psnr():
     assert eventsim.fill_psnr(t, L, mask) > 90
     noisy = L + 0.1 * (L.max() - L.min())
     assert abs(eventsim.fill_psnr(noisy, L, mask) - 20.0) < 1e-6
+
+
+def test_zero_last_layer_gives_back_L():
+    rng = np.random.default_rng(12)
+    x = rng.normal(size=(2, 3, 7, 9))
+    theta = rand_params(13)
+    w3, b3 = fill.unflatten(theta)[3]
+    theta[-(w3.size + b3.size):] = 0.0
+    pred, _ = fill.forward(fill.unflatten(theta), x)
+    np.testing.assert_array_equal(pred, x[:, 0])
