@@ -172,6 +172,154 @@ def run_batched(args, torch, dev, fb, eventsim):
     return res
 
 
+def fill_frames(torch, dev, fb, eventsim, seeds, n_events, every, stream):
+    """Readouts (L, stale mask, log age) every `every` events of 1280x720
+    sequences, reconstructed with blur on, and their calibrated ground-truth
+    targets; stacked on the device as [frames, H, W]."""
+    Ls, Ss, As, Ts = [], [], [], []
+    for seed in seeds:
+        sc = eventsim.fill_scene(seed, n_events)
+        ev = eventsim.generate(sc)
+        n = len(ev)
+        W, H = sc.width, sc.height
+        ro = list(range(every, n + 1, every))
+        gx = torch.from_numpy(ev.x.view(np.int16)).to(dev)
+        gy = torch.from_numpy(ev.y.view(np.int16)).to(dev)
+        gp = torch.from_numpy(ev.p).to(dev)
+        F = len(ro)
+        L = torch.empty((F, H, W), dtype=torch.float32, device=dev)
+        S = torch.empty((F, H, W), dtype=torch.uint8, device=dev)
+        A = torch.empty((F, H, W), dtype=torch.float32, device=dev)
+        C = torch.empty((F, H, W), dtype=torch.int32, device=dev)
+        ctx = fb.Context(W, H, stream=stream)
+        ops, r = [], 0
+        for it in eventsim.schedule(n, 16384, ro):
+            if it[0] == "push":
+                ops.append(fb.push_op(gx[it[1]:it[2]], gy[it[1]:it[2]], gp[it[1]:it[2]]))
+            else:
+                ops.append(fb.readout_op(int(ev.t[it[1] - 1]), L[r], stale=S[r], cnt=C[r],
+                                         log_age=A[r]))
+                r += 1
+        assert ctx.submit(ops) == 0 and ctx.synchronize() == 0
+        ctx.close()
+        gt = eventsim.render_frames(sc, [int(ev.t[k - 1]) for k in ro])
+        Lh, act = L.cpu().numpy(), C.cpu().numpy() > 0
+        T = np.stack([eventsim.fill_target(gt[f], Lh[f], act[f]) for f in range(F)])
+        Ls.append(L)
+        Ss.append(S)
+        As.append(A)
+        Ts.append(torch.from_numpy(T).to(dev))
+    return torch.cat(Ls), torch.cat(Ss), torch.cat(As), torch.cat(Ts)
+
+
+FILL_FWD_FLOP_PX = 10368.0      # 2 x (432 + 2304 + 2304 + 144) multiply-adds
+FILL_TRAIN_FLOP_PX = 30240.0    # forward, weight gradients, input gradients of layers 2-4
+
+
+def run_fill(args, torch, dev, fb, eventsim):
+    """Learned stale fill: train on readouts of seeded 1280x720 sequences,
+    score against the Gaussian fill on held-out ones, and time inference and
+    training steps."""
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    t0 = time.time()
+    train_seeds = list(range(5000, 5000 + args.fill_train_seqs))
+    eval_seeds = list(range(6000, 6000 + args.fill_eval_seqs))
+    Ltr, Str, Atr, Ttr = fill_frames(torch, dev, fb, eventsim, train_seeds, args.fill_events,
+                                     100_000, stream)
+    Lev, Sev, Aev, Tev = fill_frames(torch, dev, fb, eventsim, eval_seeds, args.fill_events,
+                                     100_000, stream)
+    F, H, W = Ltr.shape
+    log("fill: %d training and %d evaluation frames (%d + %d sequences) in %.1f s"
+        % (F, Lev.shape[0], len(train_seeds), len(eval_seeds), time.time() - t0))
+
+    rng = np.random.default_rng(args.fill_seed)
+    B, TS = 32, 128
+    ar = torch.arange(TS, device=dev)
+
+    def batch():
+        f = torch.from_numpy(rng.integers(0, F, B)).to(dev)[:, None, None]
+        y = torch.from_numpy(rng.integers(0, H - TS + 1, B)).to(dev)[:, None, None] + ar[None, :, None]
+        x = torch.from_numpy(rng.integers(0, W - TS + 1, B)).to(dev)[:, None, None] + ar[None, None, :]
+        return [t[f, y, x].contiguous() for t in (Ltr, Str, Atr, Ttr)]
+
+    fill = fb.Fill(eventsim.fill_init_params(args.fill_seed), stream=stream)
+    losses = []
+    t0 = time.time()
+    for step in range(args.fill_steps):
+        want = step % 100 == 0 or step == args.fill_steps - 1
+        rc, loss = fill.train_step(*batch(), lr=args.fill_lr, want_loss=want)
+        assert rc == 0
+        if want:
+            losses.append((step, round(loss, 5)))
+    torch.cuda.synchronize()
+    train_s = time.time() - t0
+    log("fill: %d Adam steps in %.1f s, batch loss %s" % (args.fill_steps, train_s, losses))
+
+    # ---- quality on held-out frames ---------------------------------------
+    out = torch.empty((H, W), dtype=torch.float32, device=dev)
+    psnr_g, psnr_l, psnr_f, fb_frac = [], [], [], []
+    tiles = ((H + 15) // 16) * ((W + 15) // 16)
+    for k in range(Lev.shape[0]):
+        st = Sev[k].cpu().numpy() != 0
+        tgt = Tev[k].cpu().numpy()
+        psnr_g.append(eventsim.fill_psnr(Lev[k].cpu().numpy(), tgt, st))
+        rc, _ = fill.apply(Lev[k], Sev[k], Aev[k], out, tile=16, tau=float("inf"))
+        assert rc == 0
+        psnr_l.append(eventsim.fill_psnr(out.cpu().numpy(), tgt, st))
+        rc, nfb = fill.apply(Lev[k], Sev[k], Aev[k], out, tile=16, tau=args.fill_tau)
+        assert rc == 0
+        psnr_f.append(eventsim.fill_psnr(out.cpu().numpy(), tgt, st))
+        fb_frac.append(nfb / tiles)
+
+    # ---- throughput ---------------------------------------------------------
+    lib = fb.load()
+    reps = 50
+    ev_a, ev_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(3):
+        lib.fibar_fill_apply(fill.handle, Lev[0].data_ptr(), Sev[0].data_ptr(), Aev[0].data_ptr(),
+                             H, W, 16, args.fill_tau, out.data_ptr(), None)
+    ev_a.record()
+    for _ in range(reps):
+        lib.fibar_fill_apply(fill.handle, Lev[0].data_ptr(), Sev[0].data_ptr(), Aev[0].data_ptr(),
+                             H, W, 16, args.fill_tau, out.data_ptr(), None)
+    ev_b.record()
+    torch.cuda.synchronize()
+    infer_ms = ev_a.elapsed_time(ev_b) / reps
+    bt = [batch() for _ in range(4)]
+    for b_ in bt:
+        fill.train_step(*b_, lr=0.0, want_loss=False)
+    ev_a.record()
+    for i in range(reps):
+        fill.train_step(*bt[i % 4], lr=0.0, want_loss=False)
+    ev_b.record()
+    torch.cuda.synchronize()
+    step_ms = ev_a.elapsed_time(ev_b) / reps
+    fill.close()
+    infer_tflops = FILL_FWD_FLOP_PX * H * W / (infer_ms * 1e-3) / 1e12
+    train_tflops = FILL_TRAIN_FLOP_PX * B * TS * TS / (step_ms * 1e-3) / 1e12
+    res = {"train_frames": int(F), "eval_frames": int(Lev.shape[0]),
+           "train_sequences": len(train_seeds), "eval_sequences": len(eval_seeds),
+           "events_per_sequence": args.fill_events, "readout_every": 100_000,
+           "steps": args.fill_steps, "batch": "%dx%dx%d" % (B, TS, TS), "lr": args.fill_lr,
+           "batch_loss": losses,
+           "psnr_db": {"gaussian_fill": round(float(np.mean(psnr_g)), 3),
+                       "learned": round(float(np.mean(psnr_l)), 3),
+                       "learned_with_fallback": round(float(np.mean(psnr_f)), 3),
+                       "gain_db": round(float(np.mean(psnr_l) - np.mean(psnr_g)), 3)},
+           "fallback": {"tile": 16, "tau": args.fill_tau,
+                        "tiles_fallen_back": round(float(np.mean(fb_frac)), 4)},
+           "inference": {"ms_per_frame": round(infer_ms, 4), "tflops": round(infer_tflops, 2),
+                         "frac_bf16_peak": round(infer_tflops / 2500.0, 5),
+                         "mev_s_at_one_frame_per_100k_events": round(0.1 / (infer_ms * 1e-3), 1)},
+           "training": {"ms_per_step": round(step_ms, 4), "tflops": round(train_tflops, 2),
+                        "frac_bf16_peak": round(train_tflops / 2500.0, 5)}}
+    log("fill: PSNR gaussian %.2f dB, learned %.2f dB (with fallback %.2f dB); inference %.3f ms "
+        "per 1280x720 frame (%.1f TFLOP/s), training step %.3f ms (%.1f TFLOP/s)"
+        % (res["psnr_db"]["gaussian_fill"], res["psnr_db"]["learned"],
+           res["psnr_db"]["learned_with_fallback"], infer_ms, infer_tflops, step_ms, train_tflops))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,6 +340,17 @@ def main():
                     help="measure only the batched streams (for profiling)")
     ap.add_argument("--multi-scale", type=float, default=1.0,
                     help="scale of the batched streams' lengths (1.0: 5-40M events each)")
+    ap.add_argument("--no-fill", action="store_true", help="skip the learned-fill leg")
+    ap.add_argument("--only-fill", action="store_true", help="run only the learned-fill leg")
+    ap.add_argument("--fill-train-seqs", type=int, default=16,
+                    help="training sequences (seeds 5000...; 200 for the full set)")
+    ap.add_argument("--fill-eval-seqs", type=int, default=4,
+                    help="held-out sequences (seeds 6000...; 20 for the full set)")
+    ap.add_argument("--fill-events", type=int, default=2_000_000)
+    ap.add_argument("--fill-steps", type=int, default=1000)
+    ap.add_argument("--fill-lr", type=float, default=1e-3)
+    ap.add_argument("--fill-tau", type=float, default=2.0)
+    ap.add_argument("--fill-seed", type=int, default=7)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one plain device-to-device copy of BYTES (for scaling the "
                          "HBM byte counters) and exit")
@@ -225,6 +384,9 @@ def main():
     fb.load()
     if args.only_multi:
         run_batched(args, torch, dev, fb, eventsim)
+        return
+    if args.only_fill:
+        print(json.dumps(run_fill(args, torch, dev, fb, eventsim)))
         return
 
     wl = eventsim.preset("hd720", n_events=args.events)
@@ -379,6 +541,9 @@ def main():
     batched = None
     if not args.no_multi:
         batched = run_batched(args, torch, dev, fb, eventsim)
+    learned_fill = None
+    if not args.no_fill:
+        learned_fill = run_fill(args, torch, dev, fb, eventsim)
 
     out = {
         "metric": "Mev/s reconstructed at 1280x720 (blur on)",
@@ -405,6 +570,7 @@ def main():
         "cpu_baseline": cpu,
         "parity": parity,
         "batched_streams": batched,
+        "learned_fill": learned_fill,
         "paper_cpu_context_mev_s": {"blur_on": 42, "blur_off": 140},
     }
     print(json.dumps(out), flush=True)

@@ -283,6 +283,14 @@ def fill_init_params(seed: int, zero_last: bool = True) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
+def fill_scene(seed: int, n_events: int = 2_000_000) -> Scene:
+    """A 1280x720 training / evaluation sequence of the learned fill: the hd720
+    preset's scene (2048 blobs, 0.5 rad/s + 300 px/s, C = 0.15, 2 % noise)
+    with its own seed (training seeds 5000-5199, evaluation 6000-6019)."""
+    return Scene(1280, 720, n_events, seed, n_blobs=2048, speed_px_s=300.0, rot_rad_s=0.5,
+                 thr_on=0.15, thr_off=0.15, noise_frac=0.02, step_px=1.0)
+
+
 def fill_target(gt, L, active):
     """Ground truth in the units of the reconstruction: the least-squares
     affine map of a frame's ground-truth log intensity onto its brightness L,

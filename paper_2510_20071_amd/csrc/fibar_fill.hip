@@ -33,6 +33,7 @@ constexpr int kTaps = 9;
 constexpr int kGradBlocks = 256;                // workgroups of a weight gradient
 constexpr int kWgEntries = kTaps * kC * kC + kC;   // one layer's (w, b) gradient, padded
 constexpr int kLossBlocks = 256;
+constexpr int kPairs = 5;                       // taps in pairs for the K = 32 products
 
 __host__ __device__ constexpr int cin_of(int l) { return l == 0 ? 3 : 16; }
 __host__ __device__ constexpr int cout_of(int l) { return l == 3 ? 1 : 16; }
@@ -44,6 +45,7 @@ __host__ __device__ constexpr int b_off(int l) { return w_off(l) + cout_of(l) * 
 static_assert(b_off(3) + 1 == FIBAR_FILL_PARAMS, "parameter layout");
 
 typedef short bf16x4 __attribute__((__vector_size__(4 * sizeof(short))));
+typedef __bf16 bf16x8 __attribute__((__vector_size__(8 * sizeof(__bf16))));
 typedef float f32x4 __attribute__((__vector_size__(4 * sizeof(float))));
 
 // FP32 -> BF16 bits, round to nearest even (inputs are finite).
@@ -64,7 +66,8 @@ __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float(
 __global__ __launch_bounds__(64) void k_fill_pack_weights(const float* __restrict__ prm,
                                                           bf16x4* __restrict__ wf,
                                                           bf16x4* __restrict__ wb,
-                                                          float* __restrict__ bias)
+                                                          float* __restrict__ bias,
+                                                          uint4* __restrict__ wk)
 {
     const int l = blockIdx.x / kTaps, t = blockIdx.x % kTaps, lane = threadIdx.x;
     const int ci = cin_of(l), co = cout_of(l);
@@ -80,6 +83,19 @@ __global__ __launch_bounds__(64) void k_fill_pack_weights(const float* __restric
     wf[(l * kTaps + t) * 64 + lane] = f;
     wb[(l * kTaps + t) * 64 + lane] = b;
     if (t == 0 && lane < kC) bias[l * kC + lane] = lane < co ? prm[b_off(l) + lane] : 0.f;
+    // K = 32 operands of tap pairs (2q, 2q + 1), q = t < 5: lane group g takes
+    // tap 2q + g / 2, input channels 8 (g % 2) + j, j = 0..7; tap 9 is zero
+    if (t < kPairs) {
+        const int g = lane >> 4, tap = 2 * t + (g >> 1), o = lane & 15;
+        uint16_t h[8];
+        for (int j = 0; j < 8; ++j) {
+            const int c = 8 * (g & 1) + j;
+            h[j] = (tap < kTaps && o < co && c < ci) ? to_bf16(w[(o * ci + c) * kTaps + tap]) : 0;
+        }
+        wk[(l * kPairs + t) * 64 + lane] =
+            make_uint4(h[0] | (uint32_t)h[1] << 16, h[2] | (uint32_t)h[3] << 16,
+                       h[4] | (uint32_t)h[5] << 16, h[6] | (uint32_t)h[7] << 16);
+    }
 }
 
 // Network input from readout planes: channels (L, stale, log(1 + age), 0 ...).
@@ -326,6 +342,180 @@ __global__ __launch_bounds__(256) void k_fill_adam(float* __restrict__ prm, cons
     prm[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
 }
 
+// ---------------------------------------------------------------------------
+// Fused inference: the four layers of one output tile of kFuseH x kFuseW
+// pixels in one workgroup, activations in LDS (two buffers used in turn), so
+// a frame costs one read of its inputs and one write of the prediction.
+//
+// Region coordinates: region row r, column c is image pixel
+// (y0 - 4 + r, x0 - 4 + c).  Layer k (1..4) computes rows [k, kFuseH + 8 - k)
+// and the 16-pixel segments starting at columns k and k + 16; columns past
+// what it needs (k + 32 > kFuseW + 8 - k) only ever feed other surplus
+// columns.  Pixels outside the image are stored as zero at every layer (the
+// layers' zero padding).  Layer 4 writes L + its channel 0 for the tile's
+// pixels inside the image.
+// ---------------------------------------------------------------------------
+constexpr int kFuseH = 16, kFuseW = 26;
+constexpr int kRegH = kFuseH + 8, kRegW = 37;      // widest read: layer 4, columns 3..36
+constexpr int kFuseThreads = 512;
+constexpr int kFuseWaves = kFuseThreads / 64;
+
+// Raw inputs of the region pixels one thread stages (two at most); they are
+// converted only when written to LDS, so their loads stay in flight while
+// the previous tile's layers run.
+struct RegionIn {
+    float l[2], age[2];
+    uint32_t st[2];
+};
+
+__device__ __forceinline__ void load_region(RegionIn& ri, const float* __restrict__ L,
+                                            const uint8_t* __restrict__ stale,
+                                            const float* __restrict__ log_age, int y0, int x0,
+                                            uint32_t H, uint32_t W)
+{
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int k = (int)threadIdx.x + q * kFuseThreads;
+        const int r = k / kRegW, c = k % kRegW;
+        const int y = y0 + r, x = x0 + c;
+        float l = 0.f, a = 0.f;
+        uint32_t st = 0u;
+        if (k < kRegH * kRegW && y >= 0 && y < (int)H && x >= 0 && x < (int)W &&
+            c < kFuseW + 8) {
+            const size_t p = (size_t)y * W + x;
+            l = L[p];
+            a = log_age[p];
+            st = stale[p];
+        }
+        ri.l[q] = l;
+        ri.age[q] = a;
+        ri.st[q] = st;
+    }
+}
+
+// The 16x16x32 products of two 16-pixel segments (rows ra, rb, pixel
+// columns pa, pb of this lane), interleaved so the two accumulation chains
+// overlap in the matrix pipeline.
+__device__ __forceinline__ void segment_pair(const uint16_t* __restrict__ in, int ra, int pa,
+                                             int rb, int pb, bool two, uint32_t lane,
+                                             const bf16x8* b, f32x4& acc0, f32x4& acc1)
+{
+    const uint32_t g = lane >> 4, ch = 8 * (g & 1);
+    bf16x8 a0[kPairs], a1[kPairs];
+#pragma unroll
+    for (int q = 0; q < kPairs; ++q) {
+        const int tap = 2 * q + (int)(g >> 1);
+        const int dr = tap / 3 - 1, dc = tap % 3 - 1;
+        bf16x8 v0 = {}, v1 = {};
+        if (tap < kTaps && pa + dc < kRegW)
+            v0 = *reinterpret_cast<const bf16x8*>(&in[((ra + dr) * kRegW + pa + dc) * kC + ch]);
+        if (two && tap < kTaps && pb + dc < kRegW)
+            v1 = *reinterpret_cast<const bf16x8*>(&in[((rb + dr) * kRegW + pb + dc) * kC + ch]);
+        a0[q] = v0;
+        a1[q] = v1;
+    }
+    acc0 = f32x4{0.f, 0.f, 0.f, 0.f};
+    acc1 = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < kPairs; ++q) {
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0[q], b[q], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[q], b[q], acc1, 0, 0, 0);
+    }
+}
+
+// Persistent: workgroup w takes tiles w, w + grid, ...; the next tile's inputs
+// are loaded into registers while the current tile's layers run.
+__global__ __launch_bounds__(kFuseThreads) void k_fill_fused(const float* __restrict__ L,
+                                                             const uint8_t* __restrict__ stale,
+                                                             const float* __restrict__ log_age,
+                                                             const uint4* __restrict__ wk,
+                                                             const float* __restrict__ bias,
+                                                             uint32_t H, uint32_t W,
+                                                             float* __restrict__ pred)
+{
+    __shared__ __align__(16) uint16_t buf[2][kRegH * kRegW * kC];
+    __shared__ __align__(16) uint4 wsh[kLayers * kPairs * 64];
+    __shared__ float bsh[kLayers * kC];
+    __shared__ float Lsh[kRegH * kRegW];
+    const uint32_t tiles_x = (W + kFuseW - 1) / kFuseW;
+    const uint32_t tiles = tiles_x * ((H + kFuseH - 1) / kFuseH);
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+
+    for (int k = threadIdx.x; k < kLayers * kPairs * 64; k += kFuseThreads) wsh[k] = wk[k];
+    if (threadIdx.x < kLayers * kC) bsh[threadIdx.x] = bias[threadIdx.x];
+    uint32_t tile = blockIdx.x;
+    RegionIn ri;
+    if (tile < tiles)
+        load_region(ri, L, stale, log_age, (int)(tile / tiles_x) * kFuseH - 4,
+                    (int)(tile % tiles_x) * kFuseW - 4, H, W);
+    for (; tile < tiles; tile += gridDim.x) {
+        const int y0 = (int)(tile / tiles_x) * kFuseH - 4;
+        const int x0 = (int)(tile % tiles_x) * kFuseW - 4;
+        // input region: (L, stale, log(1 + age), 0 ...), zero outside the image
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int k = (int)threadIdx.x + q * kFuseThreads;
+            if (k >= kRegH * kRegW) continue;
+            uint4* dst = reinterpret_cast<uint4*>(&buf[0][k * kC]);
+            dst[0] = make_uint4((uint32_t)to_bf16(ri.l[q]) |
+                                    ((uint32_t)(ri.st[q] ? to_bf16(1.f) : 0u) << 16),
+                                (uint32_t)to_bf16(ri.age[q]), 0u, 0u);
+            dst[1] = make_uint4(0u, 0u, 0u, 0u);
+            Lsh[k] = ri.l[q];
+        }
+        __syncthreads();
+        const uint32_t next = tile + gridDim.x;
+        if (next < tiles)
+            load_region(ri, L, stale, log_age, (int)(next / tiles_x) * kFuseH - 4,
+                        (int)(next % tiles_x) * kFuseW - 4, H, W);
+
+        for (int layer = 0; layer < kLayers; ++layer) {
+            const int kk = layer + 1;                       // rows [kk, kRegH - kk)
+            const uint16_t* in = buf[layer & 1];
+            uint16_t* out = buf[(layer & 1) ^ 1];
+            bf16x8 b[kPairs];
+#pragma unroll
+            for (int q = 0; q < kPairs; ++q)
+                b[q] = *reinterpret_cast<const bf16x8*>(&wsh[(layer * kPairs + q) * 64 + lane]);
+            const uint32_t o = lane & 15;
+            const float bo = bsh[layer * kC + o];
+            const int nseg = (kRegH - 2 * kk) * 2;
+            // two segments per pass: independent product chains
+            for (int s0 = (int)wv; s0 < nseg; s0 += 2 * kFuseWaves) {
+                const int s1 = s0 + kFuseWaves;
+                const bool two = s1 < nseg;
+                const int ra = kk + s0 / 2, ca = kk + (s0 % 2) * 16;
+                const int rb = kk + s1 / 2, cb = kk + (s1 % 2) * 16;
+                f32x4 acc0, acc1;
+                segment_pair(in, ra, ca + (int)(lane & 15), rb, cb + (int)(lane & 15), two, lane,
+                             b, acc0, acc1);
+#pragma unroll
+                for (int half = 0; half < 2; ++half) {
+                    if (half == 1 && !two) break;
+                    const int r = half ? rb : ra, c0 = half ? cb : ca;
+                    const f32x4 acc = half ? acc1 : acc0;
+                    const int y = y0 + r;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int c = c0 + (int)(lane >> 4) * 4 + j;
+                        const int x = x0 + c;
+                        const bool inside = y >= 0 && y < (int)H && x >= 0 && x < (int)W;
+                        float v = acc[j] + bo;
+                        if (layer < kLayers - 1) {
+                            v = (inside && v > 0.f) ? v : 0.f;
+                            if (c < kRegW) out[(r * kRegW + c) * kC + o] = to_bf16(v);
+                        } else if (o == 0 && inside && r >= 4 && r < 4 + kFuseH && c >= 4 &&
+                                   c < 4 + kFuseW) {
+                            pred[(size_t)y * W + x] = v + Lsh[r * kRegW + c];
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // Filled image with per-tile fallback; one workgroup per tile.
 __global__ __launch_bounds__(256) void k_fill_apply(const float* __restrict__ L,
                                                     const uint8_t* __restrict__ stale,
@@ -365,12 +555,14 @@ struct fibar_fill {
     float* grad = nullptr;       // canonical gradient
     bf16x4* wf = nullptr;        // [4][9][64]
     bf16x4* wb = nullptr;
+    uint4* wk = nullptr;         // [4][5][64] K = 32 operands (8 BF16 each)
     float* bias = nullptr;       // [4][16]
     float* partial = nullptr;    // [kGradBlocks][kWgEntries]
     float2* lpart = nullptr;     // [kLossBlocks]
     float* loss2 = nullptr;      // loss, stale count
     uint32_t* fallbacks = nullptr;
     int step = 0;                // Adam steps since the parameters were set
+    uint32_t cus = 256;          // compute units of the device
     // workspace for up to cap pixels
     size_t cap = 0;
     uint16_t* act[4] = {};       // x0, a1, a2, a3 (BF16 x 16 channels)
@@ -438,7 +630,22 @@ hipError_t launch_conv(fibar_fill* f, const uint16_t* in, const bf16x4* w, const
     return hipGetLastError();
 }
 
-// Pack the input and run the four layers; the prediction lands in f->pred.
+// Fused inference of n images; the prediction lands in `pred`.
+hipError_t forward_fused(fibar_fill* f, const float* L, const uint8_t* stale, const float* age,
+                         uint32_t n, uint32_t H, uint32_t W, float* pred)
+{
+    const uint32_t tiles = ((H + kFuseH - 1) / kFuseH) * ((W + kFuseW - 1) / kFuseW);
+    // two resident workgroups per CU (LDS), each looping over tiles
+    const uint32_t grid = tiles < 2 * f->cus ? tiles : 2 * f->cus;
+    const size_t P = (size_t)H * W;
+    for (uint32_t i = 0; i < n; ++i)
+        hipLaunchKernelGGL(k_fill_fused, dim3(grid), dim3(kFuseThreads), 0, f->st, L + i * P,
+                           stale + i * P, age + i * P, f->wk, f->bias, H, W, pred + i * P);
+    return hipGetLastError();
+}
+
+// Pack the input and run the four layers one by one, keeping every layer's
+// activations for the backward pass; the prediction lands in f->pred.
 int forward(fibar_fill* f, const float* L, const uint8_t* stale, const float* age, uint32_t n,
             uint32_t H, uint32_t W)
 {
@@ -492,8 +699,8 @@ int loss_grad(fibar_fill* f, const float* L, const uint8_t* stale, const float* 
 
 hipError_t pack_weights(fibar_fill* f)
 {
-    hipLaunchKernelGGL(k_fill_pack_weights, dim3(kLayers * kTaps), dim3(64), 0, f->st, f->prm, f->wf,
-                       f->wb, f->bias);
+    hipLaunchKernelGGL(k_fill_pack_weights, dim3(kLayers * kTaps), dim3(64), 0, f->st, f->prm,
+                       f->wf, f->wb, f->bias, f->wk);
     return hipGetLastError();
 }
 
@@ -502,8 +709,8 @@ void free_fill(fibar_fill* f)
     if (!f) return;
     if (f->st) (void)hipStreamSynchronize(f->st);
     free_ws(f);
-    void* p[] = {f->prm, f->m, f->v, f->grad, f->wf, f->wb, f->bias, f->partial, f->lpart,
-                 f->loss2, f->fallbacks};
+    void* p[] = {f->prm, f->m, f->v, f->grad, f->wf, f->wb, f->wk, f->bias, f->partial,
+                 f->lpart, f->loss2, f->fallbacks};
     for (void* q : p) (void)hipFree(q);
     delete f;
 }
@@ -530,11 +737,16 @@ int fibar_fill_create(void* stream, fibar_fill** out)
     alloc((void**)&f->grad, FIBAR_FILL_PARAMS * sizeof(float));
     alloc((void**)&f->wf, kLayers * kTaps * 64 * sizeof(bf16x4));
     alloc((void**)&f->wb, kLayers * kTaps * 64 * sizeof(bf16x4));
+    alloc((void**)&f->wk, kLayers * kPairs * 64 * sizeof(uint4));
     alloc((void**)&f->bias, kLayers * kC * sizeof(float));
     alloc((void**)&f->partial, (size_t)kGradBlocks * kWgEntries * sizeof(float));
     alloc((void**)&f->lpart, kLossBlocks * sizeof(float2));
     alloc((void**)&f->loss2, 2 * sizeof(float));
     alloc((void**)&f->fallbacks, sizeof(uint32_t));
+    int dev = 0, cus = 0;
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess && cus > 0) f->cus = (uint32_t)cus;
     if (e == hipSuccess) e = hipStreamSynchronize(f->st);
     if (e != hipSuccess) {
         free_fill(f);
@@ -572,10 +784,7 @@ int fibar_fill_predict(fibar_fill* f, const float* L, const uint8_t* stale, cons
     int rc = check_images(f, L, stale, log_age, n, H, W);
     if (rc) return rc;
     if (!pred) return FIBAR_E_INVALID_ARG;
-    rc = forward(f, L, stale, log_age, n, H, W);
-    if (rc) return rc;
-    FILL_TRY(hipMemcpyAsync(pred, f->pred, (size_t)n * H * W * sizeof(float),
-                            hipMemcpyDeviceToDevice, f->st));
+    FILL_TRY(forward_fused(f, L, stale, log_age, n, H, W, pred));
     return FIBAR_OK;
 }
 
@@ -631,8 +840,9 @@ int fibar_fill_apply(fibar_fill* f, const float* L, const uint8_t* stale, const 
     int rc = check_images(f, L, stale, log_age, 1, H, W);
     if (rc) return rc;
     if (!out || tile < 4 || tile > 64 || !(tau >= 0.f)) return FIBAR_E_INVALID_ARG;
-    rc = forward(f, L, stale, log_age, 1, H, W);
+    rc = ensure_ws(f, (size_t)H * W);
     if (rc) return rc;
+    FILL_TRY(forward_fused(f, L, stale, log_age, 1, H, W, f->pred));
     const uint32_t tiles = ((H + tile - 1) / tile) * ((W + tile - 1) / tile);
     FILL_TRY(hipMemsetAsync(f->fallbacks, 0, sizeof(uint32_t), f->st));
     hipLaunchKernelGGL(k_fill_apply, dim3(tiles), dim3(256), 0, f->st, L, stale, f->pred, H, W,

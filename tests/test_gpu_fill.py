@@ -108,6 +108,29 @@ def test_loss_and_gradient_match_reference():
     f.close()
 
 
+@pytest.mark.parametrize("shape", [(1, 720, 1280), (2, 37, 45), (1, 17, 27)])
+def test_fused_inference_equals_layer_by_layer(shape):
+    """Inference runs all four layers of a tile in one kernel (activations in
+    LDS); training runs them layer by layer through device memory.  Same
+    rounding points, so the loss from the layer-by-layer forward equals the
+    loss of the fused prediction."""
+    torch, d = torch_dev()
+    n, H, W = shape
+    prm = params_with_biases(17)
+    L, stale, age, target = make_batch(18, n, H, W)
+    batch = dev(L, stale, age, target)
+    f = fb.Fill(prm)
+    out = torch.empty((n, H, W), dtype=torch.float32, device=d)
+    assert f.predict(*batch[:3], out) == 0
+    p = out.cpu().numpy().astype(np.float64)
+    m = stale != 0
+    want = float(np.mean((p[m] - target[m]) ** 2))
+    rc, loss, _ = f.loss_grad(*batch, want_grad=False)
+    print("fused-inference loss %.9g, layer-by-layer loss %.9g" % (want, loss))
+    assert rc == 0 and abs(loss - want) <= 1e-6 * want
+    f.close()
+
+
 def test_gradient_is_deterministic():
     prm = params_with_biases(5)
     batch = dev(*make_batch(6, 2, 33, 40))
