@@ -77,7 +77,6 @@ void free_ctx(fibar_ctx* c)
     hipFree(c->s.Lp);
     hipFree(c->s.last);
     hipFree(c->s.cnt);
-    hipFree(c->s.tcnt);
     hipFree(c->s.ring);
     hipFree(c->s.sc);
     hipFree(c->d_chunks);
@@ -405,7 +404,6 @@ hipError_t init_state(fibar_ctx* c)
     if (e == hipSuccess) e = hipMemsetAsync(c->s.Lp, 0, c->npx * 8, c->st);
     if (e == hipSuccess) e = hipMemsetAsync(c->s.last, 0xff, c->npx * 8, c->st);   // -1
     if (e == hipSuccess) e = hipMemsetAsync(c->s.cnt, 0, c->npx * 4, c->st);
-    if (e == hipSuccess) e = hipMemsetAsync(c->s.tcnt, 0, c->ntiles * 4, c->st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->s.sc + c->cur_slot, c->h_sc, sizeof(DevScalars), hipMemcpyHostToDevice,
                            c->st);
@@ -487,8 +485,9 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
     c->coef.one_m_alpha = (float)(1.0 - a);
     c->coef.beta = (float)b;
     c->coef.c_alpha = (float)(0.5 * (1.0 + b) * a);
+    // sort keys are tile-major: 4 per 2x2 tile
     int kb = 1;
-    while (kb < 32 && (1ull << kb) < npx) ++kb;
+    while (kb < 32 && (1ull << kb) < 4 * c->ntiles) ++kb;
     c->key_bits = kb;
 
     uint64_t ring = 1;
@@ -503,11 +502,11 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
     alloc((void**)&c->s.Lp, npx * 8);
     alloc((void**)&c->s.last, npx * 8);
     alloc((void**)&c->s.cnt, npx * 4);
-    alloc((void**)&c->s.tcnt, c->ntiles * 4);
     alloc((void**)&c->s.ring, ring * 4);
     alloc((void**)&c->s.sc, 2 * sizeof(DevScalars));
     alloc((void**)&c->d_chunks, kMaxBatchChunks * sizeof(ChunkDesc));
-    alloc((void**)&c->seg, (size_t)kMaxBatchChunks * kChunk * sizeof(SegRec));
+    // 4 spare records: an item reads records up to i + 3 of its chunk
+    alloc((void**)&c->seg, ((size_t)kMaxBatchChunks * kChunk + 4) * sizeof(SegRec));
     alloc((void**)&c->seg_count, kMaxBatchChunks * 4);
     alloc((void**)&c->scratch, kMaxBatchChunks * sizeof(StepScratch));
     alloc((void**)&c->stg_x, stg * 2);

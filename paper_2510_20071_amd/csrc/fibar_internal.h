@@ -31,12 +31,13 @@ struct Coef {
 // The composition of all events of one pixel inside one chunk:
 //   s -> [[a, 0], [g, b]] s + [u1, u2]
 // n_last packs the event count (high 16 bits) and the chunk-local index of
-// the pixel's newest event (low 16 bits).
+// the pixel's newest event (low 16 bits); key is the pixel's sort key (2x2
+// tile index << 2 | position in the tile).
 struct alignas(32) SegRec {
     uint32_t pix;
     uint32_t n_last;
     float a, g, b, u1, u2;
-    uint32_t pad;
+    uint32_t key;
 };
 
 // Per-chunk work item of the bulk sort kernel.
@@ -80,7 +81,6 @@ struct State {
                       // .y: brightness of stale pixels (their one-time blur)
     int64_t* last;
     uint32_t* cnt;
-    uint32_t* tcnt;
     uint32_t* ring;
     uint64_t ring_mask;
     DevScalars* sc;   // two slots; see the commit scheme in fibar_kernels.hip

@@ -36,7 +36,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_compose(
     const ChunkDesc* __restrict__ chunks, SegRec* __restrict__ seg, uint32_t* __restrict__ seg_count,
     StepScratch* __restrict__ scratch, uint32_t W, uint32_t H, int key_bits, Coef coef)
 {
-    __shared__ uint32_t keypol[kChunk];                 // (pixel << 1) | polarity, arrival order
+    __shared__ uint32_t keypol[kChunk];                 // (tile-major key << 1) | polarity
     __shared__ __align__(16) uint16_t idxA[kChunk];     // permutation ping
     __shared__ __align__(16) uint16_t idxB[kChunk];     // permutation pong
     __shared__ uint64_t scan4[kWaves + 1][4];
@@ -50,13 +50,18 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_compose(
     if (tid == 0) bad_sh = 0u;
     __syncthreads();
 
+    // key: 2x2 tile index, then the pixel's position in its tile, so that a
+    // tile's pixels are consecutive after the sort
+    const uint32_t TW = (W + 1) >> 1;
     uint32_t bad = 0u;
     for (uint32_t e = tid; e < cn; e += kSortThreads) {
         const uint32_t x = cd.x[e], y = cd.y[e], p = cd.p[e];
         const bool inr = x < W && y < H;
         bad |= inr ? 0u : 1u;
         bad |= p > 1u ? 2u : 0u;
-        keypol[e] = ((inr ? y * W + x : 0u) << 1) | (p & 1u);
+        const uint32_t key = inr ? ((((y >> 1) * TW + (x >> 1)) << 2) | ((y & 1u) << 1) | (x & 1u))
+                                 : 0u;
+        keypol[e] = (key << 1) | (p & 1u);
         idxA[e] = (uint16_t)e;
     }
     if (bad) atomicOr(&bad_sh, bad);
@@ -67,15 +72,16 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_compose(
     SegRec* out = seg + (size_t)blockIdx.x * kChunk;
     const uint32_t total = tile_compose(keypol, sorted, cn, coef, scanp, scan1,
         [&](uint32_t key, const Aff& acc, uint32_t oid, uint32_t rank) {
+            const uint32_t t = key >> 2, ty = t / TW, tx = t - ty * TW;
             SegRec r;
-            r.pix = key;
+            r.pix = (2 * ty + ((key >> 1) & 1u)) * W + 2 * tx + (key & 1u);
             r.n_last = (acc.n << 16) | oid;
             r.a = acc.a;
             r.g = acc.g;
             r.b = acc.b;
             r.u1 = acc.u1;
             r.u2 = acc.u2;
-            r.pad = 0u;
+            r.key = key;
             out[rank] = r;
         });
     if (tid == 0) seg_count[blockIdx.x] = total;
@@ -103,14 +109,14 @@ __global__ __launch_bounds__(128) void k_apply(State s, ChunkDesc cd, const SegR
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t status = step->status;
     const uint32_t nseg = *seg_count;
-    const Item it = load_item(cd, seg, i, spatial);
+    const Group g = load_group(cd, seg, i, spatial);
     int64_t k0;
     uint64_t h0;
     current_head(s, slot_in, prev, prev_events, spatial, &k0, &h0);
     if (status) return;   // the packet was rejected
     const uint64_t first = (uint64_t)(k0 + 1) + chunk_offset;
     uint32_t dP = 0u, dT = 0u;
-    apply_loaded(s, it, cd.n, nseg, i, first, h0, spatial, dP, dT);
+    apply_group(s, g, cd.n, nseg, i, first, h0, spatial, dP, dT);
     if (spatial) add_counts(step, 0, dP, dT);
 }
 
@@ -152,7 +158,8 @@ __global__ __launch_bounds__(256) void k_readout(State s, int spatial, const Ste
         readout_pixel(s, spatial, k, (int64_t)hu, i, L, pbar, stale, cnt, last, log_age);
     if (spatial && tcnt) {
         const uint64_t nt = (uint64_t)s.TW * ((s.H + 1) / 2);
-        for (uint64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += stride) tcnt[i] = s.tcnt[i];
+        for (uint64_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += stride)
+            tcnt[t] = tile_active_pixels(s, t, (int64_t)hu);
     }
 }
 

@@ -150,19 +150,19 @@ __global__ __launch_bounds__(256) void k_multi_apply(MultiArgs a, const StreamSt
         StepScratch* stp = e->step;
         const ChunkDesc cd = e->chunk[sub];
         // i < kChunk: task counts are ceil(n / block) and every block size
-        // divides kChunk, and a chunk slot holds kChunk records
+        // divides kChunk; a chunk slot holds kChunk records and 3 more follow
         const uint32_t i = b * blockDim.x + threadIdx.x;
         // every load that only needs the record is issued before any is used
         const uint32_t status = stp->status;
         const uint32_t nseg = *e->nseg[sub];
-        const Item it = load_item(cd, e->seg[sub], i, 1);
+        const Group g = load_group(cd, e->seg[sub], i, 1);
         int64_t k0;
         uint64_t h0;
         current_head(s, e->slot_in, prev, e->prev_events, 1, &k0, &h0);
         if (status) continue;   // the packet was rejected
         const uint64_t first = (uint64_t)(k0 + 1) + (uint64_t)sub * kChunk;
         uint32_t dP = 0u, dT = 0u;
-        apply_loaded(s, it, cd.n, nseg, i, first, h0, 1, dP, dT);
+        apply_group(s, g, cd.n, nseg, i, first, h0, 1, dP, dT);
         add_counts(stp, 0, dP, dT);
     }
 }
@@ -676,7 +676,8 @@ int fibar_multi_create(fibar_ctx* const* ctxs, uint32_t n, void* stream, fibar_m
     dalloc((void**)&m->d_ros, kMultiMaxReadouts * sizeof(MultiReadout));
     dalloc((void**)&m->d_commits, kMultiMaxStreams * sizeof(CommitDesc));
     dalloc((void**)&m->d_chunks, kMultiChunks * sizeof(ChunkDesc));
-    dalloc((void**)&m->seg, (size_t)kMultiChunks * kChunk * sizeof(SegRec));
+    // 4 spare records: an item reads records up to i + 3 of its chunk
+    dalloc((void**)&m->seg, ((size_t)kMultiChunks * kChunk + 4) * sizeof(SegRec));
     dalloc((void**)&m->seg_count, kMultiChunks * sizeof(uint32_t));
     dalloc((void**)&m->scratch, recs * sizeof(StepScratch));
     dalloc((void**)&m->base, sizeof(uint32_t));

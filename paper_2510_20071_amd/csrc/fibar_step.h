@@ -110,28 +110,6 @@ __device__ __forceinline__ void current_head(const State& s, int slot_in, const 
     }
 }
 
-// Current brightness of pixel i while the pops of a step run: the blurred
-// value for pixels that were already stale before the step, L otherwise.
-__device__ __forceinline__ float cur_L(const State& s, size_t i, int64_t h_old)
-{
-    const float2 lp = s.Lp[i];
-    return s.last[i] < h_old ? lp.y : lp.x;
-}
-
-// 3x3 binomial blur of the current image at `pix`, clamp-to-edge, fixed
-// summation order.
-__device__ __forceinline__ float blur_at(const State& s, uint32_t pix, int64_t h_old)
-{
-    const uint32_t y = pix / s.W, x = pix - y * s.W;
-    const uint32_t xm = x > 0 ? x - 1 : 0, xp = x + 1 < s.W ? x + 1 : s.W - 1;
-    const uint32_t ym = y > 0 ? y - 1 : 0, yp = y + 1 < s.H ? y + 1 : s.H - 1;
-    const size_t r0 = (size_t)ym * s.W, r1 = (size_t)y * s.W, r2 = (size_t)yp * s.W;
-    const float h0 = cur_L(s, r0 + xm, h_old) + 2.f * cur_L(s, r0 + x, h_old) + cur_L(s, r0 + xp, h_old);
-    const float h1 = cur_L(s, r1 + xm, h_old) + 2.f * cur_L(s, r1 + x, h_old) + cur_L(s, r1 + xp, h_old);
-    const float h2 = cur_L(s, r2 + xm, h_old) + 2.f * cur_L(s, r2 + x, h_old) + cur_L(s, r2 + xp, h_old);
-    return (h0 + 2.f * h1 + h2) * 0.0625f;
-}
-
 // Window head before and after the pops of a step whose packet has
 // `pkt_events` events, from the scalars committed after the previous step.
 __device__ __forceinline__ void pop_bounds(const DevScalars& c, uint32_t pkt_events,
@@ -143,83 +121,165 @@ __device__ __forceinline__ void pop_bounds(const DevScalars& c, uint32_t pkt_eve
     if (k_end + 1 > c.Q && k_end + 1 - c.Q > c.h) *h_new = k_end + 1 - c.Q;
 }
 
-// Item i of a chunk's apply, in two parts so that a kernel can issue the
-// loads that need only the chunk (segment record, event coordinates) before
-// it waits for the window head: load_item, then apply_loaded, which pushes
-// event i to the back of the window and applies the composed map of segment
-// i (one distinct pixel) to the state, counting activations of pixels and
-// tiles.  i < kChunk: a chunk slot always holds kChunk records.
-struct Item {
-    SegRec rec;
-    uint32_t ex, ey;
+// A chunk's records are sorted tile-major (2x2 tile index, then the pixel's
+// position in its tile), so the records of one tile are consecutive, at most
+// four.  The first record of a tile (the group head) applies all of them:
+// it sees every pixel of its tile before and after, so the activations of
+// pixels and of the tile follow from last-event indices (a pixel is active
+// iff its newest event is inside the window, last >= h) with no atomics.
+// Item i also pushes event i to the back of the window.
+//
+// In two parts, so that a kernel can issue the loads that need only the
+// chunk (records i - 1 .. i + 3, event coordinates) before it waits for the
+// window head: load_group, then apply_group.  i < kChunk, and a chunk's
+// record slot is followed by at least 3 more records of memory.
+struct Group {
+    uint32_t prev_key;       // sort key of record i - 1, all ones for i = 0
+    SegRec r[4];             // records i .. i + 3
+    uint32_t ex, ey;         // event i
 };
 
-__device__ __forceinline__ Item load_item(const ChunkDesc& cd, const SegRec* __restrict__ seg,
-                                          uint32_t i, int spatial)
+__device__ __forceinline__ Group load_group(const ChunkDesc& cd, const SegRec* __restrict__ seg,
+                                           uint32_t i, int spatial)
 {
-    Item it;
-    it.rec = seg[i];
-    it.ex = 0u;
-    it.ey = 0u;
+    Group g;
+    const uint32_t pk = seg[i > 0 ? i - 1 : 0].key;          // unconditional: no wait
+    g.prev_key = i > 0 ? pk : 0xffffffffu;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) g.r[q] = seg[i + q];
+    g.ex = 0u;
+    g.ey = 0u;
     if (spatial && i < cd.n) {
-        it.ex = cd.x[i];
-        it.ey = cd.y[i];
+        g.ex = cd.x[i];
+        g.ey = cd.y[i];
     }
-    return it;
+    return g;
 }
 
-__device__ __forceinline__ void apply_loaded(const State& s, const Item& it, uint32_t n,
-                                             uint32_t nseg, uint32_t i, uint64_t first,
-                                             uint64_t h0, int spatial, uint32_t& dP, uint32_t& dT)
+// Every load is unconditional, from a valid address (values not needed are
+// masked afterwards), so that all of them are in flight together.
+__device__ __forceinline__ void apply_group(const State& s, const Group& g, uint32_t n,
+                                            uint32_t nseg, uint32_t i, uint64_t first,
+                                            uint64_t h0, int spatial, uint32_t& dP, uint32_t& dT)
 {
-    if (spatial && i < n) s.ring[(first + i) & s.ring_mask] = it.ey * s.W + it.ex;
-    if (i < nseg) {
-        const SegRec& r = it.rec;
-        const uint32_t pix = r.pix;
-        const float pb = s.pbar[pix];
-        float2 lp = s.Lp[pix];
-        float l = lp.x;
-        int64_t last_old = 0;
-        uint32_t old = 0u;
-        if (spatial) {
-            last_old = s.last[pix];
-            old = s.cnt[pix];
-            // a stale (or never seen) pixel's current value is its blurred one
-            l = last_old < (int64_t)h0 ? lp.y : lp.x;
+    if (spatial && i < n) s.ring[(first + i) & s.ring_mask] = g.ey * s.W + g.ex;
+    if (i >= nseg) return;
+    const uint32_t t = g.r[0].key >> 2;
+    if (i > 0 && (g.prev_key >> 2) == t) return;              // not the head of its tile
+    bool mem[4];
+    uint32_t pix[4];
+    mem[0] = true;
+#pragma unroll
+    for (int k = 1; k < 4; ++k) mem[k] = mem[k - 1] && i + k < nseg && (g.r[k].key >> 2) == t;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pix[k] = mem[k] ? g.r[k].pix : g.r[0].pix;
+    // the tile's pixels: quad q at (2 tx + (q & 1), 2 ty + (q >> 1))
+    const uint32_t k0 = g.r[0].key;
+    const uint32_t base = pix[0] - (k0 & 1u) - ((k0 >> 1) & 1u) * s.W;
+    const uint32_t ty = t / s.TW, tx = t - ty * s.TW;
+    const bool has_x1 = 2 * tx + 1 < s.W, has_y1 = 2 * ty + 1 < s.H;
+    int64_t lq[4];
+    float pb[4];
+    float2 lp[4];
+    uint32_t cn[4];
+    if (spatial) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const bool ok = (!(q & 1) || has_x1) && (!(q & 2) || has_y1);
+            lq[q] = s.last[ok ? base + (q & 1) + (q >> 1) * s.W : base];
         }
-        s.pbar[pix] = fmaf(r.a, pb, r.u1);
-        lp.x = fmaf(r.g, pb, fmaf(r.b, l, r.u2));
-        s.Lp[pix] = lp;
-        s.last[pix] = (int64_t)(first + (r.n_last & 0xffffu));
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        pb[k] = s.pbar[pix[k]];
+        lp[k] = s.Lp[pix[k]];
+        cn[k] = spatial ? s.cnt[pix[k]] : 0u;
+    }
+    bool tile_was_active = false;
+    if (spatial) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const bool ok = (!(q & 1) || has_x1) && (!(q & 2) || has_y1);
+            if (!ok) lq[q] = -1;
+            tile_was_active |= lq[q] >= (int64_t)h0;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (!mem[k]) continue;
+        const SegRec& r = g.r[k];
+        float l = lp[k].x;
         if (spatial) {
-            s.cnt[pix] = old + (r.n_last >> 16);
-            if (old == 0u) {
+            const uint32_t q = r.key & 3u;
+            const int64_t last_old = q == 3 ? lq[3] : q == 2 ? lq[2] : q == 1 ? lq[1] : lq[0];
+            // a stale (or never seen) pixel's current value is its blurred one
+            if (last_old < (int64_t)h0) {
+                l = lp[k].y;
                 dP += 1u;
-                if (atomicAdd(&s.tcnt[tile_of(s, pix)], 1u) == 0u) dT += 1u;
             }
         }
+        s.pbar[pix[k]] = fmaf(r.a, pb[k], r.u1);
+        float2 o = lp[k];
+        o.x = fmaf(r.g, pb[k], fmaf(r.b, l, r.u2));
+        s.Lp[pix[k]] = o;
+        s.last[pix[k]] = (int64_t)(first + (r.n_last & 0xffffu));
+        if (spatial) s.cnt[pix[k]] = cn[k] + (r.n_last >> 16);
     }
+    if (spatial && !tile_was_active) dT += 1u;
 }
 
-// Pops j = start, start + stride, ... below h_new: pixels whose last queued
-// event leaves the window go stale and get their blurred value in Lb,
-// computed from the image as it was before this step's blurs.
+// Pops j = start, start + stride, ... below h_new.  A pixel goes stale when
+// its newest event leaves the window, i.e. exactly when the popped j is its
+// last index; it then gets its blurred value in Lp.y, computed from the image
+// as it was before this step's blurs.  Its 2x2 tile goes inactive when no
+// pixel of the tile has a newer event: the pixel with the largest last
+// index of the tile (unique, and popped in this same step) counts it.  The
+// whole 3x3 neighbourhood (which holds the tile) is loaded for every pop,
+// before the decision; the count update needs no result.
 __device__ __forceinline__ void pop_range(const State& s, uint64_t start, uint64_t h_new,
                                           uint64_t stride, uint64_t h_old, uint32_t& dP,
                                           uint32_t& dT)
 {
     for (uint64_t j = start; j < h_new; j += stride) {
         const uint32_t pix = s.ring[j & s.ring_mask];
-        // The neighbourhood is read before the count update returns (most
-        // pops end a pixel's activity, so few of these reads are wasted):
-        // the values do not depend on the update, since a pixel that goes
-        // stale in this step is still read as L.
-        const float b = blur_at(s, pix, (int64_t)h_old);
-        if (atomicSub(&s.cnt[pix], 1u) == 1u) {
-            ++dP;
-            if (atomicSub(&s.tcnt[tile_of(s, pix)], 1u) == 1u) ++dT;
-            s.Lp[pix].y = b;
-        }
+        const uint32_t y = pix / s.W, x = pix - y * s.W;
+        const uint32_t xs[3] = {x > 0 ? x - 1 : 0, x, x + 1 < s.W ? x + 1 : s.W - 1};
+        const uint32_t ys[3] = {y > 0 ? y - 1 : 0, y, y + 1 < s.H ? y + 1 : s.H - 1};
+        int64_t lst[3][3];
+        float2 lp[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const size_t q = (size_t)ys[a] * s.W + xs[b];
+                lst[a][b] = s.last[q];
+                lp[a][b] = s.Lp[q];
+            }
+        atomicSub(&s.cnt[pix], 1u);
+        if (lst[1][1] != (int64_t)j) continue;
+        ++dP;
+        float c[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                c[a][b] = lst[a][b] < (int64_t)h_old ? lp[a][b].y : lp[a][b].x;
+        // 3x3 binomial blur, clamp-to-edge, fixed summation order
+        const float r0 = c[0][0] + 2.f * c[0][1] + c[0][2];
+        const float r1 = c[1][0] + 2.f * c[1][1] + c[1][2];
+        const float r2 = c[2][0] + 2.f * c[2][1] + c[2][2];
+        s.Lp[pix].y = (r0 + 2.f * r1 + r2) * 0.0625f;
+        // the tile's other pixels: column x ^ 1 and row y ^ 1, where they
+        // exist (selected with fixed indices: a register array indexed at run
+        // time would be moved to memory)
+        const bool ox = x & 1u, oy = y & 1u;
+        const bool hx = ox || x + 1 < s.W, hy = oy || y + 1 < s.H;
+        const int64_t lx = ox ? lst[1][0] : lst[1][2];
+        const int64_t ly = oy ? lst[0][1] : lst[2][1];
+        const int64_t lxy = oy ? (ox ? lst[0][0] : lst[0][2]) : (ox ? lst[2][0] : lst[2][2]);
+        const int64_t me = lst[1][1];
+        const bool newest = !(hx && lx > me) && !(hy && ly > me) && !(hx && hy && lxy > me);
+        if (newest) ++dT;
     }
 }
 
@@ -235,6 +295,19 @@ __device__ __forceinline__ void add_counts(StepScratch* step, int first_slot, ui
     }
 }
 
+// Active pixels of tile t (their newest event is inside the window).
+__device__ __forceinline__ uint32_t tile_active_pixels(const State& s, uint64_t t, int64_t h)
+{
+    const uint32_t ty = (uint32_t)(t / s.TW), tx = (uint32_t)(t - (uint64_t)ty * s.TW);
+    uint32_t n = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t px = 2 * tx + (q & 1), py = 2 * ty + (q >> 1);
+        if (px < s.W && py < s.H && s.last[(size_t)py * s.W + px] >= h) ++n;
+    }
+    return n;
+}
+
 // Readout of pixel i given the newest index k and window head h.
 __device__ __forceinline__ void readout_pixel(const State& s, int spatial, int64_t k, int64_t h,
                                               uint64_t i, float* L, float* pbar, uint8_t* stale,
@@ -248,9 +321,8 @@ __device__ __forceinline__ void readout_pixel(const State& s, int spatial, int64
     if (last) last[i] = li;
     if (log_age) log_age[i] = log1pf((float)(k - li));
     if (spatial) {
-        const uint32_t cn = s.cnt[i];
-        if (cnt) cnt[i] = cn;
-        if (stale) stale[i] = (li >= 0 && cn == 0u) ? 1u : 0u;
+        if (cnt) cnt[i] = s.cnt[i];
+        if (stale) stale[i] = (li >= 0 && li < h) ? 1u : 0u;
     }
 }
 
