@@ -141,6 +141,7 @@ def run_batched(args, torch, dev, fb, eventsim):
         assert group.submit(op_lists) == 0
     torch.cuda.synchronize()
     shape = group.shape()
+    config = group.config()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         reset_all()
@@ -166,7 +167,9 @@ def run_batched(args, torch, dev, fb, eventsim):
            "packets": [w.packet for w in wls], "mev_s": round(total / el / 1e6, 2),
            "ms_per_step": round(1e3 * el, 3),
            "one_stream_at_a_time_mev_s": round(total / el_seq / 1e6, 2),
-           "launch_shape": {"block": shape[0], "grid": shape[1], "autotuned": True}}
+           "launch_shape": {"block": shape[0], "grid": shape[1],
+                            "launches": "hip graphs" if config < 5 else "direct",
+                            "autotuned": True}}
     log("batched streams: %.1f Mev/s together, %.1f Mev/s one at a time"
         % (res["mev_s"], res["one_stream_at_a_time_mev_s"]))
     return res
@@ -285,6 +288,15 @@ def run_fill(args, torch, dev, fb, eventsim):
     ev_b.record()
     torch.cuda.synchronize()
     infer_ms = ev_a.elapsed_time(ev_b) / reps
+    # the fused network kernel alone (prediction without the fallback pass)
+    pred = torch.empty_like(out)
+    ev_a.record()
+    for _ in range(reps):
+        lib.fibar_fill_predict(fill.handle, Lev[0].data_ptr(), Sev[0].data_ptr(), Aev[0].data_ptr(),
+                               1, H, W, pred.data_ptr())
+    ev_b.record()
+    torch.cuda.synchronize()
+    fused_ms = ev_a.elapsed_time(ev_b) / reps
     bt = [batch() for _ in range(4)]
     for b_ in bt:
         fill.train_step(*b_, lr=0.0, want_loss=False)
@@ -296,6 +308,7 @@ def run_fill(args, torch, dev, fb, eventsim):
     step_ms = ev_a.elapsed_time(ev_b) / reps
     fill.close()
     infer_tflops = FILL_FWD_FLOP_PX * H * W / (infer_ms * 1e-3) / 1e12
+    fused_tflops = FILL_FWD_FLOP_PX * H * W / (fused_ms * 1e-3) / 1e12
     train_tflops = FILL_TRAIN_FLOP_PX * B * TS * TS / (step_ms * 1e-3) / 1e12
     res = {"train_frames": int(F), "eval_frames": int(Lev.shape[0]),
            "train_sequences": len(train_seeds), "eval_sequences": len(eval_seeds),
@@ -312,7 +325,12 @@ def run_fill(args, torch, dev, fb, eventsim):
                          "frac_bf16_peak": round(infer_tflops / 2500.0, 5),
                          "mev_s_at_one_frame_per_100k_events": round(0.1 / (infer_ms * 1e-3), 1)},
            "training": {"ms_per_step": round(step_ms, 4), "tflops": round(train_tflops, 2),
-                        "frac_bf16_peak": round(train_tflops / 2500.0, 5)}}
+                        "frac_bf16_peak": round(train_tflops / 2500.0, 5)},
+           "roofline": {"bound": "mfma", "kernel": "fill_fused", "achieved": round(fused_tflops, 2),
+                        "peak": 2500.0, "unit": "TFLOP/s",
+                        "frac": round(fused_tflops / 2500.0, 5), "traffic": None,
+                        "us_per_launch_back_to_back": round(fused_ms * 1e3, 3),
+                        "flops_per_launch": FILL_FWD_FLOP_PX * H * W}}
     log("fill: PSNR gaussian %.2f dB, learned %.2f dB (with fallback %.2f dB); inference %.3f ms "
         "per 1280x720 frame (%.1f TFLOP/s), training step %.3f ms (%.1f TFLOP/s)"
         % (res["psnr_db"]["gaussian_fill"], res["psnr_db"]["learned"],

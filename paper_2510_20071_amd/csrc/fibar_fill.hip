@@ -239,15 +239,20 @@ __global__ __launch_bounds__(256) void k_fill_wgrad(const uint16_t* __restrict__
         partial[(size_t)blockIdx.x * kWgEntries + e] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
 }
 
-// Sum the partials of layer l in workgroup order into the canonical gradient.
+// Sum the partials of layer l into the canonical gradient: one wave per
+// entry, each lane adding every 64th partial in order, then a fixed butterfly
+// over the lanes (deterministic).
 __global__ __launch_bounds__(256) void k_fill_wgrad_reduce(const float* __restrict__ partial,
                                                            uint32_t blocks, int l,
                                                            float* __restrict__ grad)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= kWgEntries) return;
+    const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (e >= kWgEntries) return;                 // whole wave
+    const uint32_t lane = threadIdx.x & 63;
     float s = 0.f;
-    for (uint32_t b = 0; b < blocks; ++b) s += partial[(size_t)b * kWgEntries + e];
+    for (uint32_t b = lane; b < blocks; b += 64) s += partial[(size_t)b * kWgEntries + e];
+    for (int m = 32; m > 0; m >>= 1) s += __shfl_xor(s, m);
+    if (lane != 0) return;
     const int ci = cin_of(l), co = cout_of(l);
     if (e < kTaps * kC * kC) {
         const int t = e / (kC * kC), o = (e / kC) % kC, c = e % kC;
@@ -684,7 +689,7 @@ int loss_grad(fibar_fill* f, const float* L, const uint8_t* stale, const float* 
     for (int l = kLayers - 1; l >= 0; --l) {
         hipLaunchKernelGGL(k_fill_wgrad, dim3(kGradBlocks), dim3(256), 0, f->st, f->act[l], f->g[cur],
                            n, H, W, f->partial);
-        hipLaunchKernelGGL(k_fill_wgrad_reduce, dim3((kWgEntries + 255) / 256), dim3(256), 0, f->st,
+        hipLaunchKernelGGL(k_fill_wgrad_reduce, dim3((kWgEntries + 3) / 4), dim3(256), 0, f->st,
                            f->partial, (uint32_t)kGradBlocks, l, f->grad);
         FILL_TRY(hipGetLastError());
         if (l > 0) {
