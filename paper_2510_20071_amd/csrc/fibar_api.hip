@@ -71,31 +71,31 @@ hipError_t timed_launch(fibar_ctx* c, int kind, F&& fn)
 void free_ctx(fibar_ctx* c)
 {
     if (!c) return;
-    if (c->st) hipStreamSynchronize(c->st);
-    else hipDeviceSynchronize();
-    hipFree(c->s.pbar);
-    hipFree(c->s.Lp);
-    hipFree(c->s.last);
-    hipFree(c->s.cnt);
-    hipFree(c->s.ring);
-    hipFree(c->s.sc);
-    hipFree(c->d_chunks);
-    hipFree(c->seg);
-    hipFree(c->seg_count);
-    hipFree(c->scratch);
-    hipFree(c->stg_x);
-    hipFree(c->stg_y);
-    hipFree(c->stg_p);
-    hipFree(c->rb.cnt);
-    hipFree(c->rb.base);
-    hipFree(c->rb.total);
-    hipFree(c->rb.chunk_k);
-    hipFree(c->rb.payload);
-    hipFree(c->rb.ro);
-    if (c->h_ro) hipHostFree(c->h_ro);
+    if (c->st) (void)hipStreamSynchronize(c->st);
+    else (void)hipDeviceSynchronize();
+    (void)hipFree(c->s.pbar);
+    (void)hipFree(c->s.Lp);
+    (void)hipFree(c->s.last);
+    (void)hipFree(c->s.cnt);
+    (void)hipFree(c->s.ring);
+    (void)hipFree(c->s.sc);
+    (void)hipFree(c->d_chunks);
+    (void)hipFree(c->seg);
+    (void)hipFree(c->seg_count);
+    (void)hipFree(c->scratch);
+    (void)hipFree(c->stg_x);
+    (void)hipFree(c->stg_y);
+    (void)hipFree(c->stg_p);
+    (void)hipFree(c->rb.cnt);
+    (void)hipFree(c->rb.base);
+    (void)hipFree(c->rb.total);
+    (void)hipFree(c->rb.chunk_k);
+    (void)hipFree(c->rb.payload);
+    (void)hipFree(c->rb.ro);
+    if (c->h_ro) (void)hipHostFree(c->h_ro);
     if (c->ro_free) (void)hipEventDestroy(c->ro_free);
-    if (c->h_chunks) hipHostFree(c->h_chunks);
-    if (c->h_sc) hipHostFree(c->h_sc);
+    if (c->h_chunks) (void)hipHostFree(c->h_chunks);
+    if (c->h_sc) (void)hipHostFree(c->h_sc);
     if (c->chunks_free) (void)hipEventDestroy(c->chunks_free);
     for (auto& v : c->timed)
         for (auto& pr : v) {

@@ -194,8 +194,11 @@ hipError_t launch_apply(const State& s, const ChunkDesc* d_chunk, const SegRec* 
 hipError_t launch_pop_blur(const State& s, uint32_t pkt_events, StepScratch* step, int slot,
                            hipStream_t st, const LaunchTiming& tm)
 {
-    // many small workgroups spread the scattered reads over more CUs
-    return launch_timed(k_pop_blur, dim3(128), dim3(128), st, tm.start, tm.stop, s, pkt_events,
+    // one pop per thread: a step pops its packet's events plus the amount
+    // the target length shrank by, so the grid has 1/8 headroom (a thread
+    // that had to take a second pop would double the kernel's latency)
+    const uint32_t blocks = (pkt_events + pkt_events / 8 + 127) / 128;
+    return launch_timed(k_pop_blur, dim3(blocks), dim3(128), st, tm.start, tm.stop, s, pkt_events,
                         step, slot);
 }
 

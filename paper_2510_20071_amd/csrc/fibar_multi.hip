@@ -546,7 +546,8 @@ int run_multi_batch(fibar_multi* m, std::vector<StreamPlan>& plans, bool* done)
             for (uint32_t k = 0; k < S; ++k) {
                 StreamStep& e = m->h_rec[(size_t)r * S + k];
                 if (e.events) {
-                    e.pop_blocks = std::max<uint32_t>(1, (e.events + B - 1) / B);
+                    // 1/8 headroom for a shrinking target length
+                    e.pop_blocks = (e.events + e.events / 8 + B - 1) / B;
                     acc[0] += (e.chunk[0].n + B - 1) / B + (e.prev ? 1u : 0u);
                     acc[1] += (e.chunk[1].n + B - 1) / B;
                     acc[2] += e.pop_blocks;
