@@ -107,16 +107,19 @@ __global__ __launch_bounds__(128) void k_apply(State s, ChunkDesc cd, const SegR
     }
     // every load that needs only the arguments is issued before any is used
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t status = step->status;
-    const uint32_t nseg = *seg_count;
     const Group g = load_group(cd, seg, i, spatial);
+    uint32_t status = step->status;
+    uint32_t nseg = *seg_count;
+    HeadIn hin = load_head(s, slot_in, prev);
+    FIBAR_ISSUE_FENCE();
+    const TileIn ti = load_tile(s, g, i);
+    scalars_after_loads(hin, status, nseg);
     int64_t k0;
     uint64_t h0;
-    current_head(s, slot_in, prev, prev_events, spatial, &k0, &h0);
-    if (status) return;   // the packet was rejected
+    head_after(hin, prev_events, spatial, &k0, &h0);
     const uint64_t first = (uint64_t)(k0 + 1) + chunk_offset;
     uint32_t dP = 0u, dT = 0u;
-    apply_group(s, g, cd.n, nseg, i, first, h0, spatial, dP, dT);
+    apply_tile(s, g, ti, cd.n, nseg, status != 0, i, first, h0, spatial, dP, dT);
     if (spatial) add_counts(step, 0, dP, dT);
 }
 
@@ -126,10 +129,11 @@ __global__ __launch_bounds__(128) void k_apply(State s, ChunkDesc cd, const SegR
 __global__ __launch_bounds__(128) void k_pop_blur(State s, uint32_t pkt_events, StepScratch* step,
                                                   int slot)
 {
+    // the status and the scalars are loaded together (a select, not a branch)
     const uint32_t status = step->status;
     uint64_t h_old, h_new;
     pop_bounds(s.sc[slot], pkt_events, &h_old, &h_new);
-    if (status) return;
+    if (status) h_new = h_old;   // a rejected packet pops nothing
     uint32_t dP = 0u, dT = 0u;
     pop_range(s, h_old + blockIdx.x * blockDim.x + threadIdx.x, h_new,
               (uint64_t)gridDim.x * blockDim.x, h_old, dP, dT);

@@ -153,16 +153,19 @@ __global__ __launch_bounds__(256) void k_multi_apply(MultiArgs a, const StreamSt
         // divides kChunk; a chunk slot holds kChunk records and 3 more follow
         const uint32_t i = b * blockDim.x + threadIdx.x;
         // every load that only needs the record is issued before any is used
+        const Group g = load_group(cd, e->seg[sub], i, 1);
         const uint32_t status = stp->status;
         const uint32_t nseg = *e->nseg[sub];
-        const Group g = load_group(cd, e->seg[sub], i, 1);
+        const HeadIn hin = load_head(s, e->slot_in, prev);
+        FIBAR_ISSUE_FENCE();
+        const TileIn ti = load_tile(s, g, i);
+        FIBAR_ISSUE_FENCE();
         int64_t k0;
         uint64_t h0;
-        current_head(s, e->slot_in, prev, e->prev_events, 1, &k0, &h0);
-        if (status) continue;   // the packet was rejected
+        head_after(hin, e->prev_events, 1, &k0, &h0);
         const uint64_t first = (uint64_t)(k0 + 1) + (uint64_t)sub * kChunk;
         uint32_t dP = 0u, dT = 0u;
-        apply_group(s, g, cd.n, nseg, i, first, h0, 1, dP, dT);
+        apply_tile(s, g, ti, cd.n, nseg, status != 0, i, first, h0, 1, dP, dT);
         add_counts(stp, 0, dP, dT);
     }
 }
@@ -179,7 +182,7 @@ __global__ __launch_bounds__(256) void k_multi_pop(MultiArgs a, const StreamStep
         const uint32_t status = stp->status;
         uint64_t h_old, h_new;
         pop_bounds(s.sc[e->pop_slot], e->events, &h_old, &h_new);
-        if (status) continue;
+        if (status) h_new = h_old;   // a rejected packet pops nothing
         uint32_t dP = 0u, dT = 0u;
         pop_range(s, h_old + (uint64_t)(t - start) * blockDim.x + threadIdx.x, h_new,
                   (uint64_t)e->pop_blocks * blockDim.x, h_old, dP, dT);

@@ -45,16 +45,18 @@ __device__ uint64_t target_div(uint64_t q, uint64_t fill_num, uint64_t T, uint64
 }
 
 // Window head and newest index after the pending step (cheap part of a
-// commit: what every thread of the next kernel needs).
+// commit: what every thread of the next kernel needs).  Selects, not
+// branches, so that the status load is issued together with the scalars.
 __device__ __forceinline__ void step_head(const DevScalars& c, const StepScratch* st, uint32_t n,
                                           int spatial, int64_t* k, uint64_t* h)
 {
-    *k = c.k;
-    *h = c.h;
-    if (st->status) return;
-    const uint64_t k_end = (uint64_t)(c.k + (int64_t)n);
-    *k = (int64_t)k_end;
-    if (spatial && k_end + 1 > c.Q && k_end + 1 - c.Q > c.h) *h = k_end + 1 - c.Q;
+    const uint32_t status = st->status;
+    const int64_t ck = c.k;
+    const uint64_t ch = c.h, cQ = c.Q;
+    const uint64_t k_end = (uint64_t)(ck + (int64_t)n);
+    const bool move = spatial && k_end + 1 > cQ && k_end + 1 - cQ > ch;
+    *k = status ? ck : (int64_t)k_end;
+    *h = (status || !move) ? ch : k_end + 1 - cQ;
 }
 
 // Full commit of the pending step: counts, Eq. (20), statistics.
@@ -96,18 +98,47 @@ __device__ DevScalars commit_step(const DevScalars& c, const StepScratch* st, ui
     return r;
 }
 
+// Read in place of a pending step's scratch when there is none (its value
+// is not used; reading it keeps the load unconditional).
+__device__ StepScratch no_pending_step;
+
+// The scalars that (k, h) after the pending step follow from, loaded
+// together (load_head), and the head computed from them (head_after).
+struct HeadIn {
+    int64_t k;
+    uint64_t h, Q;
+    uint32_t pending_status;
+    bool pending;
+};
+
+__device__ __forceinline__ HeadIn load_head(const State& s, int slot_in, const StepScratch* prev)
+{
+    const DevScalars& c = s.sc[slot_in];
+    HeadIn r;
+    r.k = c.k;
+    r.h = c.h;
+    r.Q = c.Q;
+    r.pending_status = (prev ? prev : &no_pending_step)->status;
+    r.pending = prev != nullptr;
+    return r;
+}
+
+__device__ __forceinline__ void head_after(const HeadIn& c, uint32_t prev_events, int spatial,
+                                           int64_t* k, uint64_t* h)
+{
+    const uint64_t k_end = (uint64_t)(c.k + (int64_t)prev_events);
+    const bool move = spatial && k_end + 1 > c.Q && k_end + 1 - c.Q > c.h;
+    const bool adv = c.pending && !c.pending_status;
+    *k = adv ? (int64_t)k_end : c.k;
+    *h = (adv && move) ? k_end + 1 - c.Q : c.h;
+}
+
 // (k, h) after the pending step, for every thread of a kernel.
 __device__ __forceinline__ void current_head(const State& s, int slot_in, const StepScratch* prev,
                                              uint32_t prev_events, int spatial, int64_t* k,
                                              uint64_t* h)
 {
-    const DevScalars c = s.sc[slot_in];
-    if (prev) {
-        step_head(c, prev, prev_events, spatial, k, h);
-    } else {
-        *k = c.k;
-        *h = c.h;
-    }
+    head_after(load_head(s, slot_in, prev), prev_events, spatial, k, h);
 }
 
 // Window head before and after the pops of a step whose packet has
@@ -156,76 +187,111 @@ __device__ __forceinline__ Group load_group(const ChunkDesc& cd, const SegRec* _
     return g;
 }
 
-// Every load is unconditional, from a valid address (values not needed are
-// masked afterwards), so that all of them are in flight together.
-__device__ __forceinline__ void apply_group(const State& s, const Group& g, uint32_t n,
-                                            uint32_t nseg, uint32_t i, uint64_t first,
-                                            uint64_t h0, int spatial, uint32_t& dP, uint32_t& dT)
-{
-    if (spatial && i < n) s.ring[(first + i) & s.ring_mask] = g.ey * s.W + g.ex;
-    if (i >= nseg) return;
-    const uint32_t t = g.r[0].key >> 2;
-    if (i > 0 && (g.prev_key >> 2) == t) return;              // not the head of its tile
-    bool mem[4];
+// The state of the tile of record i, loaded before the scalars (rejection
+// status, record count, window head) are waited for: its addresses need
+// only the records.  Records past the chunk's count are stale memory, so
+// every address is clamped into the image and the values are masked later.
+// No branch surrounds the loads (a value merged at a join is copied there,
+// and the copy waits for its load); the records of a tile's other pixels
+// repeat the head's addresses, which coalesce within the wavefront.
+struct TileIn {
+    bool head;               // first record of its tile
+    bool same[4];            // records i .. i + 3 belong to the tile
     uint32_t pix[4];
-    mem[0] = true;
-#pragma unroll
-    for (int k = 1; k < 4; ++k) mem[k] = mem[k - 1] && i + k < nseg && (g.r[k].key >> 2) == t;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) pix[k] = mem[k] ? g.r[k].pix : g.r[0].pix;
-    // the tile's pixels: quad q at (2 tx + (q & 1), 2 ty + (q >> 1))
-    const uint32_t k0 = g.r[0].key;
-    const uint32_t base = pix[0] - (k0 & 1u) - ((k0 >> 1) & 1u) * s.W;
-    const uint32_t ty = t / s.TW, tx = t - ty * s.TW;
-    const bool has_x1 = 2 * tx + 1 < s.W, has_y1 = 2 * ty + 1 < s.H;
-    int64_t lq[4];
+    int64_t lq[4];           // last-event index of the tile's quads
     float pb[4];
     float2 lp[4];
     uint32_t cn[4];
-    if (spatial) {
+};
+
+__device__ __forceinline__ TileIn load_tile(const State& s, const Group& g, uint32_t i)
+{
+    TileIn ti;
+    const uint32_t npx = s.W * s.H;
+    const uint32_t t = g.r[0].key >> 2;
+    ti.head = i == 0 || (g.prev_key >> 2) != t;
+    ti.same[0] = true;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const bool ok = (!(q & 1) || has_x1) && (!(q & 2) || has_y1);
-            lq[q] = s.last[ok ? base + (q & 1) + (q >> 1) * s.W : base];
-        }
+    for (int k = 1; k < 4; ++k) ti.same[k] = ti.same[k - 1] && (g.r[k].key >> 2) == t;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t p = ti.same[k] ? g.r[k].pix : g.r[0].pix;
+        ti.pix[k] = p < npx ? p : 0u;
+    }
+    // the tile's pixels: quad q at (2 tx + (q & 1), 2 ty + (q >> 1))
+    const uint32_t k0 = g.r[0].key;
+    const uint32_t base = ti.pix[0] - (k0 & 1u) - ((k0 >> 1) & 1u) * s.W;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t p = base + (q & 1) + (q >> 1) * s.W;
+        ti.lq[q] = s.last[p < npx ? p : 0u];
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        pb[k] = s.pbar[pix[k]];
-        lp[k] = s.Lp[pix[k]];
-        cn[k] = spatial ? s.cnt[pix[k]] : 0u;
+        ti.pb[k] = s.pbar[ti.pix[k]];
+        ti.lp[k] = s.Lp[ti.pix[k]];
+        ti.cn[k] = s.cnt[ti.pix[k]];
     }
+    return ti;
+}
+
+// Push event i to the window; if record i heads its tile, apply the tile's
+// records and count pixel and tile activations.
+__device__ __forceinline__ void apply_tile(const State& s, const Group& g, const TileIn& ti,
+                                           uint32_t n, uint32_t nseg, bool rejected, uint32_t i,
+                                           uint64_t first, uint64_t h0, int spatial, uint32_t& dP,
+                                           uint32_t& dT)
+{
+    if (rejected) return;
+    if (spatial && i < n) s.ring[(first + i) & s.ring_mask] = g.ey * s.W + g.ex;
+    if (i >= nseg || !ti.head) return;
+    const uint32_t t = g.r[0].key >> 2;
+    const uint32_t ty = t / s.TW, tx = t - ty * s.TW;
+    const bool has_x1 = 2 * tx + 1 < s.W, has_y1 = 2 * ty + 1 < s.H;
+    int64_t lq[4];
     bool tile_was_active = false;
-    if (spatial) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const bool ok = (!(q & 1) || has_x1) && (!(q & 2) || has_y1);
-            if (!ok) lq[q] = -1;
-            tile_was_active |= lq[q] >= (int64_t)h0;
-        }
+    for (int q = 0; q < 4; ++q) {
+        const bool ok = (!(q & 1) || has_x1) && (!(q & 2) || has_y1);
+        lq[q] = ok ? ti.lq[q] : -1;
+        tile_was_active |= lq[q] >= (int64_t)h0;
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        if (!mem[k]) continue;
+        if (!ti.same[k] || i + k >= nseg) continue;
         const SegRec& r = g.r[k];
-        float l = lp[k].x;
+        const uint32_t px = ti.pix[k];
+        float l = ti.lp[k].x;
         if (spatial) {
             const uint32_t q = r.key & 3u;
             const int64_t last_old = q == 3 ? lq[3] : q == 2 ? lq[2] : q == 1 ? lq[1] : lq[0];
             // a stale (or never seen) pixel's current value is its blurred one
             if (last_old < (int64_t)h0) {
-                l = lp[k].y;
+                l = ti.lp[k].y;
                 dP += 1u;
             }
         }
-        s.pbar[pix[k]] = fmaf(r.a, pb[k], r.u1);
-        float2 o = lp[k];
-        o.x = fmaf(r.g, pb[k], fmaf(r.b, l, r.u2));
-        s.Lp[pix[k]] = o;
-        s.last[pix[k]] = (int64_t)(first + (r.n_last & 0xffffu));
-        if (spatial) s.cnt[pix[k]] = cn[k] + (r.n_last >> 16);
+        s.pbar[px] = fmaf(r.a, ti.pb[k], r.u1);
+        float2 o = ti.lp[k];
+        o.x = fmaf(r.g, ti.pb[k], fmaf(r.b, l, r.u2));
+        s.Lp[px] = o;
+        s.last[px] = (int64_t)(first + (r.n_last & 0xffffu));
+        if (spatial) s.cnt[px] = ti.cn[k] + (r.n_last >> 16);
     }
     if (spatial && !tile_was_active) dT += 1u;
+}
+
+// Keeps every memory access above it above it and every one below below
+// (an empty statement; it neither waits for nor touches memory).
+#define FIBAR_ISSUE_FENCE() asm volatile("" ::: "memory")
+
+// Passes scalar-loaded values through an empty statement placed after the
+// state loads, so that no arithmetic on them (which waits for every
+// outstanding scalar load) is scheduled before those loads are issued.
+__device__ __forceinline__ void scalars_after_loads(HeadIn& h, uint32_t& status, uint32_t& nseg)
+{
+    asm volatile("" : "+s"(h.k), "+s"(h.h), "+s"(h.Q), "+s"(h.pending_status), "+s"(status),
+                 "+s"(nseg)::"memory");
 }
 
 // Pops j = start, start + stride, ... below h_new.  A pixel goes stale when
