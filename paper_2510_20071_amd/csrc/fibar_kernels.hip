@@ -28,6 +28,11 @@ namespace {
 using namespace tile;
 using namespace step;
 
+// Workgroup sizes of the in-order kernels (on the 1280x720 stream with
+// 16384-event packets, 64- and 256-thread workgroups were both slower).
+constexpr uint32_t kApplyBlock = 128;
+constexpr uint32_t kPopBlock = 128;
+
 // ---------------------------------------------------------------------------
 // Bulk kernel: validate, stable LDS radix sort by pixel, segmented scan of
 // the per-event affine maps.  One workgroup per chunk.
@@ -94,7 +99,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_compose(
 // Apply one chunk's compositions to the state; push the chunk's events to
 // the back of the window (spatial filter); count activations.  The last
 // workgroup only commits the previous step's scalars.
-__global__ __launch_bounds__(128) void k_apply(State s, ChunkDesc cd, const SegRec* __restrict__ seg,
+__global__ __launch_bounds__(kApplyBlock) void k_apply(State s, ChunkDesc cd, const SegRec* __restrict__ seg,
                                                const uint32_t* __restrict__ seg_count,
                                                uint32_t chunk_offset, StepScratch* step,
                                                const StepScratch* prev, uint32_t prev_events,
@@ -126,7 +131,7 @@ __global__ __launch_bounds__(128) void k_apply(State s, ChunkDesc cd, const SegR
 // Move the window head by the target of the previous step (Eq. (20)),
 // detect pixels whose last queued event leaves the window, and write their
 // blurred values to Lb.  `slot` holds the scalars after the previous step.
-__global__ __launch_bounds__(128) void k_pop_blur(State s, uint32_t pkt_events, StepScratch* step,
+__global__ __launch_bounds__(kPopBlock) void k_pop_blur(State s, uint32_t pkt_events, StepScratch* step,
                                                   int slot)
 {
     // the status and the scalars are loaded together (a select, not a branch)
@@ -189,8 +194,8 @@ hipError_t launch_apply(const State& s, const ChunkDesc* d_chunk, const SegRec* 
                         const LaunchTiming& tm)
 {
     // one extra workgroup commits the previous step's scalars
-    const uint32_t blocks = (chunk_events + 127) / 128 + 1;
-    return launch_timed(k_apply, dim3(blocks), dim3(128), st, tm.start, tm.stop, s, *d_chunk, seg,
+    const uint32_t blocks = (chunk_events + kApplyBlock - 1) / kApplyBlock + 1;
+    return launch_timed(k_apply, dim3(blocks), dim3(kApplyBlock), st, tm.start, tm.stop, s, *d_chunk, seg,
                         seg_count, chunk_offset, step, prev, prev_events, slot_in, slot_out,
                         spatial);
 }
@@ -201,8 +206,8 @@ hipError_t launch_pop_blur(const State& s, uint32_t pkt_events, StepScratch* ste
     // one pop per thread: a step pops its packet's events plus the amount
     // the target length shrank by, so the grid has 1/8 headroom (a thread
     // that had to take a second pop would double the kernel's latency)
-    const uint32_t blocks = (pkt_events + pkt_events / 8 + 127) / 128;
-    return launch_timed(k_pop_blur, dim3(blocks), dim3(128), st, tm.start, tm.stop, s, pkt_events,
+    const uint32_t blocks = (pkt_events + pkt_events / 8 + kPopBlock - 1) / kPopBlock;
+    return launch_timed(k_pop_blur, dim3(blocks), dim3(kPopBlock), st, tm.start, tm.stop, s, pkt_events,
                         step, slot);
 }
 
