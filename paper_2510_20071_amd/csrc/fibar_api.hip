@@ -73,10 +73,8 @@ void free_ctx(fibar_ctx* c)
     if (!c) return;
     if (c->st) (void)hipStreamSynchronize(c->st);
     else (void)hipDeviceSynchronize();
-    (void)hipFree(c->s.pbar);
-    (void)hipFree(c->s.Lp);
-    (void)hipFree(c->s.last);
-    (void)hipFree(c->s.cnt);
+    (void)hipFree(c->s.px);
+    (void)hipFree(c->s.pp);
     (void)hipFree(c->s.ring);
     (void)hipFree(c->s.sc);
     (void)hipFree(c->d_chunks);
@@ -400,10 +398,7 @@ hipError_t init_state(fibar_ctx* c)
     c->h_sc->err = 0;
     c->h_sc->pad = 0;
     c->cur_slot = 0;
-    hipError_t e = hipMemsetAsync(c->s.pbar, 0, c->npx * 4, c->st);
-    if (e == hipSuccess) e = hipMemsetAsync(c->s.Lp, 0, c->npx * 8, c->st);
-    if (e == hipSuccess) e = hipMemsetAsync(c->s.last, 0xff, c->npx * 8, c->st);   // -1
-    if (e == hipSuccess) e = hipMemsetAsync(c->s.cnt, 0, c->npx * 4, c->st);
+    hipError_t e = launch_init_state(c->s, c->st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->s.sc + c->cur_slot, c->h_sc, sizeof(DevScalars), hipMemcpyHostToDevice,
                            c->st);
@@ -498,10 +493,8 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
     auto alloc = [&](void** ptr, size_t bytes) {
         if (e == hipSuccess) e = hipMalloc(ptr, bytes);
     };
-    alloc((void**)&c->s.pbar, npx * 4);
-    alloc((void**)&c->s.Lp, npx * 8);
-    alloc((void**)&c->s.last, npx * 8);
-    alloc((void**)&c->s.cnt, npx * 4);
+    alloc((void**)&c->s.px, npx * sizeof(PixL));
+    alloc((void**)&c->s.pp, npx * sizeof(PixP));
     alloc((void**)&c->s.ring, ring * 4);
     alloc((void**)&c->s.sc, 2 * sizeof(DevScalars));
     alloc((void**)&c->d_chunks, kMaxBatchChunks * sizeof(ChunkDesc));

@@ -74,13 +74,24 @@ struct StepScratch {
                                      // stale pixels, deactivated tiles
 };
 
+// Per-pixel state, in two arrays of structures so that what one kernel
+// needs of a pixel comes in one load: the window kernels read brightness and
+// last-event index together (the 3x3 blur reads both for every neighbour),
+// and only the filter update reads pbar and the queued-event count.
+struct alignas(16) PixL {
+    float L;        // brightness of active / never-seen pixels
+    float Lb;       // brightness of stale pixels (their one-time blur)
+    int64_t last;   // index of the newest event (-1: none)
+};
+struct alignas(8) PixP {
+    float pbar;     // low-passed polarity
+    uint32_t cnt;   // events of the pixel in the window
+};
+
 // Device pointers of one context's state.
 struct State {
-    float* pbar;
-    float2* Lp;       // .x: brightness of active / never-seen pixels,
-                      // .y: brightness of stale pixels (their one-time blur)
-    int64_t* last;
-    uint32_t* cnt;
+    PixL* px;
+    PixP* pp;
     uint32_t* ring;
     uint64_t ring_mask;
     DevScalars* sc;   // two slots; see the commit scheme in fibar_kernels.hip
@@ -159,6 +170,9 @@ hipError_t launch_apply(const State& s, const ChunkDesc* d_chunk, const SegRec* 
 
 hipError_t launch_pop_blur(const State& s, uint32_t pkt_events, StepScratch* step, int slot,
                            hipStream_t st, const LaunchTiming& tm = LaunchTiming());
+
+// Initial per-pixel state: zero brightness and polarity, no events.
+hipError_t launch_init_state(const State& s, hipStream_t st);
 
 hipError_t launch_commit(const State& s, const StepScratch* prev, uint32_t prev_events,
                          int slot_in, int slot_out, int spatial, hipStream_t st);

@@ -9,7 +9,8 @@
 // the second runs packet by packet (k_apply, then k_pop_blur).
 //
 // Blurred values of stale pixels live in a second image Lb (stored next to
-// L, as Lp[i] = (L, Lb)): a pixel's current brightness is Lb[i] when it is
+// L and the last-event index, px[i] = (L, Lb, last)): a pixel's current
+// brightness is Lb[i] when it is
 // stale (its newest event has left the window, last[i] < h) and L[i]
 // otherwise.  The pop kernel of a step
 // writes only Lb of the pixels that go stale in that step and reads
@@ -145,6 +146,24 @@ __global__ __launch_bounds__(kPopBlock) void k_pop_blur(State s, uint32_t pkt_ev
     add_counts(step, 2, dP, dT);
 }
 
+// Initial per-pixel state.
+__global__ __launch_bounds__(256) void k_init_state(State s)
+{
+    const uint64_t npx = (uint64_t)s.W * s.H;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < npx; i += stride) {
+        PixL v;
+        v.L = 0.f;
+        v.Lb = 0.f;
+        v.last = -1;
+        s.px[i] = v;
+        PixP p;
+        p.pbar = 0.f;
+        p.cnt = 0u;
+        s.pp[i] = p;
+    }
+}
+
 // Commit a pending step into the other slot (one thread).
 __global__ void k_commit(State s, const StepScratch* prev, uint32_t prev_events, int slot_in,
                          int slot_out, int spatial)
@@ -209,6 +228,16 @@ hipError_t launch_pop_blur(const State& s, uint32_t pkt_events, StepScratch* ste
     const uint32_t blocks = (pkt_events + pkt_events / 8 + kPopBlock - 1) / kPopBlock;
     return launch_timed(k_pop_blur, dim3(blocks), dim3(kPopBlock), st, tm.start, tm.stop, s, pkt_events,
                         step, slot);
+}
+
+hipError_t launch_init_state(const State& s, hipStream_t st)
+{
+    const uint64_t npx = (uint64_t)s.W * s.H;
+    uint64_t blocks = (npx + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_init_state, dim3((uint32_t)blocks), dim3(256), 0, st, s);
+    return hipGetLastError();
 }
 
 hipError_t launch_commit(const State& s, const StepScratch* prev, uint32_t prev_events,

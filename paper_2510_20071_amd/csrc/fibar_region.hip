@@ -272,9 +272,10 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
     float pb = 0.f, l = 0.f;
     int64_t last = -1;
     if (own) {
-        pb = s.pbar[gp];
-        l = s.Lp[gp].x;
-        last = s.last[gp];
+        const PixL v = s.px[gp];
+        pb = s.pp[gp].pbar;
+        l = v.L;
+        last = v.last;
     }
     const uint64_t lo = rb.base[r], hi = rb.base[r + 1];
     for (uint32_t i = t; i < n_readouts; i += kSortThreads) {
@@ -355,9 +356,9 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
     }
     while (next_ro < n_readouts) write_readout(next_ro++);
     if (own) {
-        s.pbar[gp] = pb;
-        s.Lp[gp].x = l;
-        s.last[gp] = last;
+        s.pp[gp].pbar = pb;
+        s.px[gp].L = l;
+        s.px[gp].last = last;
     }
 }
 

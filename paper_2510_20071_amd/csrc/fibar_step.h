@@ -178,12 +178,12 @@ __device__ __forceinline__ Group load_group(const ChunkDesc& cd, const SegRec* _
     g.prev_key = i > 0 ? pk : 0xffffffffu;
 #pragma unroll
     for (int q = 0; q < 4; ++q) g.r[q] = seg[i + q];
-    g.ex = 0u;
-    g.ey = 0u;
-    if (spatial && i < cd.n) {
-        g.ex = cd.x[i];
-        g.ey = cd.y[i];
-    }
+    // unconditional too (the chunk holds at least one event): a load under a
+    // branch leaves the kernel-argument loads pending at the join, and the
+    // next use of one then waits for every outstanding scalar load
+    const uint32_t e = i < cd.n ? i : 0u;
+    g.ex = cd.x[e];
+    g.ey = cd.y[e];
     return g;
 }
 
@@ -198,10 +198,11 @@ struct TileIn {
     bool head;               // first record of its tile
     bool same[4];            // records i .. i + 3 belong to the tile
     uint32_t pix[4];
-    int64_t lq[4];           // last-event index of the tile's quads
-    float pb[4];
-    float2 lp[4];
-    uint32_t cn[4];
+    int64_t qlast[4];        // last-event index of the tile's four quads
+    float L[4], Lb[4];       // the records' pixels
+    int64_t last[4];
+    float pbar[4];
+    uint32_t cnt[4];
 };
 
 __device__ __forceinline__ TileIn load_tile(const State& s, const Group& g, uint32_t i)
@@ -224,13 +225,17 @@ __device__ __forceinline__ TileIn load_tile(const State& s, const Group& g, uint
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const uint32_t p = base + (q & 1) + (q >> 1) * s.W;
-        ti.lq[q] = s.last[p < npx ? p : 0u];
+        ti.qlast[q] = s.px[p < npx ? p : 0u].last;
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        ti.pb[k] = s.pbar[ti.pix[k]];
-        ti.lp[k] = s.Lp[ti.pix[k]];
-        ti.cn[k] = s.cnt[ti.pix[k]];
+        const PixL v = s.px[ti.pix[k]];
+        ti.L[k] = v.L;
+        ti.Lb[k] = v.Lb;
+        ti.last[k] = v.last;
+        const PixP w = s.pp[ti.pix[k]];
+        ti.pbar[k] = w.pbar;
+        ti.cnt[k] = w.cnt;
     }
     return ti;
 }
@@ -248,35 +253,33 @@ __device__ __forceinline__ void apply_tile(const State& s, const Group& g, const
     const uint32_t t = g.r[0].key >> 2;
     const uint32_t ty = t / s.TW, tx = t - ty * s.TW;
     const bool has_x1 = 2 * tx + 1 < s.W, has_y1 = 2 * ty + 1 < s.H;
-    int64_t lq[4];
     bool tile_was_active = false;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const bool ok = (!(q & 1) || has_x1) && (!(q & 2) || has_y1);
-        lq[q] = ok ? ti.lq[q] : -1;
-        tile_was_active |= lq[q] >= (int64_t)h0;
+        tile_was_active |= ok && ti.qlast[q] >= (int64_t)h0;
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         if (!ti.same[k] || i + k >= nseg) continue;
         const SegRec& r = g.r[k];
         const uint32_t px = ti.pix[k];
-        float l = ti.lp[k].x;
-        if (spatial) {
-            const uint32_t q = r.key & 3u;
-            const int64_t last_old = q == 3 ? lq[3] : q == 2 ? lq[2] : q == 1 ? lq[1] : lq[0];
-            // a stale (or never seen) pixel's current value is its blurred one
-            if (last_old < (int64_t)h0) {
-                l = ti.lp[k].y;
-                dP += 1u;
-            }
+        float l = ti.L[k];
+        // a stale (or never seen) pixel's current value is its blurred one
+        if (spatial && ti.last[k] < (int64_t)h0) {
+            l = ti.Lb[k];
+            dP += 1u;
         }
-        s.pbar[px] = fmaf(r.a, ti.pb[k], r.u1);
-        float2 o = ti.lp[k];
-        o.x = fmaf(r.g, ti.pb[k], fmaf(r.b, l, r.u2));
-        s.Lp[px] = o;
-        s.last[px] = (int64_t)(first + (r.n_last & 0xffffu));
-        if (spatial) s.cnt[px] = ti.cn[k] + (r.n_last >> 16);
+        const float pb = ti.pbar[k];
+        PixL o;
+        o.L = fmaf(r.g, pb, fmaf(r.b, l, r.u2));
+        o.Lb = ti.Lb[k];
+        o.last = (int64_t)(first + (r.n_last & 0xffffu));
+        s.px[px] = o;
+        PixP op;
+        op.pbar = fmaf(r.a, pb, r.u1);
+        op.cnt = spatial ? ti.cnt[k] + (r.n_last >> 16) : ti.cnt[k];
+        s.pp[px] = op;
     }
     if (spatial && !tile_was_active) dT += 1u;
 }
@@ -296,7 +299,7 @@ __device__ __forceinline__ void scalars_after_loads(HeadIn& h, uint32_t& status,
 
 // Pops j = start, start + stride, ... below h_new.  A pixel goes stale when
 // its newest event leaves the window, i.e. exactly when the popped j is its
-// last index; it then gets its blurred value in Lp.y, computed from the image
+// last index; it then gets its blurred value in Lb, computed from the image
 // as it was before this step's blurs.  Its 2x2 tile goes inactive when no
 // pixel of the tile has a newer event: the pixel with the largest last
 // index of the tile (unique, and popped in this same step) counts it.  The
@@ -311,39 +314,35 @@ __device__ __forceinline__ void pop_range(const State& s, uint64_t start, uint64
         const uint32_t y = pix / s.W, x = pix - y * s.W;
         const uint32_t xs[3] = {x > 0 ? x - 1 : 0, x, x + 1 < s.W ? x + 1 : s.W - 1};
         const uint32_t ys[3] = {y > 0 ? y - 1 : 0, y, y + 1 < s.H ? y + 1 : s.H - 1};
-        int64_t lst[3][3];
-        float2 lp[3][3];
+        PixL nb[3][3];
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const size_t q = (size_t)ys[a] * s.W + xs[b];
-                lst[a][b] = s.last[q];
-                lp[a][b] = s.Lp[q];
-            }
-        atomicSub(&s.cnt[pix], 1u);
-        if (lst[1][1] != (int64_t)j) continue;
+            for (int b = 0; b < 3; ++b) nb[a][b] = s.px[(size_t)ys[a] * s.W + xs[b]];
+        atomicSub(&s.pp[pix].cnt, 1u);
+        if (nb[1][1].last != (int64_t)j) continue;
         ++dP;
         float c[3][3];
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
             for (int b = 0; b < 3; ++b)
-                c[a][b] = lst[a][b] < (int64_t)h_old ? lp[a][b].y : lp[a][b].x;
+                c[a][b] = nb[a][b].last < (int64_t)h_old ? nb[a][b].Lb : nb[a][b].L;
         // 3x3 binomial blur, clamp-to-edge, fixed summation order
         const float r0 = c[0][0] + 2.f * c[0][1] + c[0][2];
         const float r1 = c[1][0] + 2.f * c[1][1] + c[1][2];
         const float r2 = c[2][0] + 2.f * c[2][1] + c[2][2];
-        s.Lp[pix].y = (r0 + 2.f * r1 + r2) * 0.0625f;
+        s.px[pix].Lb = (r0 + 2.f * r1 + r2) * 0.0625f;
         // the tile's other pixels: column x ^ 1 and row y ^ 1, where they
         // exist (selected with fixed indices: a register array indexed at run
         // time would be moved to memory)
         const bool ox = x & 1u, oy = y & 1u;
         const bool hx = ox || x + 1 < s.W, hy = oy || y + 1 < s.H;
-        const int64_t lx = ox ? lst[1][0] : lst[1][2];
-        const int64_t ly = oy ? lst[0][1] : lst[2][1];
-        const int64_t lxy = oy ? (ox ? lst[0][0] : lst[0][2]) : (ox ? lst[2][0] : lst[2][2]);
-        const int64_t me = lst[1][1];
+        const int64_t lx = ox ? nb[1][0].last : nb[1][2].last;
+        const int64_t ly = oy ? nb[0][1].last : nb[2][1].last;
+        const int64_t lxy = oy ? (ox ? nb[0][0].last : nb[0][2].last)
+                               : (ox ? nb[2][0].last : nb[2][2].last);
+        const int64_t me = nb[1][1].last;
         const bool newest = !(hx && lx > me) && !(hy && ly > me) && !(hx && hy && lxy > me);
         if (newest) ++dT;
     }
@@ -369,7 +368,7 @@ __device__ __forceinline__ uint32_t tile_active_pixels(const State& s, uint64_t 
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const uint32_t px = 2 * tx + (q & 1), py = 2 * ty + (q >> 1);
-        if (px < s.W && py < s.H && s.last[(size_t)py * s.W + px] >= h) ++n;
+        if (px < s.W && py < s.H && s.px[(size_t)py * s.W + px].last >= h) ++n;
     }
     return n;
 }
@@ -379,15 +378,14 @@ __device__ __forceinline__ void readout_pixel(const State& s, int spatial, int64
                                               uint64_t i, float* L, float* pbar, uint8_t* stale,
                                               uint32_t* cnt, int64_t* last, float* log_age)
 {
-    int64_t li = 0;
-    if (spatial || last || log_age) li = s.last[i];
-    const float2 lp = s.Lp[i];
-    L[i] = (spatial && li < h) ? lp.y : lp.x;
-    if (pbar) pbar[i] = s.pbar[i];
+    const PixL v = s.px[i];
+    const int64_t li = v.last;
+    L[i] = (spatial && li < h) ? v.Lb : v.L;
+    if (pbar) pbar[i] = s.pp[i].pbar;
     if (last) last[i] = li;
     if (log_age) log_age[i] = log1pf((float)(k - li));
     if (spatial) {
-        if (cnt) cnt[i] = s.cnt[i];
+        if (cnt) cnt[i] = s.pp[i].cnt;
         if (stale) stale[i] = (li >= 0 && li < h) ? 1u : 0u;
     }
 }
