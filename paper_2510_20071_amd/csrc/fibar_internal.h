@@ -64,14 +64,15 @@ struct DevScalars {
 };
 
 // Per-packet scratch of one batch (zeroed at the start of the batch).
-// Counters are spread over kSpread addresses (picked by workgroup index) so
-// that atomics of different workgroups rarely meet on one address.
+// Counters are spread over kSpread cache lines (picked by workgroup index)
+// so that atomics of different workgroups rarely meet on one line.
 constexpr int kSpread = 8;
-struct StepScratch {
+constexpr int kLineWords = 32;       // 128-byte cache line
+struct alignas(128) StepScratch {
     uint32_t status;                 // validation bits: 1 = range, 2 = polarity
-    uint32_t pad[3];
-    uint32_t part[kSpread][4];       // activated pixels, activated tiles,
-                                     // stale pixels, deactivated tiles
+    uint32_t pad[kLineWords - 1];
+    uint32_t part[kSpread][kLineWords];   // [0..3]: activated pixels, activated
+                                          // tiles, stale pixels, deactivated tiles
 };
 
 // Per-pixel state, in two arrays of structures so that what one kernel
