@@ -98,25 +98,39 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_compose(
 // ---------------------------------------------------------------------------
 
 // Apply one chunk's compositions to the state; push the chunk's events to
-// the back of the window (spatial filter); count activations.  The last
-// workgroup only commits the previous step's scalars.
-__global__ __launch_bounds__(kApplyBlock) void k_apply(State s, ChunkDesc cd, const SegRec* __restrict__ seg,
-                                               const uint32_t* __restrict__ seg_count,
-                                               uint32_t chunk_offset, StepScratch* step,
-                                               const StepScratch* prev, uint32_t prev_events,
-                                               int slot_in, int slot_out, int spatial)
+// the back of the window (spatial filter); count activations.  Workgroup 0
+// only commits the previous step's scalars (sc_in -> sc_out).
+//
+// The values the first loads need lead the argument list, so that they
+// arrive in preloaded scalar registers; nothing before the record loads
+// waits for another argument (the workgroup size is a constant and the
+// commit workgroup is found without the grid size).  n_prev holds the
+// chunk's event count and, in bit 31, whether a step is pending; a pending
+// step's scratch is the one before this step's.
+constexpr uint32_t kPendingBit = 1u << 31;
+
+__global__ __launch_bounds__(kApplyBlock) void k_apply(
+    const SegRec* __restrict__ seg, const uint32_t* __restrict__ seg_count, StepScratch* step,
+    const DevScalars* sc_in, const uint16_t* ex, const uint16_t* ey, uint32_t n_prev, State s,
+    uint32_t chunk_offset, uint32_t prev_events, DevScalars* sc_out, int spatial)
 {
-    if (blockIdx.x == gridDim.x - 1) {
-        if (prev && slot_out >= 0 && threadIdx.x == 0)
-            s.sc[slot_out] = commit_step(s.sc[slot_in], prev, prev_events, s, spatial);
+    const StepScratch* prev = (n_prev & kPendingBit) ? step - 1 : nullptr;
+    const uint32_t n = n_prev & ~kPendingBit;
+    if (blockIdx.x == 0) {
+        if (prev && sc_out && threadIdx.x == 0)
+            *sc_out = commit_step(*sc_in, prev, prev_events, s, spatial);
         return;
     }
     // every load that needs only the arguments is issued before any is used
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t i = (blockIdx.x - 1) * kApplyBlock + threadIdx.x;
+    ChunkDesc cd;
+    cd.x = ex;
+    cd.y = ey;
+    cd.n = n;
     const Group g = load_group(cd, seg, i, spatial);
     uint32_t status = step->status;
     uint32_t nseg = *seg_count;
-    HeadIn hin = load_head(s, slot_in, prev);
+    HeadIn hin = load_head(sc_in, prev);
     FIBAR_ISSUE_FENCE();
     const TileIn ti = load_tile(s, g, i);
     scalars_after_loads(hin, status, nseg);
@@ -131,18 +145,26 @@ __global__ __launch_bounds__(kApplyBlock) void k_apply(State s, ChunkDesc cd, co
 
 // Move the window head by the target of the previous step (Eq. (20)),
 // detect pixels whose last queued event leaves the window, and write their
-// blurred values to Lb.  `slot` holds the scalars after the previous step.
-__global__ __launch_bounds__(kPopBlock) void k_pop_blur(State s, uint32_t pkt_events, StepScratch* step,
-                                                  int slot)
+// blurred values to Lb.  `sc` holds the scalars after the previous step.
+// Leading arguments as in k_apply; `stride` is the grid's thread count.
+__global__ __launch_bounds__(kPopBlock) void k_pop_blur(const DevScalars* sc, StepScratch* step,
+                                                        const uint32_t* ring, uint64_t ring_mask,
+                                                        PixL* px, uint32_t W, uint32_t H,
+                                                        uint32_t pkt_events, uint32_t stride,
+                                                        State s)
 {
     // the status and the scalars are loaded together (a select, not a branch)
     const uint32_t status = step->status;
     uint64_t h_old, h_new;
-    pop_bounds(s.sc[slot], pkt_events, &h_old, &h_new);
+    pop_bounds(*sc, pkt_events, &h_old, &h_new);
     if (status) h_new = h_old;   // a rejected packet pops nothing
+    s.ring = const_cast<uint32_t*>(ring);
+    s.ring_mask = ring_mask;
+    s.px = px;
+    s.W = W;
+    s.H = H;
     uint32_t dP = 0u, dT = 0u;
-    pop_range(s, h_old + blockIdx.x * blockDim.x + threadIdx.x, h_new,
-              (uint64_t)gridDim.x * blockDim.x, h_old, dP, dT);
+    pop_range(s, h_old + blockIdx.x * kPopBlock + threadIdx.x, h_new, stride, h_old, dP, dT);
     add_counts(step, 2, dP, dT);
 }
 
@@ -212,11 +234,15 @@ hipError_t launch_apply(const State& s, const ChunkDesc* d_chunk, const SegRec* 
                         int slot_in, int slot_out, int spatial, hipStream_t st,
                         const LaunchTiming& tm)
 {
-    // one extra workgroup commits the previous step's scalars
+    // one extra workgroup (the first) commits the previous step's scalars
+    if (prev && prev != step - 1) return hipErrorInvalidValue;   // scratch layout
+    if (chunk_events == 0 || chunk_events > (uint32_t)kChunk) return hipErrorInvalidValue;
     const uint32_t blocks = (chunk_events + kApplyBlock - 1) / kApplyBlock + 1;
-    return launch_timed(k_apply, dim3(blocks), dim3(kApplyBlock), st, tm.start, tm.stop, s, *d_chunk, seg,
-                        seg_count, chunk_offset, step, prev, prev_events, slot_in, slot_out,
-                        spatial);
+    DevScalars* sc_out = slot_out >= 0 ? s.sc + slot_out : nullptr;
+    return launch_timed(k_apply, dim3(blocks), dim3(kApplyBlock), st, tm.start, tm.stop, seg,
+                        seg_count, step, (const DevScalars*)(s.sc + slot_in), d_chunk->x,
+                        d_chunk->y, chunk_events | (prev ? kPendingBit : 0u), s, chunk_offset,
+                        prev_events, sc_out, spatial);
 }
 
 hipError_t launch_pop_blur(const State& s, uint32_t pkt_events, StepScratch* step, int slot,
@@ -226,8 +252,9 @@ hipError_t launch_pop_blur(const State& s, uint32_t pkt_events, StepScratch* ste
     // the target length shrank by, so the grid has 1/8 headroom (a thread
     // that had to take a second pop would double the kernel's latency)
     const uint32_t blocks = (pkt_events + pkt_events / 8 + kPopBlock - 1) / kPopBlock;
-    return launch_timed(k_pop_blur, dim3(blocks), dim3(kPopBlock), st, tm.start, tm.stop, s, pkt_events,
-                        step, slot);
+    return launch_timed(k_pop_blur, dim3(blocks), dim3(kPopBlock), st, tm.start, tm.stop,
+                        (const DevScalars*)(s.sc + slot), step, (const uint32_t*)s.ring,
+                        s.ring_mask, s.px, s.W, s.H, pkt_events, blocks * kPopBlock, s);
 }
 
 hipError_t launch_init_state(const State& s, hipStream_t st)

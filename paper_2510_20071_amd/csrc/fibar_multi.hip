@@ -156,7 +156,7 @@ __global__ __launch_bounds__(256) void k_multi_apply(MultiArgs a, const StreamSt
         const Group g = load_group(cd, e->seg[sub], i, 1);
         const uint32_t status = stp->status;
         const uint32_t nseg = *e->nseg[sub];
-        const HeadIn hin = load_head(s, e->slot_in, prev);
+        const HeadIn hin = load_head(s.sc + e->slot_in, prev);
         FIBAR_ISSUE_FENCE();
         const TileIn ti = load_tile(s, g, i);
         FIBAR_ISSUE_FENCE();

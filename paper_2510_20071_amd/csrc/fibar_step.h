@@ -111,9 +111,9 @@ struct HeadIn {
     bool pending;
 };
 
-__device__ __forceinline__ HeadIn load_head(const State& s, int slot_in, const StepScratch* prev)
+__device__ __forceinline__ HeadIn load_head(const DevScalars* sc_in, const StepScratch* prev)
 {
-    const DevScalars& c = s.sc[slot_in];
+    const DevScalars& c = *sc_in;
     HeadIn r;
     r.k = c.k;
     r.h = c.h;
@@ -138,7 +138,7 @@ __device__ __forceinline__ void current_head(const State& s, int slot_in, const 
                                              uint32_t prev_events, int spatial, int64_t* k,
                                              uint64_t* h)
 {
-    head_after(load_head(s, slot_in, prev), prev_events, spatial, k, h);
+    head_after(load_head(s.sc + slot_in, prev), prev_events, spatial, k, h);
 }
 
 // Window head before and after the pops of a step whose packet has
