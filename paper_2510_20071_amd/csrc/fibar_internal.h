@@ -154,6 +154,26 @@ hipError_t launch_region_batch(const State& s, int slot, const ChunkDesc* d_chun
                                uint32_t n_readouts, int key_bits, Coef coef, hipStream_t st,
                                const LaunchTiming& tm = LaunchTiming());
 
+// ---- in-order path (fibar_kernels.hip) -----------------------------------
+// Workgroup sizes of the in-order kernels (on the 1280x720 stream with
+// 16384-event packets, 64- and 256-thread workgroups were both slower).
+constexpr uint32_t kApplyBlock = 128;
+constexpr uint32_t kPopBlock = 128;
+
+// Threads of a step's pop launch: one pop each.  A step pops its packet's
+// events plus the amount the target length shrank by, so the grid has 1/8
+// headroom (a thread that had to take a second pop would double the
+// kernel's latency).
+inline __host__ __device__ uint32_t pop_threads(uint32_t pkt_events)
+{
+    return (pkt_events + pkt_events / 8 + kPopBlock - 1) / kPopBlock * kPopBlock;
+}
+
+// Pop list: for a packet of one chunk, the apply launch copies the pixels of
+// the events its step will pop (the first pop_threads(n) of the window) so
+// that the pop launch starts from them without waiting for the window head.
+constexpr uint32_t kPopListMax = (kChunk + kChunk / 8 + kPopBlock - 1) / kPopBlock * kPopBlock;
+
 // ---- launchers (fibar_kernels.hip) ---------------------------------------
 hipError_t launch_sort_compose(const ChunkDesc* d_chunks, uint32_t n_chunks, SegRec* seg,
                                uint32_t* seg_count, StepScratch* scratch, uint32_t W,
@@ -162,15 +182,20 @@ hipError_t launch_sort_compose(const ChunkDesc* d_chunks, uint32_t n_chunks, Seg
 
 // In-order launches.  `slot_in` holds the last committed scalars; when
 // `prev` is not null the step it describes (with `prev_events` events) is
-// committed on top of them, and the result is written to `slot_out`.
+// committed on top of them, and the result is written to `slot_out`.  With
+// pop_copy > 0 (a one-chunk packet) the apply launch also fills
+// pop_list[0, pop_copy) for the pop launch of its step, which then gets the
+// same pop_list and pop_copy.
 hipError_t launch_apply(const State& s, const ChunkDesc* d_chunk, const SegRec* seg,
                         const uint32_t* seg_count, uint32_t chunk_events,
                         uint32_t chunk_offset, StepScratch* step, const StepScratch* prev,
                         uint32_t prev_events, int slot_in, int slot_out, int spatial,
-                        hipStream_t st, const LaunchTiming& tm = LaunchTiming());
+                        uint32_t* pop_list, uint32_t pop_copy, hipStream_t st,
+                        const LaunchTiming& tm = LaunchTiming());
 
 hipError_t launch_pop_blur(const State& s, uint32_t pkt_events, StepScratch* step, int slot,
-                           hipStream_t st, const LaunchTiming& tm = LaunchTiming());
+                           const uint32_t* pop_list, uint32_t pop_copy, hipStream_t st,
+                           const LaunchTiming& tm = LaunchTiming());
 
 // Initial per-pixel state: zero brightness and polarity, no events.
 hipError_t launch_init_state(const State& s, hipStream_t st);

@@ -29,10 +29,6 @@ namespace {
 using namespace tile;
 using namespace step;
 
-// Workgroup sizes of the in-order kernels (on the 1280x720 stream with
-// 16384-event packets, 64- and 256-thread workgroups were both slower).
-constexpr uint32_t kApplyBlock = 128;
-constexpr uint32_t kPopBlock = 128;
 
 // ---------------------------------------------------------------------------
 // Bulk kernel: validate, stable LDS radix sort by pixel, segmented scan of
@@ -112,7 +108,8 @@ constexpr uint32_t kPendingBit = 1u << 31;
 __global__ __launch_bounds__(kApplyBlock) void k_apply(
     const SegRec* __restrict__ seg, const uint32_t* __restrict__ seg_count, StepScratch* step,
     const DevScalars* sc_in, const uint16_t* ex, const uint16_t* ey, uint32_t n_prev, State s,
-    uint32_t chunk_offset, uint32_t prev_events, DevScalars* sc_out, int spatial)
+    uint32_t chunk_offset, uint32_t prev_events, DevScalars* sc_out, int spatial,
+    uint32_t* __restrict__ pop_list, uint32_t pop_copy)
 {
     const StepScratch* prev = (n_prev & kPendingBit) ? step - 1 : nullptr;
     const uint32_t n = n_prev & ~kPendingBit;
@@ -127,7 +124,9 @@ __global__ __launch_bounds__(kApplyBlock) void k_apply(
     cd.x = ex;
     cd.y = ey;
     cd.n = n;
-    const Group g = load_group(cd, seg, i, spatial);
+    // the grid may reach past the chunk's record slot (pop-list copies); such
+    // items read the slot's last records and apply nothing (i >= n >= nseg)
+    const Group g = load_group(cd, seg, i < (uint32_t)kChunk ? i : kChunk - 1, spatial);
     uint32_t status = step->status;
     uint32_t nseg = *seg_count;
     HeadIn hin = load_head(sc_in, prev);
@@ -138,8 +137,22 @@ __global__ __launch_bounds__(kApplyBlock) void k_apply(
     uint64_t h0;
     head_after(hin, prev_events, spatial, &k0, &h0);
     const uint64_t first = (uint64_t)(k0 + 1) + chunk_offset;
+    // pop list: the pixel of window event h0 + i, from the ring if an earlier
+    // launch pushed it, else from this chunk's events (the ring cannot hold
+    // both in one slot: it is longer than the window plus a packet)
+    uint32_t pl = 0u;
+    if (i < pop_copy) {
+        const uint64_t p = h0 + i;
+        if (p < first) {
+            pl = s.ring[p & s.ring_mask];
+        } else if (p - first < n) {
+            const uint32_t e = (uint32_t)(p - first);
+            pl = (uint32_t)ey[e] * s.W + ex[e];
+        }
+    }
     uint32_t dP = 0u, dT = 0u;
     apply_tile(s, g, ti, cd.n, nseg, status != 0, i, first, h0, spatial, dP, dT);
+    if (i < pop_copy) pop_list[i] = pl;
     if (spatial) add_counts(step, 0, dP, dT);
 }
 
@@ -147,24 +160,51 @@ __global__ __launch_bounds__(kApplyBlock) void k_apply(
 // detect pixels whose last queued event leaves the window, and write their
 // blurred values to Lb.  `sc` holds the scalars after the previous step.
 // Leading arguments as in k_apply; `stride` is the grid's thread count.
-__global__ __launch_bounds__(kPopBlock) void k_pop_blur(const DevScalars* sc, StepScratch* step,
-                                                        const uint32_t* ring, uint64_t ring_mask,
+// With pop_copy (= the grid's thread count) every thread takes its first
+// pixel from the pop list, which needs no scalar; otherwise, and in later
+// rounds, pixels come from the ring.
+__global__ __launch_bounds__(kPopBlock) void k_pop_blur(const uint32_t* __restrict__ pop_list,
+                                                        const DevScalars* sc, StepScratch* step,
                                                         PixL* px, uint32_t W, uint32_t H,
-                                                        uint32_t pkt_events, uint32_t stride,
-                                                        State s)
+                                                        uint32_t pkt_events, uint32_t pop_copy,
+                                                        const uint32_t* ring, uint64_t ring_mask,
+                                                        uint32_t stride, State s)
 {
-    // the status and the scalars are loaded together (a select, not a branch)
-    const uint32_t status = step->status;
-    uint64_t h_old, h_new;
-    pop_bounds(*sc, pkt_events, &h_old, &h_new);
-    if (status) h_new = h_old;   // a rejected packet pops nothing
+    const uint32_t t = blockIdx.x * kPopBlock + threadIdx.x;
     s.ring = const_cast<uint32_t*>(ring);
     s.ring_mask = ring_mask;
     s.px = px;
     s.W = W;
     s.H = H;
     uint32_t dP = 0u, dT = 0u;
-    pop_range(s, h_old + blockIdx.x * kPopBlock + threadIdx.x, h_new, stride, h_old, dP, dT);
+    uint64_t h_old, h_new;
+    if (pop_copy) {
+        // every thread has a listed pixel: its neighbourhood is loaded first,
+        // then the window scalars, whose latency overlaps it (entries past the
+        // step's pops, or of a rejected packet, are clamped into the image and
+        // not used)
+        const uint32_t listed = pop_list[t];
+        const uint32_t npx = W * H;
+        const uint32_t pix = listed < npx ? listed : 0u;
+        PixL nb[3][3];
+        load_pop(s, pix, nb);
+        FIBAR_ISSUE_FENCE();
+        const uint32_t status = step->status;
+        pop_bounds(*sc, pkt_events, &h_old, &h_new);
+        if (status) h_new = h_old;   // a rejected packet pops nothing
+        const uint64_t j0 = h_old + t;
+        if (j0 < h_new) {
+            decide_pop(s, j0, pix, nb, h_old, dP, dT);
+            pop_range(s, j0 + stride, h_new, stride, h_old, dP, dT);
+        }
+    } else {
+        // the status and the scalars are loaded together (a select, not a
+        // branch)
+        const uint32_t status = step->status;
+        pop_bounds(*sc, pkt_events, &h_old, &h_new);
+        if (status) h_new = h_old;
+        pop_range(s, h_old + t, h_new, stride, h_old, dP, dT);
+    }
     add_counts(step, 2, dP, dT);
 }
 
@@ -231,30 +271,34 @@ hipError_t launch_sort_compose(const ChunkDesc* d_chunks, uint32_t n_chunks, Seg
 hipError_t launch_apply(const State& s, const ChunkDesc* d_chunk, const SegRec* seg,
                         const uint32_t* seg_count, uint32_t chunk_events, uint32_t chunk_offset,
                         StepScratch* step, const StepScratch* prev, uint32_t prev_events,
-                        int slot_in, int slot_out, int spatial, hipStream_t st,
-                        const LaunchTiming& tm)
+                        int slot_in, int slot_out, int spatial, uint32_t* pop_list,
+                        uint32_t pop_copy, hipStream_t st, const LaunchTiming& tm)
 {
     // one extra workgroup (the first) commits the previous step's scalars
     if (prev && prev != step - 1) return hipErrorInvalidValue;   // scratch layout
     if (chunk_events == 0 || chunk_events > (uint32_t)kChunk) return hipErrorInvalidValue;
-    const uint32_t blocks = (chunk_events + kApplyBlock - 1) / kApplyBlock + 1;
+    if (pop_copy > kPopListMax || (pop_copy && !pop_list)) return hipErrorInvalidValue;
+    const uint32_t items = chunk_events > pop_copy ? chunk_events : pop_copy;
+    const uint32_t blocks = (items + kApplyBlock - 1) / kApplyBlock + 1;
     DevScalars* sc_out = slot_out >= 0 ? s.sc + slot_out : nullptr;
     return launch_timed(k_apply, dim3(blocks), dim3(kApplyBlock), st, tm.start, tm.stop, seg,
                         seg_count, step, (const DevScalars*)(s.sc + slot_in), d_chunk->x,
                         d_chunk->y, chunk_events | (prev ? kPendingBit : 0u), s, chunk_offset,
-                        prev_events, sc_out, spatial);
+                        prev_events, sc_out, spatial, pop_list, pop_copy);
 }
 
 hipError_t launch_pop_blur(const State& s, uint32_t pkt_events, StepScratch* step, int slot,
-                           hipStream_t st, const LaunchTiming& tm)
+                           const uint32_t* pop_list, uint32_t pop_copy, hipStream_t st,
+                           const LaunchTiming& tm)
 {
-    // one pop per thread: a step pops its packet's events plus the amount
-    // the target length shrank by, so the grid has 1/8 headroom (a thread
-    // that had to take a second pop would double the kernel's latency)
-    const uint32_t blocks = (pkt_events + pkt_events / 8 + kPopBlock - 1) / kPopBlock;
-    return launch_timed(k_pop_blur, dim3(blocks), dim3(kPopBlock), st, tm.start, tm.stop,
-                        (const DevScalars*)(s.sc + slot), step, (const uint32_t*)s.ring,
-                        s.ring_mask, s.px, s.W, s.H, pkt_events, blocks * kPopBlock, s);
+    const uint32_t threads = pop_threads(pkt_events);
+    // the kernel takes every thread's first pixel from the list, or none
+    if (threads == 0 || (pop_copy != 0 && (pop_copy != threads || !pop_list)))
+        return hipErrorInvalidValue;
+    return launch_timed(k_pop_blur, dim3(threads / kPopBlock), dim3(kPopBlock), st, tm.start,
+                        tm.stop, pop_list, (const DevScalars*)(s.sc + slot), step, s.px, s.W,
+                        s.H, pkt_events, pop_copy, (const uint32_t*)s.ring, s.ring_mask, threads,
+                        s);
 }
 
 hipError_t launch_init_state(const State& s, hipStream_t st)

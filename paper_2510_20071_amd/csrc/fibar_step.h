@@ -297,7 +297,7 @@ __device__ __forceinline__ void scalars_after_loads(HeadIn& h, uint32_t& status,
                  "+s"(nseg)::"memory");
 }
 
-// Pops j = start, start + stride, ... below h_new.  A pixel goes stale when
+// Pop event j (at pixel pix).  A pixel goes stale when
 // its newest event leaves the window, i.e. exactly when the popped j is its
 // last index; it then gets its blurred value in Lb, computed from the image
 // as it was before this step's blurs.  Its 2x2 tile goes inactive when no
@@ -305,47 +305,69 @@ __device__ __forceinline__ void scalars_after_loads(HeadIn& h, uint32_t& status,
 // index of the tile (unique, and popped in this same step) counts it.  The
 // whole 3x3 neighbourhood (which holds the tile) is loaded for every pop,
 // before the decision; the count update needs no result.
+// In two parts, so that a kernel can issue the neighbourhood loads before
+// it waits for the window head: load_pop, then decide_pop.  The caller owns
+// the neighbourhood array (a struct returned by value ended up in scratch
+// memory).
+__device__ __forceinline__ void load_pop(const State& s, uint32_t pix, PixL (&nb)[3][3])
+{
+    const uint32_t y = pix / s.W, x = pix - y * s.W;
+    const uint32_t xs[3] = {x > 0 ? x - 1 : 0, x, x + 1 < s.W ? x + 1 : s.W - 1};
+    const uint32_t ys[3] = {y > 0 ? y - 1 : 0, y, y + 1 < s.H ? y + 1 : s.H - 1};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) nb[a][b] = s.px[(size_t)ys[a] * s.W + xs[b]];
+}
+
+__device__ __forceinline__ void decide_pop(const State& s, uint64_t j, uint32_t pix,
+                                           const PixL (&nb)[3][3], uint64_t h_old, uint32_t& dP,
+                                           uint32_t& dT)
+{
+    const uint32_t y = pix / s.W, x = pix - y * s.W;
+    atomicSub(&s.pp[pix].cnt, 1u);
+    if (nb[1][1].last != (int64_t)j) return;
+    ++dP;
+    float c[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            c[a][b] = nb[a][b].last < (int64_t)h_old ? nb[a][b].Lb : nb[a][b].L;
+    // 3x3 binomial blur, clamp-to-edge, fixed summation order
+    const float r0 = c[0][0] + 2.f * c[0][1] + c[0][2];
+    const float r1 = c[1][0] + 2.f * c[1][1] + c[1][2];
+    const float r2 = c[2][0] + 2.f * c[2][1] + c[2][2];
+    s.px[pix].Lb = (r0 + 2.f * r1 + r2) * 0.0625f;
+    // the tile's other pixels: column x ^ 1 and row y ^ 1, where they
+    // exist (selected with fixed indices: a register array indexed at run
+    // time would be moved to memory)
+    const bool ox = x & 1u, oy = y & 1u;
+    const bool hx = ox || x + 1 < s.W, hy = oy || y + 1 < s.H;
+    const int64_t lx = ox ? nb[1][0].last : nb[1][2].last;
+    const int64_t ly = oy ? nb[0][1].last : nb[2][1].last;
+    const int64_t lxy = oy ? (ox ? nb[0][0].last : nb[0][2].last)
+                           : (ox ? nb[2][0].last : nb[2][2].last);
+    const int64_t me = nb[1][1].last;
+    const bool newest = !(hx && lx > me) && !(hy && ly > me) && !(hx && hy && lxy > me);
+    if (newest) ++dT;
+}
+
+__device__ __forceinline__ void pop_one(const State& s, uint64_t j, uint32_t pix, uint64_t h_old,
+                                        uint32_t& dP, uint32_t& dT)
+{
+    PixL nb[3][3];
+    load_pop(s, pix, nb);
+    decide_pop(s, j, pix, nb, h_old, dP, dT);
+}
+
+// Pops j = start, start + stride, ... below h_new, pixels from the ring.
 __device__ __forceinline__ void pop_range(const State& s, uint64_t start, uint64_t h_new,
                                           uint64_t stride, uint64_t h_old, uint32_t& dP,
                                           uint32_t& dT)
 {
-    for (uint64_t j = start; j < h_new; j += stride) {
-        const uint32_t pix = s.ring[j & s.ring_mask];
-        const uint32_t y = pix / s.W, x = pix - y * s.W;
-        const uint32_t xs[3] = {x > 0 ? x - 1 : 0, x, x + 1 < s.W ? x + 1 : s.W - 1};
-        const uint32_t ys[3] = {y > 0 ? y - 1 : 0, y, y + 1 < s.H ? y + 1 : s.H - 1};
-        PixL nb[3][3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) nb[a][b] = s.px[(size_t)ys[a] * s.W + xs[b]];
-        atomicSub(&s.pp[pix].cnt, 1u);
-        if (nb[1][1].last != (int64_t)j) continue;
-        ++dP;
-        float c[3][3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b)
-                c[a][b] = nb[a][b].last < (int64_t)h_old ? nb[a][b].Lb : nb[a][b].L;
-        // 3x3 binomial blur, clamp-to-edge, fixed summation order
-        const float r0 = c[0][0] + 2.f * c[0][1] + c[0][2];
-        const float r1 = c[1][0] + 2.f * c[1][1] + c[1][2];
-        const float r2 = c[2][0] + 2.f * c[2][1] + c[2][2];
-        s.px[pix].Lb = (r0 + 2.f * r1 + r2) * 0.0625f;
-        // the tile's other pixels: column x ^ 1 and row y ^ 1, where they
-        // exist (selected with fixed indices: a register array indexed at run
-        // time would be moved to memory)
-        const bool ox = x & 1u, oy = y & 1u;
-        const bool hx = ox || x + 1 < s.W, hy = oy || y + 1 < s.H;
-        const int64_t lx = ox ? nb[1][0].last : nb[1][2].last;
-        const int64_t ly = oy ? nb[0][1].last : nb[2][1].last;
-        const int64_t lxy = oy ? (ox ? nb[0][0].last : nb[0][2].last)
-                               : (ox ? nb[2][0].last : nb[2][2].last);
-        const int64_t me = nb[1][1].last;
-        const bool newest = !(hx && lx > me) && !(hy && ly > me) && !(hx && hy && lxy > me);
-        if (newest) ++dT;
-    }
+    for (uint64_t j = start; j < h_new; j += stride)
+        pop_one(s, j, s.ring[j & s.ring_mask], h_old, dP, dT);
 }
 
 // Add a workgroup's activation (slot 0, 1) or deactivation (slot 2, 3)
