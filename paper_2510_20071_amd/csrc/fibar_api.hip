@@ -276,9 +276,23 @@ int run_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, uint32_t
         if (pend) c->cur_slot ^= 1;
         if (sp) {
             const int slot = c->cur_slot;
-            HIP_TRY(timed_launch(c, 2, [&](const LaunchTiming& tm) {
-                return launch_pop_blur(c->s, nev, stp, slot, c->pop_list, pop_copy, c->st, tm);
-            }));
+            // a device readout right after the step (without the window
+            // count, which the pops change) is taken by the pop launch
+            const bool fuse = i + 1 < n && ops[i + 1].kind == 1 && ops[i + 1].ro.on_device &&
+                              !ops[i + 1].ro.active_count;
+            if (fuse) {
+                const fibar_readout_buf& rb = ops[i + 1].ro;
+                PopReadout pr{rb.brightness, rb.pbar,     rb.stale_mask,
+                              rb.last_index, rb.log_age, rb.tile_count};
+                HIP_TRY(launch_pop_blur(c->s, nev, stp, slot, c->pop_list, pop_copy, &pr,
+                                        c->st));
+                ++i;   // the readout op is done
+            } else {
+                HIP_TRY(timed_launch(c, 2, [&](const LaunchTiming& tm) {
+                    return launch_pop_blur(c->s, nev, stp, slot, c->pop_list, pop_copy, nullptr,
+                                           c->st, tm);
+                }));
+            }
         }
         pend = stp;
         pend_n = nev;

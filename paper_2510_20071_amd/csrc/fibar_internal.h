@@ -159,6 +159,10 @@ hipError_t launch_region_batch(const State& s, int slot, const ChunkDesc* d_chun
 // 16384-event packets, 64- and 256-thread workgroups were both slower).
 constexpr uint32_t kApplyBlock = 128;
 constexpr uint32_t kPopBlock = 128;
+// Pixels per thread of the readout workgroups of a pop launch (1, 2, 4, 8:
+// 1 was fastest on the 1280x720 stream) and their largest number.
+constexpr uint32_t kReadoutPerThread = 1;
+constexpr uint32_t kReadoutMaxBlocks = 16384;
 
 // Threads of a step's pop launch: one pop each.  A step pops its packet's
 // events plus the amount the target length shrank by, so the grid has 1/8
@@ -193,9 +197,21 @@ hipError_t launch_apply(const State& s, const ChunkDesc* d_chunk, const SegRec* 
                         uint32_t* pop_list, uint32_t pop_copy, hipStream_t st,
                         const LaunchTiming& tm = LaunchTiming());
 
+// Outputs of a readout taken in the pop launch of the step before it (any
+// may be null but L; no window count: the pops change it).
+struct PopReadout {
+    float* L;
+    float* pbar;
+    uint8_t* stale;
+    int64_t* last;
+    float* log_age;
+    uint32_t* tcnt;
+};
+
+// With `ro` the launch also writes the readout of the state after the step.
 hipError_t launch_pop_blur(const State& s, uint32_t pkt_events, StepScratch* step, int slot,
-                           const uint32_t* pop_list, uint32_t pop_copy, hipStream_t st,
-                           const LaunchTiming& tm = LaunchTiming());
+                           const uint32_t* pop_list, uint32_t pop_copy, const PopReadout* ro,
+                           hipStream_t st, const LaunchTiming& tm = LaunchTiming());
 
 // Initial per-pixel state: zero brightness and polarity, no events.
 hipError_t launch_init_state(const State& s, hipStream_t st);

@@ -168,14 +168,49 @@ __global__ __launch_bounds__(kPopBlock) void k_pop_blur(const uint32_t* __restri
                                                         PixL* px, uint32_t W, uint32_t H,
                                                         uint32_t pkt_events, uint32_t pop_copy,
                                                         const uint32_t* ring, uint64_t ring_mask,
-                                                        uint32_t stride, State s)
+                                                        uint32_t stride, State s, PopReadout ro,
+                                                        uint32_t pop_blocks)
 {
-    const uint32_t t = blockIdx.x * kPopBlock + threadIdx.x;
     s.ring = const_cast<uint32_t*>(ring);
     s.ring_mask = ring_mask;
     s.px = px;
     s.W = W;
     s.H = H;
+    if (blockIdx.x >= pop_blocks) {
+        // workgroups past the pops read out the state after the step; what
+        // they read is not written by the pops (see readout_pixel_after_pops)
+        const uint32_t status = step->status;
+        const DevScalars c = *sc;
+        uint64_t h_old, h_new;
+        pop_bounds(c, pkt_events, &h_old, &h_new);
+        if (status) h_new = h_old;
+        const int64_t k = status ? c.k : c.k + (int64_t)pkt_events;
+        const uint64_t npx = (uint64_t)W * H;
+        const uint64_t rstride = (uint64_t)(gridDim.x - pop_blocks) * kPopBlock;
+        const uint64_t r0 = (uint64_t)(blockIdx.x - pop_blocks) * kPopBlock + threadIdx.x;
+        // kReadoutPerThread pixels per thread, all loaded before any is used
+        for (uint64_t base = r0; base < npx; base += kReadoutPerThread * rstride) {
+            PixL v[kReadoutPerThread];
+#pragma unroll
+            for (uint32_t q = 0; q < kReadoutPerThread; ++q) {
+                const uint64_t i = base + q * rstride;
+                v[q] = s.px[i < npx ? i : 0];
+            }
+#pragma unroll
+            for (uint32_t q = 0; q < kReadoutPerThread; ++q) {
+                const uint64_t i = base + q * rstride;
+                if (i < npx)
+                    readout_pixel_after_pops(s, k, h_old, h_new, i, v[q], ro.L, ro.pbar,
+                                             ro.stale, ro.last, ro.log_age);
+            }
+        }
+        if (ro.tcnt) {
+            const uint64_t nt = (uint64_t)s.TW * ((H + 1) / 2);
+            for (uint64_t t = r0; t < nt; t += rstride) ro.tcnt[t] = tile_active_pixels(s, t, h_new);
+        }
+        return;
+    }
+    const uint32_t t = blockIdx.x * kPopBlock + threadIdx.x;
     uint32_t dP = 0u, dT = 0u;
     uint64_t h_old, h_new;
     if (pop_copy) {
@@ -288,17 +323,29 @@ hipError_t launch_apply(const State& s, const ChunkDesc* d_chunk, const SegRec* 
 }
 
 hipError_t launch_pop_blur(const State& s, uint32_t pkt_events, StepScratch* step, int slot,
-                           const uint32_t* pop_list, uint32_t pop_copy, hipStream_t st,
-                           const LaunchTiming& tm)
+                           const uint32_t* pop_list, uint32_t pop_copy, const PopReadout* ro,
+                           hipStream_t st, const LaunchTiming& tm)
 {
     const uint32_t threads = pop_threads(pkt_events);
     // the kernel takes every thread's first pixel from the list, or none
     if (threads == 0 || (pop_copy != 0 && (pop_copy != threads || !pop_list)))
         return hipErrorInvalidValue;
-    return launch_timed(k_pop_blur, dim3(threads / kPopBlock), dim3(kPopBlock), st, tm.start,
+    if (ro && !ro->L) return hipErrorInvalidValue;
+    const uint32_t pop_blocks = threads / kPopBlock;
+    uint32_t ro_blocks = 0;
+    PopReadout r{};
+    if (ro) {
+        // kReadoutPerThread pixels per thread; the pop workgroups come first
+        const uint64_t npx = (uint64_t)s.W * s.H;
+        const uint64_t per = (uint64_t)kReadoutPerThread * kPopBlock;
+        const uint64_t b = (npx + per - 1) / per;
+        ro_blocks = (uint32_t)(b < kReadoutMaxBlocks ? (b > 0 ? b : 1) : kReadoutMaxBlocks);
+        r = *ro;
+    }
+    return launch_timed(k_pop_blur, dim3(pop_blocks + ro_blocks), dim3(kPopBlock), st, tm.start,
                         tm.stop, pop_list, (const DevScalars*)(s.sc + slot), step, s.px, s.W,
                         s.H, pkt_events, pop_copy, (const uint32_t*)s.ring, s.ring_mask, threads,
-                        s);
+                        s, r, pop_blocks);
 }
 
 hipError_t launch_init_state(const State& s, hipStream_t st)

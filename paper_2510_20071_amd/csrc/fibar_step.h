@@ -320,6 +320,24 @@ __device__ __forceinline__ void load_pop(const State& s, uint32_t pix, PixL (&nb
         for (int b = 0; b < 3; ++b) nb[a][b] = s.px[(size_t)ys[a] * s.W + xs[b]];
 }
 
+// Blurred value of a pixel going stale in a step whose pops start at h_old:
+// 3x3 binomial, clamp-to-edge, fixed summation order, over the image before
+// the step's blurs (a neighbour's current value is Lb if it was stale
+// before the step, else L).  It reads nothing the step's pops write.
+__device__ __forceinline__ float stale_blur(const PixL (&nb)[3][3], uint64_t h_old)
+{
+    float c[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            c[a][b] = nb[a][b].last < (int64_t)h_old ? nb[a][b].Lb : nb[a][b].L;
+    const float r0 = c[0][0] + 2.f * c[0][1] + c[0][2];
+    const float r1 = c[1][0] + 2.f * c[1][1] + c[1][2];
+    const float r2 = c[2][0] + 2.f * c[2][1] + c[2][2];
+    return (r0 + 2.f * r1 + r2) * 0.0625f;
+}
+
 __device__ __forceinline__ void decide_pop(const State& s, uint64_t j, uint32_t pix,
                                            const PixL (&nb)[3][3], uint64_t h_old, uint32_t& dP,
                                            uint32_t& dT)
@@ -328,17 +346,7 @@ __device__ __forceinline__ void decide_pop(const State& s, uint64_t j, uint32_t 
     atomicSub(&s.pp[pix].cnt, 1u);
     if (nb[1][1].last != (int64_t)j) return;
     ++dP;
-    float c[3][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b)
-            c[a][b] = nb[a][b].last < (int64_t)h_old ? nb[a][b].Lb : nb[a][b].L;
-    // 3x3 binomial blur, clamp-to-edge, fixed summation order
-    const float r0 = c[0][0] + 2.f * c[0][1] + c[0][2];
-    const float r1 = c[1][0] + 2.f * c[1][1] + c[1][2];
-    const float r2 = c[2][0] + 2.f * c[2][1] + c[2][2];
-    s.px[pix].Lb = (r0 + 2.f * r1 + r2) * 0.0625f;
+    s.px[pix].Lb = stale_blur(nb, h_old);
     // the tile's other pixels: column x ^ 1 and row y ^ 1, where they
     // exist (selected with fixed indices: a register array indexed at run
     // time would be moved to memory)
@@ -393,6 +401,33 @@ __device__ __forceinline__ uint32_t tile_active_pixels(const State& s, uint64_t 
         if (px < s.W && py < s.H && s.px[(size_t)py * s.W + px].last >= h) ++n;
     }
     return n;
+}
+
+// Readout of pixel i after a step whose pops move the head from h_old to
+// h_new, taken while those pops run: a pixel going stale in the step
+// (h_old <= last < h_new) gets the blurred value its pop writes, computed
+// here from the same operands.  Every output but the window count (which
+// the pops decrement) is available this way.
+__device__ __forceinline__ void readout_pixel_after_pops(const State& s, int64_t k, uint64_t h_old,
+                                                         uint64_t h_new, uint64_t i, const PixL& v,
+                                                         float* L, float* pbar, uint8_t* stale,
+                                                         int64_t* last, float* log_age)
+{
+    const int64_t li = v.last;
+    float val = v.L;
+    if (li < (int64_t)h_new) {
+        val = v.Lb;
+        if (li >= (int64_t)h_old) {
+            PixL nb[3][3];
+            load_pop(s, (uint32_t)i, nb);
+            val = stale_blur(nb, h_old);
+        }
+    }
+    L[i] = val;
+    if (pbar) pbar[i] = s.pp[i].pbar;
+    if (last) last[i] = li;
+    if (log_age) log_age[i] = log1pf((float)(k - li));
+    if (stale) stale[i] = (li >= 0 && li < (int64_t)h_new) ? 1u : 0u;
 }
 
 // Readout of pixel i given the newest index k and window head h.

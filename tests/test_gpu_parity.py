@@ -250,6 +250,69 @@ def test_submit_equals_single_calls_and_device_readouts():
     c2.close()
 
 
+def test_readouts_taken_by_the_pop_launch():
+    """Blur on: a device readout right after a push, without the window count,
+    is written by the pop launch of that push (its own workgroups compute the
+    blurred value of pixels going stale in the step).  It must equal a
+    separate readout bit for bit and match the oracle; a second readout right
+    after the first takes the separate kernel."""
+    torch, dev = torch_dev()
+    W, H = 640, 480
+    npx, ntiles = W * H, ((W + 1) // 2) * ((H + 1) // 2)
+    w = eventsim.preset("vga", n_events=400_000, seed=11)
+    ev = eventsim.generate(w.scene)
+    gx, gy, gp = to_device(ev)
+    ro = [1, 4096, 50_001, 123_456, 250_000, 400_000]
+    sched = eventsim.schedule(len(ev), w.packet, ro)
+    # per-call pushes and host readouts (the separate readout kernel)
+    c1 = make_ctx(W, H)
+    ref = []
+    for it in sched:
+        if it[0] == "push":
+            assert c1.push(gx[it[1]:it[2]], gy[it[1]:it[2]], gp[it[1]:it[2]]) == 0
+        else:
+            ref.append((it[1], c1.readout_host(0)))
+    # one submit; every readout doubled: the first of a pair is fused
+    c2 = make_ctx(W, H)
+    ops, bufs = [], []
+    for it in sched:
+        if it[0] == "push":
+            ops.append(fb.push_op(gx[it[1]:it[2]], gy[it[1]:it[2]], gp[it[1]:it[2]]))
+            continue
+        for _ in range(2):
+            b = dict(L=torch.empty(npx, dtype=torch.float32, device=dev),
+                     pbar=torch.empty(npx, dtype=torch.float32, device=dev),
+                     stale=torch.empty(npx, dtype=torch.uint8, device=dev),
+                     last=torch.empty(npx, dtype=torch.int64, device=dev),
+                     log_age=torch.empty(npx, dtype=torch.float32, device=dev),
+                     tcnt=torch.empty(ntiles, dtype=torch.int32, device=dev))
+            bufs.append(b)
+            ops.append(fb.readout_op(0, b["L"], pbar=b["pbar"], stale=b["stale"], last=b["last"],
+                                     log_age=b["log_age"], tcnt=b["tcnt"]))
+    assert c2.submit(ops) == 0
+    torch.cuda.synchronize()
+    assert len(bufs) == 2 * len(ref)
+    orc = oracle.Oracle(W, H)
+    n = 0
+    for it in sched:
+        if it[0] == "push":
+            assert orc.push(ev.x[it[1]:it[2]], ev.y[it[1]:it[2]], ev.p[it[1]:it[2]]) == 0
+            continue
+        k, r = ref[n]
+        for b in bufs[2 * n:2 * n + 2]:
+            g = {key: v.cpu().numpy() for key, v in b.items()}
+            for key in ("L", "pbar", "stale", "last", "log_age"):
+                assert np.array_equal(g[key], r[key]), "%s at %d" % (key, k)
+            assert np.array_equal(g["tcnt"].view(np.uint32), r["tcnt"]), "tcnt at %d" % k
+        o = orc.readout(0)
+        compare_state(r, o, True, "readout at %d" % k)
+        assert np.array_equal(g["stale"], o["stale"]) and np.array_equal(g["last"], o["last"])
+        n += 1
+    assert c2.stats()["k"] == len(ev) - 1
+    c1.close()
+    c2.close()
+
+
 def test_nsf_rejects_spatial_outputs():
     ctx = make_ctx(32, 16, spatial_filter=False, q_min=1)
     npx = 32 * 16
