@@ -313,6 +313,59 @@ def test_readouts_taken_by_the_pop_launch():
     c2.close()
 
 
+def test_pop_launch_readouts_after_rejected_and_multi_chunk_packets():
+    """Readouts written by the pop launch after (i) a packet of several
+    chunks (its pops take pixels from the ring), (ii) a rejected packet (it
+    pops nothing and must leave the readout equal to the one before)."""
+    torch, dev = torch_dev()
+    W, H = 640, 480
+    npx, ntiles = W * H, (W // 2) * (H // 2)
+    w = eventsim.preset("vga", n_events=120_000, seed=13)
+    ev = eventsim.generate(w.scene)
+    gx, gy, gp = to_device(ev)
+    bad = gx[100_000:101_000].clone()
+    bad[5] = W                              # x == width: the packet is rejected
+    ctx = make_ctx(W, H)
+    ops, bufs = [], []
+
+    def readout():
+        b = dict(L=torch.empty(npx, dtype=torch.float32, device=dev),
+                 pbar=torch.empty(npx, dtype=torch.float32, device=dev),
+                 stale=torch.empty(npx, dtype=torch.uint8, device=dev),
+                 last=torch.empty(npx, dtype=torch.int64, device=dev),
+                 tcnt=torch.empty(ntiles, dtype=torch.int32, device=dev))
+        bufs.append(b)
+        ops.append(fb.readout_op(0, b["L"], pbar=b["pbar"], stale=b["stale"], last=b["last"],
+                                 tcnt=b["tcnt"]))
+
+    ops.append(fb.push_op(gx[:50_000], gy[:50_000], gp[:50_000]))        # four chunks
+    readout()
+    ops.append(fb.push_op(gx[50_000:100_000], gy[50_000:100_000], gp[50_000:100_000]))
+    readout()
+    ops.append(fb.push_op(bad, gy[100_000:101_000], gp[100_000:101_000]))
+    readout()
+    ops.append(fb.push_op(gx[100_000:], gy[100_000:], gp[100_000:]))
+    readout()
+    assert ctx.submit(ops) == 0
+    assert ctx.synchronize() == fb.FIBAR_E_RANGE
+    g = [{k: v.cpu().numpy() for k, v in b.items()} for b in bufs]
+    for key in g[1]:
+        assert np.array_equal(g[1][key], g[2][key]), "rejected packet changed " + key
+    orc = oracle.Oracle(W, H)
+    want = []
+    for a, b in ((0, 50_000), (50_000, 100_000), (100_000, len(ev))):
+        assert orc.push(ev.x[a:b], ev.y[a:b], ev.p[a:b]) == 0
+        want.append(orc.readout(0))
+    for gi, r in zip((g[0], g[1], g[3]), want):
+        assert np.array_equal(gi["last"], r["last"])
+        assert np.array_equal(gi["stale"], r["stale"])
+        assert np.array_equal(gi["tcnt"].view(np.uint32), r["tcnt"])
+        for key in ("L", "pbar"):
+            d = np.abs(gi[key].astype(np.float64) - r[key])
+            assert np.all(d <= REL * np.maximum(np.abs(r[key]), 1.0)), key
+    ctx.close()
+
+
 def test_nsf_rejects_spatial_outputs():
     ctx = make_ctx(32, 16, spatial_filter=False, q_min=1)
     npx = 32 * 16
