@@ -54,6 +54,7 @@ constexpr uint32_t kUnroll = 64;                // rounds per graph replay
 constexpr uint32_t kTuneLen = 4;                // rounds per timed group while tuning
 constexpr uint32_t kTuneGroups = 3;             // timed groups per candidate shape
 constexpr uint32_t kNone = 0xffffffffu;
+constexpr uint32_t kMaxDirectGrid = 1u << 16;   // workgroups of a direct launch
 
 // Task kinds of a round: apply sub-round 0 (a stream with a pending step
 // gets one extra task, its first, that commits it), apply sub-round 1, pops.
@@ -323,20 +324,29 @@ MultiArgs multi_args(const fibar_multi* m)
 
 // Queue the kernels of `rounds` rounds with launch sequence `var` whose
 // records start at `rec` (stride S).
+// With the host copy of the records (direct launches), every launch gets one
+// workgroup per task of its round, so no workgroup takes a second task (a
+// second dependent chain); a graph's launches keep the shape's fixed grid.
 void launch_round_kernels(fibar_multi* m, const Shape& sh, const StreamStep* rec,
-                          uint32_t rounds, int var)
+                          const StreamStep* host_rec, uint32_t rounds, int var)
 {
     const MultiArgs a = multi_args(m);
+    auto grid = [&](uint32_t j, int kind) -> uint32_t {
+        if (!host_rec) return sh.grid;
+        const StreamStep& last = host_rec[(size_t)j * m->n + (m->n - 1)];
+        const uint32_t tasks = kind < kKinds ? last.end[kind] : host_rec[(size_t)j * m->n].ro_cnt;
+        return std::min<uint32_t>(std::max<uint32_t>(tasks, 1u), kMaxDirectGrid);
+    };
     for (uint32_t j = 0; j < rounds; ++j) {
         const StreamStep* rr = rec + (size_t)j * m->n;
-        hipLaunchKernelGGL(k_multi_apply, dim3(sh.grid), dim3(sh.block), 0, m->st, a, rr, 0);
+        hipLaunchKernelGGL(k_multi_apply, dim3(grid(j, 0)), dim3(sh.block), 0, m->st, a, rr, 0);
         if (var & 1)
-            hipLaunchKernelGGL(k_multi_apply, dim3(sh.grid), dim3(sh.block), 0, m->st, a, rr, 1);
-        hipLaunchKernelGGL(k_multi_pop, dim3(sh.grid), dim3(sh.block), 0, m->st, a, rr);
+            hipLaunchKernelGGL(k_multi_apply, dim3(grid(j, 1)), dim3(sh.block), 0, m->st, a, rr, 1);
+        hipLaunchKernelGGL(k_multi_pop, dim3(grid(j, 2)), dim3(sh.block), 0, m->st, a, rr);
     }
     if (var & 2)
-        hipLaunchKernelGGL(k_multi_readout, dim3(sh.grid), dim3(sh.block), 0, m->st, a,
-                           rec + (size_t)(rounds - 1) * m->n);
+        hipLaunchKernelGGL(k_multi_readout, dim3(grid(rounds - 1, kKinds)), dim3(sh.block), 0,
+                           m->st, a, rec + (size_t)(rounds - 1) * m->n);
 }
 
 // The launches of a graph: stage the records, the rounds on the ring, advance.
@@ -345,7 +355,7 @@ hipError_t launch_rounds(fibar_multi* m, const Shape& sh, uint32_t rounds, int v
     const uint32_t n16 = (uint32_t)(rounds * m->n * sizeof(StreamStep) / 16);
     hipLaunchKernelGGL(k_multi_stage, dim3(std::min<uint32_t>(64, (n16 + 255) / 256)), dim3(256), 0,
                        m->st, m->d_rec, m->d_ring, m->base, m->n, n16);
-    launch_round_kernels(m, sh, m->d_ring, rounds, var);
+    launch_round_kernels(m, sh, m->d_ring, nullptr, rounds, var);
     hipLaunchKernelGGL(k_multi_advance, dim3(1), dim3(64), 0, m->st, m->base, rounds);
     return hipGetLastError();
 }
@@ -615,7 +625,8 @@ int run_multi_batch(fibar_multi* m, std::vector<StreamPlan>& plans, bool* done)
         } else {
             // direct launches; a later graph's first round index moves past
             // these rounds too
-            launch_round_kernels(m, kShapes[g.shape], m->d_rec + (size_t)g.r0 * S, g.len, g.var);
+            launch_round_kernels(m, kShapes[g.shape], m->d_rec + (size_t)g.r0 * S,
+                                 m->h_rec + (size_t)g.r0 * S, g.len, g.var);
             if ((int)q < last_graph)
                 hipLaunchKernelGGL(k_multi_advance, dim3(1), dim3(64), 0, m->st, m->base, g.len);
             HIP_TRY(hipGetLastError());
