@@ -171,7 +171,9 @@ int fibar_readout(fibar_ctx* c, uint64_t t, const fibar_readout_buf* out);
  * A list of operations executed in order, with the same results as calling
  * fibar_push_events / fibar_readout one by one.  Executing them together lets
  * the library group and compose the events of many packets in one parallel
- * pass before applying them in order.  Host readouts inside a list do not
+ * pass before applying them in order, and lets a device readout that directly
+ * follows a push (and asks for no window counts) be written by that push's
+ * last launch, with identical results.  Host readouts inside a list do not
  * report pending device-side packet errors (the next fibar_synchronize does).
  * Execution stops at the first error the host detects, which is returned;
  * the operations before it have been carried out.
@@ -221,8 +223,9 @@ int fibar_reset(fibar_ctx* c);
  * fibar_kernel_time() synchronises the context's stream, returns the summed
  * duration (ms) and the count of the launches of kernel `kernel` timed since
  * the last call, and clears them.  Kernels: 0 group+compose (bulk; the whole
- * blur-off batch in that mode), 1 apply, 2 window pop + stale blur values,
- * 3 (unused), 4 readout.
+ * blur-off batch in that mode), 1 apply, 2 window pop + stale blur values
+ * (launches that also write a readout are not timed), 3 (unused), 4 readout
+ * (the separate readout kernel).
  */
 int fibar_set_kernel_timing(fibar_ctx* c, uint32_t kernel_mask, uint32_t every);
 int fibar_kernel_time(fibar_ctx* c, int kernel, double* total_ms, uint64_t* launches);
