@@ -132,6 +132,54 @@ def test_hd720_twenty_million_events():
     run_pair(ev, 1280, 720, sched, check_every_read=25)
 
 
+def test_hd720_benchmark_stream_as_submitted():
+    """The benchmark's stream as bench.py submits it: 1280x720, 100 M events,
+    16384-event packets, 1000 brightness-only device readouts at random event
+    indices, all in one submit (so most readouts are written by the pop
+    launch of the push before them).  Sampled frames and the final state
+    against the FP64 oracle."""
+    torch, dev = torch_dev()
+    W, H = 1280, 720
+    npx = W * H
+    w = eventsim.preset("hd720")
+    ev = eventsim.generate(w.scene)
+    sched = eventsim.schedule(len(ev), w.packet, w.readouts)
+    n_read = sum(1 for it in sched if it[0] == "read")
+    flush("hd720 %d events, %d readouts in one submit" % (len(ev), n_read))
+    sample = sorted({0, 1, n_read // 3, n_read // 2, n_read - 2, n_read - 1})
+    gx, gy, gp = to_device(ev)
+    scratch = torch.empty(npx, dtype=torch.float32, device=dev)
+    frames = {i: torch.empty(npx, dtype=torch.float32, device=dev) for i in sample}
+    ops, r = [], 0
+    for it in sched:
+        if it[0] == "push":
+            ops.append(fb.push_op(gx[it[1]:it[2]], gy[it[1]:it[2]], gp[it[1]:it[2]]))
+        else:
+            ops.append(fb.readout_op(0, frames.get(r, scratch)))
+            r += 1
+    ctx = make_ctx(W, H, max_packet=w.packet)
+    assert ctx.submit(ops) == 0
+    assert ctx.synchronize() == 0
+    got = {i: f.cpu().numpy() for i, f in frames.items()}
+    final = ctx.readout_host(0)
+    orc = oracle.Oracle(W, H)
+    r = 0
+    for it in sched:
+        if it[0] == "push":
+            assert orc.push(ev.x[it[1]:it[2]], ev.y[it[1]:it[2]], ev.p[it[1]:it[2]]) == 0
+            continue
+        if r in got:
+            ref = orc.readout(0)["L"]
+            d = np.abs(got[r].astype(np.float64) - ref)
+            assert np.all(d <= REL * np.maximum(np.abs(ref), 1.0)), \
+                "frame %d: worst %.3g" % (r, d.max())
+        r += 1
+    compare_state(final, orc.readout(0), True, "end of the benchmark stream")
+    compare_stats(ctx.stats(), orc.stats())
+    flush("hd720 benchmark stream: %d sampled frames and the final state match" % len(got))
+    ctx.close()
+
+
 def test_empty_push_and_repeated_readout_change_nothing():
     w = eventsim.preset("sensor64x48", n_events=30000)
     ev = eventsim.generate(w.scene)
