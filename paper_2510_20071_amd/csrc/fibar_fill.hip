@@ -34,6 +34,7 @@ constexpr int kGradBlocks = 256;                // workgroups of a weight gradie
 constexpr int kWgEntries = kTaps * kC * kC + kC;   // one layer's (w, b) gradient, padded
 constexpr int kLossBlocks = 256;
 constexpr int kPairs = 5;                       // taps in pairs for the K = 32 products
+constexpr int kPairs0 = 2;                      // K = 32 products of the first layer
 
 __host__ __device__ constexpr int cin_of(int l) { return l == 0 ? 3 : 16; }
 __host__ __device__ constexpr int cout_of(int l) { return l == 3 ? 1 : 16; }
@@ -84,8 +85,19 @@ __global__ __launch_bounds__(64) void k_fill_pack_weights(const float* __restric
     wb[(l * kTaps + t) * 64 + lane] = b;
     if (t == 0 && lane < kC) bias[l * kC + lane] = lane < co ? prm[b_off(l) + lane] : 0.f;
     // K = 32 operands of tap pairs (2q, 2q + 1), q = t < 5: lane group g takes
-    // tap 2q + g / 2, input channels 8 (g % 2) + j, j = 0..7; tap 9 is zero
-    if (t < kPairs) {
+    // tap 2q + g / 2, input channels 8 (g % 2) + j, j = 0..7; tap 9 is zero.
+    // The first layer (3 input channels) instead packs 4 channels per tap:
+    // operand q < 2, lane group g takes taps 8q + 2g + j / 4, channel j % 4.
+    if (l == 0 && t < kPairs0) {
+        const int g = lane >> 4, o = lane & 15;
+        uint16_t h[8];
+        for (int j = 0; j < 8; ++j) {
+            const int tap = 8 * t + 2 * g + j / 4, c = j % 4;
+            h[j] = (tap < kTaps && o < co && c < ci) ? to_bf16(w[(o * ci + c) * kTaps + tap]) : 0;
+        }
+        wk[t * 64 + lane] = make_uint4(h[0] | (uint32_t)h[1] << 16, h[2] | (uint32_t)h[3] << 16,
+                                       h[4] | (uint32_t)h[5] << 16, h[6] | (uint32_t)h[7] << 16);
+    } else if (l > 0 && t < kPairs) {
         const int g = lane >> 4, tap = 2 * t + (g >> 1), o = lane & 15;
         uint16_t h[8];
         for (int j = 0; j < 8; ++j) {
@@ -428,9 +440,106 @@ __device__ __forceinline__ void segment_pair(const uint16_t* __restrict__ in, in
     }
 }
 
+// The first layer's two 16x16x32 products per segment: its input has 4
+// channels per pixel (L, stale, log(1 + age), 0; 8 bytes), packed 4 per tap,
+// so a lane's operand is the two taps 8q + 2g, 8q + 2g + 1 (g = lane / 16).
+__device__ __forceinline__ void segment_pair_first(const uint2* __restrict__ in4, int ra, int pa,
+                                                   int rb, int pb, bool two, uint32_t lane,
+                                                   const bf16x8* b, f32x4& acc0, f32x4& acc1)
+{
+    const uint32_t g = lane >> 4;
+    bf16x8 a0[kPairs0], a1[kPairs0];
+#pragma unroll
+    for (int q = 0; q < kPairs0; ++q) {
+        uint2 u0[2], u1[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int tap = 8 * q + 2 * (int)g + h;
+            const int dr = tap / 3 - 1, dc = tap % 3 - 1;
+            u0[h] = make_uint2(0u, 0u);
+            u1[h] = make_uint2(0u, 0u);
+            if (tap < kTaps && pa + dc < kRegW) u0[h] = in4[(ra + dr) * kRegW + pa + dc];
+            if (two && tap < kTaps && pb + dc < kRegW) u1[h] = in4[(rb + dr) * kRegW + pb + dc];
+        }
+        const uint4 w0 = make_uint4(u0[0].x, u0[0].y, u0[1].x, u0[1].y);
+        const uint4 w1 = make_uint4(u1[0].x, u1[0].y, u1[1].x, u1[1].y);
+        a0[q] = *reinterpret_cast<const bf16x8*>(&w0);
+        a1[q] = *reinterpret_cast<const bf16x8*>(&w1);
+    }
+    acc0 = f32x4{0.f, 0.f, 0.f, 0.f};
+    acc1 = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < kPairs0; ++q) {
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0[q], b[q], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[q], b[q], acc1, 0, 0, 0);
+    }
+}
+
+// One layer of a tile: 16-pixel segments of rows [k, kRegH - k), k = layer + 1,
+// two per pass (independent product chains), bias, ReLU and zero padding,
+// BF16 into the other buffer; the last layer writes L + channel 0.  The first
+// layer reads the 4-channel input in buf[1] and writes buf[0]; layer l > 0
+// reads buf[(l + 1) % 2] and writes buf[l % 2].  Ends with a barrier.
+template <bool kFirst>
+__device__ __forceinline__ void fused_layer(int layer, uint16_t (*buf)[kRegH * kRegW * kC],
+                                            const uint4* wsh, const float* bsh, const float* Lsh,
+                                            int y0, int x0, uint32_t H, uint32_t W, uint32_t lane,
+                                            uint32_t wv, float* __restrict__ pred)
+{
+    constexpr int nq = kFirst ? kPairs0 : kPairs;
+    const int kk = layer + 1;
+    const uint16_t* in = buf[(layer + 1) & 1];
+    uint16_t* out = buf[layer & 1];
+    bf16x8 b[nq];
+#pragma unroll
+    for (int q = 0; q < nq; ++q)
+        b[q] = *reinterpret_cast<const bf16x8*>(&wsh[(layer * kPairs + q) * 64 + lane]);
+    const uint32_t o = lane & 15;
+    const float bo = bsh[layer * kC + o];
+    const int nseg = (kRegH - 2 * kk) * 2;
+    for (int s0 = (int)wv; s0 < nseg; s0 += 2 * kFuseWaves) {
+        const int s1 = s0 + kFuseWaves;
+        const bool two = s1 < nseg;
+        const int ra = kk + s0 / 2, ca = kk + (s0 % 2) * 16;
+        const int rb = kk + s1 / 2, cb = kk + (s1 % 2) * 16;
+        f32x4 acc0, acc1;
+        if (kFirst)
+            segment_pair_first(reinterpret_cast<const uint2*>(buf[1]), ra, ca + (int)(lane & 15),
+                               rb, cb + (int)(lane & 15), two, lane, b, acc0, acc1);
+        else
+            segment_pair(in, ra, ca + (int)(lane & 15), rb, cb + (int)(lane & 15), two, lane, b,
+                         acc0, acc1);
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            if (half == 1 && !two) break;
+            const int r = half ? rb : ra, c0 = half ? cb : ca;
+            const f32x4 acc = half ? acc1 : acc0;
+            const int y = y0 + r;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int c = c0 + (int)(lane >> 4) * 4 + j;
+                const int x = x0 + c;
+                const bool inside = y >= 0 && y < (int)H && x >= 0 && x < (int)W;
+                float v = acc[j] + bo;
+                if (layer < kLayers - 1) {
+                    v = (inside && v > 0.f) ? v : 0.f;
+                    if (c < kRegW) out[(r * kRegW + c) * kC + o] = to_bf16(v);
+                } else if (o == 0 && inside && r >= 4 && r < 4 + kFuseH && c >= 4 &&
+                           c < 4 + kFuseW) {
+                    pred[(size_t)y * W + x] = v + Lsh[r * kRegW + c];
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
 // Persistent: workgroup w takes tiles w, w + grid, ...; the next tile's inputs
-// are loaded into registers while the current tile's layers run.
-__global__ __launch_bounds__(kFuseThreads) void k_fill_fused(const float* __restrict__ L,
+// are loaded into registers while the current tile's layers run.  The input
+// region (4 channels per pixel) sits in buf[1], which the first layer does not
+// write; the layers then go buf[0] -> buf[1] -> buf[0] -> prediction.
+// Two workgroups per CU (LDS allows two): at most 128 registers per lane.
+__global__ __launch_bounds__(kFuseThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_fill_fused(const float* __restrict__ L,
                                                              const uint8_t* __restrict__ stale,
                                                              const float* __restrict__ log_age,
                                                              const uint4* __restrict__ wk,
@@ -456,16 +565,15 @@ __global__ __launch_bounds__(kFuseThreads) void k_fill_fused(const float* __rest
     for (; tile < tiles; tile += gridDim.x) {
         const int y0 = (int)(tile / tiles_x) * kFuseH - 4;
         const int x0 = (int)(tile % tiles_x) * kFuseW - 4;
-        // input region: (L, stale, log(1 + age), 0 ...), zero outside the image
+        // input region: (L, stale, log(1 + age), 0), zero outside the image
+        uint2* in4 = reinterpret_cast<uint2*>(buf[1]);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int k = (int)threadIdx.x + q * kFuseThreads;
             if (k >= kRegH * kRegW) continue;
-            uint4* dst = reinterpret_cast<uint4*>(&buf[0][k * kC]);
-            dst[0] = make_uint4((uint32_t)to_bf16(ri.l[q]) |
+            in4[k] = make_uint2((uint32_t)to_bf16(ri.l[q]) |
                                     ((uint32_t)(ri.st[q] ? to_bf16(1.f) : 0u) << 16),
-                                (uint32_t)to_bf16(ri.age[q]), 0u, 0u);
-            dst[1] = make_uint4(0u, 0u, 0u, 0u);
+                                (uint32_t)to_bf16(ri.age[q]));
             Lsh[k] = ri.l[q];
         }
         __syncthreads();
@@ -474,50 +582,9 @@ __global__ __launch_bounds__(kFuseThreads) void k_fill_fused(const float* __rest
             load_region(ri, L, stale, log_age, (int)(next / tiles_x) * kFuseH - 4,
                         (int)(next % tiles_x) * kFuseW - 4, H, W);
 
-        for (int layer = 0; layer < kLayers; ++layer) {
-            const int kk = layer + 1;                       // rows [kk, kRegH - kk)
-            const uint16_t* in = buf[layer & 1];
-            uint16_t* out = buf[(layer & 1) ^ 1];
-            bf16x8 b[kPairs];
-#pragma unroll
-            for (int q = 0; q < kPairs; ++q)
-                b[q] = *reinterpret_cast<const bf16x8*>(&wsh[(layer * kPairs + q) * 64 + lane]);
-            const uint32_t o = lane & 15;
-            const float bo = bsh[layer * kC + o];
-            const int nseg = (kRegH - 2 * kk) * 2;
-            // two segments per pass: independent product chains
-            for (int s0 = (int)wv; s0 < nseg; s0 += 2 * kFuseWaves) {
-                const int s1 = s0 + kFuseWaves;
-                const bool two = s1 < nseg;
-                const int ra = kk + s0 / 2, ca = kk + (s0 % 2) * 16;
-                const int rb = kk + s1 / 2, cb = kk + (s1 % 2) * 16;
-                f32x4 acc0, acc1;
-                segment_pair(in, ra, ca + (int)(lane & 15), rb, cb + (int)(lane & 15), two, lane,
-                             b, acc0, acc1);
-#pragma unroll
-                for (int half = 0; half < 2; ++half) {
-                    if (half == 1 && !two) break;
-                    const int r = half ? rb : ra, c0 = half ? cb : ca;
-                    const f32x4 acc = half ? acc1 : acc0;
-                    const int y = y0 + r;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int c = c0 + (int)(lane >> 4) * 4 + j;
-                        const int x = x0 + c;
-                        const bool inside = y >= 0 && y < (int)H && x >= 0 && x < (int)W;
-                        float v = acc[j] + bo;
-                        if (layer < kLayers - 1) {
-                            v = (inside && v > 0.f) ? v : 0.f;
-                            if (c < kRegW) out[(r * kRegW + c) * kC + o] = to_bf16(v);
-                        } else if (o == 0 && inside && r >= 4 && r < 4 + kFuseH && c >= 4 &&
-                                   c < 4 + kFuseW) {
-                            pred[(size_t)y * W + x] = v + Lsh[r * kRegW + c];
-                        }
-                    }
-                }
-            }
-            __syncthreads();
-        }
+        fused_layer<true>(0, buf, wsh, bsh, Lsh, y0, x0, H, W, lane, wv, pred);
+        for (int layer = 1; layer < kLayers; ++layer)
+            fused_layer<false>(layer, buf, wsh, bsh, Lsh, y0, x0, H, W, lane, wv, pred);
     }
 }
 
