@@ -97,7 +97,18 @@ __global__ __launch_bounds__(64) void k_fill_pack_weights(const float* __restric
         }
         wk[t * 64 + lane] = make_uint4(h[0] | (uint32_t)h[1] << 16, h[2] | (uint32_t)h[3] << 16,
                                        h[4] | (uint32_t)h[5] << 16, h[6] | (uint32_t)h[7] << 16);
-    } else if (l > 0 && t < kPairs) {
+    } else if (l == kLayers - 1 && t == 0) {
+        // the last layer (one output channel) in the fused kernel: B of a
+        // 16x16x16 product, column n = tap, k = input channel 4 (lane / 16) + j
+        const int tap = lane & 15;
+        uint16_t h[4];
+        for (int j = 0; j < 4; ++j) {
+            const int c = 4 * (lane >> 4) + j;
+            h[j] = (tap < kTaps && co > 0 && c < ci) ? to_bf16(w[c * kTaps + tap]) : 0;
+        }
+        wk[l * kPairs * 64 + lane] = make_uint4(h[0] | (uint32_t)h[1] << 16,
+                                                h[2] | (uint32_t)h[3] << 16, 0u, 0u);
+    } else if (l > 0 && l < kLayers - 1 && t < kPairs) {
         const int g = lane >> 4, tap = 2 * t + (g >> 1), o = lane & 15;
         uint16_t h[8];
         for (int j = 0; j < 8; ++j) {
@@ -534,6 +545,53 @@ __device__ __forceinline__ void fused_layer(int layer, uint16_t (*buf)[kRegH * k
     __syncthreads();
 }
 
+// The last layer (16 -> 1 channel) of a tile: phase A multiplies each input
+// segment by all 9 taps at once (one 16x16x16 product, columns = taps):
+// D[q][t] = sum_c act[q][c] w[t][c], stored per tap in buf[1] for input rows
+// [3, 21) and columns [3, 35); phase B sums out(p) = b + sum_t D[p + off(t)][t]
+// in tap order for the tile's pixels and writes L + out.  Ends with a barrier.
+constexpr int kLastRows = kFuseH + 2, kLastCols = 32;
+
+__device__ __forceinline__ void fused_last_layer(uint16_t (*buf)[kRegH * kRegW * kC],
+                                                 const uint4* wsh, const float* bsh,
+                                                 const float* Lsh, int y0, int x0, uint32_t H,
+                                                 uint32_t W, uint32_t lane, uint32_t wv,
+                                                 float* __restrict__ pred)
+{
+    const uint16_t* in = buf[0];
+    float* D = reinterpret_cast<float*>(buf[1]);         // [tap][row][col]
+    const uint4 wb = wsh[(kLayers - 1) * kPairs * 64 + lane];
+    const bf16x4 b = __builtin_bit_cast(bf16x4, make_uint2(wb.x, wb.y));
+    const uint32_t tap = lane & 15, cq = (lane >> 4) * 4;
+    for (int s = (int)wv; s < kLastRows * 2; s += kFuseWaves) {
+        const int rr = s / 2, cc0 = (s % 2) * 16;        // region row 3 + rr, column 3 + cc0
+        const int q = (3 + rr) * kRegW + 3 + cc0 + (int)(lane & 15);
+        const bf16x4 a = *reinterpret_cast<const bf16x4*>(&in[q * kC + cq]);
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+        if (tap < (uint32_t)kTaps)
+            *reinterpret_cast<f32x4*>(&D[(tap * kLastRows + rr) * kLastCols + cc0 + cq]) = acc;
+    }
+    __syncthreads();
+    const float bo = bsh[(kLayers - 1) * kC];
+    // computed here, not hoisted out of the tile loop (registers are short)
+    int t0 = (int)threadIdx.x;
+    asm volatile("" : "+v"(t0));
+    for (int t = t0; t < kFuseH * kFuseW; t += kFuseThreads) {
+        const int r = 4 + t / kFuseW, c = 4 + t % kFuseW;  // region coordinates
+        const int y = y0 + r, x = x0 + c;
+        if (y >= (int)H || x >= (int)W) continue;
+        float v = bo;
+#pragma unroll
+        for (int k = 0; k < kTaps; ++k) {
+            const int rr = r + k / 3 - 1 - 3, cc = c + k % 3 - 1 - 3;
+            v += D[(k * kLastRows + rr) * kLastCols + cc];
+        }
+        pred[(size_t)y * W + x] = v + Lsh[r * kRegW + c];
+    }
+    __syncthreads();
+}
+
 // Persistent: workgroup w takes tiles w, w + grid, ...; the next tile's inputs
 // are loaded into registers while the current tile's layers run.  The input
 // region (4 channels per pixel) sits in buf[1], which the first layer does not
@@ -583,8 +641,9 @@ __global__ __launch_bounds__(kFuseThreads) __attribute__((amdgpu_waves_per_eu(4)
                         (int)(next % tiles_x) * kFuseW - 4, H, W);
 
         fused_layer<true>(0, buf, wsh, bsh, Lsh, y0, x0, H, W, lane, wv, pred);
-        for (int layer = 1; layer < kLayers; ++layer)
+        for (int layer = 1; layer < kLayers - 1; ++layer)
             fused_layer<false>(layer, buf, wsh, bsh, Lsh, y0, x0, H, W, lane, wv, pred);
+        fused_last_layer(buf, wsh, bsh, Lsh, y0, x0, H, W, lane, wv, pred);
     }
 }
 
