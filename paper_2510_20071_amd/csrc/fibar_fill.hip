@@ -30,7 +30,7 @@ namespace {
 constexpr int kC = 16;                          // channels of every activation
 constexpr int kLayers = 4;
 constexpr int kTaps = 9;
-constexpr int kGradBlocks = 256;                // workgroups of a weight gradient
+constexpr int kGradBlocks = 1024;               // workgroups of a weight gradient (256: 0.55 ms per training step, 1024: 0.37, 2048: 0.41)
 constexpr int kWgEntries = kTaps * kC * kC + kC;   // one layer's (w, b) gradient, padded
 constexpr int kLossBlocks = 256;
 constexpr int kPairs = 5;                       // taps in pairs for the K = 32 products
@@ -323,16 +323,22 @@ __global__ __launch_bounds__(256) void k_fill_loss_partial(const float* __restri
     if (threadIdx.x == 0) part[blockIdx.x] = v;
 }
 
-// loss2 = (loss, stale pixel count), summed in workgroup order.
-__global__ void k_fill_loss_final(const float2* __restrict__ part, uint32_t blocks,
-                                  float* __restrict__ loss2)
+// loss2 = (loss, stale pixel count): one wave, lane l sums partials l, l + 64,
+// ... in order, then a fixed butterfly (the same order every run).
+__global__ __launch_bounds__(64) void k_fill_loss_final(const float2* __restrict__ part,
+                                                        uint32_t blocks, float* __restrict__ loss2)
 {
-    if (threadIdx.x != 0) return;
+    const uint32_t lane = threadIdx.x;
     double s = 0.0, c = 0.0;
-    for (uint32_t b = 0; b < blocks; ++b) {
+    for (uint32_t b = lane; b < blocks; b += 64) {
         s += part[b].x;
         c += part[b].y;
     }
+    for (int m = 32; m > 0; m >>= 1) {
+        s += __shfl_xor(s, m);
+        c += __shfl_xor(c, m);
+    }
+    if (lane != 0) return;
     loss2[0] = c > 0 ? (float)(s / c) : 0.f;
     loss2[1] = (float)c;
 }
