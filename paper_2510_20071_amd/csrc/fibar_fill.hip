@@ -265,17 +265,26 @@ __global__ __launch_bounds__(256) void k_fill_wgrad(const uint16_t* __restrict__
 // Sum the partials of layer l into the canonical gradient: one wave per
 // entry, each lane adding every 64th partial in order, then a fixed butterfly
 // over the lanes (deterministic).
-__global__ __launch_bounds__(256) void k_fill_wgrad_reduce(const float* __restrict__ partial,
+__global__ __launch_bounds__(512) void k_fill_wgrad_reduce(const float* __restrict__ partial,
                                                            uint32_t blocks, int l,
                                                            float* __restrict__ grad)
 {
-    const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (e >= kWgEntries) return;                 // whole wave
-    const uint32_t lane = threadIdx.x & 63;
+    // 64 consecutive entries per workgroup (lane = entry), so each partial row
+    // is read as 256 contiguous bytes; wave w sums rows w, w + 8, ... in order,
+    // then the eight wave sums are added in wave order
+    __shared__ float sh[8][64];
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + (int)lane;
+    const int ec = e < kWgEntries ? e : kWgEntries - 1;
     float s = 0.f;
-    for (uint32_t b = lane; b < blocks; b += 64) s += partial[(size_t)b * kWgEntries + e];
-    for (int m = 32; m > 0; m >>= 1) s += __shfl_xor(s, m);
-    if (lane != 0) return;
+#pragma unroll 8
+    for (uint32_t b = wv; b < blocks; b += 8) s += partial[(size_t)b * kWgEntries + ec];
+    sh[wv][lane] = s;
+    __syncthreads();
+    if (wv != 0 || e >= kWgEntries) return;
+    s = sh[0][lane];
+#pragma unroll
+    for (int w = 1; w < 8; ++w) s += sh[w][lane];
     const int ci = cin_of(l), co = cout_of(l);
     if (e < kTaps * kC * kC) {
         const int t = e / (kC * kC), o = (e / kC) % kC, c = e % kC;
@@ -821,7 +830,7 @@ int loss_grad(fibar_fill* f, const float* L, const uint8_t* stale, const float* 
     for (int l = kLayers - 1; l >= 0; --l) {
         hipLaunchKernelGGL(k_fill_wgrad, dim3(kGradBlocks), dim3(256), 0, f->st, f->act[l], f->g[cur],
                            n, H, W, f->partial);
-        hipLaunchKernelGGL(k_fill_wgrad_reduce, dim3((kWgEntries + 3) / 4), dim3(256), 0, f->st,
+        hipLaunchKernelGGL(k_fill_wgrad_reduce, dim3((kWgEntries + 63) / 64), dim3(512), 0, f->st,
                            f->partial, (uint32_t)kGradBlocks, l, f->grad);
         FILL_TRY(hipGetLastError());
         if (l > 0) {
