@@ -129,41 +129,131 @@ __device__ __forceinline__ uint32_t owner(uint32_t e, uint32_t t, uint32_t* star
     return k;
 }
 
+// The owner's record fields come from the lane that holds them: every lane
+// loads its own record's fields together with its task count, so finding
+// the owner costs no second dependent load.  k is wave-uniform.
+__device__ __forceinline__ uint32_t bcast32(uint32_t v, uint32_t k)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)k);
+}
+template <typename P>
+__device__ __forceinline__ P* bcast_ptr(P* p, uint32_t k)
+{
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint64_t r = (uint64_t)bcast32((uint32_t)v, k) | ((uint64_t)bcast32((uint32_t)(v >> 32), k) << 32);
+    return reinterpret_cast<P*>(r);
+}
+__device__ __forceinline__ uint64_t bcast64(uint64_t v, uint32_t k)
+{
+    return (uint64_t)bcast32((uint32_t)v, k) | ((uint64_t)bcast32((uint32_t)(v >> 32), k) << 32);
+}
+
+// A stream's State as held per lane (the fields the round kernels use).
+struct LaneState {
+    PixL* px;
+    PixP* pp;
+    uint32_t* ring;
+    uint64_t ring_mask;
+    DevScalars* sc;
+    uint32_t W, H, TW, fill_num, fill_den;
+    uint64_t q_min, q_max;
+};
+
+__device__ __forceinline__ LaneState lane_state(const StreamStep* rr, uint32_t S)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const StreamStep* e = rr + (lane < S ? lane : 0u);
+    LaneState l;
+    l.px = e->s.px;
+    l.pp = e->s.pp;
+    l.ring = e->s.ring;
+    l.ring_mask = e->s.ring_mask;
+    l.sc = e->s.sc;
+    l.W = e->s.W;
+    l.H = e->s.H;
+    l.TW = e->s.TW;
+    l.fill_num = e->s.fill_num;
+    l.fill_den = e->s.fill_den;
+    l.q_min = e->s.q_min;
+    l.q_max = e->s.q_max;
+    return l;
+}
+
+__device__ __forceinline__ State owner_state(const LaneState& l, uint32_t k)
+{
+    State s;
+    s.px = bcast_ptr(l.px, k);
+    s.pp = bcast_ptr(l.pp, k);
+    s.ring = bcast_ptr(l.ring, k);
+    s.ring_mask = bcast64(l.ring_mask, k);
+    s.sc = bcast_ptr(l.sc, k);
+    s.W = bcast32(l.W, k);
+    s.H = bcast32(l.H, k);
+    s.TW = bcast32(l.TW, k);
+    s.fill_num = bcast32(l.fill_num, k);
+    s.fill_den = bcast32(l.fill_den, k);
+    s.q_min = bcast64(l.q_min, k);
+    s.q_max = bcast64(l.q_max, k);
+    return s;
+}
+
 // Every round kernel gets `rr`, the round's S records.
 __global__ __launch_bounds__(256) void k_multi_apply(MultiArgs a, const StreamStep* rr, int sub)
 {
+    // this lane's record: the fields an apply task needs, loaded together with
+    // the task counts (the fence keeps them from sinking behind the lookup)
+    const uint32_t lane = threadIdx.x & 63u;
+    const StreamStep* mine = rr + (lane < a.S ? lane : 0u);
+    const LaneState ls = lane_state(rr, a.S);
+    const StepScratch* l_prev = mine->prev;
+    StepScratch* l_step = mine->step;
+    const uint16_t* l_x = mine->chunk[sub].x;
+    const uint16_t* l_y = mine->chunk[sub].y;
+    const uint32_t l_n = mine->chunk[sub].n;
+    const SegRec* l_seg = mine->seg[sub];
+    const uint32_t* l_nseg = mine->nseg[sub];
+    const uint32_t l_prev_events = mine->prev_events;
+    const int32_t l_slot_in = mine->slot_in, l_slot_out = mine->slot_out;
     uint32_t total;
     const uint32_t le = lane_end(rr, a.S, sub, &total);
+    FIBAR_ISSUE_FENCE();
     for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
         uint32_t start;
-        const StreamStep* e = rr + owner(le, t, &start);
-        const State s = e->s;
-        const StepScratch* prev = e->prev;
+        const uint32_t k = owner(le, t, &start);
+        const State s = owner_state(ls, k);
+        const StepScratch* prev = bcast_ptr(l_prev, k);
+        const uint32_t prev_events = bcast32(l_prev_events, k);
+        const int32_t slot_in = (int32_t)bcast32((uint32_t)l_slot_in, k);
         uint32_t b = t - start;
         if (sub == 0 && prev) {
             if (b == 0) {
-                if (threadIdx.x == 0)
-                    s.sc[e->slot_out] = commit_step(s.sc[e->slot_in], prev, e->prev_events, s, 1);
+                if (threadIdx.x == 0) {
+                    const int32_t slot_out = (int32_t)bcast32((uint32_t)l_slot_out, k);
+                    s.sc[slot_out] = commit_step(s.sc[slot_in], prev, prev_events, s, 1);
+                }
                 continue;
             }
             --b;
         }
-        StepScratch* stp = e->step;
-        const ChunkDesc cd = e->chunk[sub];
+        StepScratch* stp = bcast_ptr(l_step, k);
+        ChunkDesc cd;
+        cd.x = bcast_ptr(l_x, k);
+        cd.y = bcast_ptr(l_y, k);
+        cd.n = bcast32(l_n, k);
         // i < kChunk: task counts are ceil(n / block) and every block size
         // divides kChunk; a chunk slot holds kChunk records and 3 more follow
         const uint32_t i = b * blockDim.x + threadIdx.x;
         // every load that only needs the record is issued before any is used
-        const Group g = load_group(cd, e->seg[sub], i, 1);
+        const Group g = load_group(cd, bcast_ptr(l_seg, k), i, 1);
         const uint32_t status = stp->status;
-        const uint32_t nseg = *e->nseg[sub];
-        const HeadIn hin = load_head(s.sc + e->slot_in, prev);
+        const uint32_t nseg = *bcast_ptr(l_nseg, k);
+        const HeadIn hin = load_head(s.sc + slot_in, prev);
         FIBAR_ISSUE_FENCE();
         const TileIn ti = load_tile(s, g, i);
         FIBAR_ISSUE_FENCE();
         int64_t k0;
         uint64_t h0;
-        head_after(hin, e->prev_events, 1, &k0, &h0);
+        head_after(hin, prev_events, 1, &k0, &h0);
         const uint64_t first = (uint64_t)(k0 + 1) + (uint64_t)sub * kChunk;
         uint32_t dP = 0u, dT = 0u;
         apply_tile(s, g, ti, cd.n, nseg, status != 0, i, first, h0, 1, dP, dT);
@@ -173,20 +263,29 @@ __global__ __launch_bounds__(256) void k_multi_apply(MultiArgs a, const StreamSt
 
 __global__ __launch_bounds__(256) void k_multi_pop(MultiArgs a, const StreamStep* rr)
 {
+    const uint32_t lane = threadIdx.x & 63u;
+    const StreamStep* mine = rr + (lane < a.S ? lane : 0u);
+    const LaneState ls = lane_state(rr, a.S);
+    StepScratch* l_step = mine->step;
+    const uint32_t l_events = mine->events, l_pop_blocks = mine->pop_blocks;
+    const int32_t l_pop_slot = mine->pop_slot;
     uint32_t total;
     const uint32_t le = lane_end(rr, a.S, 2, &total);
+    FIBAR_ISSUE_FENCE();
     for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
         uint32_t start;
-        const StreamStep* e = rr + owner(le, t, &start);
-        const State s = e->s;
-        StepScratch* stp = e->step;
+        const uint32_t k = owner(le, t, &start);
+        const State s = owner_state(ls, k);
+        StepScratch* stp = bcast_ptr(l_step, k);
+        const uint32_t events = bcast32(l_events, k), pop_blocks = bcast32(l_pop_blocks, k);
+        const int32_t pop_slot = (int32_t)bcast32((uint32_t)l_pop_slot, k);
         const uint32_t status = stp->status;
         uint64_t h_old, h_new;
-        pop_bounds(s.sc[e->pop_slot], e->events, &h_old, &h_new);
+        pop_bounds(s.sc[pop_slot], events, &h_old, &h_new);
         if (status) h_new = h_old;   // a rejected packet pops nothing
         uint32_t dP = 0u, dT = 0u;
         pop_range(s, h_old + (uint64_t)(t - start) * blockDim.x + threadIdx.x, h_new,
-                  (uint64_t)e->pop_blocks * blockDim.x, h_old, dP, dT);
+                  (uint64_t)pop_blocks * blockDim.x, h_old, dP, dT);
         add_counts(stp, 2, dP, dT);
     }
 }
