@@ -6,17 +6,17 @@
 // compositions to the state, moving the active-event window, detecting and
 // blurring stale pixels).  The first part runs for many packets in one bulk
 // launch (k_sort_compose, one 1024-thread workgroup per <=16384-event chunk);
-// the second runs packet by packet (k_apply, then k_pop_blur).
+// the second runs packet by packet (k_apply, then k_pop_blur, whose extra
+// workgroups also write a readout that directly follows the packet).
 //
 // Blurred values of stale pixels live in a second image Lb (stored next to
 // L and the last-event index, px[i] = (L, Lb, last)): a pixel's current
-// brightness is Lb[i] when it is
-// stale (its newest event has left the window, last[i] < h) and L[i]
-// otherwise.  The pop kernel of a step
-// writes only Lb of the pixels that go stale in that step and reads
-// neighbours with the window head h of the previous step, so every blur of
-// the step sees the pre-blur image (the blurs of one step are simultaneous)
-// without a separate write pass.
+// brightness is Lb[i] when it is stale (its newest event has left the
+// window, last[i] < h) and L[i] otherwise.  The pop kernel of a step writes
+// only Lb of the pixels that go stale in that step and reads neighbours with
+// the window head h of the previous step, so every blur of the step sees the
+// pre-blur image (the blurs of one step are simultaneous) without a separate
+// write pass.
 //
 // Paper references: temporal filter Eq. (6), (7), (10); active event queue
 // and its regulation Eq. (19), (20) (Method, "Spatial filtering"); one-time
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(kApplyBlock) void k_apply(
     cd.n = n;
     // the grid may reach past the chunk's record slot (pop-list copies); such
     // items read the slot's last records and apply nothing (i >= n >= nseg)
-    const Group g = load_group(cd, seg, i < (uint32_t)kChunk ? i : kChunk - 1, spatial);
+    const Group g = load_group(cd, seg, i < (uint32_t)kChunk ? i : kChunk - 1);
     uint32_t status = step->status;
     uint32_t nseg = *seg_count;
     HeadIn hin = load_head(sc_in, prev);

@@ -244,7 +244,7 @@ __global__ __launch_bounds__(256) void k_multi_apply(MultiArgs a, const StreamSt
         // divides kChunk; a chunk slot holds kChunk records and 3 more follow
         const uint32_t i = b * blockDim.x + threadIdx.x;
         // every load that only needs the record is issued before any is used
-        const Group g = load_group(cd, bcast_ptr(l_seg, k), i, 1);
+        const Group g = load_group(cd, bcast_ptr(l_seg, k), i);
         const uint32_t status = stp->status;
         const uint32_t nseg = *bcast_ptr(l_nseg, k);
         const HeadIn hin = load_head(s.sc + slot_in, prev);

@@ -160,10 +160,11 @@ __device__ __forceinline__ void pop_bounds(const DevScalars& c, uint32_t pkt_eve
 // iff its newest event is inside the window, last >= h) with no atomics.
 // Item i also pushes event i to the back of the window.
 //
-// In two parts, so that a kernel can issue the loads that need only the
-// chunk (records i - 1 .. i + 3, event coordinates) before it waits for the
-// window head: load_group, then apply_group.  i < kChunk, and a chunk's
-// record slot is followed by at least 3 more records of memory.
+// In parts, so that a kernel can issue the loads that need only the chunk
+// (records i - 1 .. i + 3, event coordinates) and then the tile's state
+// before it waits for the window head: load_group, load_tile, apply_tile.
+// i < kChunk (callers clamp), and a chunk's record slot is followed by at
+// least 3 more records of memory.
 struct Group {
     uint32_t prev_key;       // sort key of record i - 1, all ones for i = 0
     SegRec r[4];             // records i .. i + 3
@@ -171,7 +172,7 @@ struct Group {
 };
 
 __device__ __forceinline__ Group load_group(const ChunkDesc& cd, const SegRec* __restrict__ seg,
-                                           uint32_t i, int spatial)
+                                           uint32_t i)
 {
     Group g;
     const uint32_t pk = seg[i > 0 ? i - 1 : 0].key;          // unconditional: no wait
