@@ -81,7 +81,6 @@ void free_ctx(fibar_ctx* c)
     (void)hipFree(c->seg);
     (void)hipFree(c->seg_count);
     (void)hipFree(c->scratch);
-    (void)hipFree(c->pop_list);
     (void)hipFree(c->stg_x);
     (void)hipFree(c->stg_y);
     (void)hipFree(c->stg_p);
@@ -262,14 +261,12 @@ int run_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, uint32_t
         const uint32_t nev = ops[i].n;
         const int slot_in = c->cur_slot;
         const int slot_out = pend ? (slot_in ^ 1) : -1;
-        // a one-chunk packet's apply launch lists the pixels its pops will take
-        const uint32_t pop_copy = (sp && nev <= (uint32_t)kChunk) ? pop_threads(nev) : 0u;
         for (uint32_t off = 0; off < nev; off += kChunk) {
             const uint32_t m = nev - off < (uint32_t)kChunk ? nev - off : (uint32_t)kChunk;
             HIP_TRY(timed_launch(c, 1, [&](const LaunchTiming& tm) {
                 return launch_apply(c->s, &c->h_chunks[ci], c->seg + (size_t)ci * kChunk,
                                     c->seg_count + ci, m, off, stp, pend, pend_n, slot_in,
-                                    slot_out, sp, c->pop_list, pop_copy, c->st, tm);
+                                    slot_out, sp, c->st, tm);
             }));
             ++ci;
         }
@@ -284,13 +281,11 @@ int run_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, uint32_t
                 const fibar_readout_buf& rb = ops[i + 1].ro;
                 PopReadout pr{rb.brightness, rb.pbar,     rb.stale_mask,
                               rb.last_index, rb.log_age, rb.tile_count};
-                HIP_TRY(launch_pop_blur(c->s, nev, stp, slot, c->pop_list, pop_copy, &pr,
-                                        c->st));
+                HIP_TRY(launch_pop_blur(c->s, nev, stp, slot, &pr, c->st));
                 ++i;   // the readout op is done
             } else {
                 HIP_TRY(timed_launch(c, 2, [&](const LaunchTiming& tm) {
-                    return launch_pop_blur(c->s, nev, stp, slot, c->pop_list, pop_copy, nullptr,
-                                           c->st, tm);
+                    return launch_pop_blur(c->s, nev, stp, slot, nullptr, c->st, tm);
                 }));
             }
         }
@@ -519,7 +514,6 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
     alloc((void**)&c->seg, ((size_t)kMaxBatchChunks * kChunk + 4) * sizeof(SegRec));
     alloc((void**)&c->seg_count, kMaxBatchChunks * 4);
     alloc((void**)&c->scratch, kMaxBatchChunks * sizeof(StepScratch));
-    alloc((void**)&c->pop_list, kPopListMax * sizeof(uint32_t));
     alloc((void**)&c->stg_x, stg * 2);
     alloc((void**)&c->stg_y, stg * 2);
     alloc((void**)&c->stg_p, stg);

@@ -23,7 +23,6 @@ struct fibar_ctx {
     fibar::SegRec* seg = nullptr;
     uint32_t* seg_count = nullptr;
     fibar::StepScratch* scratch = nullptr;
-    uint32_t* pop_list = nullptr;       // kPopListMax entries
     uint16_t* stg_x = nullptr;          // device staging for host packets
     uint16_t* stg_y = nullptr;
     uint8_t* stg_p = nullptr;

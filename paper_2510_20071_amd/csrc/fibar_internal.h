@@ -159,9 +159,9 @@ hipError_t launch_region_batch(const State& s, int slot, const ChunkDesc* d_chun
 // 16384-event packets, 64- and 256-thread workgroups were both slower).
 constexpr uint32_t kApplyBlock = 128;
 constexpr uint32_t kPopBlock = 128;
-// Pixels per thread of the readout workgroups of a pop launch (1, 2, 4, 8:
-// 1 was fastest on the 1280x720 stream) and their largest number.
-constexpr uint32_t kReadoutPerThread = 1;
+// Workgroups of a pop launch's readout, one pixel per thread (1, 2, 4 and 8
+// pixels per thread were tried: 1 was fastest on the 1280x720 stream), at
+// most this many (more pixels loop).
 constexpr uint32_t kReadoutMaxBlocks = 16384;
 
 // Threads of a step's pop launch: one pop each.  A step pops its packet's
@@ -173,10 +173,6 @@ inline __host__ __device__ uint32_t pop_threads(uint32_t pkt_events)
     return (pkt_events + pkt_events / 8 + kPopBlock - 1) / kPopBlock * kPopBlock;
 }
 
-// Pop list: for a packet of one chunk, the apply launch copies the pixels of
-// the events its step will pop (the first pop_threads(n) of the window) so
-// that the pop launch starts from them without waiting for the window head.
-constexpr uint32_t kPopListMax = (kChunk + kChunk / 8 + kPopBlock - 1) / kPopBlock * kPopBlock;
 
 // ---- launchers (fibar_kernels.hip) ---------------------------------------
 hipError_t launch_sort_compose(const ChunkDesc* d_chunks, uint32_t n_chunks, SegRec* seg,
@@ -186,16 +182,12 @@ hipError_t launch_sort_compose(const ChunkDesc* d_chunks, uint32_t n_chunks, Seg
 
 // In-order launches.  `slot_in` holds the last committed scalars; when
 // `prev` is not null the step it describes (with `prev_events` events) is
-// committed on top of them, and the result is written to `slot_out`.  With
-// pop_copy > 0 (a one-chunk packet) the apply launch also fills
-// pop_list[0, pop_copy) for the pop launch of its step, which then gets the
-// same pop_list and pop_copy.
+// committed on top of them, and the result is written to `slot_out`.
 hipError_t launch_apply(const State& s, const ChunkDesc* d_chunk, const SegRec* seg,
                         const uint32_t* seg_count, uint32_t chunk_events,
                         uint32_t chunk_offset, StepScratch* step, const StepScratch* prev,
                         uint32_t prev_events, int slot_in, int slot_out, int spatial,
-                        uint32_t* pop_list, uint32_t pop_copy, hipStream_t st,
-                        const LaunchTiming& tm = LaunchTiming());
+                        hipStream_t st, const LaunchTiming& tm = LaunchTiming());
 
 // Outputs of a readout taken in the pop launch of the step before it (any
 // may be null but L; no window count: the pops change it).
@@ -210,8 +202,8 @@ struct PopReadout {
 
 // With `ro` the launch also writes the readout of the state after the step.
 hipError_t launch_pop_blur(const State& s, uint32_t pkt_events, StepScratch* step, int slot,
-                           const uint32_t* pop_list, uint32_t pop_copy, const PopReadout* ro,
-                           hipStream_t st, const LaunchTiming& tm = LaunchTiming());
+                           const PopReadout* ro, hipStream_t st,
+                           const LaunchTiming& tm = LaunchTiming());
 
 // Initial per-pixel state: zero brightness and polarity, no events.
 hipError_t launch_init_state(const State& s, hipStream_t st);

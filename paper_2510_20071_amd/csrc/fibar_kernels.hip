@@ -108,8 +108,7 @@ constexpr uint32_t kPendingBit = 1u << 31;
 __global__ __launch_bounds__(kApplyBlock) void k_apply(
     const SegRec* __restrict__ seg, const uint32_t* __restrict__ seg_count, StepScratch* step,
     const DevScalars* sc_in, const uint16_t* ex, const uint16_t* ey, uint32_t n_prev, State s,
-    uint32_t chunk_offset, uint32_t prev_events, DevScalars* sc_out, int spatial,
-    uint32_t* __restrict__ pop_list, uint32_t pop_copy)
+    uint32_t chunk_offset, uint32_t prev_events, DevScalars* sc_out, int spatial)
 {
     const StepScratch* prev = (n_prev & kPendingBit) ? step - 1 : nullptr;
     const uint32_t n = n_prev & ~kPendingBit;
@@ -124,9 +123,7 @@ __global__ __launch_bounds__(kApplyBlock) void k_apply(
     cd.x = ex;
     cd.y = ey;
     cd.n = n;
-    // the grid may reach past the chunk's record slot (pop-list copies); such
-    // items read the slot's last records and apply nothing (i >= n >= nseg)
-    const Group g = load_group(cd, seg, i < (uint32_t)kChunk ? i : kChunk - 1);
+    const Group g = load_group(cd, seg, i);
     uint32_t status = step->status;
     uint32_t nseg = *seg_count;
     HeadIn hin = load_head(sc_in, prev);
@@ -137,38 +134,22 @@ __global__ __launch_bounds__(kApplyBlock) void k_apply(
     uint64_t h0;
     head_after(hin, prev_events, spatial, &k0, &h0);
     const uint64_t first = (uint64_t)(k0 + 1) + chunk_offset;
-    // pop list: the pixel of window event h0 + i, from the ring if an earlier
-    // launch pushed it, else from this chunk's events (the ring cannot hold
-    // both in one slot: it is longer than the window plus a packet)
-    uint32_t pl = 0u;
-    if (i < pop_copy) {
-        const uint64_t p = h0 + i;
-        if (p < first) {
-            pl = s.ring[p & s.ring_mask];
-        } else if (p - first < n) {
-            const uint32_t e = (uint32_t)(p - first);
-            pl = (uint32_t)ey[e] * s.W + ex[e];
-        }
-    }
     uint32_t dP = 0u, dT = 0u;
     apply_tile(s, g, ti, cd.n, nseg, status != 0, i, first, h0, spatial, dP, dT);
-    if (i < pop_copy) pop_list[i] = pl;
     if (spatial) add_counts(step, 0, dP, dT);
 }
 
 // Move the window head by the target of the previous step (Eq. (20)),
 // detect pixels whose last queued event leaves the window, and write their
 // blurred values to Lb.  `sc` holds the scalars after the previous step.
-// Leading arguments as in k_apply; `stride` is the grid's thread count.
-// With pop_copy (= the grid's thread count) every thread takes its first
-// pixel from the pop list, which needs no scalar; otherwise, and in later
-// rounds, pixels come from the ring.
-__global__ __launch_bounds__(kPopBlock) void k_pop_blur(const uint32_t* __restrict__ pop_list,
-                                                        const DevScalars* sc, StepScratch* step,
-                                                        PixL* px, uint32_t W, uint32_t H,
-                                                        uint32_t pkt_events, uint32_t pop_copy,
+// Leading arguments as in k_apply; `stride` is the pops' thread count.
+// Workgroups from pop_blocks on write the readout that directly follows the
+// step, if there is one (`ro`).
+__global__ __launch_bounds__(kPopBlock) void k_pop_blur(const DevScalars* sc, StepScratch* step,
                                                         const uint32_t* ring, uint64_t ring_mask,
-                                                        uint32_t stride, State s, PopReadout ro,
+                                                        PixL* px, uint32_t W, uint32_t H,
+                                                        uint32_t pkt_events, uint32_t stride,
+                                                        State s, PopReadout ro,
                                                         uint32_t pop_blocks)
 {
     s.ring = const_cast<uint32_t*>(ring);
@@ -176,70 +157,30 @@ __global__ __launch_bounds__(kPopBlock) void k_pop_blur(const uint32_t* __restri
     s.px = px;
     s.W = W;
     s.H = H;
+    // the status and the scalars are loaded together (a select, not a branch)
+    const uint32_t status = step->status;
+    const DevScalars c = *sc;
+    uint64_t h_old, h_new;
+    pop_bounds(c, pkt_events, &h_old, &h_new);
+    if (status) h_new = h_old;   // a rejected packet pops nothing
     if (blockIdx.x >= pop_blocks) {
-        // workgroups past the pops read out the state after the step; what
-        // they read is not written by the pops (see readout_pixel_after_pops)
-        const uint32_t status = step->status;
-        const DevScalars c = *sc;
-        uint64_t h_old, h_new;
-        pop_bounds(c, pkt_events, &h_old, &h_new);
-        if (status) h_new = h_old;
+        // the readout of the state after the step; what it reads is not
+        // written by the pops (see readout_pixel_after_pops)
         const int64_t k = status ? c.k : c.k + (int64_t)pkt_events;
         const uint64_t npx = (uint64_t)W * H;
         const uint64_t rstride = (uint64_t)(gridDim.x - pop_blocks) * kPopBlock;
         const uint64_t r0 = (uint64_t)(blockIdx.x - pop_blocks) * kPopBlock + threadIdx.x;
-        // kReadoutPerThread pixels per thread, all loaded before any is used
-        for (uint64_t base = r0; base < npx; base += kReadoutPerThread * rstride) {
-            PixL v[kReadoutPerThread];
-#pragma unroll
-            for (uint32_t q = 0; q < kReadoutPerThread; ++q) {
-                const uint64_t i = base + q * rstride;
-                v[q] = s.px[i < npx ? i : 0];
-            }
-#pragma unroll
-            for (uint32_t q = 0; q < kReadoutPerThread; ++q) {
-                const uint64_t i = base + q * rstride;
-                if (i < npx)
-                    readout_pixel_after_pops(s, k, h_old, h_new, i, v[q], ro.L, ro.pbar,
-                                             ro.stale, ro.last, ro.log_age);
-            }
-        }
+        for (uint64_t i = r0; i < npx; i += rstride)
+            readout_pixel_after_pops(s, k, h_old, h_new, i, s.px[i], ro.L, ro.pbar, ro.stale,
+                                     ro.last, ro.log_age);
         if (ro.tcnt) {
             const uint64_t nt = (uint64_t)s.TW * ((H + 1) / 2);
             for (uint64_t t = r0; t < nt; t += rstride) ro.tcnt[t] = tile_active_pixels(s, t, h_new);
         }
         return;
     }
-    const uint32_t t = blockIdx.x * kPopBlock + threadIdx.x;
     uint32_t dP = 0u, dT = 0u;
-    uint64_t h_old, h_new;
-    if (pop_copy) {
-        // every thread has a listed pixel: its neighbourhood is loaded first,
-        // then the window scalars, whose latency overlaps it (entries past the
-        // step's pops, or of a rejected packet, are clamped into the image and
-        // not used)
-        const uint32_t listed = pop_list[t];
-        const uint32_t npx = W * H;
-        const uint32_t pix = listed < npx ? listed : 0u;
-        PixL nb[3][3];
-        load_pop(s, pix, nb);
-        FIBAR_ISSUE_FENCE();
-        const uint32_t status = step->status;
-        pop_bounds(*sc, pkt_events, &h_old, &h_new);
-        if (status) h_new = h_old;   // a rejected packet pops nothing
-        const uint64_t j0 = h_old + t;
-        if (j0 < h_new) {
-            decide_pop(s, j0, pix, nb, h_old, dP, dT);
-            pop_range(s, j0 + stride, h_new, stride, h_old, dP, dT);
-        }
-    } else {
-        // the status and the scalars are loaded together (a select, not a
-        // branch)
-        const uint32_t status = step->status;
-        pop_bounds(*sc, pkt_events, &h_old, &h_new);
-        if (status) h_new = h_old;
-        pop_range(s, h_old + t, h_new, stride, h_old, dP, dT);
-    }
+    pop_range(s, h_old + blockIdx.x * kPopBlock + threadIdx.x, h_new, stride, h_old, dP, dT);
     add_counts(step, 2, dP, dT);
 }
 
@@ -306,46 +247,37 @@ hipError_t launch_sort_compose(const ChunkDesc* d_chunks, uint32_t n_chunks, Seg
 hipError_t launch_apply(const State& s, const ChunkDesc* d_chunk, const SegRec* seg,
                         const uint32_t* seg_count, uint32_t chunk_events, uint32_t chunk_offset,
                         StepScratch* step, const StepScratch* prev, uint32_t prev_events,
-                        int slot_in, int slot_out, int spatial, uint32_t* pop_list,
-                        uint32_t pop_copy, hipStream_t st, const LaunchTiming& tm)
+                        int slot_in, int slot_out, int spatial, hipStream_t st,
+                        const LaunchTiming& tm)
 {
     // one extra workgroup (the first) commits the previous step's scalars
     if (prev && prev != step - 1) return hipErrorInvalidValue;   // scratch layout
     if (chunk_events == 0 || chunk_events > (uint32_t)kChunk) return hipErrorInvalidValue;
-    if (pop_copy > kPopListMax || (pop_copy && !pop_list)) return hipErrorInvalidValue;
-    const uint32_t items = chunk_events > pop_copy ? chunk_events : pop_copy;
-    const uint32_t blocks = (items + kApplyBlock - 1) / kApplyBlock + 1;
+    const uint32_t blocks = (chunk_events + kApplyBlock - 1) / kApplyBlock + 1;
     DevScalars* sc_out = slot_out >= 0 ? s.sc + slot_out : nullptr;
     return launch_timed(k_apply, dim3(blocks), dim3(kApplyBlock), st, tm.start, tm.stop, seg,
                         seg_count, step, (const DevScalars*)(s.sc + slot_in), d_chunk->x,
                         d_chunk->y, chunk_events | (prev ? kPendingBit : 0u), s, chunk_offset,
-                        prev_events, sc_out, spatial, pop_list, pop_copy);
+                        prev_events, sc_out, spatial);
 }
 
 hipError_t launch_pop_blur(const State& s, uint32_t pkt_events, StepScratch* step, int slot,
-                           const uint32_t* pop_list, uint32_t pop_copy, const PopReadout* ro,
-                           hipStream_t st, const LaunchTiming& tm)
+                           const PopReadout* ro, hipStream_t st, const LaunchTiming& tm)
 {
     const uint32_t threads = pop_threads(pkt_events);
-    // the kernel takes every thread's first pixel from the list, or none
-    if (threads == 0 || (pop_copy != 0 && (pop_copy != threads || !pop_list)))
-        return hipErrorInvalidValue;
-    if (ro && !ro->L) return hipErrorInvalidValue;
+    if (threads == 0 || (ro && !ro->L)) return hipErrorInvalidValue;
     const uint32_t pop_blocks = threads / kPopBlock;
     uint32_t ro_blocks = 0;
     PopReadout r{};
     if (ro) {
-        // kReadoutPerThread pixels per thread; the pop workgroups come first
-        const uint64_t npx = (uint64_t)s.W * s.H;
-        const uint64_t per = (uint64_t)kReadoutPerThread * kPopBlock;
-        const uint64_t b = (npx + per - 1) / per;
+        // one pixel per thread; the pop workgroups come first
+        const uint64_t b = ((uint64_t)s.W * s.H + kPopBlock - 1) / kPopBlock;
         ro_blocks = (uint32_t)(b < kReadoutMaxBlocks ? (b > 0 ? b : 1) : kReadoutMaxBlocks);
         r = *ro;
     }
     return launch_timed(k_pop_blur, dim3(pop_blocks + ro_blocks), dim3(kPopBlock), st, tm.start,
-                        tm.stop, pop_list, (const DevScalars*)(s.sc + slot), step, s.px, s.W,
-                        s.H, pkt_events, pop_copy, (const uint32_t*)s.ring, s.ring_mask, threads,
-                        s, r, pop_blocks);
+                        tm.stop, (const DevScalars*)(s.sc + slot), step, (const uint32_t*)s.ring,
+                        s.ring_mask, s.px, s.W, s.H, pkt_events, threads, s, r, pop_blocks);
 }
 
 hipError_t launch_init_state(const State& s, hipStream_t st)
