@@ -64,16 +64,26 @@ struct DevScalars {
 };
 
 // Per-packet scratch of one batch (zeroed at the start of the batch).
-// Counters are spread over kSpread cache lines (picked by workgroup index)
-// so that atomics of different workgroups rarely meet on one line.
+// Every 64-thread wave of a step's kernels stores its (activation or
+// deactivation) counts into a slot of its own, numbered by the wave's first
+// thread in the step's grid of that kind: plain stores, no atomics, which
+// had cost a few tenths of a microsecond at the end of every launch.  Waves
+// past the slots (packets above one chunk) add to the overflow counters,
+// spread over kSpread cache lines.  A commit sums slots and overflow.
 constexpr int kSpread = 8;
 constexpr int kLineWords = 32;       // 128-byte cache line
+constexpr uint32_t kApplySlots = kChunk / 64;              // one chunk's apply waves
+constexpr uint32_t kPopSlots = (kChunk + kChunk / 8) / 64 + 32;   // its pops' waves
 struct alignas(128) StepScratch {
     uint32_t status;                 // validation bits: 1 = range, 2 = polarity
     uint32_t pad[kLineWords - 1];
-    uint32_t part[kSpread][kLineWords];   // [0..3]: activated pixels, activated
-                                          // tiles, stale pixels, deactivated tiles
+    uint32_t part[kSpread][kLineWords];   // overflow, [0..3]: activated pixels,
+                                          // activated tiles, stale pixels,
+                                          // deactivated tiles
+    uint2 wave_apply[kApplySlots];        // (activated pixels, activated tiles)
+    uint2 wave_pop[kPopSlots];            // (stale pixels, deactivated tiles)
 };
+static_assert(kApplySlots % 2 == 0 && kPopSlots % 2 == 0, "slots are read in pairs");
 
 // Per-pixel state, in two arrays of structures so that what one kernel
 // needs of a pixel comes in one load: the window kernels read brightness and

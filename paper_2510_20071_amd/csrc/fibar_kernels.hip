@@ -113,8 +113,10 @@ __global__ __launch_bounds__(kApplyBlock) void k_apply(
     const StepScratch* prev = (n_prev & kPendingBit) ? step - 1 : nullptr;
     const uint32_t n = n_prev & ~kPendingBit;
     if (blockIdx.x == 0) {
-        if (prev && sc_out && threadIdx.x == 0)
-            *sc_out = commit_step(*sc_in, prev, prev_events, s, spatial);
+        if (prev && sc_out && threadIdx.x < 64) {
+            const DevScalars r = commit_by_wave(sc_in, prev, prev_events, s, spatial);
+            if (threadIdx.x == 0) *sc_out = r;
+        }
         return;
     }
     // every load that needs only the arguments is issued before any is used
@@ -136,7 +138,7 @@ __global__ __launch_bounds__(kApplyBlock) void k_apply(
     const uint64_t first = (uint64_t)(k0 + 1) + chunk_offset;
     uint32_t dP = 0u, dT = 0u;
     apply_tile(s, g, ti, cd.n, nseg, status != 0, i, first, h0, spatial, dP, dT);
-    if (spatial) add_counts(step, 0, dP, dT);
+    if (spatial) add_counts(step, false, chunk_offset + i, dP, dT);
 }
 
 // Move the window head by the target of the previous step (Eq. (20)),
@@ -181,7 +183,7 @@ __global__ __launch_bounds__(kPopBlock) void k_pop_blur(const DevScalars* sc, St
     }
     uint32_t dP = 0u, dT = 0u;
     pop_range(s, h_old + blockIdx.x * kPopBlock + threadIdx.x, h_new, stride, h_old, dP, dT);
-    add_counts(step, 2, dP, dT);
+    add_counts(step, true, blockIdx.x * kPopBlock + threadIdx.x, dP, dT);
 }
 
 // Initial per-pixel state.
@@ -202,12 +204,13 @@ __global__ __launch_bounds__(256) void k_init_state(State s)
     }
 }
 
-// Commit a pending step into the other slot (one thread).
-__global__ void k_commit(State s, const StepScratch* prev, uint32_t prev_events, int slot_in,
-                         int slot_out, int spatial)
+// Commit a pending step into the other slot (one wave).
+__global__ __launch_bounds__(64) void k_commit(State s, const StepScratch* prev,
+                                                uint32_t prev_events, int slot_in, int slot_out,
+                                                int spatial)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0)
-        s.sc[slot_out] = commit_step(s.sc[slot_in], prev, prev_events, s, spatial);
+    const DevScalars r = commit_by_wave(s.sc + slot_in, prev, prev_events, s, spatial);
+    if (threadIdx.x == 0) s.sc[slot_out] = r;
 }
 
 __global__ __launch_bounds__(256) void k_readout(State s, int spatial, const StepScratch* prev,

@@ -227,9 +227,10 @@ __global__ __launch_bounds__(256) void k_multi_apply(MultiArgs a, const StreamSt
         uint32_t b = t - start;
         if (sub == 0 && prev) {
             if (b == 0) {
-                if (threadIdx.x == 0) {
+                if (threadIdx.x < 64) {
+                    const DevScalars r = commit_by_wave(s.sc + slot_in, prev, prev_events, s, 1);
                     const int32_t slot_out = (int32_t)bcast32((uint32_t)l_slot_out, k);
-                    s.sc[slot_out] = commit_step(s.sc[slot_in], prev, prev_events, s, 1);
+                    if (threadIdx.x == 0) s.sc[slot_out] = r;
                 }
                 continue;
             }
@@ -257,7 +258,7 @@ __global__ __launch_bounds__(256) void k_multi_apply(MultiArgs a, const StreamSt
         const uint64_t first = (uint64_t)(k0 + 1) + (uint64_t)sub * kChunk;
         uint32_t dP = 0u, dT = 0u;
         apply_tile(s, g, ti, cd.n, nseg, status != 0, i, first, h0, 1, dP, dT);
-        add_counts(stp, 0, dP, dT);
+        add_counts(stp, false, (uint32_t)sub * kChunk + i, dP, dT);
     }
 }
 
@@ -286,7 +287,7 @@ __global__ __launch_bounds__(256) void k_multi_pop(MultiArgs a, const StreamStep
         uint32_t dP = 0u, dT = 0u;
         pop_range(s, h_old + (uint64_t)(t - start) * blockDim.x + threadIdx.x, h_new,
                   (uint64_t)pop_blocks * blockDim.x, h_old, dP, dT);
-        add_counts(stp, 2, dP, dT);
+        add_counts(stp, true, (t - start) * blockDim.x + threadIdx.x, dP, dT);
     }
 }
 
@@ -327,12 +328,14 @@ __global__ void k_multi_advance(uint32_t* base, uint32_t rounds)
     if (threadIdx.x == 0 && blockIdx.x == 0) *base += rounds;
 }
 
-__global__ void k_multi_commit(const CommitDesc* __restrict__ cd, uint32_t n)
+// One wave per commit.
+__global__ __launch_bounds__(64) void k_multi_commit(const CommitDesc* __restrict__ cd, uint32_t n)
 {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const CommitDesc c = cd[i];
-    c.s.sc[c.slot_out] = commit_step(c.s.sc[c.slot_in], c.prev, c.prev_events, c.s, 1);
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const CommitDesc c = cd[i];
+        const DevScalars r = commit_by_wave(c.s.sc + c.slot_in, c.prev, c.prev_events, c.s, 1);
+        if (threadIdx.x == 0) c.s.sc[c.slot_out] = r;
+    }
 }
 
 // Launch configurations the autotuner chooses from: workgroup size,
@@ -509,8 +512,7 @@ int commit_pending(fibar_multi* m, std::vector<StreamPlan>& plans)
         HIP_TRY(hipMemcpyAsync(m->d_commits, m->h_commits, nc * sizeof(CommitDesc),
                                hipMemcpyHostToDevice, m->st));
         HIP_TRY(hipEventRecord(m->commits_free, m->st));
-        hipLaunchKernelGGL(k_multi_commit, dim3((nc + 63) / 64), dim3(64), 0, m->st,
-                           m->d_commits, nc);
+        hipLaunchKernelGGL(k_multi_commit, dim3(nc), dim3(64), 0, m->st, m->d_commits, nc);
         HIP_TRY(hipGetLastError());
     }
     return FIBAR_OK;
@@ -793,7 +795,8 @@ int fibar_multi_create(fibar_ctx* const* ctxs, uint32_t n, void* stream, fibar_m
     // 4 spare records: an item reads records up to i + 3 of its chunk
     dalloc((void**)&m->seg, ((size_t)kMultiChunks * kChunk + 4) * sizeof(SegRec));
     dalloc((void**)&m->seg_count, kMultiChunks * sizeof(uint32_t));
-    dalloc((void**)&m->scratch, recs * sizeof(StepScratch));
+    // every step has at least one chunk (empty packets are rejected)
+    dalloc((void**)&m->scratch, kMultiChunks * sizeof(StepScratch));
     dalloc((void**)&m->base, sizeof(uint32_t));
     halloc((void**)&m->h_rec, recs * sizeof(StreamStep));
     halloc((void**)&m->h_rot, kMultiMaxRoTasks * sizeof(RoTask));

@@ -6,6 +6,10 @@
 
 #include "fibar_tile.h"
 
+// Keeps every memory access above it above it and every one below below
+// (an empty statement; it neither waits for nor touches memory).
+#define FIBAR_ISSUE_FENCE() asm volatile("" ::: "memory")
+
 namespace fibar {
 namespace step {
 namespace {
@@ -21,13 +25,13 @@ __device__ __forceinline__ uint32_t tile_of(const State& s, uint32_t pix)
 // ---------------------------------------------------------------------------
 // Window scalars without completion tickets.
 //
-// Kernels of step b add their activation / deactivation counts to the step's
-// scratch (one atomic per workgroup, spread over kSpread addresses).  Nobody
-// waits for the last workgroup: the *next* kernel that needs the scalars
-// after step b derives them from the last committed scalars plus step b's
-// counters (every workgroup computes the same values), and its workgroup 0
-// stores them into the other of two slots.  So no kernel reads a slot that a
-// kernel running at the same time writes.
+// Kernels of step b store their activation / deactivation counts into the
+// step's scratch (one slot per wave).  Nobody waits for the last workgroup:
+// the *next* kernel that needs the scalars after step b derives them from
+// the last committed scalars plus step b's counters (every workgroup
+// computes the same values), and its workgroup 0 stores them into the other
+// of two slots.  So no kernel reads a slot that a kernel running at the same
+// time writes.
 // ---------------------------------------------------------------------------
 // min(floor(num / den), cap) with num = q * fill_num * 4 * T, exact.  A
 // double quotient is within a relative 2^-51 of the true one; exact 128-bit
@@ -47,10 +51,9 @@ __device__ uint64_t target_div(uint64_t q, uint64_t fill_num, uint64_t T, uint64
 // Window head and newest index after the pending step (cheap part of a
 // commit: what every thread of the next kernel needs).  Selects, not
 // branches, so that the status load is issued together with the scalars.
-__device__ __forceinline__ void step_head(const DevScalars& c, const StepScratch* st, uint32_t n,
+__device__ __forceinline__ void step_head(const DevScalars& c, uint32_t status, uint32_t n,
                                           int spatial, int64_t* k, uint64_t* h)
 {
-    const uint32_t status = st->status;
     const int64_t ck = c.k;
     const uint64_t ch = c.h, cQ = c.Q;
     const uint64_t k_end = (uint64_t)(ck + (int64_t)n);
@@ -59,29 +62,88 @@ __device__ __forceinline__ void step_head(const DevScalars& c, const StepScratch
     *h = (status || !move) ? ch : k_end + 1 - cQ;
 }
 
-// Full commit of the pending step: counts, Eq. (20), statistics.
-__device__ DevScalars commit_step(const DevScalars& c, const StepScratch* st, uint32_t n,
-                                  const State& s, int spatial)
+// A step's counts: activated pixels and tiles, stale pixels, deactivated
+// tiles.
+struct StepCounts {
+    uint32_t act, tact, stale, toff;
+};
+
+// Sum of a step's count slots and overflow counters by one full wave (the
+// same in every lane).  Every load is issued before any is used: a fixed
+// number per lane from clamped addresses, the surplus zeroed afterwards (a
+// loop would wait for each load in turn).
+__device__ StepCounts gather_counts(const StepScratch* st)
+{
+    constexpr uint32_t kA = kApplySlots / 2, kP = kPopSlots / 2;   // slot pairs
+    constexpr int kJa = (int)((kA + 63) / 64), kJp = (int)((kP + 63) / 64);
+    const uint4* wa = reinterpret_cast<const uint4*>(st->wave_apply);
+    const uint4* wp = reinterpret_cast<const uint4*>(st->wave_pop);
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t ov = lane < (uint32_t)kSpread ? lane : 0u;
+    uint4 qa[kJa], qp[kJp];
+#pragma unroll
+    for (int j = 0; j < kJa; ++j) {
+        const uint32_t i = lane + 64u * j;
+        qa[j] = wa[i < kA ? i : 0u];
+    }
+#pragma unroll
+    for (int j = 0; j < kJp; ++j) {
+        const uint32_t i = lane + 64u * j;
+        qp[j] = wp[i < kP ? i : 0u];
+    }
+    uint4 qo = *reinterpret_cast<const uint4*>(st->part[ov]);
+    FIBAR_ISSUE_FENCE();
+    // no sum is hoisted between the loads (it would wait for the first ones
+    // before the last are issued)
+#pragma unroll
+    for (int j = 0; j < kJa; ++j)
+        asm volatile("" : "+v"(qa[j].x), "+v"(qa[j].y), "+v"(qa[j].z), "+v"(qa[j].w));
+#pragma unroll
+    for (int j = 0; j < kJp; ++j)
+        asm volatile("" : "+v"(qp[j].x), "+v"(qp[j].y), "+v"(qp[j].z), "+v"(qp[j].w));
+    asm volatile("" : "+v"(qo.x), "+v"(qo.y), "+v"(qo.z), "+v"(qo.w));
+    uint32_t v[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int j = 0; j < kJa; ++j) {
+        const bool ok = lane + 64u * j < kA;
+        v[0] += ok ? qa[j].x + qa[j].z : 0u;
+        v[1] += ok ? qa[j].y + qa[j].w : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kJp; ++j) {
+        const bool ok = lane + 64u * j < kP;
+        v[2] += ok ? qp[j].x + qp[j].z : 0u;
+        v[3] += ok ? qp[j].y + qp[j].w : 0u;
+    }
+    const bool ook = lane < (uint32_t)kSpread;
+    v[0] += ook ? qo.x : 0u;
+    v[1] += ook ? qo.y : 0u;
+    v[2] += ook ? qo.z : 0u;
+    v[3] += ook ? qo.w : 0u;
+    StepCounts r;
+    r.act = wave_sum(v[0]);
+    r.tact = wave_sum(v[1]);
+    r.stale = wave_sum(v[2]);
+    r.toff = wave_sum(v[3]);
+    return r;
+}
+
+// Full commit of the pending step (validation status, counts): Eq. (20),
+// statistics.
+__device__ DevScalars commit_step(const DevScalars& c, uint32_t status, uint32_t n,
+                                  const State& s, int spatial, const StepCounts& cn)
 {
     DevScalars r = c;
-    const uint32_t status = st->status;
     if (status) {
         if (r.err == 0) r.err = (status & 1u) ? -2 : -3;   // FIBAR_E_RANGE / FIBAR_E_POLARITY
         return r;
     }
     int64_t k;
     uint64_t h_new;
-    step_head(c, st, n, spatial, &k, &h_new);
+    step_head(c, status, n, spatial, &k, &h_new);
     r.k = k;
     if (!spatial) return r;
-    uint32_t act = 0, tact = 0, stale = 0, toff = 0;
-#pragma unroll
-    for (int i = 0; i < kSpread; ++i) {
-        act += st->part[i][0];
-        tact += st->part[i][1];
-        stale += st->part[i][2];
-        toff += st->part[i][3];
-    }
+    const uint32_t act = cn.act, tact = cn.tact, stale = cn.stale, toff = cn.toff;
     r.h = h_new;
     r.P = c.P + act - stale;
     r.T = c.T + tact - toff;
@@ -96,6 +158,20 @@ __device__ DevScalars commit_step(const DevScalars& c, const StepScratch* st, ui
     r.last_stale = stale;
     r.total_stale += stale;
     return r;
+}
+
+// Commit of the pending step `prev` (n events) on top of the scalars at
+// sc_in, by one full wave (the same in every lane).  The scalars and the
+// status are loaded before the count slots, so that one memory round trip
+// serves all of them.
+__device__ DevScalars commit_by_wave(const DevScalars* sc_in, const StepScratch* prev,
+                                          uint32_t n, const State& s, int spatial)
+{
+    const DevScalars c = *sc_in;
+    const uint32_t status = prev->status;
+    FIBAR_ISSUE_FENCE();
+    const StepCounts cn = spatial ? gather_counts(prev) : StepCounts{0u, 0u, 0u, 0u};
+    return commit_step(c, status, n, s, spatial, cn);
 }
 
 // Read in place of a pending step's scratch when there is none (its value
@@ -285,10 +361,6 @@ __device__ __forceinline__ void apply_tile(const State& s, const Group& g, const
     if (spatial && !tile_was_active) dT += 1u;
 }
 
-// Keeps every memory access above it above it and every one below below
-// (an empty statement; it neither waits for nor touches memory).
-#define FIBAR_ISSUE_FENCE() asm volatile("" ::: "memory")
-
 // Passes scalar-loaded values through an empty statement placed after the
 // state loads, so that no arithmetic on them (which waits for every
 // outstanding scalar load) is scheduled before those loads are issued.
@@ -379,15 +451,25 @@ __device__ __forceinline__ void pop_range(const State& s, uint64_t start, uint64
         pop_one(s, j, s.ring[j & s.ring_mask], h_old, dP, dT);
 }
 
-// Add a workgroup's activation (slot 0, 1) or deactivation (slot 2, 3)
-// counts to the step's scratch.
-__device__ __forceinline__ void add_counts(StepScratch* step, int first_slot, uint32_t a, uint32_t b)
+// Store a wave's activation (pops = false) or deactivation (pops = true)
+// counts into the step's scratch.  g is the thread's index in the step's
+// grid of that kind, so the wave's slot is g / 64; waves past the slots add
+// to the overflow counters.  Zero counts are not stored (the scratch starts
+// zeroed).
+__device__ __forceinline__ void add_counts(StepScratch* step, bool pops, uint32_t g, uint32_t a,
+                                           uint32_t b)
 {
-    block_sum2(a, b);
-    if (threadIdx.x == 0 && (a | b)) {
-        uint32_t* part = step->part[blockIdx.x % kSpread];
-        atomicAdd(&part[first_slot], a);
-        atomicAdd(&part[first_slot + 1], b);
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if ((threadIdx.x & 63u) == 0 && (a | b)) {
+        const uint32_t w = g >> 6;
+        if (w < (pops ? kPopSlots : kApplySlots)) {
+            (pops ? step->wave_pop : step->wave_apply)[w] = make_uint2(a, b);
+        } else {
+            uint32_t* part = step->part[w % kSpread] + (pops ? 2 : 0);
+            atomicAdd(&part[0], a);
+            atomicAdd(&part[1], b);
+        }
     }
 }
 

@@ -204,34 +204,23 @@ __device__ void block_exscan4(const uint64_t x[4], uint64_t ex[4], uint64_t tot[
     __syncthreads();
 }
 
+// Sum over a full wave (all 64 lanes active), in every lane: DPP adds make
+// each 16-lane row's sum (quads, half rows, rows), then the four rows' sums
+// are read out to scalars.
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// Sum of two counters over the workgroup (<= 1024 threads); the result is
-// valid in thread 0.  One atomic per workgroup instead of per wave: atomics
-// to one address serialise, so their number is what costs time.
-__device__ __forceinline__ void block_sum2(uint32_t& a, uint32_t& b)
-{
-    __shared__ uint32_t sa[16], sb[16];
-    a = wave_sum(a);
-    b = wave_sum(b);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) {
-        sa[wave] = a;
-        sb[wave] = b;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int nw = (blockDim.x + 63) >> 6;
-        for (int w = 1; w < nw; ++w) {
-            a += sa[w];
-            b += sb[w];
-        }
-    }
+    constexpr int kQuadSwap1 = 0xB1;      // quad_perm [1,0,3,2]
+    constexpr int kQuadSwap2 = 0x4E;      // quad_perm [2,3,0,1]
+    constexpr int kRowHalfMirror = 0x141;
+    constexpr int kRowMirror = 0x140;
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kQuadSwap1, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kQuadSwap2, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kRowHalfMirror, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kRowMirror, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 0) +
+           (uint32_t)__builtin_amdgcn_readlane((int)v, 16) +
+           (uint32_t)__builtin_amdgcn_readlane((int)v, 32) +
+           (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
 }
 
 // ---------------------------------------------------------------------------
