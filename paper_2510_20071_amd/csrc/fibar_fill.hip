@@ -48,6 +48,8 @@ static_assert(b_off(3) + 1 == FIBAR_FILL_PARAMS, "parameter layout");
 typedef short bf16x4 __attribute__((__vector_size__(4 * sizeof(short))));
 typedef __bf16 bf16x8 __attribute__((__vector_size__(8 * sizeof(__bf16))));
 typedef float f32x4 __attribute__((__vector_size__(4 * sizeof(float))));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 // FP32 -> BF16 bits, round to nearest even (inputs are finite).
 __device__ __forceinline__ uint16_t to_bf16(float f)
@@ -403,6 +405,7 @@ constexpr int kRegH = kFuseH + 8, kRegW = 37;      // widest read: layer 4, colu
 constexpr int kFuseThreads = 512;
 constexpr int kFuseWaves = kFuseThreads / 64;
 
+
 // Raw inputs of the region pixels one thread stages (two at most); they are
 // converted only when written to LDS, so their loads stay in flight while
 // the previous tile's layers run.
@@ -438,7 +441,10 @@ __device__ __forceinline__ void load_region(RegionIn& ri, const float* __restric
 
 // The 16x16x32 products of two 16-pixel segments (rows ra, rb, pixel
 // columns pa, pb of this lane), interleaved so the two accumulation chains
-// overlap in the matrix pipeline.
+// overlap in the matrix pipeline.  The weights are the A operand and the
+// activations the B operand, so the result is channels x pixels: lane l
+// holds output channels 4 (l / 16) .. + 3 of pixel l % 16 (one 8-byte store
+// of the four, instead of four 2-byte stores of one channel).
 __device__ __forceinline__ void segment_pair(const uint16_t* __restrict__ in, int ra, int pa,
                                              int rb, int pb, bool two, uint32_t lane,
                                              const bf16x8* b, f32x4& acc0, f32x4& acc1)
@@ -461,8 +467,8 @@ __device__ __forceinline__ void segment_pair(const uint16_t* __restrict__ in, in
     acc1 = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int q = 0; q < kPairs; ++q) {
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0[q], b[q], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[q], b[q], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[q], a0[q], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[q], a1[q], acc1, 0, 0, 0);
     }
 }
 
@@ -496,21 +502,20 @@ __device__ __forceinline__ void segment_pair_first(const uint2* __restrict__ in4
     acc1 = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int q = 0; q < kPairs0; ++q) {
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0[q], b[q], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[q], b[q], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[q], a0[q], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[q], a1[q], acc1, 0, 0, 0);
     }
 }
 
-// One layer of a tile: 16-pixel segments of rows [k, kRegH - k), k = layer + 1,
-// two per pass (independent product chains), bias, ReLU and zero padding,
-// BF16 into the other buffer; the last layer writes L + channel 0.  The first
-// layer reads the 4-channel input in buf[1] and writes buf[0]; layer l > 0
-// reads buf[(l + 1) % 2] and writes buf[l % 2].  Ends with a barrier.
+// One of the first three layers of a tile: 16-pixel segments of rows
+// [k, kRegH - k), k = layer + 1, two per pass (independent product chains),
+// bias, ReLU and zero padding, BF16 into the other buffer.  The first layer
+// reads the 4-channel input in buf[1] and writes buf[0]; layer l > 0 reads
+// buf[(l + 1) % 2] and writes buf[l % 2].  Ends with a barrier.
 template <bool kFirst>
 __device__ __forceinline__ void fused_layer(int layer, uint16_t (*buf)[kRegH * kRegW * kC],
-                                            const uint4* wsh, const float* bsh, const float* Lsh,
-                                            int y0, int x0, uint32_t H, uint32_t W, uint32_t lane,
-                                            uint32_t wv, float* __restrict__ pred)
+                                            const uint4* wsh, const float* bsh, int y0, int x0,
+                                            uint32_t H, uint32_t W, uint32_t lane, uint32_t wv)
 {
     constexpr int nq = kFirst ? kPairs0 : kPairs;
     const int kk = layer + 1;
@@ -520,8 +525,7 @@ __device__ __forceinline__ void fused_layer(int layer, uint16_t (*buf)[kRegH * k
 #pragma unroll
     for (int q = 0; q < nq; ++q)
         b[q] = *reinterpret_cast<const bf16x8*>(&wsh[(layer * kPairs + q) * 64 + lane]);
-    const uint32_t o = lane & 15;
-    const float bo = bsh[layer * kC + o];
+    const uint32_t o4 = (lane >> 4) * 4;                 // this lane's four output channels
     const int nseg = (kRegH - 2 * kk) * 2;
     for (int s0 = (int)wv; s0 < nseg; s0 += 2 * kFuseWaves) {
         const int s1 = s0 + kFuseWaves;
@@ -538,23 +542,25 @@ __device__ __forceinline__ void fused_layer(int layer, uint16_t (*buf)[kRegH * k
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
             if (half == 1 && !two) break;
-            const int r = half ? rb : ra, c0 = half ? cb : ca;
+            const int r = half ? rb : ra, c = (half ? cb : ca) + (int)(lane & 15);
             const f32x4 acc = half ? acc1 : acc0;
-            const int y = y0 + r;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int c = c0 + (int)(lane >> 4) * 4 + j;
-                const int x = x0 + c;
-                const bool inside = y >= 0 && y < (int)H && x >= 0 && x < (int)W;
-                float v = acc[j] + bo;
-                if (layer < kLayers - 1) {
-                    v = (inside && v > 0.f) ? v : 0.f;
-                    if (c < kRegW) out[(r * kRegW + c) * kC + o] = to_bf16(v);
-                } else if (o == 0 && inside && r >= 4 && r < 4 + kFuseH && c >= 4 &&
-                           c < 4 + kFuseW) {
-                    pred[(size_t)y * W + x] = v + Lsh[r * kRegW + c];
-                }
-            }
+            // the biases are read here, not held (registers are short)
+            const float4 bo = *reinterpret_cast<const float4*>(&bsh[layer * kC + o4]);
+            const int y = y0 + r, x = x0 + c;
+            const bool inside = y >= 0 && y < (int)H && x >= 0 && x < (int)W;
+            f32x2 v01, v23;
+            v01.x = acc[0] + bo.x;
+            v01.y = acc[1] + bo.y;
+            v23.x = acc[2] + bo.z;
+            v23.y = acc[3] + bo.w;
+            v01.x = (inside && v01.x > 0.f) ? v01.x : 0.f;
+            v01.y = (inside && v01.y > 0.f) ? v01.y : 0.f;
+            v23.x = (inside && v23.x > 0.f) ? v23.x : 0.f;
+            v23.y = (inside && v23.y > 0.f) ? v23.y : 0.f;
+            // round to nearest even, as to_bf16
+            const uint2 w = make_uint2(__builtin_bit_cast(uint32_t, __builtin_convertvector(v01, bf16x2)),
+                                       __builtin_bit_cast(uint32_t, __builtin_convertvector(v23, bf16x2)));
+            if (c < kRegW) *reinterpret_cast<uint2*>(&out[(r * kRegW + c) * kC + o4]) = w;
         }
     }
     __syncthreads();
@@ -622,7 +628,7 @@ __global__ __launch_bounds__(kFuseThreads) __attribute__((amdgpu_waves_per_eu(4)
 {
     __shared__ __align__(16) uint16_t buf[2][kRegH * kRegW * kC];
     __shared__ __align__(16) uint4 wsh[kLayers * kPairs * 64];
-    __shared__ float bsh[kLayers * kC];
+    __shared__ __align__(16) float bsh[kLayers * kC];
     __shared__ float Lsh[kRegH * kRegW];
     const uint32_t tiles_x = (W + kFuseW - 1) / kFuseW;
     const uint32_t tiles = tiles_x * ((H + kFuseH - 1) / kFuseH);
@@ -655,9 +661,9 @@ __global__ __launch_bounds__(kFuseThreads) __attribute__((amdgpu_waves_per_eu(4)
             load_region(ri, L, stale, log_age, (int)(next / tiles_x) * kFuseH - 4,
                         (int)(next % tiles_x) * kFuseW - 4, H, W);
 
-        fused_layer<true>(0, buf, wsh, bsh, Lsh, y0, x0, H, W, lane, wv, pred);
+        fused_layer<true>(0, buf, wsh, bsh, y0, x0, H, W, lane, wv);
         for (int layer = 1; layer < kLayers - 1; ++layer)
-            fused_layer<false>(layer, buf, wsh, bsh, Lsh, y0, x0, H, W, lane, wv, pred);
+            fused_layer<false>(layer, buf, wsh, bsh, y0, x0, H, W, lane, wv);
         fused_last_layer(buf, wsh, bsh, Lsh, y0, x0, H, W, lane, wv, pred);
     }
 }
