@@ -144,45 +144,79 @@ __global__ __launch_bounds__(kApplyBlock) void k_apply(
 // Move the window head by the target of the previous step (Eq. (20)),
 // detect pixels whose last queued event leaves the window, and write their
 // blurred values to Lb.  `sc` holds the scalars after the previous step.
-// Leading arguments as in k_apply; `stride` is the pops' thread count.
-// Workgroups from pop_blocks on write the readout that directly follows the
-// step, if there is one (`ro`).
+// Leading arguments as in k_apply.  The pops take pop_threads(pkt_events)
+// threads, the first workgroups; workgroups past them write the readout
+// that directly follows the step, if there is one (`ro`), kRoPix pixels per
+// thread.
+constexpr int kRoPix = 1;   // 2 and 4 (fewer workgroups) were slower
+
 __global__ __launch_bounds__(kPopBlock) void k_pop_blur(const DevScalars* sc, StepScratch* step,
                                                         const uint32_t* ring, uint64_t ring_mask,
                                                         PixL* px, uint32_t W, uint32_t H,
-                                                        uint32_t pkt_events, uint32_t stride,
-                                                        State s, PopReadout ro,
-                                                        uint32_t pop_blocks)
+                                                        uint32_t pkt_events, State s, PopReadout ro)
 {
     s.ring = const_cast<uint32_t*>(ring);
     s.ring_mask = ring_mask;
     s.px = px;
     s.W = W;
     s.H = H;
+    // from preloaded arguments only: a readout workgroup knows it is one
+    // without waiting for any load
+    const uint32_t threads = pop_threads(pkt_events);
+    const uint32_t pop_blocks = threads / kPopBlock;
+    if (blockIdx.x >= pop_blocks) {
+        // the readout of the state after the step; what it reads is not
+        // written by the pops (see readout_pixel_after_pops).  The first
+        // pass's pixels are loaded before the window scalars.
+        const uint64_t npx = (uint64_t)W * H;
+        const uint32_t rb = blockIdx.x - pop_blocks, nrb = gridDim.x - pop_blocks;
+        const uint64_t span = (uint64_t)nrb * kPopBlock * kRoPix;
+        const uint64_t first = (uint64_t)rb * kPopBlock * kRoPix + threadIdx.x;
+        PixL v[kRoPix];
+#pragma unroll
+        for (int q = 0; q < kRoPix; ++q) {
+            const uint64_t i = first + (uint64_t)q * kPopBlock;
+            v[q] = px[i < npx ? i : 0];
+        }
+        FIBAR_ISSUE_FENCE();
+        const uint32_t status = step->status;
+        const DevScalars c = *sc;
+        uint64_t h_old, h_new;
+        pop_bounds(c, pkt_events, &h_old, &h_new);
+        if (status) h_new = h_old;   // a rejected packet pops nothing
+        const int64_t k = status ? c.k : c.k + (int64_t)pkt_events;
+        for (uint64_t base = first; base < npx; base += span) {
+            if (base != first) {
+#pragma unroll
+                for (int q = 0; q < kRoPix; ++q) {
+                    const uint64_t i = base + (uint64_t)q * kPopBlock;
+                    v[q] = px[i < npx ? i : 0];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kRoPix; ++q) {
+                const uint64_t i = base + (uint64_t)q * kPopBlock;
+                if (i < npx)
+                    readout_pixel_after_pops(s, k, h_old, h_new, i, v[q], ro.L, ro.pbar,
+                                             ro.stale, ro.last, ro.log_age);
+            }
+        }
+        if (ro.tcnt) {
+            const uint64_t nt = (uint64_t)s.TW * ((H + 1) / 2);
+            const uint64_t tstride = (uint64_t)nrb * kPopBlock;
+            for (uint64_t t = (uint64_t)rb * kPopBlock + threadIdx.x; t < nt; t += tstride)
+                ro.tcnt[t] = tile_active_pixels(s, t, h_new);
+        }
+        return;
+    }
     // the status and the scalars are loaded together (a select, not a branch)
     const uint32_t status = step->status;
     const DevScalars c = *sc;
     uint64_t h_old, h_new;
     pop_bounds(c, pkt_events, &h_old, &h_new);
     if (status) h_new = h_old;   // a rejected packet pops nothing
-    if (blockIdx.x >= pop_blocks) {
-        // the readout of the state after the step; what it reads is not
-        // written by the pops (see readout_pixel_after_pops)
-        const int64_t k = status ? c.k : c.k + (int64_t)pkt_events;
-        const uint64_t npx = (uint64_t)W * H;
-        const uint64_t rstride = (uint64_t)(gridDim.x - pop_blocks) * kPopBlock;
-        const uint64_t r0 = (uint64_t)(blockIdx.x - pop_blocks) * kPopBlock + threadIdx.x;
-        for (uint64_t i = r0; i < npx; i += rstride)
-            readout_pixel_after_pops(s, k, h_old, h_new, i, s.px[i], ro.L, ro.pbar, ro.stale,
-                                     ro.last, ro.log_age);
-        if (ro.tcnt) {
-            const uint64_t nt = (uint64_t)s.TW * ((H + 1) / 2);
-            for (uint64_t t = r0; t < nt; t += rstride) ro.tcnt[t] = tile_active_pixels(s, t, h_new);
-        }
-        return;
-    }
     uint32_t dP = 0u, dT = 0u;
-    pop_range(s, h_old + blockIdx.x * kPopBlock + threadIdx.x, h_new, stride, h_old, dP, dT);
+    pop_range(s, h_old + blockIdx.x * kPopBlock + threadIdx.x, h_new, threads, h_old, dP, dT);
     add_counts(step, true, blockIdx.x * kPopBlock + threadIdx.x, dP, dT);
 }
 
@@ -269,18 +303,19 @@ hipError_t launch_pop_blur(const State& s, uint32_t pkt_events, StepScratch* ste
 {
     const uint32_t threads = pop_threads(pkt_events);
     if (threads == 0 || (ro && !ro->L)) return hipErrorInvalidValue;
-    const uint32_t pop_blocks = threads / kPopBlock;
+    const uint32_t pop_blocks = threads / kPopBlock;   // the kernel derives the same
     uint32_t ro_blocks = 0;
     PopReadout r{};
     if (ro) {
-        // one pixel per thread; the pop workgroups come first
-        const uint64_t b = ((uint64_t)s.W * s.H + kPopBlock - 1) / kPopBlock;
+        // kRoPix pixels per thread; the pop workgroups come first
+        const uint64_t per = (uint64_t)kPopBlock * kRoPix;
+        const uint64_t b = ((uint64_t)s.W * s.H + per - 1) / per;
         ro_blocks = (uint32_t)(b < kReadoutMaxBlocks ? (b > 0 ? b : 1) : kReadoutMaxBlocks);
         r = *ro;
     }
     return launch_timed(k_pop_blur, dim3(pop_blocks + ro_blocks), dim3(kPopBlock), st, tm.start,
                         tm.stop, (const DevScalars*)(s.sc + slot), step, (const uint32_t*)s.ring,
-                        s.ring_mask, s.px, s.W, s.H, pkt_events, threads, s, r, pop_blocks);
+                        s.ring_mask, s.px, s.W, s.H, pkt_events, s, r);
 }
 
 hipError_t launch_init_state(const State& s, hipStream_t st)
