@@ -37,7 +37,8 @@ sys.path.insert(0, ROOT)
 #                value written (4 B) + tile count read+write (8 B).
 #   group      : per event: x, y, p read (5 B); per distinct (pixel, chunk):
 #                one 32-B composed-map record written.
-KERNELS = ("group_compose", "apply", "pop_blur", "blur_write", "readout")
+KERNELS = ("group_compose", "apply", "pop_blur", "pop_blur_readout", "readout")
+LAUNCH_MODES = {"direct": 0, "graph": 1}
 KERNEL_SOURCES = ("paper_2510_20071_amd/csrc/fibar_kernels.hip",
                   "paper_2510_20071_amd/csrc/fibar_step.h",
                   "paper_2510_20071_amd/csrc/fibar_tile.h",
@@ -343,6 +344,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--launch", choices=sorted(LAUNCH_MODES), default="direct",
+                    help="how a batch's in-order kernels are issued (spatial filter on)")
     ap.add_argument("--events", type=int, default=100_000_000)
     ap.add_argument("--cpu-sample-events", type=int, default=100_000_000,
                     help="events of the stream the oracle is timed on")
@@ -452,14 +455,20 @@ def main():
 
     def run_mode(spatial, steps, warmup, time_kernel=None):
         ctx = fb.Context(W, H, spatial_filter=spatial, stream=stream)
+        if spatial:
+            assert fb.fibar_set_launch_mode(ctx.handle, LAUNCH_MODES[args.launch]) == 0
+        # timing is on from the warm-up, so that the warm-up already builds
+        # every graph the timed steps replay
+        if time_kernel is not None:
+            fb.fibar_set_kernel_timing(ctx.handle, 1 << KERNELS.index(time_kernel),
+                                       args.time_every)
         for _ in range(warmup):
             assert ctx.reset() == 0
             assert lib.fibar_submit(ctx.handle, ops, n_ops) == 0
         torch.cuda.synchronize()
         if time_kernel is not None:
-            fb.fibar_set_kernel_timing(ctx.handle, 1 << KERNELS.index(time_kernel),
-                                       args.time_every)
-            fb.fibar_kernel_time(ctx.handle, KERNELS.index(time_kernel))  # clear
+            for kind in range(5):
+                fb.fibar_kernel_time(ctx.handle, kind)  # clear the warm-up's
         torch.cuda.synchronize()
         t_start = time.perf_counter()
         for _ in range(steps):
@@ -471,6 +480,8 @@ def main():
         if time_kernel is not None:
             rc, ms, launches = fb.fibar_kernel_time(ctx.handle, KERNELS.index(time_kernel))
             kt = (ms, launches)
+            for kind in range(5):
+                fb.fibar_kernel_time(ctx.handle, kind)  # the others' events go back to the pool
             fb.fibar_set_kernel_timing(ctx.handle, 0)
         assert ctx.synchronize() == 0
         st = ctx.stats() if spatial else None
@@ -579,7 +590,7 @@ def main():
         "config": {"workload": "hd720: 1280x720 sensor, %d events, %d-event packets, %d readouts "
                                "(random indices), T_cut=40, r_fill=1/2, spatial filter on"
                                % (n, wl.packet, n_read),
-                   "events": n, "packets": n_push, "readouts": n_read},
+                   "events": n, "packets": n_push, "readouts": n_read, "launch": args.launch},
         "blur_off_mev_s": None if mev_off is None else round(mev_off, 2),
         "workload_stats": {"distinct_pixels_per_event": round(u, 4),
                            "stale_pixels_per_event": round(s_per_ev, 5),

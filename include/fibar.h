@@ -224,11 +224,30 @@ int fibar_reset(fibar_ctx* c);
  * duration (ms) and the count of the launches of kernel `kernel` timed since
  * the last call, and clears them.  Kernels: 0 group+compose (bulk; the whole
  * blur-off batch in that mode), 1 apply, 2 window pop + stale blur values
- * (launches that also write a readout are not timed), 3 (unused), 4 readout
- * (the separate readout kernel).
+ * (launches that also write a readout are not timed with direct launches),
+ * 3 pop launches that also write a readout (graph launches only), 4 readout
+ * (the separate readout kernel).  With graph launches (below) the count
+ * restarts with every batch, pop launches count whether or not they also
+ * write a readout, and a timed launch's events are recorded by graph nodes
+ * just before and after its kernel.
  */
 int fibar_set_kernel_timing(fibar_ctx* c, uint32_t kernel_mask, uint32_t every);
 int fibar_kernel_time(fibar_ctx* c, int kernel, double* total_ms, uint64_t* launches);
+
+/*
+ * How the in-order kernels of a batch are issued (spatial filter on).
+ * FIBAR_LAUNCH_DIRECT (the default): one HIP launch per kernel.
+ * FIBAR_LAUNCH_GRAPH: the batch's launches are recorded and replayed as one
+ * HIP graph; batches with the same sequence of kernels (the usual case:
+ * batches of the same packet count) reuse an instantiated graph whose node
+ * parameters are updated, which costs the host much less per kernel than a
+ * launch.  A batch holding a readout into host memory runs on direct
+ * launches.  Results are identical in both modes.  Returns
+ * FIBAR_E_INVALID_ARG for another mode.
+ */
+#define FIBAR_LAUNCH_DIRECT 0
+#define FIBAR_LAUNCH_GRAPH 1
+int fibar_set_launch_mode(fibar_ctx* c, int mode);
 
 /*
  * Several independent streams advanced together.  A group holds 1..64

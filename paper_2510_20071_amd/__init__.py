@@ -29,6 +29,8 @@ FIBAR_E_DEVICE = -6
 FIBAR_E_UNSUPPORTED = -7
 FIBAR_REG_PACKET = 0
 FIBAR_OP_PUSH = 0
+FIBAR_LAUNCH_DIRECT = 0
+FIBAR_LAUNCH_GRAPH = 1
 FIBAR_OP_READOUT = 1
 
 
@@ -91,6 +93,7 @@ _SIGNATURES = {
     "fibar_kernel_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_uint64)]),
+    "fibar_set_launch_mode": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
 }
 
 _SIGNATURES.update({
@@ -130,7 +133,7 @@ _SIGNATURES.update({
     "fibar_fill_destroy": (None, [ctypes.c_void_p]),
 })
 
-KERNEL_NAMES = ("group_compose", "apply", "pop_blur", "blur_write", "readout")
+KERNEL_NAMES = ("group_compose", "apply", "pop_blur", "pop_blur_readout", "readout")
 
 _lib = None
 
@@ -211,6 +214,10 @@ def fibar_reset(handle) -> int:
 
 def fibar_set_kernel_timing(handle, kernel_mask: int, every: int = 1) -> int:
     return load().fibar_set_kernel_timing(handle, int(kernel_mask), int(every))
+
+
+def fibar_set_launch_mode(handle, mode: int) -> int:
+    return load().fibar_set_launch_mode(handle, int(mode))
 
 
 def fibar_kernel_time(handle, kernel: int):

@@ -53,20 +53,197 @@ hipEvent_t pooled_event(fibar_ctx* c)
 }
 
 // Launch through `fn`; every time_every-th launch of a timed kernel kind
-// carries start/stop events on its dispatch.
+// carries start/stop events on its dispatch.  Launches count under `kind`
+// and their times are kept under `store` (a pop launch that also writes a
+// readout counts as a pop and is kept apart).  A recorded batch counts from
+// its own start, so that batches of the same shape time the same launches
+// (and replay the same graph).
 template <class F>
-hipError_t timed_launch(fibar_ctx* c, int kind, F&& fn)
+hipError_t timed_launch(fibar_ctx* c, int kind, int store, F&& fn)
 {
-    if (!(c->time_mask & (1u << kind)) || (c->time_seq[kind]++ % c->time_every) != 0)
+    uint64_t& seq = c->recording ? c->batch_seq[kind] : c->time_seq[kind];
+    if (!(c->time_mask & (1u << kind)) || (seq++ % c->time_every) != 0)
         return fn(LaunchTiming());
     LaunchTiming tm;
     tm.start = pooled_event(c);
     tm.stop = pooled_event(c);
     if (!tm.start || !tm.stop) return hipErrorOutOfMemory;
     const hipError_t e = fn(tm);
-    c->timed[kind].emplace_back(tm.start, tm.stop);
+    c->timed[store].emplace_back(tm.start, tm.stop);
     return e;
 }
+template <class F>
+hipError_t timed_launch(fibar_ctx* c, int kind, F&& fn)
+{
+    return timed_launch(c, kind, kind, fn);
+}
+
+// ---- batch graphs ------------------------------------------------------------
+
+#define HIP_CHECK_RET(expr)                   \
+    do {                                      \
+        const hipError_t e_ = (expr);         \
+        if (e_ != hipSuccess) return e_;      \
+    } while (0)
+
+void destroy_graph(BatchGraph* g)
+{
+    for (int e = 0; e < 2; ++e) {
+        if (g->done[e]) {
+            (void)hipEventSynchronize(g->done[e]);
+            (void)hipEventDestroy(g->done[e]);
+        }
+        if (g->exec[e]) (void)hipGraphExecDestroy(g->exec[e]);
+    }
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
+hipKernelNodeParams node_params(RecordedLaunch& L)
+{
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(L.func);
+    kp.gridDim = L.grid;
+    kp.blockDim = L.block;
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = L.params.data();
+    kp.extra = nullptr;
+    return kp;
+}
+
+// A chain of the recorded launches, instantiated twice.
+hipError_t build_graph(std::vector<RecordedLaunch>& ls, BatchGraph* g)
+{
+    const size_t n = ls.size();
+    g->funcs.resize(n);
+    g->timed.resize(n);
+    g->knode.assign(n, nullptr);
+    g->ev_start.assign(n, nullptr);
+    g->ev_stop.assign(n, nullptr);
+    hipError_t e = hipGraphCreate(&g->graph, 0);
+    hipGraphNode_t prev = nullptr;
+    for (size_t i = 0; i < n && e == hipSuccess; ++i) {
+        RecordedLaunch& L = ls[i];
+        g->funcs[i] = L.func;
+        g->timed[i] = L.start ? 1 : 0;
+        if (L.start) {
+            e = hipGraphAddEventRecordNode(&g->ev_start[i], g->graph, prev ? &prev : nullptr,
+                                           prev ? 1 : 0, L.start);
+            prev = g->ev_start[i];
+        }
+        const hipKernelNodeParams kp = node_params(L);
+        if (e == hipSuccess)
+            e = hipGraphAddKernelNode(&g->knode[i], g->graph, prev ? &prev : nullptr,
+                                      prev ? 1 : 0, &kp);
+        prev = g->knode[i];
+        if (e == hipSuccess && L.stop) {
+            e = hipGraphAddEventRecordNode(&g->ev_stop[i], g->graph, &prev, 1, L.stop);
+            prev = g->ev_stop[i];
+        }
+    }
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        e = hipGraphInstantiate(&g->exec[k], g->graph, nullptr, nullptr, 0);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&g->done[k], hipEventDisableTiming);
+    }
+    g->fresh[0] = true;   // copy 0 runs this batch as instantiated; copy 1 is updated first
+    return e;
+}
+
+bool same_sequence(const BatchGraph* g, const std::vector<RecordedLaunch>& ls)
+{
+    if (g->funcs.size() != ls.size()) return false;
+    for (size_t i = 0; i < ls.size(); ++i)
+        if (g->funcs[i] != ls[i].func || g->timed[i] != (ls[i].start ? 1 : 0)) return false;
+    return true;
+}
+
+constexpr size_t kMaxGraphs = 8;
+
+// Run the recorded batch: the cached graph of the same kernel sequence with
+// this batch's parameters, or a new one.
+hipError_t replay_batch(fibar_ctx* c)
+{
+    std::vector<RecordedLaunch>& ls = c->rec.launches;
+    if (ls.empty()) return hipSuccess;
+    BatchGraph* g = nullptr;
+    for (BatchGraph* b : c->graphs)
+        if (same_sequence(b, ls)) {
+            g = b;
+            break;
+        }
+    if (!g) {
+        if (c->graphs.size() >= kMaxGraphs) {
+            size_t lru = 0;
+            for (size_t i = 1; i < c->graphs.size(); ++i)
+                if (c->graphs[i]->last_use < c->graphs[lru]->last_use) lru = i;
+            destroy_graph(c->graphs[lru]);
+            c->graphs.erase(c->graphs.begin() + (long)lru);
+        }
+        g = new BatchGraph();
+        const hipError_t e = build_graph(ls, g);
+        if (e != hipSuccess) {
+            destroy_graph(g);
+            return e;
+        }
+        c->graphs.push_back(g);
+    }
+    g->last_use = ++c->graph_clock;
+    const int k = g->next;
+    g->next ^= 1;
+    // the copy's previous launch must be over before its parameters change
+    if (g->launched[k]) HIP_CHECK_RET(hipEventSynchronize(g->done[k]));
+    if (!g->fresh[k]) {
+        for (size_t i = 0; i < ls.size(); ++i) {
+            const hipKernelNodeParams kp = node_params(ls[i]);
+            HIP_CHECK_RET(hipGraphExecKernelNodeSetParams(g->exec[k], g->knode[i], &kp));
+            if (ls[i].start) {
+                HIP_CHECK_RET(hipGraphExecEventRecordNodeSetEvent(g->exec[k], g->ev_start[i],
+                                                                  ls[i].start));
+                HIP_CHECK_RET(hipGraphExecEventRecordNodeSetEvent(g->exec[k], g->ev_stop[i],
+                                                                  ls[i].stop));
+            }
+        }
+    }
+    g->fresh[k] = false;
+    HIP_CHECK_RET(hipGraphLaunch(g->exec[k], c->st));
+    HIP_CHECK_RET(hipEventRecord(g->done[k], c->st));
+    g->launched[k] = true;
+    return hipSuccess;
+}
+
+// Records the launches of its scope (graph mode) and replays them at finish().
+struct BatchRecording {
+    fibar_ctx* c;
+    bool on;
+    BatchRecording(fibar_ctx* ctx, bool enable) : c(ctx), on(enable)
+    {
+        if (!on) return;
+        c->rec.launches.clear();
+        for (auto& q : c->batch_seq) q = 0;
+        c->recording = true;
+        tl_recorder = &c->rec;
+    }
+    void stop()
+    {
+        if (!on) return;
+        tl_recorder = nullptr;
+        c->recording = false;
+    }
+    hipError_t finish()
+    {
+        if (!on) return hipSuccess;
+        stop();
+        const hipError_t e = replay_batch(c);
+        c->rec.launches.clear();
+        on = false;
+        return e;
+    }
+    ~BatchRecording()
+    {
+        stop();
+        if (c) c->rec.launches.clear();
+    }
+};
 
 void free_ctx(fibar_ctx* c)
 {
@@ -101,6 +278,7 @@ void free_ctx(fibar_ctx* c)
             (void)hipEventDestroy(pr.second);
         }
     for (hipEvent_t ev : c->event_pool) (void)hipEventDestroy(ev);
+    for (BatchGraph* g : c->graphs) destroy_graph(g);
     delete c;
 }
 
@@ -221,6 +399,12 @@ int run_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, uint32_t
 {
     if (n == 0) return FIBAR_OK;
     if (c->region_path) return run_region_batch(c, ops, n, n_chunks, n_steps);
+    // graph mode replays the batch's kernels as one graph; a readout into
+    // host memory (copies and a wait between the kernels) keeps the batch on
+    // direct launches
+    bool graph = c->graph_mode;
+    for (size_t i = 0; graph && i < n; ++i)
+        if (ops[i].kind == 1 && !ops[i].ro.on_device) graph = false;
     if (n_chunks > 0) {
         // the pinned descriptor buffer may still feed a previous copy
         HIP_TRY(hipEventSynchronize(c->chunks_free));
@@ -242,6 +426,9 @@ int run_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, uint32_t
                                hipMemcpyHostToDevice, c->st));
         HIP_TRY(hipEventRecord(c->chunks_free, c->st));
         HIP_TRY(hipMemsetAsync(c->scratch, 0, (size_t)n_steps * sizeof(StepScratch), c->st));
+    }
+    BatchRecording recording(c, graph);   // the kernels from here on
+    if (n_chunks > 0) {
         HIP_TRY(timed_launch(c, 0, [&](const LaunchTiming& tm) {
             return launch_sort_compose(c->d_chunks, n_chunks, c->seg, c->seg_count, c->scratch,
                                        c->W, c->H, c->key_bits, c->coef, c->st, tm);
@@ -281,7 +468,15 @@ int run_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, uint32_t
                 const fibar_readout_buf& rb = ops[i + 1].ro;
                 PopReadout pr{rb.brightness, rb.pbar,     rb.stale_mask,
                               rb.last_index, rb.log_age, rb.tile_count};
-                HIP_TRY(launch_pop_blur(c->s, nev, stp, slot, &pr, c->st));
+                if (graph) {
+                    // counted as a pop, so that the timed launches of a
+                    // batch do not depend on where its readouts fall
+                    HIP_TRY(timed_launch(c, 2, 3, [&](const LaunchTiming& tm) {
+                        return launch_pop_blur(c->s, nev, stp, slot, &pr, c->st, tm);
+                    }));
+                } else {
+                    HIP_TRY(launch_pop_blur(c->s, nev, stp, slot, &pr, c->st));
+                }
                 ++i;   // the readout op is done
             } else {
                 HIP_TRY(timed_launch(c, 2, [&](const LaunchTiming& tm) {
@@ -297,6 +492,7 @@ int run_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, uint32_t
         HIP_TRY(launch_commit(c->s, pend, pend_n, c->cur_slot, c->cur_slot ^ 1, sp, c->st));
         c->cur_slot ^= 1;
     }
+    HIP_TRY(recording.finish());
     return FIBAR_OK;
 }
 
@@ -501,6 +697,10 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
     while (ring < (uint64_t)p.q_max + p.max_packet) ring <<= 1;
     const uint64_t stg = (uint64_t)kMaxBatchChunks * kChunk;
 
+    const uint64_t n_regions = (npx + kRegion - 1) / kRegion;
+    c->region_path = !p.spatial_filter && n_regions <= kMaxRegions;
+    const size_t mc = kMaxBatchChunks;
+
     hipError_t e = hipSuccess;
     auto alloc = [&](void** ptr, size_t bytes) {
         if (e == hipSuccess) e = hipMalloc(ptr, bytes);
@@ -509,17 +709,15 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
     alloc((void**)&c->s.pp, npx * sizeof(PixP));
     alloc((void**)&c->s.ring, ring * 4);
     alloc((void**)&c->s.sc, 2 * sizeof(DevScalars));
-    alloc((void**)&c->d_chunks, kMaxBatchChunks * sizeof(ChunkDesc));
+    alloc((void**)&c->d_chunks, mc * sizeof(ChunkDesc));
     // 4 spare records: an item reads records up to i + 3 of its chunk
-    alloc((void**)&c->seg, ((size_t)kMaxBatchChunks * kChunk + 4) * sizeof(SegRec));
-    alloc((void**)&c->seg_count, kMaxBatchChunks * 4);
-    alloc((void**)&c->scratch, kMaxBatchChunks * sizeof(StepScratch));
+    alloc((void**)&c->seg, (mc * kChunk + 4) * sizeof(SegRec));
+    alloc((void**)&c->seg_count, mc * 4);
+    alloc((void**)&c->scratch, mc * sizeof(StepScratch));
     alloc((void**)&c->stg_x, stg * 2);
     alloc((void**)&c->stg_y, stg * 2);
     alloc((void**)&c->stg_p, stg);
-    const uint64_t n_regions = (npx + kRegion - 1) / kRegion;
-    if (!p.spatial_filter && n_regions <= kMaxRegions) {
-        c->region_path = true;
+    if (c->region_path) {
         c->rb.n_regions = (uint32_t)n_regions;
         alloc((void**)&c->rb.cnt, (size_t)kMaxBatchChunks * n_regions * 4);
         alloc((void**)&c->rb.base, (n_regions + 1) * 8);
@@ -530,7 +728,7 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
         if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_ro, kMaxBatchReadouts * sizeof(RegionReadout), 0);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ro_free, hipEventDisableTiming);
     }
-    if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_chunks, kMaxBatchChunks * sizeof(ChunkDesc), 0);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_chunks, mc * sizeof(ChunkDesc), 0);
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_sc, sizeof(DevScalars), 0);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->chunks_free, hipEventDisableTiming);
     if (e != hipSuccess) {
@@ -633,6 +831,13 @@ int fibar_set_kernel_timing(fibar_ctx* c, uint32_t kernel_mask, uint32_t every)
     c->time_mask = kernel_mask;
     c->time_every = every;
     for (auto& q : c->time_seq) q = 0;
+    return FIBAR_OK;
+}
+
+int fibar_set_launch_mode(fibar_ctx* c, int mode)
+{
+    if (!c || (mode != FIBAR_LAUNCH_DIRECT && mode != FIBAR_LAUNCH_GRAPH)) return FIBAR_E_INVALID_ARG;
+    c->graph_mode = mode == FIBAR_LAUNCH_GRAPH;
     return FIBAR_OK;
 }
 

@@ -41,6 +41,14 @@ struct fibar_ctx {
     uint64_t time_seq[5] = {};
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[5];
     std::vector<hipEvent_t> event_pool;
+    // graph launches (blur on): a batch's kernels are recorded and replayed
+    // as one HIP graph; graphs are cached by their sequence of kernels
+    bool graph_mode = false;
+    bool recording = false;             // the current batch is being recorded
+    uint64_t batch_seq[5] = {};         // timing counters of the recorded batch
+    fibar::LaunchRecorder rec;
+    std::vector<fibar::BatchGraph*> graphs;
+    uint64_t graph_clock = 0;
 };
 
 

@@ -6,6 +6,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <memory>
+#include <tuple>
+#include <utility>
+#include <vector>
+
 namespace fibar {
 
 // One LDS sort tile: 1024 threads x 16 events.  A packet larger than this is
@@ -119,10 +124,63 @@ struct LaunchTiming {
     hipEvent_t start = nullptr, stop = nullptr;
 };
 
-template <typename K, typename... A>
-inline hipError_t launch_timed(K kernel, dim3 grid, dim3 block, hipStream_t st,
+// Launch recording: while a recorder is set on the calling thread,
+// launch_timed appends the launch (kernel, shape, a copy of its parameters
+// converted to the kernel's parameter types, timing events) instead of
+// issuing it.  The host then replays a batch's launches as one HIP graph.
+struct RecordedLaunch {
+    const void* func = nullptr;
+    dim3 grid, block;
+    std::shared_ptr<void> args;      // the parameters (a std::tuple)
+    std::vector<void*> params;       // pointers to each of them
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+struct LaunchRecorder {
+    std::vector<RecordedLaunch> launches;
+};
+inline thread_local LaunchRecorder* tl_recorder = nullptr;
+
+// A batch's recorded launches as an instantiated HIP graph: a chain of kernel
+// nodes, with event-record nodes around the timed ones.  Two executable
+// copies are used in turn, so that one is updated while the other may still
+// run; `done` marks the end of each copy's last launch.
+struct BatchGraph {
+    std::vector<const void*> funcs;          // the kernels, in order
+    std::vector<uint8_t> timed;              // 1: launch carries events
+    hipGraph_t graph = nullptr;
+    std::vector<hipGraphNode_t> knode, ev_start, ev_stop;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    hipEvent_t done[2] = {nullptr, nullptr};
+    bool launched[2] = {false, false};
+    bool fresh[2] = {false, false};          // holds exactly the recorded parameters
+    int next = 0;
+    uint64_t last_use = 0;
+};
+
+template <typename T, size_t... I>
+inline std::vector<void*> tuple_ptrs(T& t, std::index_sequence<I...>)
+{
+    return {static_cast<void*>(&std::get<I>(t))...};
+}
+
+template <typename... P, typename... A>
+inline hipError_t launch_timed(void (*kernel)(P...), dim3 grid, dim3 block, hipStream_t st,
                                hipEvent_t start, hipEvent_t stop, A... args)
 {
+    if (LaunchRecorder* r = tl_recorder) {
+        auto t = std::make_shared<std::tuple<std::decay_t<P>...>>(
+            static_cast<std::decay_t<P>>(args)...);
+        RecordedLaunch L;
+        L.func = reinterpret_cast<const void*>(kernel);
+        L.grid = grid;
+        L.block = block;
+        L.params = tuple_ptrs(*t, std::index_sequence_for<P...>{});
+        L.args = std::move(t);
+        L.start = start;
+        L.stop = stop;
+        r->launches.push_back(std::move(L));
+        return hipSuccess;
+    }
     if (start || stop)
         hipExtLaunchKernelGGL(kernel, grid, block, 0, st, start, stop, 0, args...);
     else

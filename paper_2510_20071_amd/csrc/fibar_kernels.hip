@@ -331,9 +331,8 @@ hipError_t launch_init_state(const State& s, hipStream_t st)
 hipError_t launch_commit(const State& s, const StepScratch* prev, uint32_t prev_events,
                          int slot_in, int slot_out, int spatial, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_commit, dim3(1), dim3(64), 0, st, s, prev, prev_events, slot_in,
-                       slot_out, spatial);
-    return hipGetLastError();
+    return launch_timed(k_commit, dim3(1), dim3(64), st, nullptr, nullptr, s, prev, prev_events,
+                        slot_in, slot_out, spatial);
 }
 
 hipError_t launch_readout(const State& s, int spatial, const StepScratch* prev,
