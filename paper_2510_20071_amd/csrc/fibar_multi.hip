@@ -115,7 +115,7 @@ __device__ __forceinline__ uint32_t lane_end(const StreamStep* rec, uint32_t S, 
 {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t e = lane < S ? rec[lane].end[kind] : 0xffffffffu;
-    *total = __shfl(e, (int)S - 1);
+    *total = (uint32_t)__builtin_amdgcn_readlane((int)e, (int)S - 1);   // S is uniform
     return e;
 }
 
@@ -124,7 +124,7 @@ __device__ __forceinline__ uint32_t lane_end(const StreamStep* rec, uint32_t S, 
 __device__ __forceinline__ uint32_t owner(uint32_t e, uint32_t t, uint32_t* start)
 {
     const uint32_t k = (uint32_t)__popcll(__ballot(e <= t));
-    const uint32_t prev_end = __shfl(e, (int)(k > 0 ? k - 1 : 0));
+    const uint32_t prev_end = (uint32_t)__builtin_amdgcn_readlane((int)e, (int)(k > 0 ? k - 1 : 0));
     *start = k > 0 ? prev_end : 0u;
     return k;
 }
@@ -197,14 +197,17 @@ __device__ __forceinline__ State owner_state(const LaneState& l, uint32_t k)
     return s;
 }
 
-// Every round kernel gets `rr`, the round's S records.
-__global__ __launch_bounds__(256) void k_multi_apply(MultiArgs a, const StreamStep* rr, int sub)
+// Every round kernel gets `rr`, the round's S records, as its leading
+// arguments: plain ones, so that they arrive preloaded in scalar registers
+// (a leading struct argument stops the preloading, and every kernel then
+// began with a round trip for its arguments).
+__global__ __launch_bounds__(256) void k_multi_apply(const StreamStep* rr, uint32_t S, int sub)
 {
     // this lane's record: the fields an apply task needs, loaded together with
     // the task counts (the fence keeps them from sinking behind the lookup)
     const uint32_t lane = threadIdx.x & 63u;
-    const StreamStep* mine = rr + (lane < a.S ? lane : 0u);
-    const LaneState ls = lane_state(rr, a.S);
+    const StreamStep* mine = rr + (lane < S ? lane : 0u);
+    const LaneState ls = lane_state(rr, S);
     const StepScratch* l_prev = mine->prev;
     StepScratch* l_step = mine->step;
     const uint16_t* l_x = mine->chunk[sub].x;
@@ -215,7 +218,7 @@ __global__ __launch_bounds__(256) void k_multi_apply(MultiArgs a, const StreamSt
     const uint32_t l_prev_events = mine->prev_events;
     const int32_t l_slot_in = mine->slot_in, l_slot_out = mine->slot_out;
     uint32_t total;
-    const uint32_t le = lane_end(rr, a.S, sub, &total);
+    const uint32_t le = lane_end(rr, S, sub, &total);
     FIBAR_ISSUE_FENCE();
     for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
         uint32_t start;
@@ -262,16 +265,16 @@ __global__ __launch_bounds__(256) void k_multi_apply(MultiArgs a, const StreamSt
     }
 }
 
-__global__ __launch_bounds__(256) void k_multi_pop(MultiArgs a, const StreamStep* rr)
+__global__ __launch_bounds__(256) void k_multi_pop(const StreamStep* rr, uint32_t S)
 {
     const uint32_t lane = threadIdx.x & 63u;
-    const StreamStep* mine = rr + (lane < a.S ? lane : 0u);
-    const LaneState ls = lane_state(rr, a.S);
+    const StreamStep* mine = rr + (lane < S ? lane : 0u);
+    const LaneState ls = lane_state(rr, S);
     StepScratch* l_step = mine->step;
     const uint32_t l_events = mine->events, l_pop_blocks = mine->pop_blocks;
     const int32_t l_pop_slot = mine->pop_slot;
     uint32_t total;
-    const uint32_t le = lane_end(rr, a.S, 2, &total);
+    const uint32_t le = lane_end(rr, S, 2, &total);
     FIBAR_ISSUE_FENCE();
     for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
         uint32_t start;
@@ -291,7 +294,7 @@ __global__ __launch_bounds__(256) void k_multi_pop(MultiArgs a, const StreamStep
     }
 }
 
-__global__ __launch_bounds__(256) void k_multi_readout(MultiArgs a, const StreamStep* rr)
+__global__ __launch_bounds__(256) void k_multi_readout(const StreamStep* rr, MultiArgs a)
 {
     const uint32_t off = rr->ro_off, cnt = rr->ro_cnt;
     for (uint32_t t = blockIdx.x; t < cnt; t += gridDim.x) {
@@ -441,14 +444,14 @@ void launch_round_kernels(fibar_multi* m, const Shape& sh, const StreamStep* rec
     };
     for (uint32_t j = 0; j < rounds; ++j) {
         const StreamStep* rr = rec + (size_t)j * m->n;
-        hipLaunchKernelGGL(k_multi_apply, dim3(grid(j, 0)), dim3(sh.block), 0, m->st, a, rr, 0);
+        hipLaunchKernelGGL(k_multi_apply, dim3(grid(j, 0)), dim3(sh.block), 0, m->st, rr, a.S, 0);
         if (var & 1)
-            hipLaunchKernelGGL(k_multi_apply, dim3(grid(j, 1)), dim3(sh.block), 0, m->st, a, rr, 1);
-        hipLaunchKernelGGL(k_multi_pop, dim3(grid(j, 2)), dim3(sh.block), 0, m->st, a, rr);
+            hipLaunchKernelGGL(k_multi_apply, dim3(grid(j, 1)), dim3(sh.block), 0, m->st, rr, a.S, 1);
+        hipLaunchKernelGGL(k_multi_pop, dim3(grid(j, 2)), dim3(sh.block), 0, m->st, rr, a.S);
     }
     if (var & 2)
         hipLaunchKernelGGL(k_multi_readout, dim3(grid(rounds - 1, kKinds)), dim3(sh.block), 0,
-                           m->st, a, rec + (size_t)(rounds - 1) * m->n);
+                           m->st, rec + (size_t)(rounds - 1) * m->n, a);
 }
 
 // The launches of a graph: stage the records, the rounds on the ring, advance.
