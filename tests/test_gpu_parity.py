@@ -414,6 +414,66 @@ def test_pop_launch_readouts_after_rejected_and_multi_chunk_packets():
     ctx.close()
 
 
+@pytest.mark.parametrize("W,H", [(346, 260), (3, 3), (5, 4), (17, 9)])
+def test_pop_launch_readouts_on_ragged_pixel_counts(W, H):
+    """Readouts written by the pop launch when the pixel count is not a
+    multiple of its 128-thread workgroups (346 x 260, 17 x 9) or is below
+    one workgroup (3 x 3, 5 x 4), with a small target length so that pixels
+    go stale in most steps: every output equals the separate readout kernel
+    of the same state (a readout following another readout) bit for bit."""
+    torch, dev = torch_dev()
+    npx, ntiles = W * H, ((W + 1) // 2) * ((H + 1) // 2)
+    rng = np.random.default_rng(W * 1000 + H)
+    n = 40_000
+    pix = np.empty(n, np.int64)
+    cur = 0
+    for e in range(n):
+        if rng.random() < 0.3:
+            cur = int(rng.integers(0, npx))
+        pix[e] = cur
+    ev = eventsim.Events((pix % W).astype(np.uint16), (pix // W).astype(np.uint16),
+                         (rng.random(n) < 0.5).astype(np.uint8), np.arange(n, dtype=np.uint64))
+    gx, gy, gp = to_device(ev)
+    ctx = make_ctx(W, H, q_min=1, q_max=max(64, npx // 2))
+    ops, bufs, packets = [], [], []
+    a = 0
+    flush("pop-launch readouts %dx%d" % (W, H))
+    while a < n:
+        b = min(n, a + int(rng.integers(1, 3000)))
+        packets.append((a, b))
+        ops.append(fb.push_op(gx[a:b], gy[a:b], gp[a:b]))
+        for _ in range(2):   # the first is taken by the pop launch, the second is separate
+            d = dict(L=torch.empty(npx, dtype=torch.float32, device=dev),
+                     pbar=torch.empty(npx, dtype=torch.float32, device=dev),
+                     stale=torch.empty(npx, dtype=torch.uint8, device=dev),
+                     last=torch.empty(npx, dtype=torch.int64, device=dev),
+                     log_age=torch.empty(npx, dtype=torch.float32, device=dev),
+                     tcnt=torch.empty(ntiles, dtype=torch.int32, device=dev))
+            bufs.append(d)
+            ops.append(fb.readout_op(int(ev.t[b - 1]), d["L"], pbar=d["pbar"], stale=d["stale"],
+                                     last=d["last"], log_age=d["log_age"], tcnt=d["tcnt"]))
+        a = b
+    assert ctx.submit(ops) == 0
+    torch.cuda.synchronize()
+    assert ctx.stats()["total_stale"] > 0
+    for j in range(0, len(bufs), 2):
+        f = {k: v.cpu().numpy() for k, v in bufs[j].items()}
+        r = {k: v.cpu().numpy() for k, v in bufs[j + 1].items()}
+        for key in f:
+            assert np.array_equal(f[key].view(np.uint8), r[key].view(np.uint8)), \
+                "%s after push %d" % (key, j // 2)
+    orc = oracle.Oracle(W, H, q_min=1, q_max=max(64, npx // 2))
+    for a, b in packets:   # the target is regulated once per packet
+        assert orc.push(ev.x[a:b], ev.y[a:b], ev.p[a:b]) == 0
+    o = orc.readout(0)
+    g = {k: v.cpu().numpy() for k, v in bufs[-1].items()}
+    assert np.array_equal(g["last"], o["last"]) and np.array_equal(g["stale"], o["stale"])
+    assert np.array_equal(g["tcnt"].view(np.uint32), o["tcnt"])
+    d = np.abs(g["L"].astype(np.float64) - o["L"])
+    assert np.all(d <= REL * np.maximum(np.abs(o["L"]), 1.0))
+    ctx.close()
+
+
 def test_nsf_rejects_spatial_outputs():
     ctx = make_ctx(32, 16, spatial_filter=False, q_min=1)
     npx = 32 * 16
