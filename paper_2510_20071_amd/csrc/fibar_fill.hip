@@ -439,71 +439,102 @@ __device__ __forceinline__ void load_region(RegionIn& ri, const float* __restric
     }
 }
 
-// The 16x16x32 products of two 16-pixel segments (rows ra, rb, pixel
-// columns pa, pb of this lane), interleaved so the two accumulation chains
-// overlap in the matrix pipeline.  The weights are the A operand and the
-// activations the B operand, so the result is channels x pixels: lane l
-// holds output channels 4 (l / 16) .. + 3 of pixel l % 16 (one 8-byte store
-// of the four, instead of four 2-byte stores of one channel).
-__device__ __forceinline__ void segment_pair(const uint16_t* __restrict__ in, int ra, int pa,
-                                             int rb, int pb, bool two, uint32_t lane,
+// Operand addresses.  A lane's operands of a segment sit at fixed offsets
+// from the segment's first pixel, so they are computed once per layer: the
+// loop over segments then adds one wave-uniform base per segment instead of
+// recomputing, and bounds-checking, every address.  No check is needed: layer
+// k reads region rows [k - 1, kRegH - k] and columns [k - 1, k + 32], all
+// inside the region.  A tap past the ninth (its weights are zero) reads the
+// ninth tap's operand, finite data wherever the real tap's is.
+//
+// K = 32 operands (16 -> 16 layers): operand q takes tap 2q + (g >> 1) and
+// channels 8 (g & 1) .. + 7 of pixel (lane & 15), g = lane / 16; element
+// offsets in the 16-channel activation buffer.
+__device__ __forceinline__ void tap_offsets(uint32_t lane, int (&off)[kPairs])
+{
+    const int g = (int)(lane >> 4), px = (int)(lane & 15);
+#pragma unroll
+    for (int q = 0; q < kPairs; ++q) {
+        const int tap = min(2 * q + (g >> 1), kTaps - 1);
+        off[q] = ((tap / 3 - 1) * kRegW + tap % 3 - 1 + px) * kC + 8 * (g & 1);
+    }
+}
+// First layer (4 channels, 8 bytes per pixel): operand q takes taps
+// 8q + 2g and 8q + 2g + 1 of pixel (lane & 15); offsets in pixels.
+__device__ __forceinline__ void tap_offsets_first(uint32_t lane, int (&off)[kPairs0][2])
+{
+    const int g = (int)(lane >> 4), px = (int)(lane & 15);
+#pragma unroll
+    for (int q = 0; q < kPairs0; ++q)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int tap = min(8 * q + 2 * g + h, kTaps - 1);
+            off[q][h] = (tap / 3 - 1) * kRegW + tap % 3 - 1 + px;
+        }
+}
+
+// The 16x16x32 products of one or two 16-pixel segments (first pixels at
+// element indices qa, qb), the two accumulation chains interleaved so that
+// they overlap in the matrix pipeline.  The weights are the A operand and the
+// activations the B operand, so the result is channels x pixels: lane l holds
+// output channels 4 (l / 16) .. + 3 of pixel l % 16 (one 8-byte store of the
+// four, instead of four 2-byte stores of one channel).
+__device__ __forceinline__ void segment_pair(const uint16_t* __restrict__ in, int qa, int qb,
+                                             bool two, const int (&off)[kPairs],
                                              const bf16x8* b, f32x4& acc0, f32x4& acc1)
 {
-    const uint32_t g = lane >> 4, ch = 8 * (g & 1);
     bf16x8 a0[kPairs], a1[kPairs];
 #pragma unroll
-    for (int q = 0; q < kPairs; ++q) {
-        const int tap = 2 * q + (int)(g >> 1);
-        const int dr = tap / 3 - 1, dc = tap % 3 - 1;
-        bf16x8 v0 = {}, v1 = {};
-        if (tap < kTaps && pa + dc < kRegW)
-            v0 = *reinterpret_cast<const bf16x8*>(&in[((ra + dr) * kRegW + pa + dc) * kC + ch]);
-        if (two && tap < kTaps && pb + dc < kRegW)
-            v1 = *reinterpret_cast<const bf16x8*>(&in[((rb + dr) * kRegW + pb + dc) * kC + ch]);
-        a0[q] = v0;
-        a1[q] = v1;
-    }
+    for (int q = 0; q < kPairs; ++q) a0[q] = *reinterpret_cast<const bf16x8*>(&in[qa + off[q]]);
     acc0 = f32x4{0.f, 0.f, 0.f, 0.f};
     acc1 = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (two) {
 #pragma unroll
-    for (int q = 0; q < kPairs; ++q) {
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[q], a0[q], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[q], a1[q], acc1, 0, 0, 0);
+        for (int q = 0; q < kPairs; ++q) a1[q] = *reinterpret_cast<const bf16x8*>(&in[qb + off[q]]);
+#pragma unroll
+        for (int q = 0; q < kPairs; ++q) {
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[q], a0[q], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[q], a1[q], acc1, 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < kPairs; ++q)
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[q], a0[q], acc0, 0, 0, 0);
     }
 }
 
 // The first layer's two 16x16x32 products per segment: its input has 4
 // channels per pixel (L, stale, log(1 + age), 0; 8 bytes), packed 4 per tap,
-// so a lane's operand is the two taps 8q + 2g, 8q + 2g + 1 (g = lane / 16).
-__device__ __forceinline__ void segment_pair_first(const uint2* __restrict__ in4, int ra, int pa,
-                                                   int rb, int pb, bool two, uint32_t lane,
+// so a lane's operand is two taps of one pixel; qa, qb index pixels.
+__device__ __forceinline__ void segment_pair_first(const uint2* __restrict__ in4, int qa, int qb,
+                                                   bool two, const int (&off)[kPairs0][2],
                                                    const bf16x8* b, f32x4& acc0, f32x4& acc1)
 {
-    const uint32_t g = lane >> 4;
     bf16x8 a0[kPairs0], a1[kPairs0];
 #pragma unroll
     for (int q = 0; q < kPairs0; ++q) {
-        uint2 u0[2], u1[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int tap = 8 * q + 2 * (int)g + h;
-            const int dr = tap / 3 - 1, dc = tap % 3 - 1;
-            u0[h] = make_uint2(0u, 0u);
-            u1[h] = make_uint2(0u, 0u);
-            if (tap < kTaps && pa + dc < kRegW) u0[h] = in4[(ra + dr) * kRegW + pa + dc];
-            if (two && tap < kTaps && pb + dc < kRegW) u1[h] = in4[(rb + dr) * kRegW + pb + dc];
-        }
-        const uint4 w0 = make_uint4(u0[0].x, u0[0].y, u0[1].x, u0[1].y);
-        const uint4 w1 = make_uint4(u1[0].x, u1[0].y, u1[1].x, u1[1].y);
-        a0[q] = *reinterpret_cast<const bf16x8*>(&w0);
-        a1[q] = *reinterpret_cast<const bf16x8*>(&w1);
+        const uint2 u = in4[qa + off[q][0]], v = in4[qa + off[q][1]];
+        const uint4 w = make_uint4(u.x, u.y, v.x, v.y);
+        a0[q] = *reinterpret_cast<const bf16x8*>(&w);
     }
     acc0 = f32x4{0.f, 0.f, 0.f, 0.f};
     acc1 = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (two) {
 #pragma unroll
-    for (int q = 0; q < kPairs0; ++q) {
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[q], a0[q], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[q], a1[q], acc1, 0, 0, 0);
+        for (int q = 0; q < kPairs0; ++q) {
+            const uint2 u = in4[qb + off[q][0]], v = in4[qb + off[q][1]];
+            const uint4 w = make_uint4(u.x, u.y, v.x, v.y);
+            a1[q] = *reinterpret_cast<const bf16x8*>(&w);
+        }
+#pragma unroll
+        for (int q = 0; q < kPairs0; ++q) {
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[q], a0[q], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[q], a1[q], acc1, 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < kPairs0; ++q)
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[q], a0[q], acc0, 0, 0, 0);
     }
 }
 
@@ -526,6 +557,11 @@ __device__ __forceinline__ void fused_layer(int layer, uint16_t (*buf)[kRegH * k
     for (int q = 0; q < nq; ++q)
         b[q] = *reinterpret_cast<const bf16x8*>(&wsh[(layer * kPairs + q) * 64 + lane]);
     const uint32_t o4 = (lane >> 4) * 4;                 // this lane's four output channels
+    int off[kPairs], off0[kPairs0][2];
+    if (kFirst)
+        tap_offsets_first(lane, off0);
+    else
+        tap_offsets(lane, off);
     const int nseg = (kRegH - 2 * kk) * 2;
     for (int s0 = (int)wv; s0 < nseg; s0 += 2 * kFuseWaves) {
         const int s1 = s0 + kFuseWaves;
@@ -534,11 +570,11 @@ __device__ __forceinline__ void fused_layer(int layer, uint16_t (*buf)[kRegH * k
         const int rb = kk + s1 / 2, cb = kk + (s1 % 2) * 16;
         f32x4 acc0, acc1;
         if (kFirst)
-            segment_pair_first(reinterpret_cast<const uint2*>(buf[1]), ra, ca + (int)(lane & 15),
-                               rb, cb + (int)(lane & 15), two, lane, b, acc0, acc1);
+            segment_pair_first(reinterpret_cast<const uint2*>(buf[1]), ra * kRegW + ca,
+                               rb * kRegW + cb, two, off0, b, acc0, acc1);
         else
-            segment_pair(in, ra, ca + (int)(lane & 15), rb, cb + (int)(lane & 15), two, lane, b,
-                         acc0, acc1);
+            segment_pair(in, (ra * kRegW + ca) * kC, (rb * kRegW + cb) * kC, two, off, b, acc0,
+                         acc1);
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
             if (half == 1 && !two) break;
@@ -560,7 +596,7 @@ __device__ __forceinline__ void fused_layer(int layer, uint16_t (*buf)[kRegH * k
             // round to nearest even, as to_bf16
             const uint2 w = make_uint2(__builtin_bit_cast(uint32_t, __builtin_convertvector(v01, bf16x2)),
                                        __builtin_bit_cast(uint32_t, __builtin_convertvector(v23, bf16x2)));
-            if (c < kRegW) *reinterpret_cast<uint2*>(&out[(r * kRegW + c) * kC + o4]) = w;
+            *reinterpret_cast<uint2*>(&out[(r * kRegW + c) * kC + o4]) = w;   // c < kRegW
         }
     }
     __syncthreads();
