@@ -584,18 +584,16 @@ __device__ __forceinline__ void fused_layer(int layer, uint16_t (*buf)[kRegH * k
             const float4 bo = *reinterpret_cast<const float4*>(&bsh[layer * kC + o4]);
             const int y = y0 + r, x = x0 + c;
             const bool inside = y >= 0 && y < (int)H && x >= 0 && x < (int)W;
+            // bias, ReLU, BF16 (round to nearest even, as to_bf16); pixels
+            // outside the image are zero (the layers' zero padding)
             f32x2 v01, v23;
-            v01.x = acc[0] + bo.x;
-            v01.y = acc[1] + bo.y;
-            v23.x = acc[2] + bo.z;
-            v23.y = acc[3] + bo.w;
-            v01.x = (inside && v01.x > 0.f) ? v01.x : 0.f;
-            v01.y = (inside && v01.y > 0.f) ? v01.y : 0.f;
-            v23.x = (inside && v23.x > 0.f) ? v23.x : 0.f;
-            v23.y = (inside && v23.y > 0.f) ? v23.y : 0.f;
-            // round to nearest even, as to_bf16
-            const uint2 w = make_uint2(__builtin_bit_cast(uint32_t, __builtin_convertvector(v01, bf16x2)),
-                                       __builtin_bit_cast(uint32_t, __builtin_convertvector(v23, bf16x2)));
+            v01.x = fmaxf(acc[0] + bo.x, 0.f);
+            v01.y = fmaxf(acc[1] + bo.y, 0.f);
+            v23.x = fmaxf(acc[2] + bo.z, 0.f);
+            v23.y = fmaxf(acc[3] + bo.w, 0.f);
+            const uint32_t w01 = __builtin_bit_cast(uint32_t, __builtin_convertvector(v01, bf16x2));
+            const uint32_t w23 = __builtin_bit_cast(uint32_t, __builtin_convertvector(v23, bf16x2));
+            const uint2 w = make_uint2(inside ? w01 : 0u, inside ? w23 : 0u);
             *reinterpret_cast<uint2*>(&out[(r * kRegW + c) * kC + o4]) = w;   // c < kRegW
         }
     }
@@ -668,7 +666,10 @@ __global__ __launch_bounds__(kFuseThreads) __attribute__((amdgpu_waves_per_eu(4)
     __shared__ float Lsh[kRegH * kRegW];
     const uint32_t tiles_x = (W + kFuseW - 1) / kFuseW;
     const uint32_t tiles = tiles_x * ((H + kFuseH - 1) / kFuseH);
-    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // the wave index is uniform: in a scalar register, the segment loops'
+    // index arithmetic runs on the scalar unit
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
 
     for (int k = threadIdx.x; k < kLayers * kPairs * 64; k += kFuseThreads) wsh[k] = wk[k];
     if (threadIdx.x < kLayers * kC) bsh[threadIdx.x] = bias[threadIdx.x];
