@@ -179,24 +179,33 @@ __global__ __launch_bounds__(256) void k_fill_conv(const uint16_t* __restrict__ 
         a[t] = v;
         b[t] = w[t * 64 + lane];
     }
+    // weights as the A operand, activations as B: the result is channels x
+    // pixels, lane l holding output channels 4 (l / 16) .. + 3 of pixel
+    // x0 + l % 16 (one bounds check, one 8-byte gate load and store per lane)
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int t = 0; t < kTaps; ++t)
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[t], b[t], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b[t], a[t], acc, 0, 0, 0);
 
-    const uint32_t o = lane & 15;
-    const float bo = bias ? bias[o] : 0.f;
+    if (px >= (int)W) return;
+    const size_t p = row * W + (uint32_t)px;
+    uint2 g = make_uint2(0xffffffffu, 0xffffffffu);
+    if (gate) g = *reinterpret_cast<const uint2*>(gate + p * kC + cq);
+    const uint32_t gh[4] = {g.x & 0xffffu, g.x >> 16, g.y & 0xffffu, g.y >> 16};
+    uint16_t h[4];
+    float v0 = 0.f;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const uint32_t xo = x0 + (lane >> 4) * 4 + j;
-        if (xo >= W) continue;
-        const size_t p = (row * W + xo);
-        float v = acc[j] + bo;
+        float v = acc[j] + (bias ? bias[cq + j] : 0.f);
         if (relu) v = v > 0.f ? v : 0.f;
-        if (gate && (gate[p * kC + o] & 0x7fff) == 0) v = 0.f;
-        if (out16) out16[p * kC + o] = to_bf16(v);
-        if (out32 && o == 0) out32[p] = v + skip[p];
+        if ((gh[j] & 0x7fffu) == 0) v = 0.f;
+        h[j] = to_bf16(v);
+        if (j == 0) v0 = v;
     }
+    if (out16)
+        *reinterpret_cast<uint2*>(out16 + p * kC + cq) =
+            make_uint2(h[0] | (uint32_t)h[1] << 16, h[2] | (uint32_t)h[3] << 16);
+    if (out32 && cq == 0) out32[p] = v0 + skip[p];
 }
 
 // ---------------------------------------------------------------------------
