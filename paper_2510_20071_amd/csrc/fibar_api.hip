@@ -699,7 +699,6 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
 
     const uint64_t n_regions = (npx + kRegion - 1) / kRegion;
     c->region_path = !p.spatial_filter && n_regions <= kMaxRegions;
-    const size_t mc = kMaxBatchChunks;
 
     hipError_t e = hipSuccess;
     auto alloc = [&](void** ptr, size_t bytes) {
@@ -709,11 +708,11 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
     alloc((void**)&c->s.pp, npx * sizeof(PixP));
     alloc((void**)&c->s.ring, ring * 4);
     alloc((void**)&c->s.sc, 2 * sizeof(DevScalars));
-    alloc((void**)&c->d_chunks, mc * sizeof(ChunkDesc));
+    alloc((void**)&c->d_chunks, kMaxBatchChunks * sizeof(ChunkDesc));
     // 4 spare records: an item reads records up to i + 3 of its chunk
-    alloc((void**)&c->seg, (mc * kChunk + 4) * sizeof(SegRec));
-    alloc((void**)&c->seg_count, mc * 4);
-    alloc((void**)&c->scratch, mc * sizeof(StepScratch));
+    alloc((void**)&c->seg, ((size_t)kMaxBatchChunks * kChunk + 4) * sizeof(SegRec));
+    alloc((void**)&c->seg_count, kMaxBatchChunks * 4);
+    alloc((void**)&c->scratch, kMaxBatchChunks * sizeof(StepScratch));
     alloc((void**)&c->stg_x, stg * 2);
     alloc((void**)&c->stg_y, stg * 2);
     alloc((void**)&c->stg_p, stg);
@@ -728,7 +727,7 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
         if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_ro, kMaxBatchReadouts * sizeof(RegionReadout), 0);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ro_free, hipEventDisableTiming);
     }
-    if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_chunks, mc * sizeof(ChunkDesc), 0);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_chunks, kMaxBatchChunks * sizeof(ChunkDesc), 0);
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_sc, sizeof(DevScalars), 0);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->chunks_free, hipEventDisableTiming);
     if (e != hipSuccess) {
