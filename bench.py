@@ -123,7 +123,7 @@ def run_batched(args, torch, dev, fb, eventsim):
                 op.kind = fb.FIBAR_OP_READOUT
                 op.t = int(it[1])
                 op.readout = fb.fibar_readout_buf(frames.data_ptr() + 4 * W * H * r, None, None,
-                                                  None, None, None, None, 1)
+                                                  None, None, None, None, None, 1)
                 r += 1
             ops.append(op)
         op_lists.append(ops)
@@ -444,7 +444,7 @@ def main():
                 op.kind = fb.FIBAR_OP_READOUT
                 op.t = int(ev.t[it[1] - 1])
                 op.readout = fb.fibar_readout_buf(fptr + 4 * npx * r, None, None, None, None,
-                                                  None, None, 1)
+                                                  None, None, None, 1)
                 ops.append(op)
                 r += 1
         return (fb.fibar_op * len(ops))(*ops), len(ops)

@@ -83,9 +83,12 @@ typedef struct {
 void fibar_default_params(fibar_params* p);
 
 /*
- * Create a context for a width x height sensor (1..65535 each).  Allocates
- * all device state (zero brightness, no events seen).  On success *out
- * receives the context; on failure *out is NULL and the status says why
+ * Create a context for a width x height sensor (1..65535 each, and at most
+ * 2^29 two-by-two tiles, i.e. ((width+1)/2)*((height+1)/2) <= 536870912:
+ * an event's sort key holds its tile-major pixel key and polarity in 32
+ * bits; larger sensors return FIBAR_E_INVALID_ARG).  Allocates all device
+ * state (zero brightness, no events seen).  On success *out receives the
+ * context; on failure *out is NULL and the status says why
  * (FIBAR_E_INVALID_ARG for bad sizes or parameters, FIBAR_E_NOMEM if device
  * memory is short, FIBAR_E_DEVICE for other HIP errors).
  */
@@ -143,6 +146,7 @@ int fibar_push_events(fibar_ctx* c, const fibar_packet* pkt);
  *   tile_count    active pixels per 2x2 tile, ((width+1)/2)*((height+1)/2)
  *                 elements, tile (tx, ty) at ty*((width+1)/2)+tx.
  *                                                          [spatial filter]
+ *   total_count   events of that pixel since creation or reset (uint64).
  *   on_device     0: host memory (the call synchronises the stream);
  *                 1: device memory, written in stream order.
  * Outputs marked [spatial filter] return FIBAR_E_UNSUPPORTED when the
@@ -156,6 +160,7 @@ typedef struct {
     int64_t*  last_index;
     float*    log_age;
     uint32_t* tile_count;
+    uint64_t* total_count;
     int       on_device;
 } fibar_readout_buf;
 
@@ -233,6 +238,33 @@ int fibar_reset(fibar_ctx* c);
  */
 int fibar_set_kernel_timing(fibar_ctx* c, uint32_t kernel_mask, uint32_t every);
 int fibar_kernel_time(fibar_ctx* c, int kernel, double* total_ms, uint64_t* launches);
+
+/*
+ * Per-step telemetry (spatial filter on): every regulation step of the
+ * context (one per pushed packet that was not rejected; Method, "Spatial
+ * filtering", Eq. (19), (20)) writes one record of the window scalars after
+ * that step into a caller-owned device buffer of `capacity` records, at the
+ * index of the step (0-based, counting from creation or reset; steps past
+ * the capacity are not recorded).  The record's fields:
+ *   k      index of the newest event after the step,
+ *   h      index of the oldest event left in the window,
+ *   q      window length k - h + 1,
+ *   Q      target length for the next step (Eq. (20)),
+ *   P, T   active pixels and active 2x2 tiles after the step,
+ *   stale  pixels that went stale (and were blurred) in the step,
+ *   n      events of the step's packet.
+ * The buffer is written in stream order by the step's device work; the
+ * caller keeps it alive while that work runs and reads it after a
+ * synchronising call.  NULL with capacity 0 turns recording off.  Returns
+ * FIBAR_E_INVALID_ARG for NULL with a nonzero capacity and
+ * FIBAR_E_UNSUPPORTED for a context without the spatial filter.
+ */
+typedef struct {
+    int64_t  k;
+    uint64_t h, q, Q, P, T, stale, n;
+} fibar_step_record;
+
+int fibar_set_telemetry(fibar_ctx* c, fibar_step_record* records, uint64_t capacity);
 
 /*
  * How the in-order kernels of a batch are issued (spatial filter on).

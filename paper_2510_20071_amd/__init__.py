@@ -57,7 +57,8 @@ class fibar_readout_buf(ctypes.Structure):
     _fields_ = [("brightness", ctypes.c_void_p), ("pbar", ctypes.c_void_p),
                 ("stale_mask", ctypes.c_void_p), ("active_count", ctypes.c_void_p),
                 ("last_index", ctypes.c_void_p), ("log_age", ctypes.c_void_p),
-                ("tile_count", ctypes.c_void_p), ("on_device", ctypes.c_int)]
+                ("tile_count", ctypes.c_void_p), ("total_count", ctypes.c_void_p),
+                ("on_device", ctypes.c_int)]
 
 
 class fibar_op(ctypes.Structure):
@@ -94,6 +95,7 @@ _SIGNATURES = {
                                          ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_uint64)]),
     "fibar_set_launch_mode": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "fibar_set_telemetry": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64]),
 }
 
 _SIGNATURES.update({
@@ -214,6 +216,15 @@ def fibar_reset(handle) -> int:
 
 def fibar_set_kernel_timing(handle, kernel_mask: int, every: int = 1) -> int:
     return load().fibar_set_kernel_timing(handle, int(kernel_mask), int(every))
+
+
+def fibar_set_telemetry(handle, records, capacity: int) -> int:
+    """records: a device buffer of capacity * STEP_RECORD_WORDS int64 (or None)."""
+    return load().fibar_set_telemetry(handle, _addr(records), int(capacity))
+
+
+STEP_RECORD_FIELDS = ("k", "h", "q", "Q", "P", "T", "stale", "n")
+STEP_RECORD_WORDS = len(STEP_RECORD_FIELDS)
 
 
 def fibar_set_launch_mode(handle, mode: int) -> int:
@@ -341,22 +352,27 @@ class Context:
         sp = self.spatial_filter if spatial_outputs is None else spatial_outputs
         out = {"L": np.empty(npx, np.float32), "pbar": np.empty(npx, np.float32),
                "last": np.empty(npx, np.int64), "log_age": np.empty(npx, np.float32)}
+        out["tot"] = np.empty(npx, np.uint64)
         if sp:
             out.update(stale=np.empty(npx, np.uint8), cnt=np.empty(npx, np.uint32),
                        tcnt=np.empty(self.tiles, np.uint32))
         buf = fibar_readout_buf(_addr(out["L"]), _addr(out["pbar"]), _addr(out.get("stale")),
                                 _addr(out.get("cnt")), _addr(out["last"]),
-                                _addr(out["log_age"]), _addr(out.get("tcnt")), 0)
+                                _addr(out["log_age"]), _addr(out.get("tcnt")),
+                                _addr(out["tot"]), 0)
         rc = fibar_readout(self.handle, t, buf)
         if rc != FIBAR_OK:
             return rc
         return out
 
     def readout_device(self, t, L, pbar=None, stale=None, cnt=None, last=None, log_age=None,
-                       tcnt=None) -> int:
+                       tcnt=None, tot=None) -> int:
         buf = fibar_readout_buf(_addr(L), _addr(pbar), _addr(stale), _addr(cnt), _addr(last),
-                                _addr(log_age), _addr(tcnt), 1)
+                                _addr(log_age), _addr(tcnt), _addr(tot), 1)
         return fibar_readout(self.handle, t, buf)
+
+    def set_telemetry(self, records, capacity: int) -> int:
+        return fibar_set_telemetry(self.handle, records, capacity)
 
     def stats(self):
         rc, s = fibar_get_stats(self.handle)
@@ -382,12 +398,12 @@ def push_op(x, y, p, t=None, on_device=None) -> fibar_op:
 
 
 def readout_op(t, L, pbar=None, stale=None, cnt=None, last=None, log_age=None, tcnt=None,
-               on_device=1) -> fibar_op:
+               on_device=1, tot=None) -> fibar_op:
     op = fibar_op()
     op.kind = FIBAR_OP_READOUT
     op.t = int(t)
     op.readout = fibar_readout_buf(_addr(L), _addr(pbar), _addr(stale), _addr(cnt), _addr(last),
-                                   _addr(log_age), _addr(tcnt), int(on_device))
+                                   _addr(log_age), _addr(tcnt), _addr(tot), int(on_device))
     return op
 
 

@@ -25,6 +25,7 @@ using namespace fibar;
 namespace {
 
 constexpr uint32_t kMaxPacket = 1u << 20;
+constexpr uint64_t kMaxKeySpan = 1ull << 31;
 
 // Eq. (17) and Eq. (18), evaluated in double precision.
 void filter_coefficients(double t_cut, double* alpha, double* beta)
@@ -252,6 +253,7 @@ void free_ctx(fibar_ctx* c)
     else (void)hipDeviceSynchronize();
     (void)hipFree(c->s.px);
     (void)hipFree(c->s.pp);
+    (void)hipFree(c->s.cnt);
     (void)hipFree(c->s.ring);
     (void)hipFree(c->s.sc);
     (void)hipFree(c->d_chunks);
@@ -310,7 +312,7 @@ int do_readout_kernel(fibar_ctx* c, const fibar_readout_buf& ro, const StepScrat
         HIP_TRY(timed_launch(c, 4, [&](const LaunchTiming& tm) {
             return launch_readout(c->s, sp, pend, pend_n, slot, ro.brightness, ro.pbar,
                                   ro.stale_mask, ro.active_count, ro.last_index, ro.log_age,
-                                  ro.tile_count, c->st, tm);
+                                  ro.tile_count, ro.total_count, c->st, tm);
         }));
         return FIBAR_OK;
     }
@@ -323,6 +325,7 @@ int do_readout_kernel(fibar_ctx* c, const fibar_readout_buf& ro, const StepScrat
     if (ro.last_index) bytes += npx * 8;
     if (ro.log_age) bytes += npx * 4;
     if (ro.tile_count) bytes += c->ntiles * 4;
+    if (ro.total_count) bytes += npx * 8;
     bytes += 8 * 256;
     uint8_t* stage = nullptr;
     HIP_TRY(hipMallocAsync((void**)&stage, bytes, c->st));
@@ -335,7 +338,9 @@ int do_readout_kernel(fibar_ctx* c, const fibar_readout_buf& ro, const StepScrat
     int64_t* dLi = ro.last_index ? (int64_t*)take(npx * 8) : nullptr;
     float* dA = ro.log_age ? (float*)take(npx * 4) : nullptr;
     uint32_t* dT = ro.tile_count ? (uint32_t*)take(c->ntiles * 4) : nullptr;
-    hipError_t e = launch_readout(c->s, sp, pend, pend_n, slot, dL, dP, dS, dC, dLi, dA, dT, c->st);
+    uint64_t* dN = ro.total_count ? (uint64_t*)take(npx * 8) : nullptr;
+    hipError_t e = launch_readout(c->s, sp, pend, pend_n, slot, dL, dP, dS, dC, dLi, dA, dT, dN,
+                                  c->st);
     if (e == hipSuccess) e = hipMemcpyAsync(ro.brightness, dL, npx * 4, hipMemcpyDeviceToHost, c->st);
     if (e == hipSuccess && dP) e = hipMemcpyAsync(ro.pbar, dP, npx * 4, hipMemcpyDeviceToHost, c->st);
     if (e == hipSuccess && dS) e = hipMemcpyAsync(ro.stale_mask, dS, npx, hipMemcpyDeviceToHost, c->st);
@@ -343,6 +348,7 @@ int do_readout_kernel(fibar_ctx* c, const fibar_readout_buf& ro, const StepScrat
     if (e == hipSuccess && dLi) e = hipMemcpyAsync(ro.last_index, dLi, npx * 8, hipMemcpyDeviceToHost, c->st);
     if (e == hipSuccess && dA) e = hipMemcpyAsync(ro.log_age, dA, npx * 4, hipMemcpyDeviceToHost, c->st);
     if (e == hipSuccess && dT) e = hipMemcpyAsync(ro.tile_count, dT, c->ntiles * 4, hipMemcpyDeviceToHost, c->st);
+    if (e == hipSuccess && dN) e = hipMemcpyAsync(ro.total_count, dN, npx * 8, hipMemcpyDeviceToHost, c->st);
     hipError_t e2 = hipFreeAsync(stage, c->st);
     hipError_t e3 = hipStreamSynchronize(c->st);
     if (e == hipSuccess) e = e2;
@@ -365,6 +371,7 @@ int run_region_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, u
             d.pbar = ops[i].ro.pbar;
             d.last = ops[i].ro.last_index;
             d.log_age = ops[i].ro.log_age;
+            d.tot = ops[i].ro.total_count;
             continue;
         }
         for (uint32_t off = 0; off < ops[i].n; off += kChunk) {
@@ -467,7 +474,8 @@ int run_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, uint32_t
             if (fuse) {
                 const fibar_readout_buf& rb = ops[i + 1].ro;
                 PopReadout pr{rb.brightness, rb.pbar,     rb.stale_mask,
-                              rb.last_index, rb.log_age, rb.tile_count};
+                              rb.last_index, rb.log_age, rb.tile_count,
+                              rb.total_count};
                 if (graph) {
                     // counted as a pop, so that the timed launches of a
                     // batch do not depend on where its readouts fall
@@ -604,7 +612,7 @@ hipError_t init_state(fibar_ctx* c)
     c->h_sc->P = c->h_sc->T = 0;
     c->h_sc->n_reg = c->h_sc->last_stale = c->h_sc->total_stale = 0;
     c->h_sc->err = 0;
-    c->h_sc->pad = 0;
+    c->h_sc->stepped = 0;
     c->cur_slot = 0;
     hipError_t e = launch_init_state(c->s, c->st);
     if (e == hipSuccess)
@@ -669,6 +677,10 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
     if (p.spatial_filter > 1 || p.regulation != FIBAR_REG_PACKET) return FIBAR_E_INVALID_ARG;
     if (p.max_packet == 0 || p.max_packet > kMaxPacket) return FIBAR_E_INVALID_ARG;
     const uint64_t npx = (uint64_t)width * height;
+    // the sort key of an event is (tile-major pixel key << 1) | polarity in
+    // 32 bits, with 4 keys per 2x2 tile
+    const uint64_t key_span = 4ull * ((width + 1) / 2) * ((height + 1) / 2);
+    if (key_span > kMaxKeySpan) return FIBAR_E_INVALID_ARG;
     if (p.q_max == 0) p.q_max = (uint32_t)npx;
     if (p.q_min == 0 || p.q_min > p.q_max) return FIBAR_E_INVALID_ARG;
 
@@ -706,6 +718,7 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
     };
     alloc((void**)&c->s.px, npx * sizeof(PixL));
     alloc((void**)&c->s.pp, npx * sizeof(PixP));
+    alloc((void**)&c->s.cnt, npx * 4);
     alloc((void**)&c->s.ring, ring * 4);
     alloc((void**)&c->s.sc, 2 * sizeof(DevScalars));
     alloc((void**)&c->d_chunks, kMaxBatchChunks * sizeof(ChunkDesc));
@@ -830,6 +843,16 @@ int fibar_set_kernel_timing(fibar_ctx* c, uint32_t kernel_mask, uint32_t every)
     c->time_mask = kernel_mask;
     c->time_every = every;
     for (auto& q : c->time_seq) q = 0;
+    return FIBAR_OK;
+}
+
+int fibar_set_telemetry(fibar_ctx* c, fibar_step_record* records, uint64_t capacity)
+{
+    if (!c || (!records && capacity)) return FIBAR_E_INVALID_ARG;
+    if (!c->prm.spatial_filter && records) return FIBAR_E_UNSUPPORTED;
+    // launches already queued keep the buffer they were given
+    c->s.tel = capacity ? reinterpret_cast<StepRecord*>(records) : nullptr;
+    c->s.tel_cap = capacity;
     return FIBAR_OK;
 }
 

@@ -65,7 +65,7 @@ struct DevScalars {
     uint64_t last_stale;   // pixels blurred in the last step
     uint64_t total_stale;  // pixels blurred so far
     int32_t err;           // first device-side packet error (0: none)
-    int32_t pad;
+    int32_t stepped;       // 1: the commit that wrote these was a regulation step
 };
 
 // Per-packet scratch of one batch (zeroed at the start of the batch).
@@ -93,27 +93,41 @@ static_assert(kApplySlots % 2 == 0 && kPopSlots % 2 == 0, "slots are read in pai
 // Per-pixel state, in two arrays of structures so that what one kernel
 // needs of a pixel comes in one load: the window kernels read brightness and
 // last-event index together (the 3x3 blur reads both for every neighbour),
-// and only the filter update reads pbar and the queued-event count.
+// and only the filter update reads pbar and the event total.  The count of a
+// pixel's events in the window is a third array, changed only by atomic
+// additions (pushes) and subtractions (pops), so that pushes and pops may
+// run in the same launch.
 struct alignas(16) PixL {
     float L;        // brightness of active / never-seen pixels
     float Lb;       // brightness of stale pixels (their one-time blur)
     int64_t last;   // index of the newest event (-1: none)
 };
-struct alignas(8) PixP {
+struct alignas(16) PixP {
     float pbar;     // low-passed polarity
-    uint32_t cnt;   // events of the pixel in the window
+    uint32_t pad;
+    uint64_t tot;   // events of the pixel so far
+};
+
+// Window scalars after one regulation step, as recorded for the caller's
+// telemetry buffer (the layout of fibar_step_record in fibar.h).
+struct StepRecord {
+    int64_t k;
+    uint64_t h, q, Q, P, T, stale, n;
 };
 
 // Device pointers of one context's state.
 struct State {
     PixL* px;
     PixP* pp;
+    uint32_t* cnt;    // events of each pixel in the window
     uint32_t* ring;
     uint64_t ring_mask;
     DevScalars* sc;   // two slots; see the commit scheme in fibar_kernels.hip
     uint32_t W, H, TW;
     uint32_t fill_num, fill_den;
     uint64_t q_min, q_max;
+    StepRecord* tel;   // per-step telemetry (null: none), tel_cap records
+    uint64_t tel_cap;
 };
 
 // Optional HIP events attached to a launch's dispatch (hipExtLaunchKernel):
@@ -205,6 +219,7 @@ struct RegionReadout {
     float* pbar;
     int64_t* last;
     float* log_age;
+    uint64_t* tot;
 };
 
 struct RegionBuffers {
@@ -266,6 +281,7 @@ struct PopReadout {
     int64_t* last;
     float* log_age;
     uint32_t* tcnt;
+    uint64_t* tot;
 };
 
 // With `ro` the launch also writes the readout of the state after the step.
@@ -282,7 +298,7 @@ hipError_t launch_commit(const State& s, const StepScratch* prev, uint32_t prev_
 hipError_t launch_readout(const State& s, int spatial, const StepScratch* prev,
                           uint32_t prev_events, int slot, float* L, float* pbar,
                           uint8_t* stale, uint32_t* cnt, int64_t* last, float* log_age,
-                          uint32_t* tcnt, hipStream_t st,
+                          uint32_t* tcnt, uint64_t* tot, hipStream_t st,
                           const LaunchTiming& tm = LaunchTiming());
 
 }  // namespace fibar

@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kApplyBlock) void k_apply(
     if (blockIdx.x == 0) {
         if (prev && sc_out && threadIdx.x < 64) {
             const DevScalars r = commit_by_wave(sc_in, prev, prev_events, s, spatial);
-            if (threadIdx.x == 0) *sc_out = r;
+            if (threadIdx.x == 0) store_commit(s, sc_out, r, prev_events);
         }
         return;
     }
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(kPopBlock) void k_pop_blur(const DevScalars* sc, St
                 const uint64_t i = base + (uint64_t)q * kPopBlock;
                 if (i < npx)
                     readout_pixel_after_pops(s, k, h_old, h_new, i, v[q], ro.L, ro.pbar,
-                                             ro.stale, ro.last, ro.log_age);
+                                             ro.stale, ro.last, ro.log_age, ro.tot);
             }
         }
         if (ro.tcnt) {
@@ -233,8 +233,10 @@ __global__ __launch_bounds__(256) void k_init_state(State s)
         s.px[i] = v;
         PixP p;
         p.pbar = 0.f;
-        p.cnt = 0u;
+        p.pad = 0u;
+        p.tot = 0u;
         s.pp[i] = p;
+        s.cnt[i] = 0u;
     }
 }
 
@@ -244,13 +246,14 @@ __global__ __launch_bounds__(64) void k_commit(State s, const StepScratch* prev,
                                                 int spatial)
 {
     const DevScalars r = commit_by_wave(s.sc + slot_in, prev, prev_events, s, spatial);
-    if (threadIdx.x == 0) s.sc[slot_out] = r;
+    if (threadIdx.x == 0) store_commit(s, s.sc + slot_out, r, prev_events);
 }
 
 __global__ __launch_bounds__(256) void k_readout(State s, int spatial, const StepScratch* prev,
                                                  uint32_t prev_events, int slot, float* L,
                                                  float* pbar, uint8_t* stale, uint32_t* cnt,
-                                                 int64_t* last, float* log_age, uint32_t* tcnt)
+                                                 int64_t* last, float* log_age, uint32_t* tcnt,
+                                                 uint64_t* tot)
 {
     int64_t k;
     uint64_t hu;
@@ -258,7 +261,7 @@ __global__ __launch_bounds__(256) void k_readout(State s, int spatial, const Ste
     const uint64_t npx = (uint64_t)s.W * s.H;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < npx; i += stride)
-        readout_pixel(s, spatial, k, (int64_t)hu, i, L, pbar, stale, cnt, last, log_age);
+        readout_pixel(s, spatial, k, (int64_t)hu, i, L, pbar, stale, cnt, last, log_age, tot);
     if (spatial && tcnt) {
         const uint64_t nt = (uint64_t)s.TW * ((s.H + 1) / 2);
         for (uint64_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += stride)
@@ -338,14 +341,14 @@ hipError_t launch_commit(const State& s, const StepScratch* prev, uint32_t prev_
 hipError_t launch_readout(const State& s, int spatial, const StepScratch* prev,
                           uint32_t prev_events, int slot, float* L, float* pbar, uint8_t* stale,
                           uint32_t* cnt, int64_t* last, float* log_age, uint32_t* tcnt,
-                          hipStream_t st, const LaunchTiming& tm)
+                          uint64_t* tot, hipStream_t st, const LaunchTiming& tm)
 {
     const uint64_t npx = (uint64_t)s.W * s.H;
     uint64_t blocks = (npx + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     return launch_timed(k_readout, dim3((uint32_t)blocks), dim3(256), st, tm.start, tm.stop, s,
                         spatial, prev, prev_events, slot, L, pbar, stale, cnt, last, log_age,
-                        tcnt);
+                        tcnt, tot);
 }
 
 }  // namespace fibar

@@ -93,6 +93,7 @@ struct MultiReadout {
     uint32_t* cnt;
     int64_t* last;
     float* log_age;
+    uint64_t* tot;
 };
 
 struct CommitDesc {
@@ -152,11 +153,14 @@ __device__ __forceinline__ uint64_t bcast64(uint64_t v, uint32_t k)
 struct LaneState {
     PixL* px;
     PixP* pp;
+    uint32_t* cnt;
     uint32_t* ring;
     uint64_t ring_mask;
     DevScalars* sc;
     uint32_t W, H, TW, fill_num, fill_den;
     uint64_t q_min, q_max;
+    StepRecord* tel;
+    uint64_t tel_cap;
 };
 
 __device__ __forceinline__ LaneState lane_state(const StreamStep* rr, uint32_t S)
@@ -166,6 +170,7 @@ __device__ __forceinline__ LaneState lane_state(const StreamStep* rr, uint32_t S
     LaneState l;
     l.px = e->s.px;
     l.pp = e->s.pp;
+    l.cnt = e->s.cnt;
     l.ring = e->s.ring;
     l.ring_mask = e->s.ring_mask;
     l.sc = e->s.sc;
@@ -176,6 +181,8 @@ __device__ __forceinline__ LaneState lane_state(const StreamStep* rr, uint32_t S
     l.fill_den = e->s.fill_den;
     l.q_min = e->s.q_min;
     l.q_max = e->s.q_max;
+    l.tel = e->s.tel;
+    l.tel_cap = e->s.tel_cap;
     return l;
 }
 
@@ -184,6 +191,7 @@ __device__ __forceinline__ State owner_state(const LaneState& l, uint32_t k)
     State s;
     s.px = bcast_ptr(l.px, k);
     s.pp = bcast_ptr(l.pp, k);
+    s.cnt = bcast_ptr(l.cnt, k);
     s.ring = bcast_ptr(l.ring, k);
     s.ring_mask = bcast64(l.ring_mask, k);
     s.sc = bcast_ptr(l.sc, k);
@@ -194,6 +202,8 @@ __device__ __forceinline__ State owner_state(const LaneState& l, uint32_t k)
     s.fill_den = bcast32(l.fill_den, k);
     s.q_min = bcast64(l.q_min, k);
     s.q_max = bcast64(l.q_max, k);
+    s.tel = bcast_ptr(l.tel, k);
+    s.tel_cap = bcast64(l.tel_cap, k);
     return s;
 }
 
@@ -233,7 +243,7 @@ __global__ __launch_bounds__(256) void k_multi_apply(const StreamStep* rr, uint3
                 if (threadIdx.x < 64) {
                     const DevScalars r = commit_by_wave(s.sc + slot_in, prev, prev_events, s, 1);
                     const int32_t slot_out = (int32_t)bcast32((uint32_t)l_slot_out, k);
-                    if (threadIdx.x == 0) s.sc[slot_out] = r;
+                    if (threadIdx.x == 0) store_commit(s, s.sc + slot_out, r, prev_events);
                 }
                 continue;
             }
@@ -309,7 +319,7 @@ __global__ __launch_bounds__(256) void k_multi_readout(const StreamStep* rr, Mul
         const uint64_t p0 = (uint64_t)task.blk * kReadoutBlock;
         for (uint64_t i = p0 + threadIdx.x; i < npx && i < p0 + kReadoutBlock; i += blockDim.x)
             readout_pixel(s, 1, k, (int64_t)h, i, ro.L, ro.pbar, ro.stale, ro.cnt, ro.last,
-                          ro.log_age);
+                          ro.log_age, ro.tot);
     }
 }
 
@@ -337,7 +347,7 @@ __global__ __launch_bounds__(64) void k_multi_commit(const CommitDesc* __restric
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
         const CommitDesc c = cd[i];
         const DevScalars r = commit_by_wave(c.s.sc + c.slot_in, c.prev, c.prev_events, c.s, 1);
-        if (threadIdx.x == 0) c.s.sc[c.slot_out] = r;
+        if (threadIdx.x == 0) store_commit(c.s, c.s.sc + c.slot_out, r, c.prev_events);
     }
 }
 
@@ -610,6 +620,7 @@ int run_multi_batch(fibar_multi* m, std::vector<StreamPlan>& plans, bool* done)
                 ro.cnt = rb.active_count;
                 ro.last = rb.last_index;
                 ro.log_age = rb.log_age;
+                ro.tot = rb.total_count;
                 for (uint64_t blk = 0; blk * kReadoutBlock < m->ctx[i]->npx; ++blk)
                     m->h_rot[n_rot++] = RoTask{k, n_ro, (uint32_t)blk, 0u};
                 ++n_ro;

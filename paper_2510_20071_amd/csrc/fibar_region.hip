@@ -271,9 +271,12 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
     const float c = 0.5f + 0.5f * coef.beta;
     float pb = 0.f, l = 0.f;
     int64_t last = -1;
+    uint64_t tot = 0u;
     if (own) {
         const PixL v = s.px[gp];
-        pb = s.pp[gp].pbar;
+        const PixP w = s.pp[gp];
+        pb = w.pbar;
+        tot = w.tot;
         l = v.L;
         last = v.last;
     }
@@ -307,6 +310,7 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
             const float p = (kp & 1u) ? 1.f : -1.f;
             pb = fmaf(coef.alpha, pb, coef.one_m_alpha * p);    // Eq. (7)
             l = fmaf(coef.beta, l, c * (p - pb));                 // Eq. (6), (10)
+            ++tot;
             last_pos = run_at;
             ++run_at;
         }
@@ -317,6 +321,7 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
         if (own) {
             d.L[gp] = l;
             if (d.pbar) d.pbar[gp] = pb;
+            if (d.tot) d.tot[gp] = tot;
             if (d.last) d.last[gp] = last;
             if (d.log_age) d.log_age[gp] = log1pf((float)(rb.chunk_k[d.chunk_end] - 1 - last));
         }
@@ -357,6 +362,7 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
     while (next_ro < n_readouts) write_readout(next_ro++);
     if (own) {
         s.pp[gp].pbar = pb;
+        s.pp[gp].tot = tot;
         s.px[gp].L = l;
         s.px[gp].last = last;
     }

@@ -134,6 +134,7 @@ __device__ DevScalars commit_step(const DevScalars& c, uint32_t status, uint32_t
                                   const State& s, int spatial, const StepCounts& cn)
 {
     DevScalars r = c;
+    r.stepped = 0;
     if (status) {
         if (r.err == 0) r.err = (status & 1u) ? -2 : -3;   // FIBAR_E_RANGE / FIBAR_E_POLARITY
         return r;
@@ -155,6 +156,7 @@ __device__ DevScalars commit_step(const DevScalars& c, uint32_t status, uint32_t
         r.Q = Qn;
     }
     r.n_reg += 1;
+    r.stepped = 1;
     r.last_stale = stale;
     r.total_stale += stale;
     return r;
@@ -172,6 +174,27 @@ __device__ DevScalars commit_by_wave(const DevScalars* sc_in, const StepScratch*
     FIBAR_ISSUE_FENCE();
     const StepCounts cn = spatial ? gather_counts(prev) : StepCounts{0u, 0u, 0u, 0u};
     return commit_step(c, status, n, s, spatial, cn);
+}
+
+// Store a commit `r` of a step of n events (one lane): the scalars, and the
+// step's record into the telemetry buffer when the commit was a regulation
+// step and the buffer has room.
+__device__ __forceinline__ void store_commit(const State& s, DevScalars* out, const DevScalars& r,
+                                             uint32_t n)
+{
+    *out = r;
+    if (s.tel && r.stepped && r.n_reg - 1 < s.tel_cap) {
+        StepRecord t;
+        t.k = r.k;
+        t.h = r.h;
+        t.q = (uint64_t)(r.k + 1) - r.h;
+        t.Q = r.Q;
+        t.P = r.P;
+        t.T = r.T;
+        t.stale = r.last_stale;
+        t.n = n;
+        s.tel[r.n_reg - 1] = t;
+    }
 }
 
 // Read in place of a pending step's scratch when there is none (its value
@@ -279,7 +302,7 @@ struct TileIn {
     float L[4], Lb[4];       // the records' pixels
     int64_t last[4];
     float pbar[4];
-    uint32_t cnt[4];
+    uint64_t tot[4];
 };
 
 __device__ __forceinline__ TileIn load_tile(const State& s, const Group& g, uint32_t i)
@@ -312,7 +335,7 @@ __device__ __forceinline__ TileIn load_tile(const State& s, const Group& g, uint
         ti.last[k] = v.last;
         const PixP w = s.pp[ti.pix[k]];
         ti.pbar[k] = w.pbar;
-        ti.cnt[k] = w.cnt;
+        ti.tot[k] = w.tot;
     }
     return ti;
 }
@@ -355,8 +378,10 @@ __device__ __forceinline__ void apply_tile(const State& s, const Group& g, const
         s.px[px] = o;
         PixP op;
         op.pbar = fmaf(r.a, pb, r.u1);
-        op.cnt = spatial ? ti.cnt[k] + (r.n_last >> 16) : ti.cnt[k];
+        op.pad = 0u;
+        op.tot = ti.tot[k] + (r.n_last >> 16);
         s.pp[px] = op;
+        if (spatial) atomicAdd(&s.cnt[px], r.n_last >> 16);
     }
     if (spatial && !tile_was_active) dT += 1u;
 }
@@ -416,7 +441,7 @@ __device__ __forceinline__ void decide_pop(const State& s, uint64_t j, uint32_t 
                                            uint32_t& dT)
 {
     const uint32_t y = pix / s.W, x = pix - y * s.W;
-    atomicSub(&s.pp[pix].cnt, 1u);
+    atomicSub(&s.cnt[pix], 1u);
     if (nb[1][1].last != (int64_t)j) return;
     ++dP;
     s.px[pix].Lb = stale_blur(nb, h_old);
@@ -494,7 +519,8 @@ __device__ __forceinline__ uint32_t tile_active_pixels(const State& s, uint64_t 
 __device__ __forceinline__ void readout_pixel_after_pops(const State& s, int64_t k, uint64_t h_old,
                                                          uint64_t h_new, uint64_t i, const PixL& v,
                                                          float* L, float* pbar, uint8_t* stale,
-                                                         int64_t* last, float* log_age)
+                                                         int64_t* last, float* log_age,
+                                                         uint64_t* tot)
 {
     const int64_t li = v.last;
     float val = v.L;
@@ -508,6 +534,7 @@ __device__ __forceinline__ void readout_pixel_after_pops(const State& s, int64_t
     }
     L[i] = val;
     if (pbar) pbar[i] = s.pp[i].pbar;
+    if (tot) tot[i] = s.pp[i].tot;
     if (last) last[i] = li;
     if (log_age) log_age[i] = log1pf((float)(k - li));
     if (stale) stale[i] = (li >= 0 && li < (int64_t)h_new) ? 1u : 0u;
@@ -516,16 +543,18 @@ __device__ __forceinline__ void readout_pixel_after_pops(const State& s, int64_t
 // Readout of pixel i given the newest index k and window head h.
 __device__ __forceinline__ void readout_pixel(const State& s, int spatial, int64_t k, int64_t h,
                                               uint64_t i, float* L, float* pbar, uint8_t* stale,
-                                              uint32_t* cnt, int64_t* last, float* log_age)
+                                              uint32_t* cnt, int64_t* last, float* log_age,
+                                              uint64_t* tot)
 {
     const PixL v = s.px[i];
     const int64_t li = v.last;
     L[i] = (spatial && li < h) ? v.Lb : v.L;
     if (pbar) pbar[i] = s.pp[i].pbar;
+    if (tot) tot[i] = s.pp[i].tot;
     if (last) last[i] = li;
     if (log_age) log_age[i] = log1pf((float)(k - li));
     if (spatial) {
-        if (cnt) cnt[i] = s.pp[i].cnt;
+        if (cnt) cnt[i] = s.cnt[i];
         if (stale) stale[i] = (li >= 0 && li < h) ? 1u : 0u;
     }
 }

@@ -42,6 +42,9 @@ def oracle_kw(kw):
 def compare_state(g, r, spatial, where=""):
     """g: readout_host dict of the GPU; r: oracle readout."""
     assert np.array_equal(g["last"], r["last"]), "last_index " + where
+    if "tot" in g:
+        assert np.array_equal(g["tot"].astype(np.uint64), r["tot"].astype(np.uint64)), \
+            "total_count " + where
     if spatial:
         assert np.array_equal(g["cnt"].astype(np.int64), r["cnt"].astype(np.int64)), "cnt " + where
         assert np.array_equal(g["stale"], r["stale"]), "stale " + where
@@ -61,18 +64,50 @@ def compare_stats(gs, os_, where=""):
         assert gs[f] == os_[f], "%s %s: gpu %d oracle %d" % (f, where, gs[f], os_[f])
 
 
-def run_pair(ev, W, H, sched, check_every_read=1, check_stats=True, **kw):
-    """Run `sched` on GPU (device packets) and oracle; compare at readouts."""
+def oracle_step_record(st, n):
+    """The oracle's window scalars after a regulation step, in the field
+    order of fibar_step_record."""
+    return [st["k"], st["h"], st["q"], st["Q"], st["P"], st["T"], st["last_stale"], n]
+
+
+def telemetry_buffer(ctx, capacity):
+    """A device buffer for `capacity` step records, registered with ctx."""
+    torch, dev = torch_dev()
+    buf = torch.full((capacity, fb.STEP_RECORD_WORDS), -7, dtype=torch.int64, device=dev)
+    assert ctx.set_telemetry(buf, capacity) == fb.FIBAR_OK
+    return buf
+
+
+def compare_telemetry(buf, want, where=""):
+    """Records written by the device against the oracle's, bit for bit."""
+    got = buf.cpu().numpy()
+    want = np.asarray(want, dtype=np.int64).reshape(-1, fb.STEP_RECORD_WORDS)
+    n = min(len(want), got.shape[0])
+    for i in range(n):
+        if not np.array_equal(got[i], want[i]):
+            raise AssertionError("step record %d %s: gpu %s oracle %s (fields %s)" % (
+                i, where, got[i].tolist(), want[i].tolist(), fb.STEP_RECORD_FIELDS))
+    assert np.all(got[n:] == -7), "records written past the regulation steps " + where
+
+
+def run_pair(ev, W, H, sched, check_every_read=1, check_stats=True, telemetry=True, **kw):
+    """Run `sched` on GPU (device packets) and oracle; compare at readouts,
+    and (spatial filter on) every step's window scalars."""
     ctx = make_ctx(W, H, **kw)
     orc = oracle.Oracle(W, H, **oracle_kw(kw))
     gx, gy, gp = to_device(ev)
     spatial = kw.get("spatial_filter", True)
+    tel, want = None, []
+    if spatial and telemetry:
+        tel = telemetry_buffer(ctx, sum(1 for it in sched if it[0] == "push") + 2)
     nread = 0
     for item in sched:
         if item[0] == "push":
             a, b = item[1], item[2]
             assert ctx.push(gx[a:b], gy[a:b], gp[a:b]) == 0
             assert orc.push(ev.x[a:b], ev.y[a:b], ev.p[a:b]) == 0
+            if tel is not None and b > a:
+                want.append(oracle_step_record(orc.stats(), b - a))
         else:
             nread += 1
             if (nread - 1) % check_every_read:
@@ -89,5 +124,7 @@ def run_pair(ev, W, H, sched, check_every_read=1, check_stats=True, **kw):
     compare_state(g, r, spatial, "final")
     if spatial:
         compare_stats(ctx.stats(), orc.stats(), "final")
+    if tel is not None:
+        compare_telemetry(tel, want, "(%dx%d)" % (W, H))
     ctx.close()
     return g, r

@@ -47,7 +47,8 @@ def test_binding_structs_match_header_sizes():
     # x86-64 SysV layout of the public structs
     assert ctypes.sizeof(fb.fibar_params) == 8 + 7 * 4 + 4 + 8
     assert ctypes.sizeof(fb.fibar_packet) == 4 * 8 + 8 + 8
-    assert ctypes.sizeof(fb.fibar_readout_buf) == 7 * 8 + 8
+    assert ctypes.sizeof(fb.fibar_readout_buf) == 8 * 8 + 8
+    assert fb.STEP_RECORD_WORDS * 8 == 64   # fibar_step_record: one int64 and seven uint64
     assert ctypes.sizeof(fb.fibar_stats) == 9 * 8
 
 
@@ -82,3 +83,19 @@ def test_fill_entry_points_reject_null_handles_without_gpu():
         fb.FIBAR_E_INVALID_ARG
     lib.fibar_fill_destroy(None)
     assert fb.FILL_PARAMS == 5233
+
+
+def test_sensor_size_limit_of_the_sort_key_without_gpu():
+    # an event's sort key is (tile-major pixel key << 1) | polarity in 32 bits,
+    # four keys per 2x2 tile: sensors above 2^29 tiles are rejected before any
+    # device call (at 65535 x 65535 the key would lose its top bit)
+    p = fb.fibar_default_params()
+    for w, h in ((65535, 65535), (46341, 46341), (65535, 32769), (32769, 65535)):
+        tiles = ((w + 1) // 2) * ((h + 1) // 2)
+        assert 4 * tiles > 2 ** 31
+        assert fb.fibar_create(w, h, p)[0] == fb.FIBAR_E_INVALID_ARG, (w, h)
+
+
+def test_telemetry_rejects_bad_arguments_without_gpu():
+    lib = fb.load()
+    assert lib.fibar_set_telemetry(None, None, 0) == fb.FIBAR_E_INVALID_ARG

@@ -479,7 +479,8 @@ def test_nsf_rejects_spatial_outputs():
     npx = 32 * 16
     L = np.empty(npx, np.float32)
     st = np.empty(npx, np.uint8)
-    buf = fb.fibar_readout_buf(L.ctypes.data, None, st.ctypes.data, None, None, None, None, 0)
+    buf = fb.fibar_readout_buf(L.ctypes.data, None, st.ctypes.data, None, None, None, None, None,
+                               0)
     assert fb.fibar_readout(ctx.handle, 0, buf) == fb.FIBAR_E_UNSUPPORTED
     ctx.close()
 
@@ -557,3 +558,44 @@ def test_nsf_device_packet_rejection():
     compare_state(ctx.readout_host(0), orc.readout(0), False, "after rejected packet")
     assert ctx.stats()["k"] == len(ev) - 1000 - 1
     ctx.close()
+
+
+def test_telemetry_skips_rejected_and_empty_pushes():
+    # one record per regulation step: a rejected device packet and an empty
+    # push make no step, and records past the buffer are not written
+    from _harness import compare_telemetry, oracle_step_record, telemetry_buffer
+    w = eventsim.preset("sensor64x48", n_events=30000, seed=5)
+    ev = eventsim.generate(w.scene)
+    ctx = make_ctx(64, 48, q_min=16)
+    orc = oracle.Oracle(64, 48, q_min=16)
+    gx, gy, gp = to_device(ev)
+    cap = 20
+    tel = telemetry_buffer(ctx, cap)
+    want = []
+    bounds = list(range(0, len(ev), 1500)) + [len(ev)]
+    for i, (a, b) in enumerate(zip(bounds[:-1], bounds[1:])):
+        if i == 3:
+            bx = gx[a:b].clone()
+            bx[5] = 64                       # rejected on the device
+            assert ctx.push(bx, gy[a:b], gp[a:b]) == 0
+        if i == 5:
+            assert ctx.push(gx[a:a], gy[a:a], gp[a:a]) == 0   # empty: no step
+        assert ctx.push(gx[a:b], gy[a:b], gp[a:b]) == 0
+        assert orc.push(ev.x[a:b], ev.y[a:b], ev.p[a:b]) == 0
+        want.append(oracle_step_record(orc.stats(), b - a))
+    assert ctx.synchronize() == fb.FIBAR_E_RANGE
+    assert len(want) == 20 == cap
+    compare_telemetry(tel, want, "with a rejected and an empty push")
+    compare_stats(ctx.stats(), orc.stats(), "after telemetry")
+    compare_state(ctx.readout_host(0), orc.readout(0), True, "after telemetry")
+    ctx.close()
+
+
+def test_total_count_blur_off_region_path():
+    # the blur-off batch path keeps the per-pixel event total too
+    w = eventsim.preset("vga", n_events=400000, seed=9)
+    ev = eventsim.generate(w.scene)
+    sched = eventsim.schedule(len(ev), w.packet, [150000, 400000])
+    g, r = run_pair(ev, 640, 480, sched, spatial_filter=False)
+    assert np.array_equal(g["tot"], r["tot"])
+    assert int(g["tot"].sum()) == len(ev)
