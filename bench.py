@@ -267,10 +267,10 @@ def run_fill(args, torch, dev, fb, eventsim):
         st = Sev[k].cpu().numpy() != 0
         tgt = Tev[k].cpu().numpy()
         psnr_g.append(eventsim.fill_psnr(Lev[k].cpu().numpy(), tgt, st))
-        rc, _ = fill.apply(Lev[k], Sev[k], Aev[k], out, tile=16, tau=float("inf"))
+        rc, _ = fill.apply(Lev[k], Sev[k], Aev[k], out, tile=16, theta=0.0)
         assert rc == 0
         psnr_l.append(eventsim.fill_psnr(out.cpu().numpy(), tgt, st))
-        rc, nfb = fill.apply(Lev[k], Sev[k], Aev[k], out, tile=16, tau=args.fill_tau)
+        rc, nfb = fill.apply(Lev[k], Sev[k], Aev[k], out, tile=16, theta=args.fill_tau)
         assert rc == 0
         psnr_f.append(eventsim.fill_psnr(out.cpu().numpy(), tgt, st))
         fb_frac.append(nfb / tiles)

@@ -70,13 +70,17 @@ int fibar_fill_train_step(fibar_fill* f, const float* L, const uint8_t* stale,
                           uint32_t W, float lr, float* loss);
 
 /* Filled image of one readout (H x W): L where the pixel is not stale; at
- * stale pixels the network's prediction, except in tiles of tile x tile
- * pixels (tile in 4..64) where some stale pixel's prediction differs from
- * L by more than tau, which keep L (the Gaussian fill) -- the per-tile
- * fallback.  `fallback_tiles` (host, may be NULL) receives the number of
- * tiles that fell back, which synchronises the stream. */
+ * stale pixels the network's prediction in tiles of tile x tile pixels
+ * (tile in 4..64; edge tiles cut by the image) where more than a fraction
+ * theta (>= 0) of the tile's pixels are stale and every stale prediction is
+ * finite; every other tile keeps L, the reconstruction's own one-time
+ * Gaussian fill -- the per-tile fallback.  theta = 0 uses the network in
+ * every tile with a stale pixel, theta >= 1 in none.  `fallback_tiles`
+ * (host, may be NULL) receives the number of tiles with stale pixels that
+ * kept L, which synchronises the stream.  The prediction buffer is owned by
+ * the handle and grows to the largest H * W used. */
 int fibar_fill_apply(fibar_fill* f, const float* L, const uint8_t* stale, const float* log_age,
-                     uint32_t H, uint32_t W, uint32_t tile, float tau, float* out,
+                     uint32_t H, uint32_t W, uint32_t tile, float theta, float* out,
                      uint32_t* fallback_tiles);
 
 void fibar_fill_destroy(fibar_fill* f);

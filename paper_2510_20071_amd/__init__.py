@@ -489,11 +489,11 @@ def fibar_fill_train_step(handle, L, stale, log_age, target, n, H, W, lr, want_l
     return rc, (float(loss.value) if want_loss else None)
 
 
-def fibar_fill_apply(handle, L, stale, log_age, H, W, tile, tau, out):
-    """Returns (status, tiles that fell back)."""
+def fibar_fill_apply(handle, L, stale, log_age, H, W, tile, theta, out):
+    """Returns (status, tiles with stale pixels that kept L)."""
     fb = ctypes.c_uint32()
     rc = load().fibar_fill_apply(handle, _addr(L), _addr(stale), _addr(log_age), H, W, int(tile),
-                                 float(tau), _addr(out), ctypes.byref(fb))
+                                 float(theta), _addr(out), ctypes.byref(fb))
     return rc, int(fb.value)
 
 
@@ -541,9 +541,9 @@ class Fill:
         return fibar_fill_train_step(self.handle, L, stale, log_age, target, *self._dims(L), lr,
                                      want_loss=want_loss)
 
-    def apply(self, L, stale, log_age, out, tile=16, tau=4.0):
+    def apply(self, L, stale, log_age, out, tile=16, theta=0.0):
         _, H, W = self._dims(L)
-        return fibar_fill_apply(self.handle, L, stale, log_age, H, W, tile, tau, out)
+        return fibar_fill_apply(self.handle, L, stale, log_age, H, W, tile, theta, out)
 
     def close(self):
         if getattr(self, "handle", None):

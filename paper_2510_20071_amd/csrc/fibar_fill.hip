@@ -714,34 +714,52 @@ __global__ __launch_bounds__(kFuseThreads) __attribute__((amdgpu_waves_per_eu(4)
     }
 }
 
-// Filled image with per-tile fallback; one workgroup per tile.
+// Filled image with the per-tile fallback; one workgroup per tile.  A tile
+// takes the network's predictions at its stale pixels when more than a
+// fraction theta of its pixels (inside the image) are stale and every one of
+// those predictions is finite; otherwise it keeps L, the reconstruction's own
+// blurred value.  `fallbacks` counts the tiles with stale pixels that keep L.
 __global__ __launch_bounds__(256) void k_fill_apply(const float* __restrict__ L,
                                                     const uint8_t* __restrict__ stale,
                                                     const float* __restrict__ pred, uint32_t H,
-                                                    uint32_t W, uint32_t tile, float tau,
+                                                    uint32_t W, uint32_t tile, float theta,
                                                     float* __restrict__ out,
                                                     uint32_t* __restrict__ fallbacks)
 {
-    __shared__ float sh[4];
+    __shared__ uint32_t sh[2][4];
     const uint32_t tw = (W + tile - 1) / tile;
     const uint32_t ty0 = (blockIdx.x / tw) * tile, tx0 = (blockIdx.x % tw) * tile;
     const uint32_t th = min(tile, H - ty0), twd = min(tile, W - tx0);
-    float dev = 0.f;
+    uint32_t nst = 0u, bad = 0u;
     for (uint32_t k = threadIdx.x; k < th * twd; k += blockDim.x) {
         const size_t p = (size_t)(ty0 + k / twd) * W + tx0 + k % twd;
-        if (stale[p]) dev = fmaxf(dev, fabsf(pred[p] - L[p]));
+        if (stale[p]) {
+            ++nst;
+            bad += isfinite(pred[p]) ? 0u : 1u;
+        }
     }
-    for (int m = 32; m > 0; m >>= 1) dev = fmaxf(dev, __shfl_xor(dev, m));
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = dev;
+    for (int m = 32; m > 0; m >>= 1) {
+        nst += __shfl_xor(nst, m);
+        bad += __shfl_xor(bad, m);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][threadIdx.x >> 6] = nst;
+        sh[1][threadIdx.x >> 6] = bad;
+    }
     __syncthreads();
-    dev = fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
-    const bool fb = dev > tau;
-    if (fb && threadIdx.x == 0) atomicAdd(fallbacks, 1u);
+    nst = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
+    bad = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+    // stale fraction > theta, compared exactly: nst > theta * pixels
+    const bool use = nst > 0u && bad == 0u && (double)nst > (double)theta * (double)(th * twd);
+    if (nst > 0u && !use && threadIdx.x == 0) atomicAdd(fallbacks, 1u);
     for (uint32_t k = threadIdx.x; k < th * twd; k += blockDim.x) {
         const size_t p = (size_t)(ty0 + k / twd) * W + tx0 + k % twd;
-        out[p] = (stale[p] && !fb) ? pred[p] : L[p];
+        out[p] = (stale[p] && use) ? pred[p] : L[p];
     }
 }
+
+__global__ void k_fill_clear(uint32_t* __restrict__ c) { *c = 0u; }
+
 
 }  // namespace
 
@@ -761,6 +779,8 @@ struct fibar_fill {
     uint32_t* fallbacks = nullptr;
     int step = 0;                // Adam steps since the parameters were set
     uint32_t cus = 256;          // compute units of the device
+    float* apply_pred = nullptr; // prediction buffer of fibar_fill_apply
+    size_t apply_cap = 0;
     // workspace for up to cap pixels
     size_t cap = 0;
     uint16_t* act[4] = {};       // x0, a1, a2, a3 (BF16 x 16 channels)
@@ -791,6 +811,19 @@ void free_ws(fibar_fill* f)
     f->pred = nullptr;
     f->cap = 0;
 }
+
+int ensure_apply_pred(fibar_fill* f, size_t P)
+{
+    if (P <= f->apply_cap) return FIBAR_OK;
+    FILL_TRY(hipStreamSynchronize(f->st));
+    (void)hipFree(f->apply_pred);
+    f->apply_pred = nullptr;
+    f->apply_cap = 0;
+    FILL_TRY(hipMalloc((void**)&f->apply_pred, P * sizeof(float)));
+    f->apply_cap = P;
+    return FIBAR_OK;
+}
+
 
 int ensure_ws(fibar_fill* f, size_t P)
 {
@@ -840,6 +873,27 @@ hipError_t forward_fused(fibar_fill* f, const float* L, const uint8_t* stale, co
         hipLaunchKernelGGL(k_fill_fused, dim3(grid), dim3(kFuseThreads), 0, f->st, L + i * P,
                            stale + i * P, age + i * P, f->wk, f->bias, H, W, pred + i * P);
     return hipGetLastError();
+}
+
+// The filled image of one frame (prediction into `pred`, fallback counter at
+// `counter`); allocates nothing.
+int apply_with(fibar_fill* f, const float* L, const uint8_t* stale, const float* log_age,
+               uint32_t H, uint32_t W, uint32_t tile, float theta, float* out, float* pred,
+               uint32_t* counter, uint32_t* fallback_tiles)
+{
+    FILL_TRY(forward_fused(f, L, stale, log_age, 1, H, W, pred));
+    const uint32_t tiles = ((H + tile - 1) / tile) * ((W + tile - 1) / tile);
+    // a kernel, not a memset: callers may capture this into a graph
+    hipLaunchKernelGGL(k_fill_clear, dim3(1), dim3(1), 0, f->st, counter);
+    hipLaunchKernelGGL(k_fill_apply, dim3(tiles), dim3(256), 0, f->st, L, stale, pred, H, W,
+                       tile, theta, out, counter);
+    FILL_TRY(hipGetLastError());
+    if (fallback_tiles) {
+        FILL_TRY(hipMemcpyAsync(fallback_tiles, counter, sizeof(uint32_t),
+                                hipMemcpyDeviceToHost, f->st));
+        FILL_TRY(hipStreamSynchronize(f->st));
+    }
+    return FIBAR_OK;
 }
 
 // Pack the input and run the four layers one by one, keeping every layer's
@@ -907,6 +961,7 @@ void free_fill(fibar_fill* f)
     if (!f) return;
     if (f->st) (void)hipStreamSynchronize(f->st);
     free_ws(f);
+    (void)hipFree(f->apply_pred);
     void* p[] = {f->prm, f->m, f->v, f->grad, f->wf, f->wb, f->wk, f->bias, f->partial,
                  f->lpart, f->loss2, f->fallbacks};
     for (void* q : p) (void)hipFree(q);
@@ -1032,26 +1087,16 @@ int fibar_fill_train_step(fibar_fill* f, const float* L, const uint8_t* stale,
 }
 
 int fibar_fill_apply(fibar_fill* f, const float* L, const uint8_t* stale, const float* log_age,
-                     uint32_t H, uint32_t W, uint32_t tile, float tau, float* out,
+                     uint32_t H, uint32_t W, uint32_t tile, float theta, float* out,
                      uint32_t* fallback_tiles)
 {
     int rc = check_images(f, L, stale, log_age, 1, H, W);
     if (rc) return rc;
-    if (!out || tile < 4 || tile > 64 || !(tau >= 0.f)) return FIBAR_E_INVALID_ARG;
-    rc = ensure_ws(f, (size_t)H * W);
+    if (!out || tile < 4 || tile > 64 || !(theta >= 0.f)) return FIBAR_E_INVALID_ARG;
+    rc = ensure_apply_pred(f, (size_t)H * W);
     if (rc) return rc;
-    FILL_TRY(forward_fused(f, L, stale, log_age, 1, H, W, f->pred));
-    const uint32_t tiles = ((H + tile - 1) / tile) * ((W + tile - 1) / tile);
-    FILL_TRY(hipMemsetAsync(f->fallbacks, 0, sizeof(uint32_t), f->st));
-    hipLaunchKernelGGL(k_fill_apply, dim3(tiles), dim3(256), 0, f->st, L, stale, f->pred, H, W,
-                       tile, tau, out, f->fallbacks);
-    FILL_TRY(hipGetLastError());
-    if (fallback_tiles) {
-        FILL_TRY(hipMemcpyAsync(fallback_tiles, f->fallbacks, sizeof(uint32_t),
-                                hipMemcpyDeviceToHost, f->st));
-        FILL_TRY(hipStreamSynchronize(f->st));
-    }
-    return FIBAR_OK;
+    return apply_with(f, L, stale, log_age, H, W, tile, theta, out, f->apply_pred, f->fallbacks,
+                      fallback_tiles);
 }
 
 void fibar_fill_destroy(fibar_fill* f) { free_fill(f); }

@@ -185,21 +185,56 @@ def test_apply_uses_prediction_or_falls_back_per_tile(tile):
     assert f.predict(gL, gS, gA, pred) == 0
     p = pred.cpu().numpy()
     tiles = [(ty, tx) for ty in range(0, H, tile) for tx in range(0, W, tile)]
-    with_stale = sum(1 for ty, tx in tiles if stale[0, ty:ty + tile, tx:tx + tile].any())
-    # tau = inf: prediction at every stale pixel, L elsewhere
-    rc, nfb = f.apply(gL, gS, gA, out, tile=tile, tau=float("inf"))
+    frac = {t: float(np.mean(stale[0, t[0]:t[0] + tile, t[1]:t[1] + tile] != 0)) for t in tiles}
+    with_stale = sum(1 for t in tiles if frac[t] > 0)
+    # theta = 0: prediction at every stale pixel, L elsewhere
+    rc, nfb = f.apply(gL, gS, gA, out, tile=tile, theta=0.0)
     assert rc == 0 and nfb == 0
     assert np.array_equal(out.cpu().numpy(), np.where(stale[0] != 0, p, L[0]))
-    # tau = 0: every tile with a stale pixel keeps L
-    rc, nfb = f.apply(gL, gS, gA, out, tile=tile, tau=0.0)
+    # theta = 1: every tile with a stale pixel keeps L
+    rc, nfb = f.apply(gL, gS, gA, out, tile=tile, theta=1.0)
     assert rc == 0 and nfb == with_stale
     assert np.array_equal(out.cpu().numpy(), L[0])
-    # a middle tau: exactly the tiles whose largest stale deviation exceeds it
-    dev_t = [np.max(np.abs(p - L[0])[ty:ty + tile, tx:tx + tile][stale[0, ty:ty + tile, tx:tx + tile] != 0],
-                    initial=0.0) for ty, tx in tiles]
-    tau = float(np.median(dev_t))
-    rc, nfb = f.apply(gL, gS, gA, out, tile=tile, tau=tau)
-    assert rc == 0 and nfb == sum(1 for v in dev_t if v > tau)
+    # a middle theta: exactly the tiles whose stale fraction exceeds it use the net
+    theta = float(np.median([v for v in frac.values() if v > 0]))
+    rc, nfb = f.apply(gL, gS, gA, out, tile=tile, theta=theta)
+    assert rc == 0 and nfb == sum(1 for v in frac.values() if 0 < v <= theta)
+    want = L[0].copy()
+    for (ty, tx), v in frac.items():
+        if v > theta:
+            sl = (slice(ty, ty + tile), slice(tx, tx + tile))
+            want[sl] = np.where(stale[0][sl] != 0, p[sl], L[0][sl])
+    assert np.array_equal(out.cpu().numpy(), want)
+    f.close()
+
+
+def test_apply_falls_back_where_a_prediction_is_not_finite():
+    torch, d = torch_dev()
+    H, W = 32, 32
+    prm = params_with_biases(17)
+    L, stale, age, _ = make_batch(18, 1, H, W)
+    stale[0] = 1
+    Lnan = L[0].copy()
+    Lnan[3, 4] = np.nan                       # the net's prediction there is NaN
+    gL, gS, gA = dev(Lnan, stale[0], age[0])
+    f = fb.Fill(prm)
+    out = torch.empty((H, W), dtype=torch.float32, device=d)
+    rc, nfb = f.apply(gL, gS, gA, out, tile=16, theta=0.0)
+    assert rc == 0
+    o = out.cpu().numpy()
+    pred = torch.empty_like(out)
+    assert f.predict(gL, gS, gA, pred) == 0
+    p = pred.cpu().numpy()
+    bad_tiles = {(ty, tx) for ty in range(0, H, 16) for tx in range(0, W, 16)
+                 if not np.all(np.isfinite(p[ty:ty + 16, tx:tx + 16]))}
+    assert bad_tiles and nfb == len(bad_tiles)
+    for ty in range(0, H, 16):
+        for tx in range(0, W, 16):
+            sl = (slice(ty, ty + 16), slice(tx, tx + 16))
+            if (ty, tx) in bad_tiles:
+                assert np.array_equal(o[sl], Lnan[sl], equal_nan=True)
+            else:
+                assert np.array_equal(o[sl], p[sl])
     f.close()
 
 
