@@ -83,6 +83,19 @@ int fibar_fill_apply(fibar_fill* f, const float* L, const uint8_t* stale, const 
                      uint32_t H, uint32_t W, uint32_t tile, float theta, float* out,
                      uint32_t* fallback_tiles);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same result
+ * as fibar_fill_apply, bit for bit, with no allocation at all.  The
+ * prediction and the fallback counter live in a fixed device array of the
+ * library, one per GPU (4 MiB + 256 bytes, looked up when a handle is created
+ * on that GPU and held until the process ends), so H * W may be at most
+ * 1048576 pixels (FIBAR_E_INVALID_ARG beyond).  Every call on a GPU uses that
+ * GPU's array: calls that overlap on one GPU (on different streams, or from
+ * different threads) race and must be serialised by the caller. */
+int fibar_fill_apply_noalloc(fibar_fill* f, const float* L, const uint8_t* stale,
+                             const float* log_age, uint32_t H, uint32_t W, uint32_t tile,
+                             float theta, float* out, uint32_t* fallback_tiles);
+
 void fibar_fill_destroy(fibar_fill* f);
 
 #ifdef __cplusplus

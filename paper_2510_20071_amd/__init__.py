@@ -132,8 +132,15 @@ _SIGNATURES.update({
                                         ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
                                         ctypes.c_uint32, ctypes.c_float, ctypes.c_void_p,
                                         ctypes.POINTER(ctypes.c_uint32)]),
+    "fibar_fill_apply_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                                ctypes.c_void_p, ctypes.c_void_p,
+                                                ctypes.c_uint32, ctypes.c_uint32,
+                                                ctypes.c_uint32, ctypes.c_float,
+                                                ctypes.c_void_p,
+                                                ctypes.POINTER(ctypes.c_uint32)]),
     "fibar_fill_destroy": (None, [ctypes.c_void_p]),
 })
+FILL_NOALLOC_MAX_PIXELS = 1 << 20
 
 KERNEL_NAMES = ("group_compose", "apply", "pop_blur", "pop_blur_readout", "readout")
 
@@ -497,6 +504,14 @@ def fibar_fill_apply(handle, L, stale, log_age, H, W, tile, theta, out):
     return rc, int(fb.value)
 
 
+def fibar_fill_apply_noalloc(handle, L, stale, log_age, H, W, tile, theta, out):
+    """Returns (status, tiles with stale pixels that kept L)."""
+    fb = ctypes.c_uint32()
+    rc = load().fibar_fill_apply_noalloc(handle, _addr(L), _addr(stale), _addr(log_age), H, W,
+                                         int(tile), float(theta), _addr(out), ctypes.byref(fb))
+    return rc, int(fb.value)
+
+
 def fibar_fill_destroy(handle) -> None:
     load().fibar_fill_destroy(handle)
 
@@ -544,6 +559,10 @@ class Fill:
     def apply(self, L, stale, log_age, out, tile=16, theta=0.0):
         _, H, W = self._dims(L)
         return fibar_fill_apply(self.handle, L, stale, log_age, H, W, tile, theta, out)
+
+    def apply_noalloc(self, L, stale, log_age, out, tile=16, theta=0.0):
+        _, H, W = self._dims(L)
+        return fibar_fill_apply_noalloc(self.handle, L, stale, log_age, H, W, tile, theta, out)
 
     def close(self):
         if getattr(self, "handle", None):

@@ -22,6 +22,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -760,6 +761,13 @@ __global__ __launch_bounds__(256) void k_fill_apply(const float* __restrict__ L,
 
 __global__ void k_fill_clear(uint32_t* __restrict__ c) { *c = 0u; }
 
+// Scratch of fibar_fill_apply_noalloc: the prediction of one frame of up to
+// kNoAllocPixels pixels, then the fallback counter.  One copy per device,
+// held until the process ends; host code reaches it only through the address
+// hipGetSymbolAddress gives on that device (noalloc_scratch below).
+constexpr size_t kNoAllocPixels = 1u << 20;
+constexpr size_t kNoAllocBytes = kNoAllocPixels * sizeof(float) + 256;
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
 
 }  // namespace
 
@@ -779,6 +787,7 @@ struct fibar_fill {
     uint32_t* fallbacks = nullptr;
     int step = 0;                // Adam steps since the parameters were set
     uint32_t cus = 256;          // compute units of the device
+    uint8_t* noalloc = nullptr;  // this device's copy of `scratch`
     float* apply_pred = nullptr; // prediction buffer of fibar_fill_apply
     size_t apply_cap = 0;
     // workspace for up to cap pixels
@@ -841,6 +850,26 @@ int ensure_ws(fibar_fill* f, size_t P)
         return map_hip(e);
     }
     f->cap = P;
+    return FIBAR_OK;
+}
+
+// Device address of this device's `scratch` array, looked up once per
+// device with that device current.
+constexpr int kMaxDevices = 64;
+uint8_t* g_noalloc[kMaxDevices] = {};
+std::mutex g_noalloc_mu;
+
+int noalloc_scratch(int dev, uint8_t** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return FIBAR_E_DEVICE;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return map_hip(e == hipSuccess ? hipErrorInvalidSymbol : e);
+        g_noalloc[dev] = static_cast<uint8_t*>(p);
+    }
+    *out = g_noalloc[dev];
     return FIBAR_OK;
 }
 
@@ -1000,6 +1029,13 @@ int fibar_fill_create(void* stream, fibar_fill** out)
     if (e == hipSuccess) e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess && cus > 0) f->cus = (uint32_t)cus;
+    if (e == hipSuccess) {
+        const int rc = noalloc_scratch(dev, &f->noalloc);
+        if (rc) {
+            free_fill(f);
+            return rc;
+        }
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(f->st);
     if (e != hipSuccess) {
         free_fill(f);
@@ -1096,6 +1132,21 @@ int fibar_fill_apply(fibar_fill* f, const float* L, const uint8_t* stale, const 
     rc = ensure_apply_pred(f, (size_t)H * W);
     if (rc) return rc;
     return apply_with(f, L, stale, log_age, H, W, tile, theta, out, f->apply_pred, f->fallbacks,
+                      fallback_tiles);
+}
+
+int fibar_fill_apply_noalloc(fibar_fill* f, const float* L, const uint8_t* stale,
+                             const float* log_age, uint32_t H, uint32_t W, uint32_t tile,
+                             float theta, float* out, uint32_t* fallback_tiles)
+{
+    int rc = check_images(f, L, stale, log_age, 1, H, W);
+    if (rc) return rc;
+    if (!out || tile < 4 || tile > 64 || !(theta >= 0.f)) return FIBAR_E_INVALID_ARG;
+    if ((size_t)H * W > kNoAllocPixels) return FIBAR_E_INVALID_ARG;
+    if (!f->noalloc) return FIBAR_E_DEVICE;
+    float* pred = reinterpret_cast<float*>(f->noalloc);
+    uint32_t* counter = reinterpret_cast<uint32_t*>(f->noalloc + kNoAllocPixels * sizeof(float));
+    return apply_with(f, L, stale, log_age, H, W, tile, theta, out, pred, counter,
                       fallback_tiles);
 }
 
