@@ -142,7 +142,8 @@ _SIGNATURES.update({
 })
 FILL_NOALLOC_MAX_PIXELS = 1 << 20
 
-KERNEL_NAMES = ("group_compose", "apply", "pop_blur", "pop_blur_readout", "readout")
+KERNEL_NAMES = ("group_compose", "apply", "pop", "pop_readout", "readout", "fused",
+                "fused_readout")
 
 _lib = None
 

@@ -271,7 +271,7 @@ __global__ __launch_bounds__(256) void k_multi_apply(const StreamStep* rr, uint3
         const uint64_t first = (uint64_t)(k0 + 1) + (uint64_t)sub * kChunk;
         uint32_t dP = 0u, dT = 0u;
         apply_tile(s, g, ti, cd.n, nseg, status != 0, i, first, h0, 1, dP, dT);
-        add_counts(stp, false, (uint32_t)sub * kChunk + i, dP, dT);
+        add_counts(stp, kCountApply, (uint32_t)sub * kChunk + i, dP, dT);
     }
 }
 
@@ -300,7 +300,7 @@ __global__ __launch_bounds__(256) void k_multi_pop(const StreamStep* rr, uint32_
         uint32_t dP = 0u, dT = 0u;
         pop_range(s, h_old + (uint64_t)(t - start) * blockDim.x + threadIdx.x, h_new,
                   (uint64_t)pop_blocks * blockDim.x, h_old, dP, dT);
-        add_counts(stp, true, (t - start) * blockDim.x + threadIdx.x, dP, dT);
+        add_counts(stp, kCountPop, (t - start) * blockDim.x + threadIdx.x, dP, dT);
     }
 }
 
