@@ -37,7 +37,7 @@ sys.path.insert(0, ROOT)
 #                value written (4 B) + tile count read+write (8 B).
 #   group      : per event: x, y, p read (5 B); per distinct (pixel, chunk):
 #                one 32-B composed-map record written.
-KERNELS = ("group_compose", "apply", "pop", "pop_readout", "readout", "fused", "fused_readout")
+KERNELS = ("group_compose", "apply", "pop_blur", "pop_blur_readout", "readout")
 LAUNCH_MODES = {"direct": 0, "graph": 1}
 KERNEL_SOURCES = ("paper_2510_20071_amd/csrc/fibar_kernels.hip",
                   "paper_2510_20071_amd/csrc/fibar_step.h",
@@ -353,7 +353,7 @@ def main():
     ap.add_argument("--no-nsf", action="store_true", help="skip the blur-off measurement")
     ap.add_argument("--only-nsf", action="store_true",
                     help="measure only the blur-off mode (for profiling)")
-    ap.add_argument("--roofline-kernel", default="fused", choices=KERNELS)
+    ap.add_argument("--roofline-kernel", default="pop_blur", choices=KERNELS)
     ap.add_argument("--time-every", type=int, default=16,
                     help="time every n-th launch of the roofline kernel (events on its dispatch)")
     ap.add_argument("--no-multi", action="store_true", help="skip the batched-streams measurement")
@@ -467,7 +467,7 @@ def main():
             assert lib.fibar_submit(ctx.handle, ops, n_ops) == 0
         torch.cuda.synchronize()
         if time_kernel is not None:
-            for kind in range(len(KERNELS)):
+            for kind in range(5):
                 fb.fibar_kernel_time(ctx.handle, kind)  # clear the warm-up's
         torch.cuda.synchronize()
         t_start = time.perf_counter()
@@ -480,7 +480,7 @@ def main():
         if time_kernel is not None:
             rc, ms, launches = fb.fibar_kernel_time(ctx.handle, KERNELS.index(time_kernel))
             kt = (ms, launches)
-            for kind in range(len(KERNELS)):
+            for kind in range(5):
                 fb.fibar_kernel_time(ctx.handle, kind)  # the others' events go back to the pool
             fb.fibar_set_kernel_timing(ctx.handle, 0)
         assert ctx.synchronize() == 0
@@ -509,7 +509,7 @@ def main():
     pops_per_ev = (st_on["h"]) / n                              # popped events / event
     ms, launches = kt
     avg_s = ms / 1e3 / max(launches, 1)
-    if args.roofline_kernel in ("pop", "fused"):
+    if args.roofline_kernel == "pop_blur":
         per_launch = (12.0 * pops_per_ev + 48.0 * s_per_ev) * n / n_push
     elif args.roofline_kernel == "apply":
         per_launch = (32.0 * u + 8.0) * n / n_push

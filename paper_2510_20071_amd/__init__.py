@@ -142,8 +142,7 @@ _SIGNATURES.update({
 })
 FILL_NOALLOC_MAX_PIXELS = 1 << 20
 
-KERNEL_NAMES = ("group_compose", "apply", "pop", "pop_readout", "readout", "fused",
-                "fused_readout")
+KERNEL_NAMES = ("group_compose", "apply", "pop_blur", "pop_blur_readout", "readout")
 
 _lib = None
 

@@ -253,17 +253,12 @@ void free_ctx(fibar_ctx* c)
     else (void)hipDeviceSynchronize();
     (void)hipFree(c->s.px);
     (void)hipFree(c->s.pp);
-    (void)hipFree(c->s.cnt);
     (void)hipFree(c->s.ring);
     (void)hipFree(c->s.sc);
     (void)hipFree(c->d_chunks);
     (void)hipFree(c->seg);
     (void)hipFree(c->seg_count);
     (void)hipFree(c->scratch);
-    for (int k = 0; k < 2; ++k) {
-        (void)hipFree(c->stage[k]);
-        (void)hipFree(c->ttag[k]);
-    }
     (void)hipFree(c->stg_x);
     (void)hipFree(c->stg_y);
     (void)hipFree(c->stg_p);
@@ -308,9 +303,10 @@ int host_validate(const fibar_ctx* c, const fibar_packet* pk)
 }
 
 int do_readout_kernel(fibar_ctx* c, const fibar_readout_buf& ro, const StepScratch* pend,
-                      uint32_t pend_n, int slot)
+                      uint32_t pend_n)
 {
     const int sp = (int)c->prm.spatial_filter;
+    const int slot = c->cur_slot;
     if (ro.on_device) {
         HIP_TRY(timed_launch(c, 4, [&](const LaunchTiming& tm) {
             return launch_readout(c->s, sp, pend, pend_n, slot, ro.brightness, ro.pbar,
@@ -404,24 +400,7 @@ int run_region_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, u
     return FIBAR_OK;
 }
 
-// A device readout a pop launch can write (it needs no window count, which
-// the pops change while it runs).
-bool fusable_readout(const Op& o)
-{
-    return o.kind == 1 && o.ro.on_device && !o.ro.active_count;
-}
-
 // Execute ops[0..n): bulk sort for all pushes, then the in-order steps.
-//
-// Launch plan (spatial filter on).  A packet is pushed and its window popped
-// by different launches: the launch that pushes packet b + 1 also pops step
-// b (k_step, fused) when packet b + 1 is one chunk and nothing but a
-// device readout without window counts lies between them (that readout is
-// written by the same launch).  Otherwise step b is popped alone (with such
-// a readout, or followed by a separate readout kernel) and the next packet
-// is pushed chunk by chunk.  Every launch derives the window from the last
-// committed scalars and commits the step before the one it pops; the batch
-// ends with the last step popped and committed.
 int run_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, uint32_t n_steps)
 {
     if (n == 0) return FIBAR_OK;
@@ -432,16 +411,12 @@ int run_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, uint32_t
     bool graph = c->graph_mode;
     for (size_t i = 0; graph && i < n; ++i)
         if (ops[i].kind == 1 && !ops[i].ro.on_device) graph = false;
-    // per push op: its first chunk, chunk count, step index
-    std::vector<uint32_t> first_chunk(n, 0), nchunks(n, 0), step_of(n, 0);
     if (n_chunks > 0) {
         // the pinned descriptor buffer may still feed a previous copy
         HIP_TRY(hipEventSynchronize(c->chunks_free));
         uint32_t ci = 0, step = 0;
         for (size_t i = 0; i < n; ++i) {
             if (ops[i].kind != 0) continue;
-            first_chunk[i] = ci;
-            step_of[i] = step;
             for (uint32_t off = 0; off < ops[i].n; off += kChunk) {
                 ChunkDesc& d = c->h_chunks[ci++];
                 const uint32_t m = ops[i].n - off < (uint32_t)kChunk ? ops[i].n - off : (uint32_t)kChunk;
@@ -451,7 +426,6 @@ int run_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, uint32_t
                 d.n = m;
                 d.pkt = step;
             }
-            nchunks[i] = ci - first_chunk[i];
             ++step;
         }
         HIP_TRY(hipMemcpyAsync(c->d_chunks, c->h_chunks, (size_t)n_chunks * sizeof(ChunkDesc),
@@ -466,194 +440,65 @@ int run_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, uint32_t
                                        c->W, c->H, c->key_bits, c->coef, c->st, tm);
         }));
     }
-    const bool sp = c->prm.spatial_filter != 0;
-    // push op index -> the next push op (n if none); whether the pops of the
-    // step of push op i run in the launch that pushes the next one
-    std::vector<size_t> next_push(n, n);
-    for (size_t i = n, nxt = n; i-- > 0;) {
-        next_push[i] = nxt;
-        if (ops[i].kind == 0) nxt = i;
-    }
-    auto fuse_after = [&](size_t i) {
-        if (!sp) return false;
-        const size_t q = next_push[i];
-        if (q >= n || nchunks[q] != 1) return false;
-        // at most one readout between them, and it must be fusable
-        if (q == i + 1) return true;
-        return q == i + 2 && fusable_readout(ops[i + 1]);
-    };
-    struct Step {
-        StepScratch* sc = nullptr;
-        uint32_t n = 0;
-        uint64_t seq = 0;
-    };
-    Step commit_pend;   // complete (pushed and popped) but not committed
-    Step pop_pend;      // pushed, not popped
-    bool staged = false;           // pop_pend's staging list is complete
-    uint64_t older_staged = 0;     // packet whose staging list a pop launch began
-    int slot = c->cur_slot;
-    size_t last_push = n;          // index of the last push op
-
-    // pops of pop_pend alone (optionally writing a readout); q: the next
-    // push op, whose step is the next to be popped
-    auto pop_alone = [&](const fibar_readout_buf* rb, size_t q) -> int {
-        StepLaunch L;
-        L.slot_in = slot;
-        if (commit_pend.sc) {
-            L.commit = commit_pend.sc;
-            L.n_commit = commit_pend.n;
-            L.slot_out = slot ^ 1;
-        }
-        L.head = pop_pend.sc;
-        L.n_head = pop_pend.n;
-        L.pops = true;
-        L.stage_in = staged ? c->stage[pop_pend.seq & 1] : nullptr;
-        if (q < n) {
-            L.stage_out = c->stage[(pop_pend.seq + 1) & 1];
-            L.copy_count = std::min<uint32_t>(kStage, pop_threads(ops[q].n));
-        }
-        PopReadout pr{};
-        if (rb) {
-            pr = PopReadout{rb->brightness, rb->pbar, rb->stale_mask, rb->last_index,
-                            rb->log_age,    rb->tile_count, rb->total_count};
-            L.ro = &pr;
-        }
-        const int kind = rb ? 3 : 2;
-        HIP_TRY(timed_launch(c, graph ? 2 : kind, kind, [&](const LaunchTiming& tm) {
-            return launch_step(c->s, L, c->st, tm);
-        }));
-        if (L.commit) slot ^= 1;
-        older_staged = q < n ? pop_pend.seq + 1 : 0;
-        commit_pend = pop_pend;
-        pop_pend = Step{};
-        return FIBAR_OK;
-    };
-
+    uint32_t ci = 0, step = 0;
+    const int sp = (int)c->prm.spatial_filter;
+    const StepScratch* pend = nullptr;   // step applied but not yet committed
+    uint32_t pend_n = 0;
     for (size_t i = 0; i < n; ++i) {
         if (ops[i].kind == 1) {
-            const Op& o = ops[i];
-            if (pop_pend.sc) {
-                // a readout that the next fused launch writes
-                if (fusable_readout(o) && last_push < n && fuse_after(last_push)) continue;
-                int rc = pop_alone(fusable_readout(o) ? &o.ro : nullptr, next_push[i]);
-                if (rc) return rc;
-                if (fusable_readout(o)) continue;
-            }
-            int rc = do_readout_kernel(c, o.ro, commit_pend.sc, commit_pend.n, slot);
+            int rc = do_readout_kernel(c, ops[i].ro, pend, pend_n);
             if (rc) return rc;
             continue;
         }
-        const uint32_t nev = ops[i].n;
-        const uint32_t step = step_of[i];
         StepScratch* stp = c->scratch + step;
-        const uint64_t seq = ++c->push_seq;
-        const uint32_t ci0 = first_chunk[i];
-        const bool fuse_now = pop_pend.sc && last_push < n && fuse_after(last_push);
-        last_push = i;
-        StepLaunch L;
-        L.spatial = sp;
-        L.app = stp;
-        L.ex = ops[i].x;
-        L.ey = ops[i].y;
-        L.seq = seq;
-        if (fuse_after(i)) {
-            // the next push's launch pops this packet: tag its tiles
-            const size_t q = next_push[i];
-            L.next_seg = c->seg + (size_t)first_chunk[q] * kChunk;
-            L.next_count = c->seg_count + first_chunk[q];
-            L.next = c->scratch + step_of[q];
-            L.ttag_out = c->ttag[(seq + 1) & 1];
-        }
-        if (sp) {
-            // this packet's events go to the staging list of its pop step
-            L.stage_out = c->stage[seq & 1];
-            L.copy_count = std::min<uint32_t>(kStage, pop_threads(nev));
-        }
-        if (fuse_now) {
-            // the previous step's pops with this packet's pushes
-            const Op* ro_op = ops[i - 1].kind == 1 ? &ops[i - 1] : nullptr;
-            L.slot_in = slot;
-            if (commit_pend.sc) {
-                L.commit = commit_pend.sc;
-                L.n_commit = commit_pend.n;
-                L.slot_out = slot ^ 1;
-            }
-            L.head = pop_pend.sc;
-            L.n_head = pop_pend.n;
-            L.pops = true;
-            L.stage_in = staged ? c->stage[pop_pend.seq & 1] : nullptr;
-            L.fused = true;
-            L.ttag_in = c->ttag[seq & 1];
-            L.seg = c->seg + (size_t)ci0 * kChunk;
-            L.seg_count = c->seg_count + ci0;
-            L.n_app = nev;
-            PopReadout pr{};
-            if (ro_op) {
-                const fibar_readout_buf& rb = ro_op->ro;
-                pr = PopReadout{rb.brightness, rb.pbar,     rb.stale_mask, rb.last_index,
-                                rb.log_age,    rb.tile_count, rb.total_count};
-                L.ro = &pr;
-            }
-            const int kind = ro_op ? 6 : 5;
-            HIP_TRY(timed_launch(c, graph ? 5 : kind, kind, [&](const LaunchTiming& tm) {
-                return launch_step(c->s, L, c->st, tm);
-            }));
-            if (L.commit) slot ^= 1;
-            commit_pend = pop_pend;
-            pop_pend = Step{stp, nev, seq};
-            staged = true;
-            continue;
-        }
-        if (pop_pend.sc) {
-            int rc = pop_alone(nullptr, i);
-            if (rc) return rc;
-        }
-        // pushes chunk by chunk, from the window after the last popped step
-        for (uint32_t k = 0; k < nchunks[i]; ++k) {
-            const uint32_t off = k * (uint32_t)kChunk;
+        const uint32_t nev = ops[i].n;
+        const int slot_in = c->cur_slot;
+        const int slot_out = pend ? (slot_in ^ 1) : -1;
+        for (uint32_t off = 0; off < nev; off += kChunk) {
             const uint32_t m = nev - off < (uint32_t)kChunk ? nev - off : (uint32_t)kChunk;
-            StepLaunch A = L;
-            A.slot_in = slot;
-            if (sp) {
-                A.head = commit_pend.sc;
-                A.n_head = commit_pend.n;
-            } else if (commit_pend.sc) {
-                // no window: the previous packet is committed here
-                A.commit = commit_pend.sc;
-                A.n_commit = commit_pend.n;
-                A.slot_out = slot ^ 1;
-            }
-            A.seg = c->seg + (size_t)(ci0 + k) * kChunk;
-            A.seg_count = c->seg_count + ci0 + k;
-            A.n_app = m;
-            A.chunk_offset = off;
-            A.ex = ops[i].x + off;
-            A.ey = ops[i].y + off;
-            if (k > 0) A.next_seg = nullptr;   // tagged by the first chunk
             HIP_TRY(timed_launch(c, 1, [&](const LaunchTiming& tm) {
-                return launch_step(c->s, A, c->st, tm);
+                return launch_apply(c->s, &c->h_chunks[ci], c->seg + (size_t)ci * kChunk,
+                                    c->seg_count + ci, m, off, stp, pend, pend_n, slot_in,
+                                    slot_out, sp, c->st, tm);
             }));
-            if (A.commit) {
-                slot ^= 1;
-                commit_pend = Step{};
+            ++ci;
+        }
+        if (pend) c->cur_slot ^= 1;
+        if (sp) {
+            const int slot = c->cur_slot;
+            // a device readout right after the step (without the window
+            // count, which the pops change) is taken by the pop launch
+            const bool fuse = i + 1 < n && ops[i + 1].kind == 1 && ops[i + 1].ro.on_device &&
+                              !ops[i + 1].ro.active_count;
+            if (fuse) {
+                const fibar_readout_buf& rb = ops[i + 1].ro;
+                PopReadout pr{rb.brightness, rb.pbar,     rb.stale_mask,
+                              rb.last_index, rb.log_age, rb.tile_count,
+                              rb.total_count};
+                if (graph) {
+                    // counted as a pop, so that the timed launches of a
+                    // batch do not depend on where its readouts fall
+                    HIP_TRY(timed_launch(c, 2, 3, [&](const LaunchTiming& tm) {
+                        return launch_pop_blur(c->s, nev, stp, slot, &pr, c->st, tm);
+                    }));
+                } else {
+                    HIP_TRY(launch_pop_blur(c->s, nev, stp, slot, &pr, c->st));
+                }
+                ++i;   // the readout op is done
+            } else {
+                HIP_TRY(timed_launch(c, 2, [&](const LaunchTiming& tm) {
+                    return launch_pop_blur(c->s, nev, stp, slot, nullptr, c->st, tm);
+                }));
             }
         }
-        if (sp) {
-            staged = older_staged == seq;
-            pop_pend = Step{stp, nev, seq};
-        } else {
-            commit_pend = Step{stp, nev, seq};
-        }
+        pend = stp;
+        pend_n = nev;
+        ++step;
     }
-    if (pop_pend.sc) {
-        int rc = pop_alone(nullptr, n);
-        if (rc) return rc;
+    if (pend) {
+        HIP_TRY(launch_commit(c->s, pend, pend_n, c->cur_slot, c->cur_slot ^ 1, sp, c->st));
+        c->cur_slot ^= 1;
     }
-    if (commit_pend.sc) {
-        HIP_TRY(launch_commit(c->s, commit_pend.sc, commit_pend.n, slot, slot ^ 1, (int)sp, c->st));
-        slot ^= 1;
-    }
-    c->cur_slot = slot;
     HIP_TRY(recording.finish());
     return FIBAR_OK;
 }
@@ -734,7 +579,7 @@ int execute(fibar_ctx* c, const fibar_op* ops, size_t n_ops)
                     batch.clear();
                     n_chunks = n_steps = 0;
                     stg_used = 0;
-                    rc2 = do_readout_kernel(c, ro, nullptr, 0, c->cur_slot);
+                    rc2 = do_readout_kernel(c, ro, nullptr, 0);
                     if (rc2) return rc2;
                     continue;
                 }
@@ -768,10 +613,7 @@ hipError_t init_state(fibar_ctx* c)
     c->h_sc->err = 0;
     c->h_sc->stepped = 0;
     c->cur_slot = 0;
-    c->push_seq = 0;
     hipError_t e = launch_init_state(c->s, c->st);
-    for (int k = 0; k < 2 && e == hipSuccess; ++k)
-        if (c->ttag[k]) e = launch_fill_u64(c->ttag[k], c->ntiles, 0, c->st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->s.sc + c->cur_slot, c->h_sc, sizeof(DevScalars), hipMemcpyHostToDevice,
                            c->st);
@@ -875,7 +717,6 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
     };
     alloc((void**)&c->s.px, npx * sizeof(PixL));
     alloc((void**)&c->s.pp, npx * sizeof(PixP));
-    alloc((void**)&c->s.cnt, npx * 4);
     alloc((void**)&c->s.ring, ring * 4);
     alloc((void**)&c->s.sc, 2 * sizeof(DevScalars));
     alloc((void**)&c->d_chunks, kMaxBatchChunks * sizeof(ChunkDesc));
@@ -883,12 +724,6 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
     alloc((void**)&c->seg, ((size_t)kMaxBatchChunks * kChunk + 4) * sizeof(SegRec));
     alloc((void**)&c->seg_count, kMaxBatchChunks * 4);
     alloc((void**)&c->scratch, kMaxBatchChunks * sizeof(StepScratch));
-    if (p.spatial_filter) {
-        for (int k = 0; k < 2; ++k) {
-            alloc((void**)&c->stage[k], (size_t)kStage * 4);
-            alloc((void**)&c->ttag[k], c->ntiles * 8);
-        }
-    }
     alloc((void**)&c->stg_x, stg * 2);
     alloc((void**)&c->stg_y, stg * 2);
     alloc((void**)&c->stg_p, stg);
@@ -1002,7 +837,7 @@ int fibar_reset(fibar_ctx* c)
 
 int fibar_set_kernel_timing(fibar_ctx* c, uint32_t kernel_mask, uint32_t every)
 {
-    if (!c || kernel_mask >= (1u << kKernelKinds) || every == 0) return FIBAR_E_INVALID_ARG;
+    if (!c || kernel_mask >= (1u << 5) || every == 0) return FIBAR_E_INVALID_ARG;
     c->time_mask = kernel_mask;
     c->time_every = every;
     for (auto& q : c->time_seq) q = 0;
@@ -1028,8 +863,7 @@ int fibar_set_launch_mode(fibar_ctx* c, int mode)
 
 int fibar_kernel_time(fibar_ctx* c, int kernel, double* total_ms, uint64_t* launches)
 {
-    if (!c || kernel < 0 || kernel >= kKernelKinds || !total_ms || !launches)
-        return FIBAR_E_INVALID_ARG;
+    if (!c || kernel < 0 || kernel >= 5 || !total_ms || !launches) return FIBAR_E_INVALID_ARG;
     HIP_TRY(hipStreamSynchronize(c->st));
     double sum = 0.0;
     for (auto& pr : c->timed[kernel]) {

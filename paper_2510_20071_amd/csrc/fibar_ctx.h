@@ -23,11 +23,6 @@ struct fibar_ctx {
     fibar::SegRec* seg = nullptr;
     uint32_t* seg_count = nullptr;
     fibar::StepScratch* scratch = nullptr;
-    // in-order launches (spatial filter on): staging lists of the next pop
-    // step and tile tags of the next packet, two of each (by sequence parity)
-    uint32_t* stage[2] = {nullptr, nullptr};
-    uint64_t* ttag[2] = {nullptr, nullptr};
-    uint64_t push_seq = 0;              // sequence number of the last push
     uint16_t* stg_x = nullptr;          // device staging for host packets
     uint16_t* stg_y = nullptr;
     uint8_t* stg_p = nullptr;
@@ -43,14 +38,14 @@ struct fibar_ctx {
     // optional per-kernel timing: every time_every-th launch of a selected
     // kind carries a pair of events
     uint32_t time_mask = 0, time_every = 1;
-    uint64_t time_seq[fibar::kKernelKinds] = {};
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[fibar::kKernelKinds];
+    uint64_t time_seq[5] = {};
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> timed[5];
     std::vector<hipEvent_t> event_pool;
     // graph launches (blur on): a batch's kernels are recorded and replayed
     // as one HIP graph; graphs are cached by their sequence of kernels
     bool graph_mode = false;
     bool recording = false;             // the current batch is being recorded
-    uint64_t batch_seq[fibar::kKernelKinds] = {};   // timing counters of the recorded batch
+    uint64_t batch_seq[5] = {};         // timing counters of the recorded batch
     fibar::LaunchRecorder rec;
     std::vector<fibar::BatchGraph*> graphs;
     uint64_t graph_clock = 0;

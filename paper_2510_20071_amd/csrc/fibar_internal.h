@@ -69,40 +69,32 @@ struct DevScalars {
 };
 
 // Per-packet scratch of one batch (zeroed at the start of the batch).
-// Every 64-thread wave of a step's kernels stores its counts into a slot of
-// its own, numbered by the wave's first thread in the step's grid of that
-// kind: plain stores, no atomics, which had cost a few tenths of a
-// microsecond at the end of every launch.  A slot packs two 16-bit counts:
-// (activated pixels, activated tiles) for the waves that apply the step's
-// packet, (stale pixels, deactivated tiles) for the waves that pop the
-// step's window and for the waves of the next packet's apply that take over
-// the step's stale pixels in their tiles.  Waves past the slots, or with a
-// count above 16 bits, add to the overflow counters, spread over kSpread
-// cache lines.  A commit sums slots and overflow.
+// Every 64-thread wave of a step's kernels stores its (activation or
+// deactivation) counts into a slot of its own, numbered by the wave's first
+// thread in the step's grid of that kind: plain stores, no atomics, which
+// had cost a few tenths of a microsecond at the end of every launch.  Waves
+// past the slots (packets above one chunk) add to the overflow counters,
+// spread over kSpread cache lines.  A commit sums slots and overflow.
 constexpr int kSpread = 8;
 constexpr int kLineWords = 32;       // 128-byte cache line
 constexpr uint32_t kApplySlots = kChunk / 64;              // one chunk's apply waves
 constexpr uint32_t kPopSlots = (kChunk + kChunk / 8) / 64 + 32;   // its pops' waves
-enum CountKind { kCountApply = 0, kCountHead = 1, kCountPop = 2 };
 struct alignas(128) StepScratch {
     uint32_t status;                 // validation bits: 1 = range, 2 = polarity
     uint32_t pad[kLineWords - 1];
     uint32_t part[kSpread][kLineWords];   // overflow, [0..3]: activated pixels,
                                           // activated tiles, stale pixels,
                                           // deactivated tiles
-    uint32_t wave_apply[kApplySlots];     // activated pixels | activated tiles << 16
-    uint32_t wave_head[kApplySlots];      // stale pixels | deactivated tiles << 16
-    uint32_t wave_pop[kPopSlots];         // stale pixels | deactivated tiles << 16
+    uint2 wave_apply[kApplySlots];        // (activated pixels, activated tiles)
+    uint2 wave_pop[kPopSlots];            // (stale pixels, deactivated tiles)
 };
-static_assert(kApplySlots % 4 == 0 && kPopSlots % 4 == 0, "slots are read in fours");
+static_assert(kApplySlots % 2 == 0 && kPopSlots % 2 == 0, "slots are read in pairs");
 
 // Per-pixel state, in two arrays of structures so that what one kernel
 // needs of a pixel comes in one load: the window kernels read brightness and
 // last-event index together (the 3x3 blur reads both for every neighbour),
-// and only the filter update reads pbar and the event total.  The count of a
-// pixel's events in the window is a third array, changed only by atomic
-// additions (pushes) and subtractions (pops), so that pushes and pops may
-// run in the same launch.
+// and only the filter update reads pbar, the queued-event count and the
+// event total.
 struct alignas(16) PixL {
     float L;        // brightness of active / never-seen pixels
     float Lb;       // brightness of stale pixels (their one-time blur)
@@ -110,7 +102,7 @@ struct alignas(16) PixL {
 };
 struct alignas(16) PixP {
     float pbar;     // low-passed polarity
-    uint32_t pad;
+    uint32_t cnt;   // events of the pixel in the window
     uint64_t tot;   // events of the pixel so far
 };
 
@@ -125,7 +117,6 @@ struct StepRecord {
 struct State {
     PixL* px;
     PixP* pp;
-    uint32_t* cnt;    // events of each pixel in the window
     uint32_t* ring;
     uint64_t ring_mask;
     DevScalars* sc;   // two slots; see the commit scheme in fibar_kernels.hip
@@ -243,11 +234,6 @@ hipError_t launch_region_batch(const State& s, int slot, const ChunkDesc* d_chun
                                uint32_t n_readouts, int key_bits, Coef coef, hipStream_t st,
                                const LaunchTiming& tm = LaunchTiming());
 
-// Kernel kinds of the per-kernel timing (fibar_set_kernel_timing): group +
-// compose, apply only, pops only, pops + readout, separate readout, fused
-// pops + apply, fused pops + apply + readout.
-constexpr int kKernelKinds = 7;
-
 // ---- in-order path (fibar_kernels.hip) -----------------------------------
 // Workgroup sizes of the in-order kernels (on the 1280x720 stream with
 // 16384-event packets, 64- and 256-thread workgroups were both slower).
@@ -274,12 +260,17 @@ hipError_t launch_sort_compose(const ChunkDesc* d_chunks, uint32_t n_chunks, Seg
                                uint32_t H, int key_bits, Coef coef, hipStream_t st,
                                const LaunchTiming& tm = LaunchTiming());
 
-// Staging list of a pop step: the pixels of the first kStage events it may
-// pop (one full-chunk pop launch).
-constexpr uint32_t kStage = (kChunk + kChunk / 8 + kPopBlock - 1) / kPopBlock * kPopBlock;
+// In-order launches.  `slot_in` holds the last committed scalars; when
+// `prev` is not null the step it describes (with `prev_events` events) is
+// committed on top of them, and the result is written to `slot_out`.
+hipError_t launch_apply(const State& s, const ChunkDesc* d_chunk, const SegRec* seg,
+                        const uint32_t* seg_count, uint32_t chunk_events,
+                        uint32_t chunk_offset, StepScratch* step, const StepScratch* prev,
+                        uint32_t prev_events, int slot_in, int slot_out, int spatial,
+                        hipStream_t st, const LaunchTiming& tm = LaunchTiming());
 
-// Outputs of a readout taken in the launch that pops the step before it
-// (any may be null but L; no window count: the pops change it).
+// Outputs of a readout taken in the pop launch of the step before it (any
+// may be null but L; no window count: the pops change it).
 struct PopReadout {
     float* L;
     float* pbar;
@@ -290,74 +281,16 @@ struct PopReadout {
     uint64_t* tot;
 };
 
-// Launch arguments of k_step past the preloaded leading ones.
-struct StepAux {
-    StepScratch* sp_commit;         // step committed here
-    StepScratch* sp_app;            // packet applied here
-    uint32_t n_commit;              // events of the committed step
-    uint32_t chunk_offset;          // of the applied chunk in its packet
-    uint32_t copy_count;            // staging entries to prepare
-    uint32_t flags;
-    const uint32_t* seg_count;      // records of the applied chunk
-    DevScalars* sc_out;             // the commit's slot
-    uint32_t* stage_out;            // staging list of the next pop step
-    uint64_t* ttag_out;             // tile tags of the next packet
-    const SegRec* next_seg;         // the next packet's records (one chunk), or null
-    const uint32_t* next_count;
-    const StepScratch* sp_next;     // the next packet's status
-    uint64_t seq;                   // sequence number of the applied packet
-    PopReadout ro;
-};
-
-// One in-order launch (k_step).  Starting from the scalars in slot_in, it
-// may commit a step whose counts are complete (`commit`, n_commit events,
-// into slot_out), derive the window after the step `head` (n_head events),
-// pop that step (`pops`, pixels staged in stage_in, or read from the ring
-// when it is null), apply one chunk of the
-// next packet (`app`, with its records), and write a readout of the state
-// after the popped step.  `fused` (pops and apply together) hands the tiles
-// of the applied packet (tagged `seq` in ttag_in) to the apply.  Every pop
-// launch prepares the staging list of the next pop step (copy_count entries
-// into stage_out), every apply stages its own events there, and an apply
-// tags the tiles of the next packet (next_seg) with seq + 1 in ttag_out.
-struct StepLaunch {
-    bool spatial = true;
-    int slot_in = 0, slot_out = -1;
-    StepScratch* commit = nullptr;
-    uint32_t n_commit = 0;
-    StepScratch* head = nullptr;
-    uint32_t n_head = 0;
-    bool pops = false;
-    const uint32_t* stage_in = nullptr;
-    StepScratch* app = nullptr;
-    const SegRec* seg = nullptr;
-    const uint32_t* seg_count = nullptr;
-    const uint16_t* ex = nullptr;
-    const uint16_t* ey = nullptr;
-    uint32_t n_app = 0, chunk_offset = 0;
-    bool fused = false;
-    uint64_t seq = 0;
-    const uint64_t* ttag_in = nullptr;
-    uint32_t* stage_out = nullptr;
-    uint32_t copy_count = 0;
-    uint64_t* ttag_out = nullptr;
-    const SegRec* next_seg = nullptr;
-    const uint32_t* next_count = nullptr;
-    const StepScratch* next = nullptr;
-    const PopReadout* ro = nullptr;
-};
-
-hipError_t launch_step(const State& s, const StepLaunch& L, hipStream_t st,
-                       const LaunchTiming& tm = LaunchTiming());
+// With `ro` the launch also writes the readout of the state after the step.
+hipError_t launch_pop_blur(const State& s, uint32_t pkt_events, StepScratch* step, int slot,
+                           const PopReadout* ro, hipStream_t st,
+                           const LaunchTiming& tm = LaunchTiming());
 
 // Initial per-pixel state: zero brightness and polarity, no events.
 hipError_t launch_init_state(const State& s, hipStream_t st);
 
 hipError_t launch_commit(const State& s, const StepScratch* prev, uint32_t prev_events,
                          int slot_in, int slot_out, int spatial, hipStream_t st);
-
-// Fill n 64-bit words with v.
-hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t st);
 
 hipError_t launch_readout(const State& s, int spatial, const StepScratch* prev,
                           uint32_t prev_events, int slot, float* L, float* pbar,

@@ -6,8 +6,8 @@
 // compositions to the state, moving the active-event window, detecting and
 // blurring stale pixels).  The first part runs for many packets in one bulk
 // launch (k_sort_compose, one 1024-thread workgroup per <=16384-event chunk);
-// the second runs packet by packet (k_step: the pops of one packet together
-// with the pushes of the next, and a readout between them if there is one).
+// the second runs packet by packet (k_apply, then k_pop_blur, whose extra
+// workgroups also write a readout that directly follows the packet).
 //
 // Blurred values of stale pixels live in a second image Lb (stored next to
 // L and the last-event index, px[i] = (L, Lb, last)): a pixel's current
@@ -90,197 +90,134 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_compose(
 }
 
 // ---------------------------------------------------------------------------
-// In-order kernel (one stream): one launch per packet.
-//
-// A launch may commit the scalars of a step, pop the window of the step
-// after it, and apply one chunk of the packet after that, all at once: the
-// pops of step b and the pushes of packet b + 1 need the same committed
-// scalars, and neither reads a value the other writes, except through two
-// hand-offs.  (1) The tiles of packet b + 1 (tagged with its sequence number
-// by the launch before) are left by the pops to the packet's apply, which
-// sees their records before rewriting them.  (2) A record rewritten by the
-// apply keeps, in Lb, the value the blurs of step b read (preblur_value).
-// The pops read their pixels from a staging list that the launch before
-// wrote at a fixed place, so that their neighbourhoods load in the second
-// memory round trip.  Workgroups: pops, then apply, then readout.
+// In-order kernels (one stream)
 // ---------------------------------------------------------------------------
-constexpr uint32_t kPendingBit = 1u << 31;   // n_pop: a step is committed here
-constexpr uint32_t kHeadBit = 1u << 30;      // n_pop: the head step is given
-constexpr uint32_t kPopsBit = 1u << 29;      // n_pop: the head step is popped here
-constexpr uint32_t kCountMask = kPopsBit - 1u;
-constexpr uint32_t kFusedFlag = 1u;
-constexpr uint32_t kReadoutFlag = 2u;
-constexpr uint32_t kSpatialFlag = 4u;
 
-__device__ StepScratch no_step;              // read in place of an absent step
+// Apply one chunk's compositions to the state; push the chunk's events to
+// the back of the window (spatial filter); count activations.  Workgroup 0
+// only commits the previous step's scalars (sc_in -> sc_out).
+//
+// The values the first loads need lead the argument list, so that they
+// arrive in preloaded scalar registers; nothing before the record loads
+// waits for another argument (the workgroup size is a constant and the
+// commit workgroup is found without the grid size).  n_prev holds the
+// chunk's event count and, in bit 31, whether a step is pending; a pending
+// step's scratch is the one before this step's.
+constexpr uint32_t kPendingBit = 1u << 31;
 
-__global__ __launch_bounds__(kPopBlock) void k_step(const SegRec* __restrict__ seg,
-                                                    const uint32_t* __restrict__ stage_in,
-                                                    const DevScalars* sc_in, StepScratch* sp_head,
-                                                    const uint64_t* __restrict__ ttag_in,
-                                                    const uint16_t* ex, const uint16_t* ey,
-                                                    uint32_t n_pop, uint32_t n_app, State s,
-                                                    StepAux a)
+__global__ __launch_bounds__(kApplyBlock) void k_apply(
+    const SegRec* __restrict__ seg, const uint32_t* __restrict__ seg_count, StepScratch* step,
+    const DevScalars* sc_in, const uint16_t* ex, const uint16_t* ey, uint32_t n_prev, State s,
+    uint32_t chunk_offset, uint32_t prev_events, DevScalars* sc_out, int spatial)
 {
-    const uint32_t n_head = n_pop & kCountMask;
-    const bool pending = (n_pop & kPendingBit) != 0u, has_head = (n_pop & kHeadBit) != 0u;
-    const bool pops = (n_pop & kPopsBit) != 0u;
-    const bool fused = (a.flags & kFusedFlag) != 0u;
-    const int spatial = (a.flags & kSpatialFlag) != 0u ? 1 : 0;
-    // workgroup roles, from preloaded arguments only
-    const uint32_t pop_blocks = pops ? pop_threads(n_head) / kPopBlock : 0u;
-    const uint32_t app_blocks = (n_app + kPopBlock - 1) / kPopBlock;
-    const uint32_t blk = blockIdx.x, tid = threadIdx.x;
-    const int role = blk < pop_blocks ? 0 : blk < pop_blocks + app_blocks ? 1 : 2;
-    const StepScratch* hd = has_head ? sp_head : &no_step;
-    const StepScratch* cm = pending ? a.sp_commit : &no_step;
-
-    // first round trip: the role's own loads, then the scalars and the
-    // commit's counts
-    uint32_t sp_pix = 0u;
-    Group g;
-    uint32_t nseg = 0u, st_app = 0u, next_key = 0u, next_n = 0u, st_next = 1u;
-    PixL rv;
-    uint64_t rtag = 0u;
-    const uint32_t gi = (role == 0 ? blk : role == 1 ? blk - pop_blocks
-                                                     : blk - pop_blocks - app_blocks) *
-                            kPopBlock + tid;
-    const uint64_t npx = (uint64_t)s.W * s.H;
-    if (role == 0) {
-        if (stage_in) sp_pix = stage_in[gi < kStage ? gi : 0u];
-    } else if (role == 1) {
-        ChunkDesc cd;
-        cd.x = ex;
-        cd.y = ey;
-        cd.n = n_app;
-        g = load_group(cd, seg, gi);
-        nseg = *a.seg_count;
-        st_app = a.sp_app->status;
-        if (a.next_seg) {
-            next_key = a.next_seg[gi < kChunk ? gi : 0u].key;
-            next_n = *a.next_count;
-            st_next = a.sp_next->status;
+    const StepScratch* prev = (n_prev & kPendingBit) ? step - 1 : nullptr;
+    const uint32_t n = n_prev & ~kPendingBit;
+    if (blockIdx.x == 0) {
+        if (prev && sc_out && threadIdx.x < 64) {
+            const DevScalars r = commit_by_wave(sc_in, prev, prev_events, s, spatial);
+            if (threadIdx.x == 0) store_commit(s, sc_out, r, prev_events);
         }
-    } else {
-        const uint64_t i = gi < npx ? gi : 0u;
-        rv = load_rec(&s.px[i]);
-        if (fused) {
-            const uint32_t y = (uint32_t)(i / s.W), x = (uint32_t)(i - (uint64_t)y * s.W);
-            rtag = ttag_in[(y >> 1) * s.TW + (x >> 1)];
-        }
+        return;
     }
-    const DevScalars cin = *sc_in;
-    const uint32_t st_head = hd->status, st_commit = cm->status;
+    // every load that needs only the arguments is issued before any is used
+    const uint32_t i = (blockIdx.x - 1) * kApplyBlock + threadIdx.x;
+    ChunkDesc cd;
+    cd.x = ex;
+    cd.y = ey;
+    cd.n = n;
+    const Group g = load_group(cd, seg, i);
+    uint32_t status = step->status;
+    uint32_t nseg = *seg_count;
+    HeadIn hin = load_head(sc_in, prev);
     FIBAR_ISSUE_FENCE();
-    const StepCounts cn = pending && spatial ? gather_counts(cm) : StepCounts{0u, 0u, 0u, 0u};
-    const DevScalars c = pending ? commit_step(cin, st_commit, a.n_commit, s, spatial, cn) : cin;
-    if (blk == 0 && tid == 0 && pending) store_commit(s, a.sc_out, c, a.n_commit);
-    // the window around the head step
-    StepWin w;
-    w.h_old = c.h;
-    int64_t k_end = c.k;
-    uint64_t h_new = c.h;
-    if (has_head) step_head(c, st_head, n_head, spatial, &k_end, &h_new);
-    w.h_new = h_new;
-    w.k_prev = k_end;
-    w.fused = fused;
-    w.spatial = spatial != 0;
-    w.kpost = fused ? k_end + 1 : kNoPost;
-    w.first = (uint64_t)(k_end + 1) + a.chunk_offset;
-    const uint64_t seq = fused ? a.seq : ~0ull;
+    const TileIn ti = load_tile(s, g, i);
+    scalars_after_loads(hin, status, nseg);
+    int64_t k0;
+    uint64_t h0;
+    head_after(hin, prev_events, spatial, &k0, &h0);
+    const uint64_t first = (uint64_t)(k0 + 1) + chunk_offset;
+    uint32_t dP = 0u, dT = 0u;
+    apply_tile(s, g, ti, cd.n, nseg, status != 0, i, first, h0, spatial, dP, dT);
+    if (spatial) add_counts(step, false, chunk_offset + i, dP, dT);
+}
 
-    if (role == 0) {
-        // pop j = h_old + gi (and, past the first pass, every pop_threads-th
-        // after it, with pixels from the ring)
-        const uint32_t G = pop_blocks * kPopBlock;
-        const uint64_t j = w.h_old + gi;
-        // without a staging list (the first pops of a batch) the pixel comes
-        // from the window ring
-        if (!stage_in) sp_pix = s.ring[j & s.ring_mask];
-        const uint32_t pix = sp_pix < npx ? sp_pix : 0u;
-        PixL nb[3][3];
-        load_pop(s, pix, nb);
-        uint64_t tag = 0u;
-        if (fused) tag = ttag_in[tile_of(s, pix)];
-        // the next pop step's staging list: window events that are pushed
-        // already (the apply below stages the packet it pushes)
-        for (uint32_t k = gi; k < a.copy_count; k += G) {
-            const uint64_t jj = h_new + k;
-            if ((int64_t)jj <= k_end) a.stage_out[k] = s.ring[jj & s.ring_mask];
+// Move the window head by the target of the previous step (Eq. (20)),
+// detect pixels whose last queued event leaves the window, and write their
+// blurred values to Lb.  `sc` holds the scalars after the previous step.
+// Leading arguments as in k_apply.  The pops take pop_threads(pkt_events)
+// threads, the first workgroups; workgroups past them write the readout
+// that directly follows the step, if there is one (`ro`), kRoPix pixels per
+// thread.
+constexpr int kRoPix = 1;   // 2 and 4 (fewer workgroups) were slower
+
+__global__ __launch_bounds__(kPopBlock) void k_pop_blur(const DevScalars* sc, StepScratch* step,
+                                                        const uint32_t* ring, uint64_t ring_mask,
+                                                        PixL* px, uint32_t W, uint32_t H,
+                                                        uint32_t pkt_events, State s, PopReadout ro)
+{
+    s.ring = const_cast<uint32_t*>(ring);
+    s.ring_mask = ring_mask;
+    s.px = px;
+    s.W = W;
+    s.H = H;
+    // from preloaded arguments only: a readout workgroup knows it is one
+    // without waiting for any load
+    const uint32_t threads = pop_threads(pkt_events);
+    const uint32_t pop_blocks = threads / kPopBlock;
+    if (blockIdx.x >= pop_blocks) {
+        // the readout of the state after the step; what it reads is not
+        // written by the pops (see readout_pixel_after_pops).  The first
+        // pass's pixels are loaded before the window scalars.
+        const uint64_t npx = (uint64_t)W * H;
+        const uint32_t rb = blockIdx.x - pop_blocks, nrb = gridDim.x - pop_blocks;
+        const uint64_t span = (uint64_t)nrb * kPopBlock * kRoPix;
+        const uint64_t first = (uint64_t)rb * kPopBlock * kRoPix + threadIdx.x;
+        PixL v[kRoPix];
+#pragma unroll
+        for (int q = 0; q < kRoPix; ++q) {
+            const uint64_t i = first + (uint64_t)q * kPopBlock;
+            v[q] = px[i < npx ? i : 0];
         }
-        uint32_t dP = 0u, dT = 0u;
-        if (j < h_new) {
-            if (gi < kStage || !stage_in) {
-                step_pop(s, j, pix, nb, tag, seq, w.h_old, w.kpost, dP, dT);
-            } else {
-                const uint32_t p2 = s.ring[j & s.ring_mask];
-                PixL nb2[3][3];
-                load_pop(s, p2, nb2);
-                const uint64_t tag2 = fused ? ttag_in[tile_of(s, p2)] : 0u;
-                step_pop(s, j, p2, nb2, tag2, seq, w.h_old, w.kpost, dP, dT);
+        FIBAR_ISSUE_FENCE();
+        const uint32_t status = step->status;
+        const DevScalars c = *sc;
+        uint64_t h_old, h_new;
+        pop_bounds(c, pkt_events, &h_old, &h_new);
+        if (status) h_new = h_old;   // a rejected packet pops nothing
+        const int64_t k = status ? c.k : c.k + (int64_t)pkt_events;
+        for (uint64_t base = first; base < npx; base += span) {
+            if (base != first) {
+#pragma unroll
+                for (int q = 0; q < kRoPix; ++q) {
+                    const uint64_t i = base + (uint64_t)q * kPopBlock;
+                    v[q] = px[i < npx ? i : 0];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kRoPix; ++q) {
+                const uint64_t i = base + (uint64_t)q * kPopBlock;
+                if (i < npx)
+                    readout_pixel_after_pops(s, k, h_old, h_new, i, v[q], ro.L, ro.pbar,
+                                             ro.stale, ro.last, ro.log_age, ro.tot);
             }
         }
-        add_counts(sp_head, kCountPop, gi, dP, dT);
-        // pops past the first pass; their counts are summed over the whole
-        // wave afterwards (a wave sum needs every lane)
-        uint32_t eP = 0u, eT = 0u;
-        for (uint64_t jj = j + G; jj < h_new; jj += G) {
-            const uint32_t p2 = s.ring[jj & s.ring_mask];
-            PixL nb2[3][3];
-            load_pop(s, p2, nb2);
-            const uint64_t tag2 = fused ? ttag_in[tile_of(s, p2)] : 0u;
-            step_pop(s, jj, p2, nb2, tag2, seq, w.h_old, w.kpost, eP, eT);
+        if (ro.tcnt) {
+            const uint64_t nt = (uint64_t)s.TW * ((H + 1) / 2);
+            const uint64_t tstride = (uint64_t)nrb * kPopBlock;
+            for (uint64_t t = (uint64_t)rb * kPopBlock + threadIdx.x; t < nt; t += tstride)
+                ro.tcnt[t] = tile_active_pixels(s, t, h_new);
         }
-        add_overflow_counts(sp_head, kCountPop, gi, eP, eT);
         return;
     }
-    if (role == 1) {
-        const TileIn ti = load_tile(s, g, gi);
-        const bool rejected = st_app != 0u;
-        uint32_t act = 0u, tact = 0u, hst = 0u, hoff = 0u;
-        const PopReadout ro = a.ro;
-        const bool want_ro = (a.flags & kReadoutFlag) && fused;
-        apply_tile_step(s, g, ti, n_app, nseg, rejected, gi, w, act, tact, hst, hoff, ro,
-                        want_ro);
-        // stage the pushed event for the next pop step, tag the next packet's
-        // tiles for the launch that pops this one
-        if (!rejected && gi < n_app) {
-            const uint64_t rel = w.first + gi - h_new;
-            if (rel < a.copy_count) a.stage_out[rel] = g.ey * s.W + g.ex;
-        }
-        if (a.next_seg && st_next == 0u) {
-            const uint32_t G = app_blocks * kPopBlock;
-            for (uint32_t k = gi; k < next_n; k += G) {
-                const uint32_t key = k == gi ? next_key : a.next_seg[k].key;
-                a.ttag_out[key >> 2] = a.seq + 1u;
-            }
-        }
-        add_counts(a.sp_app, kCountApply, a.chunk_offset + gi, act, tact);
-        if (fused) add_counts(sp_head, kCountHead, gi, hst, hoff);
-        return;
-    }
-    // readout of the state after the head step's pops (workgroups past the
-    // pops and the apply, one pixel per thread)
-    const PopReadout ro = a.ro;
-    const uint32_t nrb = gridDim.x - pop_blocks - app_blocks;
-    const uint64_t span = (uint64_t)nrb * kPopBlock;
-    for (uint64_t i = gi; i < npx; i += span) {
-        if (i != gi) {
-            rv = load_rec(&s.px[i]);
-            if (fused) {
-                const uint32_t y = (uint32_t)(i / s.W), x = (uint32_t)(i - (uint64_t)y * s.W);
-                rtag = ttag_in[(y >> 1) * s.TW + (x >> 1)];
-            }
-        }
-        if (fused && rtag == seq) continue;   // written by the tile's head
-        readout_pixel_after_pops(s, k_end, w.h_old, h_new, i, rv, ro.L, ro.pbar, ro.stale,
-                                 ro.last, ro.log_age, ro.tot, w.kpost);
-    }
-    if (ro.tcnt) {
-        const uint64_t nt = (uint64_t)s.TW * ((s.H + 1) / 2);
-        for (uint64_t t = gi; t < nt; t += span)
-            if (!fused || ttag_in[t] != seq) ro.tcnt[t] = tile_active_pixels(s, t, h_new);
-    }
+    // the status and the scalars are loaded together (a select, not a branch)
+    const uint32_t status = step->status;
+    const DevScalars c = *sc;
+    uint64_t h_old, h_new;
+    pop_bounds(c, pkt_events, &h_old, &h_new);
+    if (status) h_new = h_old;   // a rejected packet pops nothing
+    uint32_t dP = 0u, dT = 0u;
+    pop_range(s, h_old + blockIdx.x * kPopBlock + threadIdx.x, h_new, threads, h_old, dP, dT);
+    add_counts(step, true, blockIdx.x * kPopBlock + threadIdx.x, dP, dT);
 }
 
 // Initial per-pixel state.
@@ -296,17 +233,10 @@ __global__ __launch_bounds__(256) void k_init_state(State s)
         s.px[i] = v;
         PixP p;
         p.pbar = 0.f;
-        p.pad = 0u;
+        p.cnt = 0u;
         p.tot = 0u;
         s.pp[i] = p;
-        s.cnt[i] = 0u;
     }
-}
-
-__global__ __launch_bounds__(256) void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v)
-{
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
 // Commit a pending step into the other slot (one wave).
@@ -353,51 +283,41 @@ hipError_t launch_sort_compose(const ChunkDesc* d_chunks, uint32_t n_chunks, Seg
                         d_chunks, seg, seg_count, scratch, W, H, key_bits, coef);
 }
 
-hipError_t launch_step(const State& s, const StepLaunch& L, hipStream_t st,
-                       const LaunchTiming& tm)
+hipError_t launch_apply(const State& s, const ChunkDesc* d_chunk, const SegRec* seg,
+                        const uint32_t* seg_count, uint32_t chunk_events, uint32_t chunk_offset,
+                        StepScratch* step, const StepScratch* prev, uint32_t prev_events,
+                        int slot_in, int slot_out, int spatial, hipStream_t st,
+                        const LaunchTiming& tm)
 {
-    const bool pops = L.pops && L.head && L.spatial;
-    if (L.n_app > (uint32_t)kChunk || (L.n_app && (!L.app || !L.seg || !L.seg_count))) return hipErrorInvalidValue;
-    if (L.fused && !(pops && L.n_app && L.ttag_in)) return hipErrorInvalidValue;
-    if (L.commit && (L.slot_out < 0 || L.slot_out > 1)) return hipErrorInvalidValue;
-    if (L.n_head > kCountMask || L.n_commit > kCountMask) return hipErrorInvalidValue;
-    if (L.ro && (!L.ro->L || !pops)) return hipErrorInvalidValue;
-    if (L.copy_count > kStage || (L.copy_count && !L.stage_out)) return hipErrorInvalidValue;
-    if (L.next_seg && !(L.next_count && L.next && L.ttag_out)) return hipErrorInvalidValue;
-    const uint32_t pop_blocks = pops ? pop_threads(L.n_head) / kPopBlock : 0u;
-    const uint32_t app_blocks = (L.n_app + kPopBlock - 1) / kPopBlock;
+    // one extra workgroup (the first) commits the previous step's scalars
+    if (prev && prev != step - 1) return hipErrorInvalidValue;   // scratch layout
+    if (chunk_events == 0 || chunk_events > (uint32_t)kChunk) return hipErrorInvalidValue;
+    const uint32_t blocks = (chunk_events + kApplyBlock - 1) / kApplyBlock + 1;
+    DevScalars* sc_out = slot_out >= 0 ? s.sc + slot_out : nullptr;
+    return launch_timed(k_apply, dim3(blocks), dim3(kApplyBlock), st, tm.start, tm.stop, seg,
+                        seg_count, step, (const DevScalars*)(s.sc + slot_in), d_chunk->x,
+                        d_chunk->y, chunk_events | (prev ? kPendingBit : 0u), s, chunk_offset,
+                        prev_events, sc_out, spatial);
+}
+
+hipError_t launch_pop_blur(const State& s, uint32_t pkt_events, StepScratch* step, int slot,
+                           const PopReadout* ro, hipStream_t st, const LaunchTiming& tm)
+{
+    const uint32_t threads = pop_threads(pkt_events);
+    if (threads == 0 || (ro && !ro->L)) return hipErrorInvalidValue;
+    const uint32_t pop_blocks = threads / kPopBlock;   // the kernel derives the same
     uint32_t ro_blocks = 0;
-    StepAux a{};
-    if (L.ro) {
-        const uint64_t b = ((uint64_t)s.W * s.H + kPopBlock - 1) / kPopBlock;
+    PopReadout r{};
+    if (ro) {
+        // kRoPix pixels per thread; the pop workgroups come first
+        const uint64_t per = (uint64_t)kPopBlock * kRoPix;
+        const uint64_t b = ((uint64_t)s.W * s.H + per - 1) / per;
         ro_blocks = (uint32_t)(b < kReadoutMaxBlocks ? (b > 0 ? b : 1) : kReadoutMaxBlocks);
-        a.ro = *L.ro;
-        a.flags |= kReadoutFlag;
+        r = *ro;
     }
-    const uint32_t blocks = pop_blocks + app_blocks + ro_blocks;
-    if (blocks == 0) return hipSuccess;
-    uint32_t n_pop = L.n_head;
-    if (L.commit) n_pop |= kPendingBit;
-    if (L.head) n_pop |= kHeadBit;
-    if (pops) n_pop |= kPopsBit;
-    if (L.fused) a.flags |= kFusedFlag;
-    if (L.spatial) a.flags |= kSpatialFlag;
-    a.sp_commit = L.commit;
-    a.sp_app = L.app;
-    a.n_commit = L.n_commit;
-    a.chunk_offset = L.chunk_offset;
-    a.copy_count = L.copy_count;
-    a.seg_count = L.seg_count;
-    a.sc_out = L.commit ? s.sc + L.slot_out : nullptr;
-    a.stage_out = L.stage_out;
-    a.ttag_out = L.ttag_out;
-    a.next_seg = L.next_seg;
-    a.next_count = L.next_count;
-    a.sp_next = L.next;
-    a.seq = L.seq;
-    return launch_timed(k_step, dim3(blocks), dim3(kPopBlock), st, tm.start, tm.stop, L.seg,
-                        L.stage_in, (const DevScalars*)(s.sc + L.slot_in), L.head,
-                        L.ttag_in, L.ex, L.ey, n_pop, L.n_app, s, a);
+    return launch_timed(k_pop_blur, dim3(pop_blocks + ro_blocks), dim3(kPopBlock), st, tm.start,
+                        tm.stop, (const DevScalars*)(s.sc + slot), step, (const uint32_t*)s.ring,
+                        s.ring_mask, s.px, s.W, s.H, pkt_events, s, r);
 }
 
 hipError_t launch_init_state(const State& s, hipStream_t st)
@@ -407,15 +327,6 @@ hipError_t launch_init_state(const State& s, hipStream_t st)
     if (blocks > 4096) blocks = 4096;
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_init_state, dim3((uint32_t)blocks), dim3(256), 0, st, s);
-    return hipGetLastError();
-}
-
-hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t st)
-{
-    if (n == 0) return hipSuccess;
-    uint64_t blocks = (n + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_fill_u64, dim3((uint32_t)blocks), dim3(256), 0, st, p, (uint64_t)n, v);
     return hipGetLastError();
 }
 

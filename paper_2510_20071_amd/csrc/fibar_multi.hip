@@ -153,7 +153,6 @@ __device__ __forceinline__ uint64_t bcast64(uint64_t v, uint32_t k)
 struct LaneState {
     PixL* px;
     PixP* pp;
-    uint32_t* cnt;
     uint32_t* ring;
     uint64_t ring_mask;
     DevScalars* sc;
@@ -170,7 +169,6 @@ __device__ __forceinline__ LaneState lane_state(const StreamStep* rr, uint32_t S
     LaneState l;
     l.px = e->s.px;
     l.pp = e->s.pp;
-    l.cnt = e->s.cnt;
     l.ring = e->s.ring;
     l.ring_mask = e->s.ring_mask;
     l.sc = e->s.sc;
@@ -191,7 +189,6 @@ __device__ __forceinline__ State owner_state(const LaneState& l, uint32_t k)
     State s;
     s.px = bcast_ptr(l.px, k);
     s.pp = bcast_ptr(l.pp, k);
-    s.cnt = bcast_ptr(l.cnt, k);
     s.ring = bcast_ptr(l.ring, k);
     s.ring_mask = bcast64(l.ring_mask, k);
     s.sc = bcast_ptr(l.sc, k);
@@ -271,7 +268,7 @@ __global__ __launch_bounds__(256) void k_multi_apply(const StreamStep* rr, uint3
         const uint64_t first = (uint64_t)(k0 + 1) + (uint64_t)sub * kChunk;
         uint32_t dP = 0u, dT = 0u;
         apply_tile(s, g, ti, cd.n, nseg, status != 0, i, first, h0, 1, dP, dT);
-        add_counts(stp, kCountApply, (uint32_t)sub * kChunk + i, dP, dT);
+        add_counts(stp, false, (uint32_t)sub * kChunk + i, dP, dT);
     }
 }
 
@@ -300,7 +297,7 @@ __global__ __launch_bounds__(256) void k_multi_pop(const StreamStep* rr, uint32_
         uint32_t dP = 0u, dT = 0u;
         pop_range(s, h_old + (uint64_t)(t - start) * blockDim.x + threadIdx.x, h_new,
                   (uint64_t)pop_blocks * blockDim.x, h_old, dP, dT);
-        add_counts(stp, kCountPop, (t - start) * blockDim.x + threadIdx.x, dP, dT);
+        add_counts(stp, true, (t - start) * blockDim.x + threadIdx.x, dP, dT);
     }
 }
 

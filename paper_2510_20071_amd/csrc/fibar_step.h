@@ -16,30 +16,6 @@ namespace {
 
 using namespace tile;
 
-// A pixel's (L, Lb, last) record is read and written as one 16-byte access:
-// a launch that applies a packet rewrites records that other workgroups of
-// the same launch read, and a read split into two loads could pair one
-// half of the old record with the other half of the new one.
-__device__ __forceinline__ PixL load_rec(const PixL* p)
-{
-    const uint4 v = *reinterpret_cast<const uint4*>(p);
-    PixL r;
-    r.L = __uint_as_float(v.x);
-    r.Lb = __uint_as_float(v.y);
-    r.last = (int64_t)(((uint64_t)v.w << 32) | v.z);
-    return r;
-}
-
-__device__ __forceinline__ void store_rec(PixL* p, const PixL& r)
-{
-    uint4 v;
-    v.x = __float_as_uint(r.L);
-    v.y = __float_as_uint(r.Lb);
-    v.z = (uint32_t)(uint64_t)r.last;
-    v.w = (uint32_t)((uint64_t)r.last >> 32);
-    *reinterpret_cast<uint4*>(p) = v;
-}
-
 __device__ __forceinline__ uint32_t tile_of(const State& s, uint32_t pix)
 {
     const uint32_t y = pix / s.W, x = pix - y * s.W;
@@ -57,15 +33,18 @@ __device__ __forceinline__ uint32_t tile_of(const State& s, uint32_t pix)
 // of two slots.  So no kernel reads a slot that a kernel running at the same
 // time writes.
 // ---------------------------------------------------------------------------
-// min(floor(num / den), cap) with num = q * fill_num * 4 * T, exact.  A
-// double quotient is within a relative 2^-51 of the true one; exact 128-bit
-// products then fix the last unit (no 128-bit division, which is slow here).
+// min(floor(num / den), cap) with num = q * fill_num * 4 * T, exact.  The
+// factors q and f = fill_num * 4 * T (< 2^48) and den (< 2^48) are exact in
+// double, so the double quotient is within a relative 2^-51 of the true one;
+// exact 128-bit products then fix the last unit (no 128-bit division or
+// conversion, which are slow here).
 __device__ uint64_t target_div(uint64_t q, uint64_t fill_num, uint64_t T, uint64_t den,
                                uint64_t cap)
 {
-    const unsigned __int128 num = (unsigned __int128)q * fill_num * 4u * T;
-    const double est = (double)num / (double)den;
+    const uint64_t f = fill_num * 4u * T;
+    const double est = ((double)q * (double)f) / (double)den;
     if (est > (double)cap + 4096.0) return cap;
+    const unsigned __int128 num = (unsigned __int128)q * f;
     uint64_t v = (uint64_t)est;
     while (v > 0 && (unsigned __int128)v * den > num) --v;
     while ((unsigned __int128)(v + 1) * den <= num) ++v;
@@ -95,43 +74,49 @@ struct StepCounts {
 // Sum of a step's count slots and overflow counters by one full wave (the
 // same in every lane).  Every load is issued before any is used: a fixed
 // number per lane from clamped addresses, the surplus zeroed afterwards (a
-// loop would wait for each load in turn).  The slots are one array of
-// 16-byte words: the first kApplySlots / 4 hold activation counts, the rest
-// stale counts.
+// loop would wait for each load in turn).
 __device__ StepCounts gather_counts(const StepScratch* st)
 {
-    constexpr uint32_t kA = kApplySlots / 4;                          // activation words
-    constexpr uint32_t kW = (2 * kApplySlots + kPopSlots) / 4;        // all words
-    constexpr int kJ = (int)((kW + 63) / 64);
-    const uint4* w = reinterpret_cast<const uint4*>(st->wave_apply);
+    constexpr uint32_t kA = kApplySlots / 2, kP = kPopSlots / 2;   // slot pairs
+    constexpr int kJa = (int)((kA + 63) / 64), kJp = (int)((kP + 63) / 64);
+    const uint4* wa = reinterpret_cast<const uint4*>(st->wave_apply);
+    const uint4* wp = reinterpret_cast<const uint4*>(st->wave_pop);
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t ov = lane < (uint32_t)kSpread ? lane : 0u;
-    uint4 q[kJ];
+    uint4 qa[kJa], qp[kJp];
 #pragma unroll
-    for (int j = 0; j < kJ; ++j) {
+    for (int j = 0; j < kJa; ++j) {
         const uint32_t i = lane + 64u * j;
-        q[j] = w[i < kW ? i : 0u];
+        qa[j] = wa[i < kA ? i : 0u];
+    }
+#pragma unroll
+    for (int j = 0; j < kJp; ++j) {
+        const uint32_t i = lane + 64u * j;
+        qp[j] = wp[i < kP ? i : 0u];
     }
     uint4 qo = *reinterpret_cast<const uint4*>(st->part[ov]);
     FIBAR_ISSUE_FENCE();
     // no sum is hoisted between the loads (it would wait for the first ones
     // before the last are issued)
 #pragma unroll
-    for (int j = 0; j < kJ; ++j)
-        asm volatile("" : "+v"(q[j].x), "+v"(q[j].y), "+v"(q[j].z), "+v"(q[j].w));
+    for (int j = 0; j < kJa; ++j)
+        asm volatile("" : "+v"(qa[j].x), "+v"(qa[j].y), "+v"(qa[j].z), "+v"(qa[j].w));
+#pragma unroll
+    for (int j = 0; j < kJp; ++j)
+        asm volatile("" : "+v"(qp[j].x), "+v"(qp[j].y), "+v"(qp[j].z), "+v"(qp[j].w));
     asm volatile("" : "+v"(qo.x), "+v"(qo.y), "+v"(qo.z), "+v"(qo.w));
     uint32_t v[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-    for (int j = 0; j < kJ; ++j) {
-        const uint32_t i = lane + 64u * j;
-        const uint32_t lo = (q[j].x & 0xffffu) + (q[j].y & 0xffffu) + (q[j].z & 0xffffu) +
-                            (q[j].w & 0xffffu);
-        const uint32_t hi = (q[j].x >> 16) + (q[j].y >> 16) + (q[j].z >> 16) + (q[j].w >> 16);
-        const bool ok = i < kW, act = i < kA;
-        v[0] += ok && act ? lo : 0u;
-        v[1] += ok && act ? hi : 0u;
-        v[2] += ok && !act ? lo : 0u;
-        v[3] += ok && !act ? hi : 0u;
+    for (int j = 0; j < kJa; ++j) {
+        const bool ok = lane + 64u * j < kA;
+        v[0] += ok ? qa[j].x + qa[j].z : 0u;
+        v[1] += ok ? qa[j].y + qa[j].w : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kJp; ++j) {
+        const bool ok = lane + 64u * j < kP;
+        v[2] += ok ? qp[j].x + qp[j].z : 0u;
+        v[3] += ok ? qp[j].y + qp[j].w : 0u;
     }
     const bool ook = lane < (uint32_t)kSpread;
     v[0] += ook ? qo.x : 0u;
@@ -316,10 +301,11 @@ struct TileIn {
     bool head;               // first record of its tile
     bool same[4];            // records i .. i + 3 belong to the tile
     uint32_t pix[4];
-    PixL quad[4];            // the tile's four pixels, (x & 1) + 2 (y & 1)
+    int64_t qlast[4];        // last-event index of the tile's four quads
     float L[4], Lb[4];       // the records' pixels
     int64_t last[4];
     float pbar[4];
+    uint32_t cnt[4];
     uint64_t tot[4];
 };
 
@@ -343,16 +329,17 @@ __device__ __forceinline__ TileIn load_tile(const State& s, const Group& g, uint
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const uint32_t p = base + (q & 1) + (q >> 1) * s.W;
-        ti.quad[q] = load_rec(&s.px[p < npx ? p : 0u]);
+        ti.qlast[q] = s.px[p < npx ? p : 0u].last;
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const PixL v = load_rec(&s.px[ti.pix[k]]);
+        const PixL v = s.px[ti.pix[k]];
         ti.L[k] = v.L;
         ti.Lb[k] = v.Lb;
         ti.last[k] = v.last;
         const PixP w = s.pp[ti.pix[k]];
         ti.pbar[k] = w.pbar;
+        ti.cnt[k] = w.cnt;
         ti.tot[k] = w.tot;
     }
     return ti;
@@ -375,7 +362,7 @@ __device__ __forceinline__ void apply_tile(const State& s, const Group& g, const
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const bool ok = (!(q & 1) || has_x1) && (!(q & 2) || has_y1);
-        tile_was_active |= ok && ti.quad[q].last >= (int64_t)h0;
+        tile_was_active |= ok && ti.qlast[q] >= (int64_t)h0;
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -393,13 +380,12 @@ __device__ __forceinline__ void apply_tile(const State& s, const Group& g, const
         o.L = fmaf(r.g, pb, fmaf(r.b, l, r.u2));
         o.Lb = ti.Lb[k];
         o.last = (int64_t)(first + (r.n_last & 0xffffu));
-        store_rec(&s.px[px], o);
+        s.px[px] = o;
         PixP op;
         op.pbar = fmaf(r.a, pb, r.u1);
-        op.pad = 0u;
+        op.cnt = spatial ? ti.cnt[k] + (r.n_last >> 16) : ti.cnt[k];
         op.tot = ti.tot[k] + (r.n_last >> 16);
         s.pp[px] = op;
-        if (spatial) atomicAdd(&s.cnt[px], r.n_last >> 16);
     }
     if (spatial && !tile_was_active) dT += 1u;
 }
@@ -433,54 +419,36 @@ __device__ __forceinline__ void load_pop(const State& s, uint32_t pix, PixL (&nb
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) nb[a][b] = load_rec(&s.px[(size_t)ys[a] * s.W + xs[b]]);
+        for (int b = 0; b < 3; ++b) nb[a][b] = s.px[(size_t)ys[a] * s.W + xs[b]];
 }
 
 // Blurred value of a pixel going stale in a step whose pops start at h_old:
 // 3x3 binomial, clamp-to-edge, fixed summation order, over the image before
 // the step's blurs (a neighbour's current value is Lb if it was stale
 // before the step, else L).  It reads nothing the step's pops write.
-// Records never rewritten by a concurrent apply: kpost past every index.
-constexpr int64_t kNoPost = INT64_MAX;
-
-// A pixel's value in the image a step's blurs read (after the step's
-// pushes, before its blurs): Lb if it was stale before the step (last <
-// h_old), else L.  A launch that also applies the next packet may already
-// have rewritten the record (last >= kpost, the next packet's first index);
-// such a record carries that same value in Lb.
-__device__ __forceinline__ float preblur_value(const PixL& r, uint64_t h_old, int64_t kpost)
+__device__ __forceinline__ float stale_blur(const PixL (&nb)[3][3], uint64_t h_old)
 {
-    return (r.last >= kpost || r.last < (int64_t)h_old) ? r.Lb : r.L;
-}
-
-// 3x3 binomial of c, fixed summation order.
-__device__ __forceinline__ float binomial9(const float (&c)[3][3])
-{
+    float c[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            c[a][b] = nb[a][b].last < (int64_t)h_old ? nb[a][b].Lb : nb[a][b].L;
     const float r0 = c[0][0] + 2.f * c[0][1] + c[0][2];
     const float r1 = c[1][0] + 2.f * c[1][1] + c[1][2];
     const float r2 = c[2][0] + 2.f * c[2][1] + c[2][2];
     return (r0 + 2.f * r1 + r2) * 0.0625f;
 }
 
-__device__ __forceinline__ float stale_blur(const PixL (&nb)[3][3], uint64_t h_old,
-                                            int64_t kpost = kNoPost)
-{
-    float c[3][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) c[a][b] = preblur_value(nb[a][b], h_old, kpost);
-    return binomial9(c);
-}
-
-__device__ __forceinline__ void decide_pop_core(const State& s, uint64_t j, uint32_t pix,
-                                                const PixL (&nb)[3][3], uint64_t h_old,
-                                                int64_t kpost, uint32_t& dP, uint32_t& dT)
+__device__ __forceinline__ void decide_pop(const State& s, uint64_t j, uint32_t pix,
+                                           const PixL (&nb)[3][3], uint64_t h_old, uint32_t& dP,
+                                           uint32_t& dT)
 {
     const uint32_t y = pix / s.W, x = pix - y * s.W;
+    atomicSub(&s.pp[pix].cnt, 1u);
     if (nb[1][1].last != (int64_t)j) return;
     ++dP;
-    s.px[pix].Lb = stale_blur(nb, h_old, kpost);
+    s.px[pix].Lb = stale_blur(nb, h_old);
     // the tile's other pixels: column x ^ 1 and row y ^ 1, where they
     // exist (selected with fixed indices: a register array indexed at run
     // time would be moved to memory)
@@ -493,182 +461,6 @@ __device__ __forceinline__ void decide_pop_core(const State& s, uint64_t j, uint
     const int64_t me = nb[1][1].last;
     const bool newest = !(hx && lx > me) && !(hy && ly > me) && !(hx && hy && lxy > me);
     if (newest) ++dT;
-}
-
-__device__ __forceinline__ void decide_pop(const State& s, uint64_t j, uint32_t pix,
-                                           const PixL (&nb)[3][3], uint64_t h_old, uint32_t& dP,
-                                           uint32_t& dT)
-{
-    atomicSub(&s.cnt[pix], 1u);
-    decide_pop_core(s, j, pix, nb, h_old, kNoPost, dP, dT);
-}
-
-// Pop of event j (pixel pix) in a launch that may also apply the next
-// packet: a tile of that packet (its tag equals `seq`) is left to the
-// packet's apply, which sees the tile's records before it rewrites them; the
-// other tiles are decided here, their neighbours read through
-// preblur_value.
-__device__ __forceinline__ void step_pop(const State& s, uint64_t j, uint32_t pix,
-                                         const PixL (&nb)[3][3], uint64_t tag, uint64_t seq,
-                                         uint64_t h_old, int64_t kpost, uint32_t& dP, uint32_t& dT)
-{
-    atomicSub(&s.cnt[pix], 1u);
-    if (tag == seq) return;
-    decide_pop_core(s, j, pix, nb, h_old, kpost, dP, dT);
-}
-
-// What one launch knows of the steps around the packet it applies.
-struct StepWin {
-    uint64_t h_old;      // window head before the previous step's pops
-    uint64_t h_new;      // ... and after them (the head this packet's pushes see)
-    int64_t kpost;       // first index of this packet (fused), else kNoPost
-    uint64_t first;      // global index of this chunk's first event
-    int64_t k_prev;      // newest index before this packet
-    bool fused;          // the previous step's pops run in this launch
-    bool spatial;        // spatial filter on (window, blur)
-};
-
-// Outputs of a readout of the state after the previous step, written by the
-// heads of this packet's tiles for their four pixels (the others by the
-// readout workgroups).
-__device__ __forceinline__ void head_readout(const State& s, const PopReadout& ro, uint32_t t,
-                                             const uint32_t (&qpix)[4], const bool (&ex)[4],
-                                             const PixL (&q)[4], const float (&val)[4],
-                                             uint64_t h_new, int64_t k_prev)
-{
-    uint32_t act = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        if (!ex[k]) continue;
-        const uint32_t p = qpix[k];
-        const int64_t li = q[k].last;
-        act += li >= (int64_t)h_new ? 1u : 0u;
-        ro.L[p] = val[k];
-        if (ro.pbar || ro.tot) {
-            const PixP w = s.pp[p];
-            if (ro.pbar) ro.pbar[p] = w.pbar;
-            if (ro.tot) ro.tot[p] = w.tot;
-        }
-        if (ro.last) ro.last[p] = li;
-        if (ro.log_age) ro.log_age[p] = log1pf((float)(k_prev - li));
-        if (ro.stale) ro.stale[p] = (li >= 0 && li < (int64_t)h_new) ? 1u : 0u;
-    }
-    if (ro.tcnt) ro.tcnt[t] = act;
-}
-
-// Apply the records of one tile (record i heads it) with the window of `w`.
-// In a fused launch the head also takes over the previous step's pops for
-// its tile (the pops skip tiles of this packet): pixels whose newest event
-// left the window in that step (h_old <= last < h_new) go stale, are
-// blurred from the pre-blur image (a 4x4 block around the tile, neighbours
-// through preblur_value) and counted with the tile's deactivation; an applied
-// pixel keeps, in Lb, the value it had in that image (see preblur_value).
-// Without fusion the previous step's blurs are done and a stale pixel's
-// value is Lb.  Pushes event i to the window.
-__device__ __forceinline__ void apply_tile_step(const State& s, const Group& g, const TileIn& ti,
-                                                uint32_t n, uint32_t nseg, bool rejected,
-                                                uint32_t i, const StepWin& w, uint32_t& act,
-                                                uint32_t& tact, uint32_t& hst, uint32_t& hoff,
-                                                const PopReadout& ro, bool want_ro)
-{
-    if (rejected) return;
-    if (w.spatial && i < n) s.ring[(w.first + i) & s.ring_mask] = g.ey * s.W + g.ex;
-    if (i >= nseg || !ti.head) return;
-    const uint32_t t = g.r[0].key >> 2;
-    const uint32_t ty = t / s.TW, tx = t - ty * s.TW;
-    const bool has_x1 = 2 * tx + 1 < s.W, has_y1 = 2 * ty + 1 < s.H;
-    // without the spatial filter nothing is stale: every value is L
-    const int64_t h_old = w.spatial ? (int64_t)w.h_old : -1;
-    const int64_t h_new = w.spatial ? (int64_t)w.h_new : -1;
-    const uint32_t k0 = g.r[0].key;
-    const uint32_t base = ti.pix[0] - (k0 & 1u) - ((k0 >> 1) & 1u) * s.W;
-    bool ex[4];
-    uint32_t qpix[4];
-    uint32_t sm = 0u;            // quads that go stale in the previous step
-    int64_t mx = -1;             // newest index of the tile
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        ex[q] = (!(q & 1) || has_x1) && (!(q & 2) || has_y1);
-        qpix[q] = base + (q & 1) + (q >> 1) * s.W;
-        const int64_t lq = ti.quad[q].last;
-        if (ex[q] && lq > mx) mx = lq;
-        if (w.fused && ex[q] && lq >= h_old && lq < h_new) sm |= 1u << q;
-    }
-    float bq[4] = {0.f, 0.f, 0.f, 0.f};
-    if (sm) {
-        // the tile's pixels and their neighbours: rows 2ty-1 .. 2ty+2,
-        // columns 2tx-1 .. 2tx+2, clamped to the image
-        const uint32_t x0 = 2 * tx, y0 = 2 * ty;
-        const uint32_t xs[4] = {x0 > 0 ? x0 - 1 : 0u, x0, x0 + 1 < s.W ? x0 + 1 : s.W - 1,
-                                x0 + 2 < s.W ? x0 + 2 : s.W - 1};
-        const uint32_t ys[4] = {y0 > 0 ? y0 - 1 : 0u, y0, y0 + 1 < s.H ? y0 + 1 : s.H - 1,
-                                y0 + 2 < s.H ? y0 + 2 : s.H - 1};
-        float c[4][4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-                c[a][b] = preblur_value(load_rec(&s.px[(size_t)ys[a] * s.W + xs[b]]), w.h_old,
-                                        w.kpost);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int oy = q >> 1, ox = q & 1;
-            float n9[3][3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) n9[a][b] = c[oy + a][ox + b];
-            bq[q] = binomial9(n9);
-        }
-    }
-    if (w.fused) {
-        hst += (uint32_t)__popc(sm);
-        if (mx >= h_old && mx < h_new) hoff += 1u;
-    }
-    if (want_ro) {
-        float val[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const PixL& r = ti.quad[q];
-            val[q] = r.last >= h_new ? r.L : ((sm >> q) & 1u) ? bq[q] : r.Lb;
-        }
-        head_readout(s, ro, t, qpix, ex, ti.quad, val, w.h_new, w.k_prev);
-    }
-    uint32_t cov = 0u;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        if (!ti.same[k] || i + k >= nseg) continue;
-        const SegRec& r = g.r[k];
-        const uint32_t px = ti.pix[k];
-        const uint32_t qk = r.key & 3u;
-        cov |= 1u << qk;
-        const int64_t li = ti.last[k];
-        // the value the pushes start from: L while active, else the blurred
-        // (or never-touched) value
-        float l = ti.L[k];
-        if (li < h_new) {
-            l = ti.Lb[k];
-            act += 1u;
-            if ((sm >> qk) & 1u)
-                l = qk == 0u ? bq[0] : qk == 1u ? bq[1] : qk == 2u ? bq[2] : bq[3];
-        }
-        const float pb = ti.pbar[k];
-        PixL o;
-        o.L = fmaf(r.g, pb, fmaf(r.b, l, r.u2));
-        o.Lb = (w.fused && li >= h_old) ? ti.L[k] : ti.Lb[k];
-        o.last = (int64_t)(w.first + (r.n_last & 0xffffu));
-        store_rec(&s.px[px], o);
-        PixP op;
-        op.pbar = fmaf(r.a, pb, r.u1);
-        op.pad = 0u;
-        op.tot = ti.tot[k] + (r.n_last >> 16);
-        s.pp[px] = op;
-        if (w.spatial) atomicAdd(&s.cnt[px], r.n_last >> 16);
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-        if (((sm & ~cov) >> q) & 1u) s.px[qpix[q]].Lb = bq[q];
-    if (w.spatial && mx < h_new) tact += 1u;
 }
 
 __device__ __forceinline__ void pop_one(const State& s, uint64_t j, uint32_t pix, uint64_t h_old,
@@ -688,42 +480,25 @@ __device__ __forceinline__ void pop_range(const State& s, uint64_t start, uint64
         pop_one(s, j, s.ring[j & s.ring_mask], h_old, dP, dT);
 }
 
-// Store a wave's counts into the step's scratch: (activated pixels,
-// activated tiles) for kCountApply, (stale pixels, deactivated tiles) for
-// kCountHead and kCountPop.  g is the thread's index in the step's grid of
-// that kind, so the wave's slot is g / 64; waves past the slots, or with a
-// count that does not fit 16 bits, add to the overflow counters.  Zero
-// counts are not stored (the scratch starts zeroed).
-__device__ __forceinline__ void add_counts(StepScratch* step, CountKind kind, uint32_t g,
-                                           uint32_t a, uint32_t b)
+// Store a wave's activation (pops = false) or deactivation (pops = true)
+// counts into the step's scratch.  g is the thread's index in the step's
+// grid of that kind, so the wave's slot is g / 64; waves past the slots add
+// to the overflow counters.  Zero counts are not stored (the scratch starts
+// zeroed).
+__device__ __forceinline__ void add_counts(StepScratch* step, bool pops, uint32_t g, uint32_t a,
+                                           uint32_t b)
 {
     a = wave_sum(a);
     b = wave_sum(b);
     if ((threadIdx.x & 63u) == 0 && (a | b)) {
         const uint32_t w = g >> 6;
-        const uint32_t slots = kind == kCountPop ? kPopSlots : kApplySlots;
-        uint32_t* slot = kind == kCountApply ? step->wave_apply
-                         : kind == kCountHead ? step->wave_head : step->wave_pop;
-        if (w < slots && a <= 0xffffu && b <= 0xffffu) {
-            slot[w] = a | (b << 16);
+        if (w < (pops ? kPopSlots : kApplySlots)) {
+            (pops ? step->wave_pop : step->wave_apply)[w] = make_uint2(a, b);
         } else {
-            uint32_t* part = step->part[w % kSpread] + (kind == kCountApply ? 0 : 2);
+            uint32_t* part = step->part[w % kSpread] + (pops ? 2 : 0);
             atomicAdd(&part[0], a);
             atomicAdd(&part[1], b);
         }
-    }
-}
-
-// Counts of a wave that go straight to the overflow counters.
-__device__ __forceinline__ void add_overflow_counts(StepScratch* step, CountKind kind, uint32_t g,
-                                                    uint32_t a, uint32_t b)
-{
-    a = wave_sum(a);
-    b = wave_sum(b);
-    if ((threadIdx.x & 63u) == 0 && (a | b)) {
-        uint32_t* part = step->part[(g >> 6) % kSpread] + (kind == kCountApply ? 0 : 2);
-        atomicAdd(&part[0], a);
-        atomicAdd(&part[1], b);
     }
 }
 
@@ -735,7 +510,7 @@ __device__ __forceinline__ uint32_t tile_active_pixels(const State& s, uint64_t 
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const uint32_t px = 2 * tx + (q & 1), py = 2 * ty + (q >> 1);
-        if (px < s.W && py < s.H && load_rec(&s.px[(size_t)py * s.W + px]).last >= h) ++n;
+        if (px < s.W && py < s.H && s.px[(size_t)py * s.W + px].last >= h) ++n;
     }
     return n;
 }
@@ -749,7 +524,7 @@ __device__ __forceinline__ void readout_pixel_after_pops(const State& s, int64_t
                                                          uint64_t h_new, uint64_t i, const PixL& v,
                                                          float* L, float* pbar, uint8_t* stale,
                                                          int64_t* last, float* log_age,
-                                                         uint64_t* tot, int64_t kpost = kNoPost)
+                                                         uint64_t* tot)
 {
     const int64_t li = v.last;
     float val = v.L;
@@ -758,7 +533,7 @@ __device__ __forceinline__ void readout_pixel_after_pops(const State& s, int64_t
         if (li >= (int64_t)h_old) {
             PixL nb[3][3];
             load_pop(s, (uint32_t)i, nb);
-            val = stale_blur(nb, h_old, kpost);
+            val = stale_blur(nb, h_old);
         }
     }
     L[i] = val;
@@ -775,7 +550,7 @@ __device__ __forceinline__ void readout_pixel(const State& s, int spatial, int64
                                               uint32_t* cnt, int64_t* last, float* log_age,
                                               uint64_t* tot)
 {
-    const PixL v = load_rec(&s.px[i]);
+    const PixL v = s.px[i];
     const int64_t li = v.last;
     L[i] = (spatial && li < h) ? v.Lb : v.L;
     if (pbar) pbar[i] = s.pp[i].pbar;
@@ -783,7 +558,7 @@ __device__ __forceinline__ void readout_pixel(const State& s, int spatial, int64
     if (last) last[i] = li;
     if (log_age) log_age[i] = log1pf((float)(k - li));
     if (spatial) {
-        if (cnt) cnt[i] = s.cnt[i];
+        if (cnt) cnt[i] = s.pp[i].cnt;
         if (stale) stale[i] = (li >= 0 && li < h) ? 1u : 0u;
     }
 }

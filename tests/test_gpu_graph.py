@@ -157,59 +157,33 @@ def test_graph_launches_multi_chunk_packets_and_mode_switch():
         c.close()
 
 
-def _fused_per_batch(sched, chunk=16384, max_chunks=256):
-    """Fused launches (pops of one packet with the pushes of the next) per
-    batch of the op list: a push is fused with the pops of the push before it
-    in the same batch when nothing, or one device readout without window
-    counts, lies between them (every readout of `_ops(..., ("dev",))`)."""
-    batches, cur, chunks = [], [], 0
-    for it in sched:
-        if it[0] == "push":
-            need = -(-(it[2] - it[1]) // chunk)
-            if chunks + need > max_chunks:
-                batches.append(cur)
-                cur, chunks = [], 0
-            chunks += need
-        cur.append(it[0])
-    batches.append(cur)
-    out = []
-    for ops in batches:
-        fused, gap = 0, None
-        for kind in ops:
-            if kind == "push":
-                if gap is not None and gap <= 1:
-                    fused += 1
-                gap = 0
-            elif gap is not None:
-                gap += 1
-        out.append(fused)
-    return out
-
-
 def test_graph_launch_timing_counts_per_batch():
-    """With graph launches the timed count restarts with every batch and
-    fused launches that also write a readout count as fused launches (kept
-    under their own kind): batches timed every 16th fused launch give
-    ceil(fused / 16) timed launches each, with positive durations."""
+    """With graph launches the timed count restarts with every batch and pop
+    launches that also write a readout count as pops (kept under kernel 3):
+    batches of 256 and 49 packets timed every 16th pop give 16 + 4 timed pop
+    (and apply) launches per submission, with positive durations."""
     torch, dev = torch_dev()
     ev, sched = _stream()
     g = to_device(ev)
     ctx = make_ctx(W, H)
-    fused, fused_ro = fb.KERNEL_NAMES.index("fused"), fb.KERNEL_NAMES.index("fused_readout")
     assert fb.fibar_set_launch_mode(ctx.handle, fb.FIBAR_LAUNCH_GRAPH) == fb.FIBAR_OK
-    assert fb.fibar_set_kernel_timing(ctx.handle, 1 << fused, 16) == fb.FIBAR_OK
-    per_batch = _fused_per_batch(sched)
-    assert len(per_batch) == 2 and all(f > 16 for f in per_batch)
-    expect = sum((f + 15) // 16 for f in per_batch)
+    assert fb.fibar_set_kernel_timing(ctx.handle, (1 << 1) | (1 << 2), 16) == fb.FIBAR_OK
+    n_push = sum(1 for it in sched if it[0] == "push")
+    batches = [256, n_push - 256]            # one chunk per packet, 256 chunks per batch
+    assert 0 < batches[1] <= 256
+    expect = sum((b + 15) // 16 for b in batches)
     for rep in range(2):
         assert ctx.reset() == 0
         ops, _ = _ops(sched, g, ("dev",))
         assert ctx.submit(ops) == 0
-        rc5, ms5, n5 = fb.fibar_kernel_time(ctx.handle, fused)
-        rc6, ms6, n6 = fb.fibar_kernel_time(ctx.handle, fused_ro)
-        assert rc5 == rc6 == fb.FIBAR_OK
-        assert n5 + n6 == expect, (n5, n6, expect)
-        assert n5 > 0 and 0.0 < ms5 / n5 < 1.0, (ms5, n5)
+        rc2, ms2, n2 = fb.fibar_kernel_time(ctx.handle, 2)
+        rc3, ms3, n3 = fb.fibar_kernel_time(ctx.handle, 3)
+        rc1, ms1, n1 = fb.fibar_kernel_time(ctx.handle, 1)
+        assert rc1 == rc2 == rc3 == fb.FIBAR_OK
+        assert n2 + n3 == expect, (n2, n3, expect)
+        assert n1 == expect, (n1, expect)
+        assert n2 > 0 and 0.0 < ms2 / n2 < 1.0, (ms2, n2)
+        assert n1 > 0 and 0.0 < ms1 / n1 < 1.0, (ms1, n1)
     ctx.close()
 
 
