@@ -281,3 +281,77 @@ def test_argument_checks():
     assert fb.fibar_fill_train_step(f.handle, gL, gS, gA, out, 1, 8, 8, float("nan"))[0] == \
         fb.FIBAR_E_INVALID_ARG
     f.close()
+
+
+# Per-pixel bound of the device prediction against the FP64 network.  BF16
+# keeps 8 significant bits: the inputs, the weights and every layer's stored
+# activations are rounded to it (relative 2^-9 each), sums are FP32.  A
+# worst-case bound that adds absolute values through four 3x3 layers of 144
+# terms each is ~100x the output itself, so the bound is statistical:
+# roundings of independent sign add in quadrature, and after four layers the
+# correction's error stays a few 2^-8 of its scale.  Per pixel, |error| <=
+# 16 * 2^-8 * the RMS of the network's correction (prediction - L) over the
+# band, checked beside the normwise bound.
+PIX_BOUND = 16 * 2.0 ** -8
+
+
+def test_full_frame_forward_matches_reference_on_bands():
+    """One 1280x720 frame: the fused kernel's workgroups each loop over many
+    tiles with the next tile's loads in flight.  The reference evaluates
+    bands of full rows (top edge, interior, bottom edge), each from a crop
+    four rows wider on each side, which is exact for a four-layer 3x3
+    network; every pixel of the bands is checked."""
+    torch, d = torch_dev()
+    n, H, W = 1, 720, 1280
+    prm = params_with_biases(21)
+    L, stale, age, _ = make_batch(22, n, H, W)
+    gL, gS, gA = dev(L, stale, age)
+    out = torch.empty((n, H, W), dtype=torch.float32, device=d)
+    f = fb.Fill(prm)
+    assert f.predict(gL, gS, gA, out) == 0
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    f.close()
+    params = ref.unflatten(prm)
+    worst = 0.0
+    for r0, r1 in ((0, 24), (233, 251), (400, 432), (696, 720)):
+        c0, c1 = max(0, r0 - 4), min(H, r1 + 4)
+        x = ref.make_input(L[:, c0:c1], stale[:, c0:c1], age[:, c0:c1])
+        want = ref.forward(params, x)[0][:, r0 - c0:r1 - c0]
+        corr = want - L[:, r0:r1]
+        bound = PIX_BOUND * float(np.sqrt(np.mean(corr * corr)))
+        g = got[:, r0:r1]
+        err = rel(g, want)
+        d_pix = np.abs(g.astype(np.float64) - want)
+        print("rows %d-%d: normwise rel err %.3g, worst pixel error / bound %.3g"
+              % (r0, r1, err, float((d_pix / bound).max())))
+        assert err < TOL
+        assert float(d_pix.max()) <= bound, (r0, r1)
+        worst = max(worst, err)
+
+
+def test_gradient_where_every_wave_loops():
+    """8 x 96 x 250: 12288 16-pixel segments (the last of each row ragged)
+    over the weight-gradient kernel's 4096 waves, so every wave accumulates
+    three segments before the partial sums are reduced."""
+    n, H, W = 8, 96, 250
+    assert n * H * ((W + 15) // 16) == 3 * 4096
+    prm = bf16_values(params_with_biases(23))
+    L, stale, age, target = make_batch(24, n, H, W)
+    L, age = bf16_values(L), bf16_values(age)
+    f = fb.Fill(prm)
+    rc, loss, g = f.loss_grad(*dev(L, stale, age, target))
+    assert rc == 0
+    f.close()
+    want_loss, want_g = ref.loss_and_grad(prm.astype(np.float64), ref.make_input(L, stale, age),
+                                          target, stale)
+    print("loss %.6g ref %.6g" % (loss, want_loss))
+    assert abs(loss - want_loss) <= TOL * want_loss
+    k = 0
+    for l, (ws, bs) in enumerate(ref.layer_shapes()):
+        nw, nb = int(np.prod(ws)), int(np.prod(bs))
+        ew = rel(g[k:k + nw], want_g[k:k + nw])
+        eb = rel(g[k + nw:k + nw + nb], want_g[k + nw:k + nw + nb])
+        print("layer %d: grad w rel err %.3g, grad b rel err %.3g" % (l, ew, eb))
+        assert ew < TOL and eb < TOL, l
+        k += nw + nb

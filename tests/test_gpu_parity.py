@@ -124,6 +124,56 @@ def test_vga_two_million_events(spatial):
     run_pair(ev, 640, 480, sched, check_every_read=8, spatial_filter=spatial)
 
 
+@pytest.mark.parametrize("spatial", [True, False])
+def test_vga_full_stream_as_submitted(spatial):
+    """The 640x480 configuration at its full length: 20 M events in
+    8192-event packets with a brightness readout every 50 000 events (400),
+    all in one submit, blur on and off.  Sampled frames (first, last and
+    every 40th) and the final state against the FP64 oracle."""
+    torch, dev = torch_dev()
+    W, H = 640, 480
+    npx = W * H
+    w = eventsim.preset("vga")
+    ev = eventsim.generate(w.scene)
+    assert len(ev) == 20_000_000
+    sched = eventsim.schedule(len(ev), w.packet, w.readouts)
+    n_read = sum(1 for it in sched if it[0] == "read")
+    flush("vga %d events, %d readouts in one submit, spatial=%s" % (len(ev), n_read, spatial))
+    sample = sorted(set(range(0, n_read, 40)) | {1, n_read - 1})
+    gx, gy, gp = to_device(ev)
+    scratch = torch.empty(npx, dtype=torch.float32, device=dev)
+    frames = {i: torch.empty(npx, dtype=torch.float32, device=dev) for i in sample}
+    ops, r = [], 0
+    for it in sched:
+        if it[0] == "push":
+            ops.append(fb.push_op(gx[it[1]:it[2]], gy[it[1]:it[2]], gp[it[1]:it[2]]))
+        else:
+            ops.append(fb.readout_op(0, frames.get(r, scratch)))
+            r += 1
+    ctx = make_ctx(W, H, spatial_filter=spatial)
+    assert ctx.submit(ops) == 0
+    assert ctx.synchronize() == 0
+    got = {i: f.cpu().numpy() for i, f in frames.items()}
+    final = ctx.readout_host(0)
+    orc = oracle.Oracle(W, H, spatial_filter=spatial)
+    r = 0
+    for it in sched:
+        if it[0] == "push":
+            assert orc.push(ev.x[it[1]:it[2]], ev.y[it[1]:it[2]], ev.p[it[1]:it[2]]) == 0
+            continue
+        if r in got:
+            ref = orc.readout(0)["L"]
+            d = np.abs(got[r].astype(np.float64) - ref)
+            assert np.all(d <= REL * np.maximum(np.abs(ref), 1.0)), \
+                "frame %d: worst %.3g" % (r, d.max())
+        r += 1
+    compare_state(final, orc.readout(0), spatial, "end of the 640x480 stream")
+    if spatial:
+        compare_stats(ctx.stats(), orc.stats())
+    flush("vga full stream: %d sampled frames and the final state match" % len(got))
+    ctx.close()
+
+
 def test_hd720_twenty_million_events():
     w = eventsim.preset("hd720", n_events=20_000_000)
     ev = eventsim.generate(w.scene)
