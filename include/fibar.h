@@ -15,11 +15,17 @@
  *     target regulated by Eq. (19), (20) (Method, "Spatial filtering");
  *   - one-time 3x3 Gaussian blur of pixels that go stale.
  *
- * Regulation granularity: the library regulates once per pushed packet
- * (all events of the packet are applied, then old events leave the window,
- * every pixel that went stale in that step is blurred from the same pre-blur
- * image, then the target length is updated).  A packet of one event is the
- * paper's per-event step.
+ * Regulation granularity: by default the library regulates once per pushed
+ * packet (all events of the packet are applied, then old events leave the
+ * window, every pixel that went stale in that step is blurred from the same
+ * pre-blur image, then the target length is updated).  A packet of one event
+ * is the paper's per-event step.  FIBAR_REG_EVENT runs the paper's
+ * procedure literally (Method, "Spatial filtering", steps 1-3; Eq. (20)
+ * after every event): each event is applied, enters the window, old events
+ * leave while the window is longer than the target, each pixel going stale
+ * is blurred at once from the current image (so later blurs of the same
+ * event see earlier ones), and the target is updated; results then do not
+ * depend on how events are grouped into packets.
  *
  * Threading: a context is not thread-safe; calls on one context must be
  * serialised by the caller.  All device work of a context is ordered on the
@@ -49,7 +55,8 @@ typedef enum {
 } fibar_status;
 
 typedef enum {
-    FIBAR_REG_PACKET = 0        /* regulate once per pushed packet            */
+    FIBAR_REG_PACKET = 0,       /* regulate once per pushed packet            */
+    FIBAR_REG_EVENT = 1         /* regulate after every event (see below)     */
 } fibar_regulation;
 
 /*
@@ -64,7 +71,14 @@ typedef enum {
  *                  width*height (the paper's queue limit).
  *   spatial_filter 1 = FIBAR (stale detection + blur), 0 = FIBAR-NSF
  *                  (temporal filter only).
- *   regulation     FIBAR_REG_PACKET.
+ *   regulation     FIBAR_REG_PACKET or FIBAR_REG_EVENT.  Per-event
+ *                  regulation (with spatial_filter = 1) keeps a packet's whole
+ *                  state in one workgroup's local memory: sensors of at most
+ *                  8192 pixels and q_max <= 16382 (FIBAR_E_INVALID_ARG
+ *                  otherwise); step telemetry and batched groups
+ *                  (fibar_multi_create) are not available for such contexts
+ *                  (FIBAR_E_UNSUPPORTED).  With spatial_filter = 0 nothing
+ *                  is regulated and both settings are the same.
  *   max_packet     largest packet accepted by fibar_push_events (events),
  *                  1 .. 1048576; sizes device buffers.  Default 65536.
  *   stream         hipStream_t all work is ordered on; NULL = the null stream.

@@ -28,6 +28,7 @@ FIBAR_E_NOMEM = -5
 FIBAR_E_DEVICE = -6
 FIBAR_E_UNSUPPORTED = -7
 FIBAR_REG_PACKET = 0
+FIBAR_REG_EVENT = 1
 FIBAR_OP_PUSH = 0
 FIBAR_LAUNCH_DIRECT = 0
 FIBAR_LAUNCH_GRAPH = 1
@@ -322,8 +323,9 @@ class Context:
     """One reconstruction context (owns its device state)."""
 
     def __init__(self, width, height, t_cut=40.0, fill=(1, 2), q_min=64, q_max=0,
-                 spatial_filter=True, max_packet=65536, stream=None):
+                 spatial_filter=True, max_packet=65536, stream=None, regulation="packet"):
         prm = fibar_default_params()
+        prm.regulation = FIBAR_REG_EVENT if regulation == "event" else FIBAR_REG_PACKET
         prm.t_cut = float(t_cut)
         prm.fill_num, prm.fill_den = int(fill[0]), int(fill[1])
         prm.q_min = int(q_min)

@@ -404,11 +404,27 @@ int run_region_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, u
     return FIBAR_OK;
 }
 
+// Per-event regulation: one launch per packet, readouts between them.
+int run_event_batch(fibar_ctx* c, const Op* ops, size_t n)
+{
+    for (size_t i = 0; i < n; ++i) {
+        if (ops[i].kind == 1) {
+            int rc = do_readout_kernel(c, ops[i].ro, nullptr, 0);
+            if (rc) return rc;
+            continue;
+        }
+        HIP_TRY(launch_event_packet(c->s, c->cur_slot, ops[i].x, ops[i].y, ops[i].p, ops[i].n,
+                                    c->coef, c->ev_cap, c->ev_lds, c->st));
+    }
+    return FIBAR_OK;
+}
+
 // Execute ops[0..n): bulk sort for all pushes, then the in-order steps.
 int run_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, uint32_t n_steps)
 {
     if (n == 0) return FIBAR_OK;
     if (c->region_path) return run_region_batch(c, ops, n, n_chunks, n_steps);
+    if (c->event_mode) return run_event_batch(c, ops, n);
     // graph mode replays the batch's kernels as one graph; a readout into
     // host memory (copies and a wait between the kernels) keeps the batch on
     // direct launches
@@ -677,7 +693,7 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
     if (!(p.t_cut > 4.0) || !isfinite(p.t_cut)) return FIBAR_E_INVALID_ARG;
     if (p.fill_num == 0 || p.fill_den == 0 || p.fill_num > p.fill_den || p.fill_den > 65535)
         return FIBAR_E_INVALID_ARG;
-    if (p.spatial_filter > 1 || p.regulation != FIBAR_REG_PACKET) return FIBAR_E_INVALID_ARG;
+    if (p.spatial_filter > 1 || p.regulation > FIBAR_REG_EVENT) return FIBAR_E_INVALID_ARG;
     if (p.max_packet == 0 || p.max_packet > kMaxPacket) return FIBAR_E_INVALID_ARG;
     const uint64_t npx = (uint64_t)width * height;
     // the sort key of an event is (tile-major pixel key << 1) | polarity in
@@ -686,6 +702,14 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
     if (key_span > kMaxKeySpan) return FIBAR_E_INVALID_ARG;
     if (p.q_max == 0) p.q_max = (uint32_t)npx;
     if (p.q_min == 0 || p.q_min > p.q_max) return FIBAR_E_INVALID_ARG;
+    // per-event regulation with the spatial filter on keeps a packet's state
+    // in one workgroup's LDS (without the filter there is nothing to regulate)
+    const bool event_mode = p.regulation == FIBAR_REG_EVENT && p.spatial_filter;
+    uint32_t ev_cap = 1;
+    if (event_mode) {
+        if (npx > kEventMaxPixels || p.q_max > kEventMaxRing - 2) return FIBAR_E_INVALID_ARG;
+        while (ev_cap < p.q_max + 2) ev_cap <<= 1;
+    }
 
     fibar_ctx* c = new (std::nothrow) fibar_ctx();
     if (!c) return FIBAR_E_NOMEM;
@@ -714,6 +738,11 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
 
     const uint64_t n_regions = (npx + kRegion - 1) / kRegion;
     c->region_path = !p.spatial_filter && n_regions <= kMaxRegions;
+    c->event_mode = event_mode;
+    if (event_mode) {
+        c->ev_cap = ev_cap;
+        c->ev_lds = event_lds_bytes(width, height, c->TW, ev_cap);
+    }
 
     hipError_t e = hipSuccess;
     auto alloc = [&](void** ptr, size_t bytes) {
@@ -760,7 +789,8 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
     c->s.q_min = p.q_min;
     c->s.q_max = p.q_max;
 
-    e = init_state(c);
+    if (event_mode) e = prepare_event_kernel(c->ev_lds);
+    if (e == hipSuccess) e = init_state(c);
     if (e == hipSuccess) e = hipEventRecord(c->chunks_free, c->st);
     if (e == hipSuccess && c->ro_free) e = hipEventRecord(c->ro_free, c->st);
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
@@ -851,7 +881,7 @@ int fibar_set_kernel_timing(fibar_ctx* c, uint32_t kernel_mask, uint32_t every)
 int fibar_set_telemetry(fibar_ctx* c, fibar_step_record* records, uint64_t capacity)
 {
     if (!c || (!records && capacity)) return FIBAR_E_INVALID_ARG;
-    if (!c->prm.spatial_filter && records) return FIBAR_E_UNSUPPORTED;
+    if ((!c->prm.spatial_filter || c->event_mode) && records) return FIBAR_E_UNSUPPORTED;
     // launches already queued keep the buffer they were given
     c->s.tel = capacity ? reinterpret_cast<StepRecord*>(records) : nullptr;
     c->s.tel_cap = capacity;

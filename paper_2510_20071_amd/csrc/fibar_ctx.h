@@ -32,6 +32,10 @@ struct fibar_ctx {
     uint64_t t_hi = 0;
     // blur-off batch path
     bool region_path = false;
+    // per-event regulation: packets run in one LDS-resident workgroup
+    bool event_mode = false;
+    uint32_t ev_cap = 0;                // LDS ring entries (a power of two)
+    size_t ev_lds = 0;                  // dynamic LDS bytes of the event kernel
     fibar::RegionBuffers rb{};
     fibar::RegionReadout* h_ro = nullptr;      // pinned
     hipEvent_t ro_free = nullptr;

@@ -298,4 +298,16 @@ hipError_t launch_readout(const State& s, int spatial, const StepScratch* prev,
                           uint32_t* tcnt, uint64_t* tot, hipStream_t st,
                           const LaunchTiming& tm = LaunchTiming());
 
+// Per-event regulation (fibar_event.hip): one packet in one workgroup with
+// the state in LDS.  Limits of a context regulated per event: at most
+// kEventMaxPixels pixels, and windows of at most kEventMaxRing - 2 events
+// (the LDS ring of pixel ids has kEventMaxRing entries at most).
+constexpr uint32_t kEventMaxPixels = 8192;
+constexpr uint32_t kEventMaxRing = 16384;
+size_t event_lds_bytes(uint32_t W, uint32_t H, uint32_t TW, uint32_t cap);
+hipError_t prepare_event_kernel(size_t lds_bytes);
+hipError_t launch_event_packet(const State& s, int slot, const uint16_t* x, const uint16_t* y,
+                               const uint8_t* p, uint32_t n, const Coef& coef, uint32_t cap,
+                               size_t lds_bytes, hipStream_t st);
+
 }  // namespace fibar

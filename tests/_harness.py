@@ -35,7 +35,7 @@ def make_ctx(W, H, **kw):
 
 def oracle_kw(kw):
     keep = {k: v for k, v in kw.items() if k in ("t_cut", "fill", "q_min", "q_max",
-                                                  "spatial_filter")}
+                                                  "spatial_filter", "regulation")}
     return keep
 
 

@@ -99,3 +99,16 @@ def test_sensor_size_limit_of_the_sort_key_without_gpu():
 def test_telemetry_rejects_bad_arguments_without_gpu():
     lib = fb.load()
     assert lib.fibar_set_telemetry(None, None, 0) == fb.FIBAR_E_INVALID_ARG
+
+
+def test_event_regulation_limits_without_gpu():
+    # per-event regulation keeps the state of a packet in one workgroup's
+    # local memory: at most 8192 pixels and windows of at most 16382 events
+    p = fb.fibar_default_params()
+    p.regulation = fb.FIBAR_REG_EVENT
+    assert fb.fibar_create(128, 65, p)[0] == fb.FIBAR_E_INVALID_ARG      # 8320 pixels
+    p.q_max = 16383
+    assert fb.fibar_create(64, 48, p)[0] == fb.FIBAR_E_INVALID_ARG
+    p = fb.fibar_default_params()
+    p.regulation = 2
+    assert fb.fibar_create(64, 48, p)[0] == fb.FIBAR_E_INVALID_ARG
