@@ -382,6 +382,80 @@ def test_event_mode_equals_packet_mode_for_single_events():
             assert np.array_equal(re[key], rp[key])
 
 
+def brute_event_mode(W, H, xs, ys, ps, t_cut, q_min, q_max, fill):
+    """The per-event procedure written out with Python lists: after each
+    event (temporal filter, then the event joins the window) events leave
+    from the front while the window is longer than Q; a pixel with no event
+    left in the window is blurred right away from the image as it is at that
+    moment (3x3 binomial, borders clamped); Q is then recomputed from the
+    distinct pixels and 2x2 tiles of the window.  Yields (L, stats) after
+    every event."""
+    a, b = oracle.coefficients(t_cut)
+    L = [0.0] * (W * H)
+    pbar = [0.0] * (W * H)
+    ev, h, Q = [], 0, q_max
+    wts = (0.25, 0.5, 0.25)
+    for x, y, p in zip(xs, ys, ps):
+        i = int(y) * W + int(x)
+        pk = 1.0 if p else -1.0
+        pbar[i] = a * pbar[i] + (1.0 - a) * pk
+        L[i] = b * L[i] + 0.5 * (1.0 + b) * (pk - pbar[i])
+        ev.append(i)
+        stale = 0
+        while len(ev) - h > Q:
+            j = ev[h]
+            h += 1
+            if j not in ev[h:]:
+                jx, jy = j % W, j // W
+                acc = 0.0
+                for dy in (-1, 0, 1):
+                    for dx in (-1, 0, 1):
+                        xx = min(max(jx + dx, 0), W - 1)
+                        yy = min(max(jy + dy, 0), H - 1)
+                        acc += wts[dy + 1] * wts[dx + 1] * L[yy * W + xx]
+                L[j] = acc
+                stale += 1
+        win = ev[h:]
+        P = len(set(win))
+        T = len(set((k // W // 2) * ((W + 1) // 2) + (k % W) // 2 for k in win))
+        if P:
+            Q = max(q_min, min(q_max, (len(win) * fill[0] * 4 * T) // (fill[1] * P)))
+        yield list(L), {"h": h, "Q": Q, "P": P, "T": T, "last_stale": stale}
+
+
+def test_event_mode_sequential_blurs_against_brute_force():
+    """Per-event regulation blurs the pixels that go stale in one step one
+    after another, each from the image with the earlier blurs in it.  On a
+    5x4 sensor with bursts of several stale pixels per step the oracle
+    follows the list-based procedure after every event; packet regulation
+    (simultaneous blurs) ends up elsewhere on the same events."""
+    W, H = 5, 4
+    rng = np.random.default_rng(17)
+    n = 1500
+    pix, cur = [], 0
+    for _ in range(n):
+        if rng.random() < 0.5:
+            cur = int(rng.integers(0, W * H))
+        pix.append(cur)
+    xs = np.array([q % W for q in pix], np.uint16)
+    ys = np.array([q // W for q in pix], np.uint16)
+    ps = rng.integers(0, 2, n).astype(np.uint8)
+    q_min, q_max, fill = 1, W * H, (1, 2)
+    orc = oracle.Oracle(W, H, q_min=q_min, q_max=q_max, fill=fill, regulation="event")
+    bursts = 0
+    for e, (Lb, sb) in enumerate(brute_event_mode(W, H, xs, ys, ps, 40.0, q_min, q_max, fill)):
+        assert orc.push(xs[e:e + 1], ys[e:e + 1], ps[e:e + 1]) == 0
+        s = orc.stats()
+        assert {k: s[k] for k in sb} == sb, e
+        assert np.allclose(orc.readout(0)["L"], Lb, rtol=0, atol=1e-12), e
+        bursts += sb["last_stale"] > 1
+    assert bursts > 20
+    pk = oracle.Oracle(W, H, q_min=q_min, q_max=q_max, fill=fill)
+    for e in range(n):
+        pk.push(xs[e:e + 1], ys[e:e + 1], ps[e:e + 1])
+    assert not np.allclose(pk.readout(0)["L"], orc.readout(0)["L"], rtol=0, atol=1e-9)
+
+
 # ---------------------------------------------------------------------------
 # Brute force on tiny sensors: recount the window from scratch
 # ---------------------------------------------------------------------------
