@@ -227,6 +227,62 @@ def schedule(n_events: int, packet: int, readouts) -> list:
 
 
 # --------------------------------------------------------------------------
+# Calibration recording for relative contrast thresholds: a spatially uniform
+# screen whose log brightness is a triangle wave (the threshold appendix's
+# set-up), seen by pixels with thresholds of their own.
+# --------------------------------------------------------------------------
+def pixel_thresholds(width: int, height: int, seed: int, thr: float = 0.2, jitter: float = 0.02):
+    """Per-pixel ON and OFF thresholds, uniform over [thr - jitter, thr + jitter],
+    drawn independently (FP64, [H * W] each)."""
+    rng = np.random.default_rng(seed)
+    n = width * height
+    return (rng.uniform(thr - jitter, thr + jitter, n), rng.uniform(thr - jitter, thr + jitter, n))
+
+
+def calibration_stream(width: int, height: int, c_on, c_off, periods: int = 20,
+                       amplitude: float = 2.0, period_ns: int = 1_000_000_000) -> Events:
+    """Events of `periods` periods of a uniform triangle wave of log brightness
+    (0 -> amplitude -> 0, one period per `period_ns`): each pixel emits an ON
+    event when the brightness has risen by its c_on above its reference
+    level and an OFF event when it has fallen by its c_off below it, the
+    reference moving by one threshold per event.  Event times are the exact
+    crossing times; events are ordered by (time, pixel)."""
+    npx = width * height
+    c_on = np.asarray(c_on, np.float64)
+    c_off = np.asarray(c_off, np.float64)
+    ref = np.zeros(npx)
+    half = period_ns / 2.0
+    slope = amplitude / half
+    pix_all, t_all, p_all = [], [], []
+    idx = np.arange(npx)
+    for per in range(periods):
+        t0 = per * period_ns
+        for rising in (True, False):
+            c = c_on if rising else c_off
+            nmax = int(np.ceil(amplitude / c.min())) + 2
+            m = np.arange(1, nmax + 1)[None, :]
+            if rising:
+                lvl = ref[:, None] + m * c[:, None]
+                ok = lvl <= amplitude
+                tt = t0 + lvl / slope
+            else:
+                lvl = ref[:, None] - m * c[:, None]
+                ok = lvl >= 0.0
+                tt = t0 + half + (amplitude - lvl) / slope
+            cnt = ok.sum(axis=1)
+            ref = ref + (cnt * c if rising else -cnt * c)
+            pix_all.append(np.broadcast_to(idx[:, None], ok.shape)[ok])
+            t_all.append(tt[ok])
+            p_all.append(np.full(int(cnt.sum()), 1 if rising else 0, np.uint8))
+    pix = np.concatenate(pix_all)
+    t = np.round(np.concatenate(t_all)).astype(np.uint64)
+    p = np.concatenate(p_all)
+    order = np.lexsort((pix, t))
+    pix, t, p = pix[order], t[order], p[order]
+    return Events((pix % width).astype(np.uint16), (pix // width).astype(np.uint16), p, t)
+
+
+# --------------------------------------------------------------------------
 # Many streams of uneven resolution and rate.
 # --------------------------------------------------------------------------
 RESOLUTIONS = ((346, 260), (640, 480), (1280, 720))

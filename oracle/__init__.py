@@ -71,6 +71,7 @@ def _load():
         lib.fibar_ref_coefficients.argtypes = [ctypes.c_double, ctypes.POINTER(ctypes.c_double),
                                                ctypes.POINTER(ctypes.c_double)]
         lib.fibar_ref_coefficients.restype = None
+        lib.fibar_ref_set_gain.argtypes = [vp, vp]
         _lib = lib
     return _lib
 
@@ -146,10 +147,42 @@ class Oracle:
             return rc
         return out
 
+    def set_gain(self, gain) -> int:
+        """Per-pixel multipliers of Eq. (6) (the relative thresholds C'_i);
+        None removes them."""
+        if gain is None:
+            return _load().fibar_ref_set_gain(self._h, None)
+        g = np.ascontiguousarray(gain, np.float64).reshape(-1)
+        if g.shape[0] != self.width * self.height:
+            raise ValueError("one gain per pixel")
+        return _load().fibar_ref_set_gain(self._h, g.ctypes.data)
+
     def stats(self) -> dict:
         s = RefStats()
         _load().fibar_ref_get_stats(self._h, ctypes.byref(s))
         return s.as_dict()
+
+
+def relative_thresholds(x, y, p, width, height):
+    """Relative contrast thresholds from the events of a calibration recording
+    (threshold appendix, Eq. (21)-(30)): with N_on_i, N_off_i the ON and OFF
+    events of pixel i and N_tot the mean over all pixels of N_on_i + N_off_i,
+    C'_i = N_tot / (N_on_i + N_off_i) and C'_on_i = N_tot / (2 N_on_i),
+    C'_off_i = N_tot / (2 N_off_i).  Reading: a pixel without events of a
+    kind gets 1 for the ratios that would divide by zero.  FP64.  Returns
+    (c_rel, c_on_rel, c_off_rel, n_on, n_off)."""
+    npx = int(width) * int(height)
+    pix = np.asarray(y, np.int64) * int(width) + np.asarray(x, np.int64)
+    on = np.asarray(p) != 0
+    n_on = np.bincount(pix[on], minlength=npx).astype(np.int64)
+    n_off = np.bincount(pix[~on], minlength=npx).astype(np.int64)
+    n_tot = n_on + n_off
+    mean = n_tot.sum() / npx
+    with np.errstate(divide="ignore"):
+        c = np.where(n_tot > 0, mean / np.maximum(n_tot, 1), 1.0)
+        c_on = np.where(n_on > 0, 0.5 * mean / np.maximum(n_on, 1), 1.0)
+        c_off = np.where(n_off > 0, 0.5 * mean / np.maximum(n_off, 1), 1.0)
+    return c, c_on, c_off, n_on, n_off
 
 
 def run_schedule(orc: Oracle, ev, sched, on_read=None, on_push=None):

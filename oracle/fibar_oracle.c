@@ -101,6 +101,7 @@ typedef struct fibar_ref {
     uint32_t* S;         /* stale list of one regulation step (PACKET mode) */
     double* Sval;
     size_t S_cap;
+    double* gain;        /* per-pixel multiplier of Eq. (6), NULL: none */
 } fibar_ref;
 
 /* Eq. (17): alpha_cut = (1 - sin w) / cos w. */
@@ -134,7 +135,7 @@ void fibar_ref_destroy(fibar_ref* c)
 {
     if (!c) return;
     free(c->pbar); free(c->L); free(c->tot); free(c->last); free(c->cnt);
-    free(c->tcnt); free(c->ring); free(c->S); free(c->Sval);
+    free(c->tcnt); free(c->ring); free(c->S); free(c->Sval); free(c->gain);
     free(c);
 }
 
@@ -298,6 +299,7 @@ int fibar_ref_push_events(fibar_ref* c, const uint16_t* x, const uint16_t* y, co
         c->k++;
         c->pbar[i] = a * c->pbar[i] + (1.0 - a) * pk;    /* Eq. (7)  */
         double d = pk - c->pbar[i];                      /* Eq. (6)  */
+        if (c->gain) d *= c->gain[i];                    /* relative threshold C'_i */
         c->L[i] = b * c->L[i] + g * d;                   /* Eq. (10) */
         c->tot[i]++;
         c->last[i] = c->k;
@@ -360,6 +362,29 @@ int fibar_ref_get_stats(const fibar_ref* c, fibar_ref_stats* s)
     s->n_regulations = c->n_reg;
     s->last_stale = c->last_stale;
     s->total_stale = c->total_stale;
+    return REF_OK;
+}
+
+/*
+ * Relative-threshold variant (Experiments, "Inter-pixel threshold
+ * variation"): the detrended increment of Eq. (6) at pixel i is multiplied
+ * by gain[i] (the relative threshold C'_i of the threshold appendix).
+ * gain == NULL removes the multipliers.  The values are copied.
+ */
+int fibar_ref_set_gain(fibar_ref* c, const double* gain)
+{
+    if (!c) return REF_E_INVALID_ARG;
+    if (!gain) {
+        free(c->gain);
+        c->gain = NULL;
+        return REF_OK;
+    }
+    uint64_t npx = (uint64_t)c->W * c->H;
+    if (!c->gain) {
+        c->gain = (double*)malloc(npx * sizeof(double));
+        if (!c->gain) return REF_E_NOMEM;
+    }
+    memcpy(c->gain, gain, npx * sizeof(double));
     return REF_OK;
 }
 

@@ -608,3 +608,69 @@ def test_invalid_arguments_rejected():
                     np.array([100], np.uint64)) == 0
     assert orc.readout(99) == oracle.E_TIME
     assert isinstance(orc.readout(100), dict)
+
+
+# ---------------------------------------------------------------------------
+# Relative-threshold variant (Experiments, "Inter-pixel threshold variation";
+# threshold appendix, Eq. (21)-(30))
+# ---------------------------------------------------------------------------
+def test_relative_thresholds_recover_the_pixels_own_thresholds():
+    """A uniform triangle wave seen by pixels with thresholds of their own:
+    the estimate from event counts matches C_i / C with C_i the harmonic mean
+    of the pixel's ON and OFF thresholds and C the harmonic mean of all C_i
+    (Eq. (23), (28)), within what one lost threshold per ramp (a reference
+    level never reaches the wave's extremes exactly) and the count
+    granularity allow; the spread of the true values is ten times that."""
+    W, H, A, periods = 32, 24, 40.0, 5
+    con, coff = eventsim.pixel_thresholds(W, H, 7)
+    ev = eventsim.calibration_stream(W, H, con, coff, periods=periods, amplitude=A)
+    c, c_on, c_off, n_on, n_off = oracle.relative_thresholds(ev.x, ev.y, ev.p, W, H)
+    Ci = 2 * con * coff / (con + coff)
+    C = 1.0 / np.mean(1.0 / Ci)
+    tol = max(con.max(), coff.max()) / A + 2.0 / (n_on + n_off).min()
+    assert np.abs(c / (Ci / C) - 1).max() <= tol
+    assert np.abs(c_on / (con / C) - 1).max() <= tol
+    assert np.abs(c_off / (coff / C) - 1).max() <= tol
+    assert np.std(Ci / C) > 5 * tol
+    # by construction the relative thresholds have a harmonic mean of one
+    assert np.mean(1.0 / c) == pytest.approx(1.0, rel=1e-14, abs=0)
+
+
+def test_relative_thresholds_of_pixels_without_events():
+    x = np.array([0, 0, 1, 1, 1], np.uint16)
+    y = np.array([0, 0, 0, 0, 0], np.uint16)
+    p = np.array([1, 0, 1, 1, 0], np.uint8)
+    c, c_on, c_off, n_on, n_off = oracle.relative_thresholds(x, y, p, 3, 1)
+    mean = 5.0 / 3.0
+    assert c.tolist() == [mean / 2, mean / 3, 1.0]
+    assert c_on.tolist() == [0.5 * mean, 0.5 * mean / 2, 1.0]
+    assert c_off.tolist() == [0.5 * mean, 0.5 * mean, 1.0]
+
+
+def test_gain_multiplies_the_detrended_increment():
+    """The variant multiplies the right-hand side of Eq. (6) by C'_i: pbar is
+    untouched, and since L is linear in the increments and starts at zero,
+    one pixel's brightness scales by its gain (temporal filter alone, and
+    with the spatial filter a uniform gain scales the whole image, blurs
+    included, while the window state stays the same)."""
+    sc, ev = small_stream(20000, seed=31)
+    W, H = 64, 48
+    gain = np.full(W * H, 1.0)
+    gain[5 * W + 7] = 1.7
+    for spatial in (False, True):
+        ref = oracle.Oracle(W, H, spatial_filter=spatial)
+        one = oracle.Oracle(W, H, spatial_filter=spatial)
+        var = oracle.Oracle(W, H, spatial_filter=spatial)
+        assert one.set_gain(np.ones(W * H)) == 0
+        assert var.set_gain(gain if not spatial else np.full(W * H, 0.8)) == 0
+        for o in (ref, one, var):
+            assert o.push(ev.x, ev.y, ev.p) == 0
+        r, r1, rv = ref.readout(0), one.readout(0), var.readout(0)
+        for key in r:
+            assert np.array_equal(r[key], r1[key]), key
+        assert np.array_equal(r["pbar"], rv["pbar"])
+        for key in ("cnt", "last", "stale", "tcnt", "tot"):
+            assert np.array_equal(r[key], rv[key]), key
+        want = r["L"] * (gain if not spatial else 0.8)
+        assert np.allclose(rv["L"], want, rtol=1e-12, atol=1e-14)
+        assert np.abs(rv["L"] - r["L"]).max() > 1e-3
