@@ -238,6 +238,9 @@ def run_config(args, torch, dev, fb, eventsim, name):
         log("%s %s: %.1f Mev/s (oracle %.2f Mev/s), parity %s"
             % (name, key, mev, m / secs / 1e6, par))
     res["distinct_pixels_per_event"] = round(u, 4)
+    if name == "vga":
+        res["relative_thresholds"] = thresholds_leg(args, torch, dev, fb, eventsim, oracle, W, H,
+                                                    ev, sched, ops, stream, n)
     if name == "sensor64x48":
         # per-event regulation (the paper's literal procedure), GPU and oracle
         ctx = fb.Context(W, H, stream=stream, regulation="event")
@@ -263,6 +266,58 @@ def run_config(args, torch, dev, fb, eventsim, name):
                                    "oracle_mev_s": round(m / secs / 1e6, 3), "parity": par}
         log("%s per-event regulation: %.1f Mev/s (oracle %.2f Mev/s), parity %s"
             % (name, n / el / 1e6, m / secs / 1e6, par))
+    return res
+
+
+def thresholds_leg(args, torch, dev, fb, eventsim, oracle, W, H, ev, sched, ops, stream, n):
+    """Relative contrast thresholds on the 640x480 sensor: a calibration
+    recording (uniform triangle wave, per-pixel thresholds 0.2 +- 0.02)
+    counted and turned into C'_i on the device, then the stream reconstructed
+    with C'_i multiplying Eq. (6)'s increment (blur on), against the oracle
+    with the same multipliers."""
+    con, coff = eventsim.pixel_thresholds(W, H, 7)
+    cal = eventsim.calibration_stream(W, H, con, coff, periods=1, amplitude=4.0)
+    cx = torch.from_numpy(cal.x.view(np.int16)).to(dev)
+    cy = torch.from_numpy(cal.y.view(np.int16)).to(dev)
+    cp = torch.from_numpy(cal.p).to(dev)
+    n_on = torch.zeros(W * H, dtype=torch.int32, device=dev)
+    n_off = torch.zeros_like(n_on)
+    c_rel = torch.empty(W * H, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    assert fb.fibar_count_polarities(cx, cy, cp, W, H, n_on, n_off, stream) == 0
+    assert fb.fibar_relative_thresholds(n_on, n_off, W, H, c_rel, None, None, stream) == 0
+    torch.cuda.synchronize()
+    cal_s = time.perf_counter() - t0
+    gain = c_rel.cpu().numpy()
+    ctx = fb.Context(W, H, stream=stream)
+    assert ctx.set_gain(c_rel) == 0
+    for _ in range(args.warmup):
+        assert ctx.reset() == 0 and ctx.submit(ops) == 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        assert ctx.reset() == 0 and ctx.submit(ops) == 0
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    assert ctx.synchronize() == 0
+    st = ctx.stats()
+    g = ctx.readout_host(int(ev.t[-1]))
+    ctx.close()
+    orc = oracle.Oracle(W, H)
+    assert orc.set_gain(gain.astype(np.float64)) == 0
+    for it in sched:
+        if it[0] == "push":   # readouts change no state
+            assert orc.push(ev.x[it[1]:it[2]], ev.y[it[1]:it[2]], ev.p[it[1]:it[2]]) == 0
+    par = final_parity(g, orc.readout(int(ev.t[-1])), True)
+    par["window_scalars_equal"] = all(st[f] == orc.stats()[f] for f in ("k", "h", "Q", "P", "T"))
+    orc.close()
+    res = {"calibration_events": len(cal), "calibration_ms": round(1e3 * cal_s, 3),
+           "calibration_mev_s": round(len(cal) / cal_s / 1e6, 1),
+           "relative_threshold_spread": round(float(gain.std()), 4),
+           "blur_on_mev_s": round(n / el / 1e6, 3), "parity": par}
+    log("vga relative thresholds: calibration of %d events in %.2f ms; reconstruction %.1f "
+        "Mev/s, parity %s" % (len(cal), 1e3 * cal_s, n / el / 1e6, par))
     return res
 
 

@@ -296,6 +296,45 @@ int fibar_set_telemetry(fibar_ctx* c, fibar_step_record* records, uint64_t capac
 int fibar_set_launch_mode(fibar_ctx* c, int mode);
 
 /*
+ * Relative contrast thresholds (Experiments, "Inter-pixel threshold
+ * variation"; the threshold appendix, Eq. (21)-(30)).  The temporal filter
+ * already balances a pixel's ON against its OFF threshold; this variant also
+ * corrects for thresholds that differ between pixels, by multiplying the
+ * right-hand side of Eq. (6) at pixel i by its relative threshold C'_i (the
+ * paper found no material gain in its application).
+ *
+ * fibar_count_polarities adds the ON and OFF events of one packet of a
+ * calibration recording (device arrays x, y, p of n events, as in
+ * fibar_packet) to per-pixel counters n_on and n_off (device, width*height
+ * uint32 each, row-major, initialised by the caller; counts wrap at 2^32).
+ * The packet is checked first and counted only if every event is in range
+ * (FIBAR_E_RANGE) with a polarity byte of 0 or 1 (FIBAR_E_POLARITY), so a
+ * rejected packet adds nothing.  It synchronises `stream` (hipStream_t, NULL
+ * = the null stream) for that check.
+ *
+ * fibar_relative_thresholds forms, with N the mean of n_on + n_off over all
+ * width*height pixels, C'_i = N / (n_on_i + n_off_i) (Eq. (30)) into c_rel,
+ * and, when the pointers are not NULL, C'_on_i = N / (2 n_on_i) and
+ * C'_off_i = N / (2 n_off_i) (device float arrays, width*height each).  A
+ * pixel without events of the kind a ratio divides by gets 1.  Computed in
+ * double precision and rounded once; queued on `stream` without waiting.
+ *
+ * fibar_set_pixel_gain makes every later push of the context multiply the
+ * increment of Eq. (6) at each pixel by gain[i] (device, width*height
+ * floats, copied in stream order into the context, so the caller may reuse
+ * the buffer once the stream has passed the call; the values are used as
+ * given, e.g. c_rel above).  NULL removes the multipliers.  Every path
+ * applies them: both regulation modes, blur on and off, and groups.
+ */
+int fibar_count_polarities(const uint16_t* x, const uint16_t* y, const uint8_t* p, size_t n,
+                           uint32_t width, uint32_t height, uint32_t* n_on, uint32_t* n_off,
+                           void* stream);
+int fibar_relative_thresholds(const uint32_t* n_on, const uint32_t* n_off, uint32_t width,
+                              uint32_t height, float* c_rel, float* c_on_rel, float* c_off_rel,
+                              void* stream);
+int fibar_set_pixel_gain(fibar_ctx* c, const float* gain);
+
+/*
  * Several independent streams advanced together.  A group holds 1..64
  * contexts (spatial filter on; the blur-off path already batches well on its
  * own); fibar_multi_submit takes one op list per context and gives the same

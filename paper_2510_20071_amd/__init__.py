@@ -97,6 +97,13 @@ _SIGNATURES = {
                                          ctypes.POINTER(ctypes.c_uint64)]),
     "fibar_set_launch_mode": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "fibar_set_telemetry": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64]),
+    "fibar_count_polarities": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_size_t, ctypes.c_uint32, ctypes.c_uint32,
+                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fibar_relative_thresholds": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+                                                 ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.c_void_p, ctypes.c_void_p]),
+    "fibar_set_pixel_gain": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 _SIGNATURES.update({
@@ -229,6 +236,26 @@ def fibar_set_kernel_timing(handle, kernel_mask: int, every: int = 1) -> int:
 def fibar_set_telemetry(handle, records, capacity: int) -> int:
     """records: a device buffer of capacity * STEP_RECORD_WORDS int64 (or None)."""
     return load().fibar_set_telemetry(handle, _addr(records), int(capacity))
+
+
+def fibar_count_polarities(x, y, p, width, height, n_on, n_off, stream=None) -> int:
+    """Device arrays: events x, y (uint16 / int16), p (uint8); counters n_on,
+    n_off (int32 / uint32, width*height each), which receive the counts."""
+    return load().fibar_count_polarities(_addr(x), _addr(y), _addr(p), int(x.shape[0]),
+                                         int(width), int(height), _addr(n_on), _addr(n_off),
+                                         stream)
+
+
+def fibar_relative_thresholds(n_on, n_off, width, height, c_rel, c_on_rel=None, c_off_rel=None,
+                              stream=None) -> int:
+    return load().fibar_relative_thresholds(_addr(n_on), _addr(n_off), int(width), int(height),
+                                            _addr(c_rel), _addr(c_on_rel), _addr(c_off_rel),
+                                            stream)
+
+
+def fibar_set_pixel_gain(handle, gain) -> int:
+    """gain: a device float buffer of width*height values, or None."""
+    return load().fibar_set_pixel_gain(handle, _addr(gain))
 
 
 STEP_RECORD_FIELDS = ("k", "h", "q", "Q", "P", "T", "stale", "n")
@@ -379,6 +406,9 @@ class Context:
         buf = fibar_readout_buf(_addr(L), _addr(pbar), _addr(stale), _addr(cnt), _addr(last),
                                 _addr(log_age), _addr(tcnt), _addr(tot), 1)
         return fibar_readout(self.handle, t, buf)
+
+    def set_gain(self, gain) -> int:
+        return fibar_set_pixel_gain(self.handle, gain)
 
     def set_telemetry(self, records, capacity: int) -> int:
         return fibar_set_telemetry(self.handle, records, capacity)

@@ -258,6 +258,7 @@ void free_ctx(fibar_ctx* c)
     (void)hipFree(c->s.px);
     (void)hipFree(c->s.pp);
     (void)hipFree(c->s.ring);
+    (void)hipFree(c->gain);
     (void)hipFree(c->s.sc);
     (void)hipFree(c->d_chunks);
     (void)hipFree(c->seg);
@@ -457,7 +458,7 @@ int run_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, uint32_t
     if (n_chunks > 0) {
         HIP_TRY(timed_launch(c, 0, [&](const LaunchTiming& tm) {
             return launch_sort_compose(c->d_chunks, n_chunks, c->seg, c->seg_count, c->scratch,
-                                       c->W, c->H, c->key_bits, c->coef, c->st, tm);
+                                       c->W, c->H, c->key_bits, c->coef, c->s.gain, c->st, tm);
         }));
     }
     uint32_t ci = 0, step = 0;

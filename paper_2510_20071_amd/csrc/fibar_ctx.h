@@ -34,6 +34,7 @@ struct fibar_ctx {
     bool region_path = false;
     // per-event regulation: packets run in one LDS-resident workgroup
     bool event_mode = false;
+    float* gain = nullptr;              // relative thresholds, once set
     uint32_t ev_cap = 0;                // LDS ring entries (a power of two)
     size_t ev_lds = 0;                  // dynamic LDS bytes of the event kernel
     fibar::RegionBuffers rb{};

@@ -11,8 +11,8 @@
 // The chain of one event depends on the one before it (window head, target,
 // counts, and the image through the blur), so a packet runs in one
 // workgroup with the whole state in LDS: brightness, polarity average,
-// per-pixel window counts, per-tile active counts, and the window's pixel
-// ids.  One wave walks the events; the others only help load and store the
+// per-pixel window counts, per-tile active counts, the window's pixel ids,
+// and the pixels' relative thresholds (1 without them).  One wave walks the events; the others only help load and store the
 // state around it.  Sensors up to kEventMaxPixels pixels, windows up to
 // kEventMaxRing - 2 events.
 #include "fibar_internal.h"
@@ -25,7 +25,7 @@ constexpr int kEvBlock = 256;
 
 struct EvLayout {
     uint32_t npx, ntiles, cap;
-    size_t off_pb, off_ring, off_cnt, off_tcnt, bytes;
+    size_t off_pb, off_gn, off_ring, off_cnt, off_tcnt, bytes;
 };
 
 __host__ __device__ inline size_t ev_align(size_t v) { return (v + 15) & ~size_t(15); }
@@ -37,7 +37,8 @@ __host__ __device__ inline EvLayout ev_layout(uint32_t W, uint32_t H, uint32_t T
     l.ntiles = TW * ((H + 1) / 2);
     l.cap = cap;
     l.off_pb = ev_align((size_t)l.npx * 4);
-    l.off_ring = l.off_pb + ev_align((size_t)l.npx * 4);
+    l.off_gn = l.off_pb + ev_align((size_t)l.npx * 4);
+    l.off_ring = l.off_gn + ev_align((size_t)l.npx * 4);
     l.off_cnt = l.off_ring + ev_align((size_t)cap * 2);
     l.off_tcnt = l.off_cnt + ev_align((size_t)l.npx * 2);
     l.bytes = l.off_tcnt + ev_align(l.ntiles);
@@ -67,6 +68,7 @@ __global__ __launch_bounds__(kEvBlock) void k_event_packet(State s, int slot,
     const EvLayout lay = ev_layout(s.W, s.H, s.TW, cap);
     float* L = reinterpret_cast<float*>(lds);
     float* pb = reinterpret_cast<float*>(lds + lay.off_pb);
+    float* gn = reinterpret_cast<float*>(lds + lay.off_gn);   // relative thresholds
     uint16_t* ring = reinterpret_cast<uint16_t*>(lds + lay.off_ring);
     uint16_t* cnt = reinterpret_cast<uint16_t*>(lds + lay.off_cnt);
     uint8_t* tcnt = lds + lay.off_tcnt;
@@ -97,6 +99,7 @@ __global__ __launch_bounds__(kEvBlock) void k_event_packet(State s, int slot,
         const PixP w = s.pp[i];
         pb[i] = w.pbar;
         cnt[i] = (uint16_t)w.cnt;
+        gn[i] = s.gain ? s.gain[i] : 1.f;
     }
     for (uint64_t e = c0.h + tid; (int64_t)e <= c0.k; e += kEvBlock)
         ring[e & cmask] = (uint16_t)s.ring[e & s.ring_mask];
@@ -145,7 +148,7 @@ __global__ __launch_bounds__(kEvBlock) void k_event_packet(State s, int slot,
                 const uint32_t ci = cnt[i], tci = tcnt[t];
                 const float pbn = fmaf(coef.alpha, pbi, coef.one_m_alpha * pk);
                 pb[i] = pbn;
-                L[i] = fmaf(coef.beta, Li, g * (pk - pbn));
+                L[i] = fmaf(coef.beta, Li, (g * gn[i]) * (pk - pbn));
                 if (lane == 0) {
                     s.px[i].last = k;
                     atomicAdd(reinterpret_cast<unsigned long long*>(&s.pp[i].tot), 1ull);

@@ -125,6 +125,7 @@ struct State {
     uint64_t q_min, q_max;
     StepRecord* tel;   // per-step telemetry (null: none), tel_cap records
     uint64_t tel_cap;
+    const float* gain; // per-pixel multiplier of Eq. (6)'s increment (null: none)
 };
 
 // Optional HIP events attached to a launch's dispatch (hipExtLaunchKernel):
@@ -255,10 +256,12 @@ inline __host__ __device__ uint32_t pop_threads(uint32_t pkt_events)
 
 
 // ---- launchers (fibar_kernels.hip) ---------------------------------------
+// `gain` (null: none) scales each pixel's composed increment (the relative
+// threshold C'_i multiplying Eq. (6)).
 hipError_t launch_sort_compose(const ChunkDesc* d_chunks, uint32_t n_chunks, SegRec* seg,
                                uint32_t* seg_count, StepScratch* scratch, uint32_t W,
-                               uint32_t H, int key_bits, Coef coef, hipStream_t st,
-                               const LaunchTiming& tm = LaunchTiming());
+                               uint32_t H, int key_bits, Coef coef, const float* gain,
+                               hipStream_t st, const LaunchTiming& tm = LaunchTiming());
 
 // In-order launches.  `slot_in` holds the last committed scalars; when
 // `prev` is not null the step it describes (with `prev_events` events) is

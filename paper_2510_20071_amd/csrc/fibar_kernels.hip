@@ -36,7 +36,8 @@ using namespace step;
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kSortThreads) void k_sort_compose(
     const ChunkDesc* __restrict__ chunks, SegRec* __restrict__ seg, uint32_t* __restrict__ seg_count,
-    StepScratch* __restrict__ scratch, uint32_t W, uint32_t H, int key_bits, Coef coef)
+    StepScratch* __restrict__ scratch, uint32_t W, uint32_t H, int key_bits, Coef coef,
+    const float* __restrict__ gain)
 {
     __shared__ uint32_t keypol[kChunk];                 // (tile-major key << 1) | polarity
     __shared__ __align__(16) uint16_t idxA[kChunk];     // permutation ping
@@ -84,6 +85,14 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_compose(
             r.u1 = acc.u1;
             r.u2 = acc.u2;
             r.key = key;
+            if (gain) {
+                // every event map of the pixel has its increment scaled by
+                // the same C'_i, and so has their composition: the pbar
+                // column of the L row and the L offset
+                const float c = gain[r.pix];
+                r.g *= c;
+                r.u2 *= c;
+            }
             out[rank] = r;
         });
     if (tid == 0) seg_count[blockIdx.x] = total;
@@ -275,12 +284,12 @@ __global__ __launch_bounds__(256) void k_readout(State s, int spatial, const Ste
 // ---------------------------------------------------------------------------
 hipError_t launch_sort_compose(const ChunkDesc* d_chunks, uint32_t n_chunks, SegRec* seg,
                                uint32_t* seg_count, StepScratch* scratch, uint32_t W,
-                               uint32_t H, int key_bits, Coef coef, hipStream_t st,
-                               const LaunchTiming& tm)
+                               uint32_t H, int key_bits, Coef coef, const float* gain,
+                               hipStream_t st, const LaunchTiming& tm)
 {
     if (n_chunks == 0) return hipSuccess;
     return launch_timed(k_sort_compose, dim3(n_chunks), dim3(kSortThreads), st, tm.start, tm.stop,
-                        d_chunks, seg, seg_count, scratch, W, H, key_bits, coef);
+                        d_chunks, seg, seg_count, scratch, W, H, key_bits, coef, gain);
 }
 
 hipError_t launch_apply(const State& s, const ChunkDesc* d_chunk, const SegRec* seg,

@@ -719,7 +719,7 @@ int run_multi_batch(fibar_multi* m, std::vector<StreamPlan>& plans, bool* done)
         const fibar_ctx* c = m->ctx[i];
         HIP_TRY(launch_sort_compose(m->d_chunks + first[i], cnt, m->seg + (size_t)first[i] * kChunk,
                                     m->seg_count + first[i], m->scratch, c->W, c->H, c->key_bits,
-                                    c->coef, m->st));
+                                    c->coef, c->s.gain, m->st));
     }
 
     // index of the last group replayed as a graph (the device round index is

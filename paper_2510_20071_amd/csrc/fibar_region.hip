@@ -268,7 +268,8 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
     const uint64_t p0 = (uint64_t)r * kRegion;
     const bool own = p0 + t < npx;
     const uint64_t gp = p0 + t;
-    const float c = 0.5f + 0.5f * coef.beta;
+    // the increment's factor, times the pixel's relative threshold if any
+    float c = 0.5f + 0.5f * coef.beta;
     float pb = 0.f, l = 0.f;
     int64_t last = -1;
     uint64_t tot = 0u;
@@ -279,6 +280,7 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
         tot = w.tot;
         l = v.L;
         last = v.last;
+        if (s.gain) c *= s.gain[gp];
     }
     const uint64_t lo = rb.base[r], hi = rb.base[r + 1];
     for (uint32_t i = t; i < n_readouts; i += kSortThreads) {

@@ -90,11 +90,19 @@ def compare_telemetry(buf, want, where=""):
     assert np.all(got[n:] == -7), "records written past the regulation steps " + where
 
 
-def run_pair(ev, W, H, sched, check_every_read=1, check_stats=True, telemetry=True, **kw):
+def run_pair(ev, W, H, sched, check_every_read=1, check_stats=True, telemetry=True, gain=None,
+             **kw):
     """Run `sched` on GPU (device packets) and oracle; compare at readouts,
-    and (spatial filter on) every step's window scalars."""
+    and (spatial filter on) every step's window scalars.  `gain`: per-pixel
+    multipliers of Eq. (6)'s increment (float32 values, given to both)."""
     ctx = make_ctx(W, H, **kw)
     orc = oracle.Oracle(W, H, **oracle_kw(kw))
+    if gain is not None:
+        torch, dev = torch_dev()
+        g32 = np.ascontiguousarray(gain, np.float32)
+        gd = torch.from_numpy(g32).to(dev)
+        assert ctx.set_gain(gd) == fb.FIBAR_OK
+        assert orc.set_gain(g32.astype(np.float64)) == 0
     gx, gy, gp = to_device(ev)
     spatial = kw.get("spatial_filter", True)
     tel, want = None, []

@@ -112,3 +112,14 @@ def test_event_regulation_limits_without_gpu():
     p = fb.fibar_default_params()
     p.regulation = 2
     assert fb.fibar_create(64, 48, p)[0] == fb.FIBAR_E_INVALID_ARG
+
+
+def test_threshold_entry_points_reject_bad_arguments_without_gpu():
+    lib = fb.load()
+    assert lib.fibar_count_polarities(None, None, None, 0, 4, 4, None, None, None) == \
+        fb.FIBAR_E_INVALID_ARG
+    assert lib.fibar_count_polarities(None, None, None, 0, 0, 4, 8, 8, None) == \
+        fb.FIBAR_E_INVALID_ARG
+    assert lib.fibar_relative_thresholds(None, None, 4, 4, None, None, None, None) == \
+        fb.FIBAR_E_INVALID_ARG
+    assert lib.fibar_set_pixel_gain(None, None) == fb.FIBAR_E_INVALID_ARG
