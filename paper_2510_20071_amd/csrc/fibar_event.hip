@@ -116,13 +116,21 @@ __global__ __launch_bounds__(kEvBlock) void k_event_packet(State s, int slot,
     __syncthreads();
 
     if (tid < 64) {
-        // wave 0: the events in order, every lane computing the same values
+        // wave 0 loads the events, 64 per block with the next block in
+        // flight; lane 0 alone walks them (one lane issues every LDS access
+        // of the walk).  Inside a packet the window head, the newest index,
+        // the counts and the target fit 32 bits: indices are taken relative
+        // to the head the packet starts from.
         const uint32_t lane = tid;
-        int64_t k = c0.k;
-        uint64_t h = c0.h, Q = c0.Q, P = c0.P, T = c0.T, total = c0.total_stale;
-        uint32_t st = 0;
+        const uint64_t base = c0.h;
+        const uint32_t bm = (uint32_t)(base & cmask);
+        uint32_t hl = 0;                                     // head - base
+        uint32_t kq = (uint32_t)((uint64_t)(c0.k + 1) - base);   // newest + 1 - base
+        uint32_t Q = (uint32_t)c0.Q, P = (uint32_t)c0.P, T = (uint32_t)c0.T;
+        uint32_t st = 0, total = 0;
+        const uint32_t num4 = 4u * s.fill_num, den = s.fill_den;
+        const uint32_t q_min = (uint32_t)s.q_min, q_max = (uint32_t)s.q_max;
         const float g = 0.5f * (1.0f + coef.beta);
-        // 64 events per block in the lanes' registers, the next block in flight
         auto load_block = [&](uint32_t b, uint32_t& xy, uint32_t& pol) {
             const uint32_t e = b * 64 + lane;
             const uint32_t ec = e < n ? e : n - 1;
@@ -136,23 +144,20 @@ __global__ __launch_bounds__(kEvBlock) void k_event_packet(State s, int slot,
             uint32_t nxt_xy = 0, nxt_p = 0;
             if (b + 1 < nblocks) load_block(b + 1, nxt_xy, nxt_p);
             const uint32_t m = n - b * 64 < 64 ? n - b * 64 : 64;
-            for (uint32_t e = 0; e < m; ++e) {
+            for (uint32_t e = 0; lane == 0 && e < m; ++e) {
                 const uint32_t xy = __builtin_amdgcn_readlane(cur_xy, e);
                 const uint32_t pol = __builtin_amdgcn_readlane(cur_p, e);
                 const uint32_t x = xy & 0xffffu, y = xy >> 16;
                 const uint32_t i = y * W + x, t = (y >> 1) * TW + (x >> 1);
-                ++k;
                 // step 1: the temporal filter (Eq. (7), then (6) and (10))
                 const float pk = pol ? 1.f : -1.f;
-                const float pbi = pb[i], Li = L[i];
+                const float pbi = pb[i], Li = L[i], gi = gn[i];
                 const uint32_t ci = cnt[i], tci = tcnt[t];
                 const float pbn = fmaf(coef.alpha, pbi, coef.one_m_alpha * pk);
                 pb[i] = pbn;
-                L[i] = fmaf(coef.beta, Li, (g * gn[i]) * (pk - pbn));
-                if (lane == 0) {
-                    s.px[i].last = k;
-                    atomicAdd(reinterpret_cast<unsigned long long*>(&s.pp[i].tot), 1ull);
-                }
+                L[i] = fmaf(coef.beta, Li, (g * gi) * (pk - pbn));
+                s.px[i].last = c0.k + 1 + (int64_t)(b * 64 + e);
+                atomicAdd(reinterpret_cast<unsigned long long*>(&s.pp[i].tot), 1ull);
                 // step 2: the event enters the window
                 if (ci == 0) {
                     ++P;
@@ -160,13 +165,14 @@ __global__ __launch_bounds__(kEvBlock) void k_event_packet(State s, int slot,
                     tcnt[t] = (uint8_t)(tci + 1);
                 }
                 cnt[i] = (uint16_t)(ci + 1);
-                ring[(uint64_t)k & cmask] = (uint16_t)i;
+                ring[(bm + kq) & cmask] = (uint16_t)i;
+                ++kq;
                 // step 3: old events leave; a pixel without window events
                 // goes stale and is blurred from the current image
                 st = 0;
-                while ((uint64_t)(k + 1) - h > Q) {
-                    const uint32_t j = ring[h & cmask];
-                    ++h;
+                while (kq - hl > Q) {
+                    const uint32_t j = ring[(bm + hl) & cmask];
+                    ++hl;
                     const uint32_t yj = ev_row(j, W, inv_w), xj = j - yj * W;
                     const uint32_t xs[3] = {xj > 0 ? xj - 1 : 0, xj, xj + 1 < W ? xj + 1 : W - 1};
                     const uint32_t ys[3] = {yj > 0 ? yj - 1 : 0, yj, yj + 1 < H ? yj + 1 : H - 1};
@@ -189,11 +195,17 @@ __global__ __launch_bounds__(kEvBlock) void k_event_packet(State s, int slot,
                         ++st;
                     }
                 }
-                // the target of Eq. (20) from the integer counts
+                // the target of Eq. (20) from the integer counts:
+                // floor(q num 4 T / (den P)); the numerator is below 2^53 and
+                // the divisor below 2^32, so the double quotient is within
+                // one unit and one integer check fixes it
                 if (P > 0) {
-                    const uint64_t q = (uint64_t)(k + 1) - h;
-                    uint64_t Qn = step::target_div(q, s.fill_num, T, (uint64_t)s.fill_den * P, s.q_max);
-                    Q = Qn < s.q_min ? s.q_min : Qn;
+                    const uint64_t num = (uint64_t)(kq - hl) * T * num4;
+                    const uint64_t dv = (uint64_t)den * P;
+                    uint64_t v = (uint64_t)((double)num / (double)dv);
+                    if (v * dv > num) --v;
+                    else if ((v + 1) * dv <= num) ++v;
+                    Q = v > q_max ? q_max : (v < q_min ? q_min : (uint32_t)v);
                 }
                 total += st;
             }
@@ -202,18 +214,18 @@ __global__ __launch_bounds__(kEvBlock) void k_event_packet(State s, int slot,
         }
         if (lane == 0) {
             DevScalars r = c0;
-            r.k = k;
-            r.h = h;
+            r.k = c0.k + (int64_t)n;
+            r.h = base + hl;
             r.Q = Q;
             r.P = P;
             r.T = T;
             r.n_reg = c0.n_reg + n;
             r.last_stale = st;
-            r.total_stale = total;
+            r.total_stale = c0.total_stale + total;
             r.stepped = 1;
             s.sc[slot] = r;
-            fin_h = h;
-            fin_k = k;
+            fin_h = r.h;
+            fin_k = r.k;
         }
     }
     __syncthreads();
