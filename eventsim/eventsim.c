@@ -344,7 +344,7 @@ int64_t sim_generate(const sim_params* p, uint16_t* xs, uint16_t* ys, uint8_t* p
             }
         }
         if (all.oom) goto done;
-        qsort(all.v, all.n, sizeof(ev_t), ev_cmp);
+        if (all.n > 1) qsort(all.v, all.n, sizeof(ev_t), ev_cmp);   /* a step may emit nothing */
         for (size_t j = 0; j < all.n && produced < p->n_events; ++j, ++produced) {
             xs[produced] = (uint16_t)(all.v[j].pix % (uint32_t)W);
             ys[produced] = (uint16_t)(all.v[j].pix / (uint32_t)W);
