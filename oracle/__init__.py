@@ -39,7 +39,8 @@ class RefParams(ctypes.Structure):
     _fields_ = [("t_cut", ctypes.c_double), ("fill_num", ctypes.c_uint32),
                 ("fill_den", ctypes.c_uint32), ("q_min", ctypes.c_uint32),
                 ("q_max", ctypes.c_uint32), ("spatial_filter", ctypes.c_uint32),
-                ("regulation", ctypes.c_uint32)]
+                ("regulation", ctypes.c_uint32), ("region", ctypes.c_uint32),
+                ("age_max", ctypes.c_uint64)]
 
 
 class RefStats(ctypes.Structure):
@@ -72,6 +73,7 @@ def _load():
                                                ctypes.POINTER(ctypes.c_double)]
         lib.fibar_ref_coefficients.restype = None
         lib.fibar_ref_set_gain.argtypes = [vp, vp]
+        lib.fibar_ref_region_stats.argtypes = [vp, vp, vp, vp, vp, vp]
         _lib = lib
     return _lib
 
@@ -91,7 +93,7 @@ class Oracle:
     """One FP64 reconstruction context."""
 
     def __init__(self, width, height, t_cut=40.0, fill=(1, 2), q_min=64, q_max=0,
-                 spatial_filter=True, regulation="packet"):
+                 spatial_filter=True, regulation="packet", region=0, age_max=0):
         lib = _load()
         prm = RefParams()
         lib.fibar_ref_default_params(ctypes.byref(prm))
@@ -101,6 +103,8 @@ class Oracle:
         prm.q_max = int(q_max)
         prm.spatial_filter = 1 if spatial_filter else 0
         prm.regulation = REG_EVENT if regulation == "event" else REG_PACKET
+        prm.region = int(region)
+        prm.age_max = int(age_max)
         h = ctypes.c_void_p()
         rc = lib.fibar_ref_create(int(width), int(height), ctypes.byref(prm), ctypes.byref(h))
         if rc != OK:
@@ -109,6 +113,10 @@ class Oracle:
         self.width, self.height = int(width), int(height)
         self.tiles_w, self.tiles_h = (self.width + 1) // 2, (self.height + 1) // 2
         self.spatial_filter = bool(spatial_filter)
+        self.region = int(region)
+        if self.region:
+            self.regions_w = (self.width + self.region - 1) // self.region
+            self.regions_h = (self.height + self.region - 1) // self.region
 
     def close(self):
         if self._h:
@@ -156,6 +164,17 @@ class Oracle:
         if g.shape[0] != self.width * self.height:
             raise ValueError("one gain per pixel")
         return _load().fibar_ref_set_gain(self._h, g.ctypes.data)
+
+    def region_stats(self) -> dict:
+        """Per-tile scalars (per-tile queues): q, Q, P, T and the global index
+        of each tile's oldest window event (k + 1 if empty), row-major."""
+        n = self.regions_w * self.regions_h
+        out = {k: np.empty(n, np.uint64) for k in ("q", "Q", "P", "T", "front")}
+        rc = _load().fibar_ref_region_stats(self._h, *(out[k].ctypes.data for k in
+                                                         ("q", "Q", "P", "T", "front")))
+        if rc != OK:
+            raise ValueError("not a per-tile-queue oracle")
+        return out
 
     def stats(self) -> dict:
         s = RefStats()

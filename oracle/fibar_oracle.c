@@ -69,6 +69,8 @@ typedef struct {
     uint32_t q_min, q_max;
     uint32_t spatial_filter;
     uint32_t regulation;
+    uint32_t region;     /* per-tile queues: tile side in pixels (even), 0 = one queue */
+    uint64_t age_max;    /* per-tile queues: events older than this leave (0 = W*H) */
 } fibar_ref_params;
 
 typedef struct {
@@ -102,7 +104,18 @@ typedef struct fibar_ref {
     double* Sval;
     size_t S_cap;
     double* gain;        /* per-pixel multiplier of Eq. (6), NULL: none */
+    /* per-tile queues (region > 0): one FIFO of (global index, pixel) per tile */
+    uint32_t RW, RH;     /* tiles across and down */
+    struct ref_region* reg;
 } fibar_ref;
+
+typedef struct ref_region {
+    uint64_t* ev;        /* global indices of the tile's window events, [head, tail) */
+    uint32_t* pix;
+    size_t head, tail, cap;
+    uint64_t Q, P, T;
+    uint64_t npix;       /* pixels of the tile (edge tiles are cut by the image) */
+} ref_region;
 
 /* Eq. (17): alpha_cut = (1 - sin w) / cos w. */
 static double coef_alpha(double w) { return (1.0 - sin(w)) / cos(w); }
@@ -122,6 +135,8 @@ void fibar_ref_default_params(fibar_ref_params* p)
     p->q_max = 0;         /* 0 -> number of pixels */
     p->spatial_filter = 1;
     p->regulation = REF_REG_PACKET;
+    p->region = 0;
+    p->age_max = 0;
 }
 
 void fibar_ref_coefficients(double t_cut, double* alpha, double* beta)
@@ -136,6 +151,13 @@ void fibar_ref_destroy(fibar_ref* c)
     if (!c) return;
     free(c->pbar); free(c->L); free(c->tot); free(c->last); free(c->cnt);
     free(c->tcnt); free(c->ring); free(c->S); free(c->Sval); free(c->gain);
+    if (c->reg) {
+        for (uint64_t r = 0; r < (uint64_t)c->RW * c->RH; ++r) {
+            free(c->reg[r].ev);
+            free(c->reg[r].pix);
+        }
+        free(c->reg);
+    }
     free(c);
 }
 
@@ -153,6 +175,11 @@ int fibar_ref_create(uint32_t W, uint32_t H, const fibar_ref_params* prm, fibar_
     uint64_t npx = (uint64_t)W * H;
     if (p.q_max == 0) p.q_max = (uint32_t)(npx > 0xffffffffu ? 0xffffffffu : npx);
     if (p.q_min == 0 || p.q_min > p.q_max) return REF_E_INVALID_ARG;
+    /* per-tile queues: even tile sides (whole 2x2 fill-ratio cells), packet
+     * regulation with the spatial filter */
+    if (p.region && ((p.region & 1u) || p.regulation != REF_REG_PACKET || !p.spatial_filter))
+        return REF_E_INVALID_ARG;
+    if (p.age_max == 0) p.age_max = npx;
 
     fibar_ref* c = (fibar_ref*)calloc(1, sizeof(fibar_ref));
     if (!c) return REF_E_NOMEM;
@@ -177,6 +204,23 @@ int fibar_ref_create(uint32_t W, uint32_t H, const fibar_ref_params* prm, fibar_
     c->k = -1;
     c->h = 0;
     c->Q = p.q_max;
+    if (p.region) {
+        c->RW = (W + p.region - 1) / p.region;
+        c->RH = (H + p.region - 1) / p.region;
+        c->reg = (ref_region*)calloc((size_t)c->RW * c->RH, sizeof(ref_region));
+        if (!c->reg) {
+            fibar_ref_destroy(c);
+            return REF_E_NOMEM;
+        }
+        for (uint32_t ry = 0; ry < c->RH; ++ry)
+            for (uint32_t rx = 0; rx < c->RW; ++rx) {
+                ref_region* g = &c->reg[(size_t)ry * c->RW + rx];
+                uint32_t w = W - rx * p.region < p.region ? W - rx * p.region : p.region;
+                uint32_t h = H - ry * p.region < p.region ? H - ry * p.region : p.region;
+                g->npix = (uint64_t)w * h;
+                g->Q = g->npix;
+            }
+    }
     *out = c;
     return REF_OK;
 }
@@ -280,6 +324,126 @@ static int regulate(fibar_ref* c)
     return REF_OK;
 }
 
+/*
+ * Per-tile queues (Limitations: event queues operated separately for each
+ * tile of the image).  Readings, the paper leaving them open: tiles are
+ * region x region pixels (even, so the 2x2 cells of Eq. (19) never straddle
+ * two tiles; edge tiles are cut by the image); each tile keeps its own FIFO
+ * window of its own events, its own active pixel and 2x2 cell counts, and its
+ * own target of Eq. (20) from them, clamped to [min(q_min, n), n] with n the
+ * tile's pixels and starting at n; a tile that no longer registers events
+ * still advances, because an event also leaves once age_max newer events
+ * have arrived anywhere on the sensor (0 = W*H, the single queue's bound).
+ * Regulation is per pushed packet: after the packet's events, every tile
+ * pops, all pixels gone stale are blurred from the same pre-blur image, and
+ * every tile with an active pixel updates its target.
+ */
+static uint32_t region_of(const fibar_ref* c, uint32_t i)
+{
+    uint32_t x = i % c->W, y = i / c->W;
+    return (y / c->prm.region) * c->RW + x / c->prm.region;
+}
+
+static int region_push(ref_region* g, uint64_t e, uint32_t pix)
+{
+    if (g->tail == g->cap) {
+        size_t live = g->tail - g->head;
+        if (g->head > 0 && live < g->cap / 2) {
+            memmove(g->ev, g->ev + g->head, live * sizeof(uint64_t));
+            memmove(g->pix, g->pix + g->head, live * sizeof(uint32_t));
+        } else {
+            size_t nc = g->cap ? 2 * g->cap : 64;
+            uint64_t* ne = (uint64_t*)malloc(nc * sizeof(uint64_t));
+            uint32_t* np = (uint32_t*)malloc(nc * sizeof(uint32_t));
+            if (!ne || !np) { free(ne); free(np); return REF_E_NOMEM; }
+            if (live) {
+                memcpy(ne, g->ev + g->head, live * sizeof(uint64_t));
+                memcpy(np, g->pix + g->head, live * sizeof(uint32_t));
+            }
+            free(g->ev); free(g->pix);
+            g->ev = ne; g->pix = np; g->cap = nc;
+        }
+        g->head = 0;
+        g->tail = live;
+    }
+    g->ev[g->tail] = e;
+    g->pix[g->tail] = pix;
+    g->tail++;
+    return REF_OK;
+}
+
+static int regulate_regions(fibar_ref* c)
+{
+    c->last_stale = 0;
+    const uint64_t nreg = (uint64_t)c->RW * c->RH;
+    for (uint64_t r = 0; r < nreg; ++r) {
+        ref_region* g = &c->reg[r];
+        while (g->tail > g->head &&
+               (g->tail - g->head > g->Q || (uint64_t)c->k - g->ev[g->head] >= c->prm.age_max)) {
+            uint32_t j = g->pix[g->head];
+            g->head++;
+            c->cnt[j]--;
+            if (c->cnt[j] == 0) {
+                g->P--;
+                uint32_t t = tile_of(c, j);
+                c->tcnt[t]--;
+                if (c->tcnt[t] == 0) g->T--;
+                int rc = stale_append(c, j);
+                if (rc) return rc;
+                c->last_stale++;
+            }
+        }
+    }
+    for (uint64_t s = 0; s < c->last_stale; ++s) c->Sval[s] = blur_at(c, c->S[s]);
+    for (uint64_t s = 0; s < c->last_stale; ++s) c->L[c->S[s]] = c->Sval[s];
+    c->total_stale += c->last_stale;
+    uint64_t q_all = 0, P_all = 0, T_all = 0, Q_all = 0;
+    for (uint64_t r = 0; r < nreg; ++r) {
+        ref_region* g = &c->reg[r];
+        uint64_t q = g->tail - g->head;
+        if (g->P > 0) {
+            unsigned __int128 num = (unsigned __int128)q * c->prm.fill_num * 4u * g->T;
+            unsigned __int128 den = (unsigned __int128)c->prm.fill_den * g->P;
+            unsigned __int128 v = num / den;
+            uint64_t lo = c->prm.q_min < g->npix ? c->prm.q_min : g->npix;
+            uint64_t Q = v > g->npix ? g->npix : (uint64_t)v;
+            if (Q < lo) Q = lo;
+            g->Q = Q;
+        }
+        q_all += q;
+        P_all += g->P;
+        T_all += g->T;
+        Q_all += g->Q;
+    }
+    /* whole-sensor figures: q, Q, P and T summed over tiles, h = k + 1 - q */
+    c->h = (uint64_t)(c->k + 1) - q_all;
+    c->Q = Q_all;
+    c->P = P_all;
+    c->T = T_all;
+    c->n_reg++;
+    return REF_OK;
+}
+
+/* Per-tile scalars after the last step (per-tile queues only): window
+ * length, target, active pixels and cells, and the global index of the
+ * oldest window event (k + 1 when the window is empty).  Arrays of
+ * tiles_x * tiles_y entries, row-major; any pointer may be NULL. */
+int fibar_ref_region_stats(const fibar_ref* c, uint64_t* q, uint64_t* Q, uint64_t* P, uint64_t* T,
+                           uint64_t* front)
+{
+    if (!c || !c->reg) return REF_E_INVALID_ARG;
+    const uint64_t nreg = (uint64_t)c->RW * c->RH;
+    for (uint64_t r = 0; r < nreg; ++r) {
+        const ref_region* g = &c->reg[r];
+        if (q) q[r] = g->tail - g->head;
+        if (Q) Q[r] = g->Q;
+        if (P) P[r] = g->P;
+        if (T) T[r] = g->T;
+        if (front) front[r] = g->tail > g->head ? g->ev[g->head] : (uint64_t)(c->k + 1);
+    }
+    return REF_OK;
+}
+
 int fibar_ref_push_events(fibar_ref* c, const uint16_t* x, const uint16_t* y, const uint8_t* p,
                           const uint64_t* t, size_t n)
 {
@@ -303,7 +467,18 @@ int fibar_ref_push_events(fibar_ref* c, const uint16_t* x, const uint16_t* y, co
         c->L[i] = b * c->L[i] + g * d;                   /* Eq. (10) */
         c->tot[i]++;
         c->last[i] = c->k;
-        if (c->prm.spatial_filter) {
+        if (c->prm.spatial_filter && c->reg) {
+            ref_region* g = &c->reg[region_of(c, i)];
+            if (c->cnt[i] == 0) {
+                g->P++;
+                uint32_t tl = tile_of(c, i);
+                if (c->tcnt[tl] == 0) g->T++;
+                c->tcnt[tl]++;
+            }
+            c->cnt[i]++;
+            int rc = region_push(g, (uint64_t)c->k, i);
+            if (rc) return rc;
+        } else if (c->prm.spatial_filter) {
             if (c->cnt[i] == 0) {
                 c->P++;
                 uint32_t tl = tile_of(c, i);
@@ -320,7 +495,7 @@ int fibar_ref_push_events(fibar_ref* c, const uint16_t* x, const uint16_t* y, co
         }
     }
     if (c->prm.spatial_filter && c->prm.regulation == REF_REG_PACKET) {
-        int rc = regulate(c);
+        int rc = c->reg ? regulate_regions(c) : regulate(c);
         if (rc) return rc;
     }
     if (t && t[n - 1] > c->t_hi) c->t_hi = t[n - 1];

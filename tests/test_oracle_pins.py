@@ -674,3 +674,134 @@ def test_gain_multiplies_the_detrended_increment():
         want = r["L"] * (gain if not spatial else 0.8)
         assert np.allclose(rv["L"], want, rtol=1e-12, atol=1e-14)
         assert np.abs(rv["L"] - r["L"]).max() > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# Per-tile queues (Limitations: event queues operated separately per tile)
+# ---------------------------------------------------------------------------
+def test_one_tile_covering_the_sensor_is_the_single_queue():
+    """A tile that covers the whole sensor, with an age limit never reached,
+    is exactly FIBAR's single queue: every output after every packet."""
+    sc, ev = small_stream(30000, seed=41)
+    W, H = 64, 48
+    one = oracle.Oracle(W, H)
+    til = oracle.Oracle(W, H, region=64, age_max=1 << 62)
+    for a in range(0, len(ev), 777):
+        b = min(len(ev), a + 777)
+        for o in (one, til):
+            assert o.push(ev.x[a:b], ev.y[a:b], ev.p[a:b]) == 0
+        assert til.stats() == one.stats()
+        if a % (777 * 8) == 0:
+            r1, r2 = one.readout(0), til.readout(0)
+            for key in r1:
+                assert np.array_equal(r1[key], r2[key]), key
+    assert one.stats()["total_stale"] > 1000
+
+
+class BruteTiles:
+    """Each tile's window recounted from the list of its events after every
+    packet: events leave from the front while the window is longer than the
+    tile's target or its oldest event is age_max or more events old."""
+
+    def __init__(self, W, H, R, q_min, age_max, num, den):
+        self.W, self.H, self.R = W, H, R
+        self.RW, self.RH = -(-W // R), -(-H // R)
+        self.q_min, self.age_max, self.num, self.den = q_min, age_max, num, den
+        self.win = [[] for _ in range(self.RW * self.RH)]   # (global index, pixel)
+        self.npix = []
+        for ry in range(self.RH):
+            for rx in range(self.RW):
+                self.npix.append(min(R, W - rx * R) * min(R, H - ry * R))
+        self.Q = list(self.npix)
+        self.k = -1
+
+    def region(self, i):
+        return (i // self.W // self.R) * self.RW + (i % self.W) // self.R
+
+    def push(self, pixels):
+        for i in pixels:
+            self.k += 1
+            self.win[self.region(i)].append((self.k, i))
+        for r, w in enumerate(self.win):
+            while w and (len(w) > self.Q[r] or self.k - w[0][0] >= self.age_max):
+                w.pop(0)
+            P = len(set(i for _, i in w))
+            T = len(set((i // self.W // 2, (i % self.W) // 2) for _, i in w))
+            if P:
+                v = (len(w) * self.num * 4 * T) // (self.den * P)
+                self.Q[r] = max(min(self.q_min, self.npix[r]), min(self.npix[r], v))
+
+    def stats(self):
+        q = [len(w) for w in self.win]
+        P = [len(set(i for _, i in w)) for w in self.win]
+        T = [len(set((i // self.W // 2, (i % self.W) // 2) for _, i in w)) for w in self.win]
+        front = [w[0][0] if w else self.k + 1 for w in self.win]
+        return q, list(self.Q), P, T, front
+
+    def cnt(self):
+        c = np.zeros(self.W * self.H, np.int64)
+        for w in self.win:
+            for _, i in w:
+                c[i] += 1
+        return c
+
+
+@pytest.mark.parametrize("W,H,R,age", [(6, 6, 2, 40), (8, 4, 4, 1000), (7, 5, 4, 25)])
+def test_tiles_against_brute_force(W, H, R, age):
+    rng = np.random.default_rng(W * 10 + H + R)
+    n = 2500
+    pix, cur = [], 0
+    for _ in range(n):
+        if rng.random() < 0.3:
+            cur = int(rng.integers(0, W * H))
+        pix.append(cur)
+    q_min = 2
+    orc = oracle.Oracle(W, H, q_min=q_min, region=R, age_max=age)
+    bt = BruteTiles(W, H, R, q_min, age, 1, 2)
+    seen = np.zeros(W * H, bool)
+    pos = 0
+    while pos < n:
+        m = int(min(n - pos, rng.integers(1, 30)))
+        chunk = pix[pos:pos + m]
+        pos += m
+        xs = np.array([i % W for i in chunk], np.uint16)
+        ys = np.array([i // W for i in chunk], np.uint16)
+        assert orc.push(xs, ys, np.ones(m, np.uint8)) == 0
+        bt.push(chunk)
+        seen[chunk] = True
+        rs = orc.region_stats()
+        q, Q, P, T, front = bt.stats()
+        assert rs["q"].tolist() == q and rs["Q"].tolist() == Q
+        assert rs["P"].tolist() == P and rs["T"].tolist() == T
+        assert rs["front"].tolist() == front
+        r = orc.readout(0)
+        c = bt.cnt()
+        assert np.array_equal(r["cnt"].astype(np.int64), c)
+        assert np.array_equal(r["stale"] == 1, seen & (c == 0))
+        s = orc.stats()
+        assert (s["q"], s["P"], s["T"]) == (sum(q), sum(P), sum(T))
+
+
+def test_slow_feature_keeps_its_events_in_its_own_tile():
+    """The paper's example: with one queue, a slowly moving feature's events
+    are pushed out by a fast one's and it is blurred early; with a queue per
+    tile the slow pixel stays active as long as its events are younger than
+    the age limit."""
+    W, H = 8, 8
+    seq = []
+    fast = [0, 1, 9, 10, 8, 2]            # a few pixels of the top-left 4x4 tile
+    for e in range(6000):
+        seq.append(fast[e % len(fast)] if e % 50 else 6)   # pixel (6, 0): top-right tile
+    xs = np.array([i % W for i in seq], np.uint16)
+    ys = np.array([i // W for i in seq], np.uint16)
+    ps = np.ones(len(seq), np.uint8)
+    blurred = {}
+    for name, kw in (("single", {}), ("tiles", {"region": 4})):
+        o = oracle.Oracle(W, H, q_min=4, **kw)
+        stale_slow = 0
+        for a in range(0, len(seq), 10):
+            assert o.push(xs[a:a + 10], ys[a:a + 10], ps[a:a + 10]) == 0
+            stale_slow += int(o.readout(0)["stale"][6])
+        blurred[name] = stale_slow
+    assert blurred["single"] > 100
+    assert blurred["tiles"] == 0
