@@ -269,6 +269,48 @@ def run_config(args, torch, dev, fb, eventsim, name):
     return res
 
 
+def tiles_leg(args, torch, dev, fb, W, H, ev, sched, ops, n_ops, stream, n):
+    """The hd720 stream with per-tile event queues (tiles of --tile pixels,
+    age limit W x H events): GPU Mev/s, and the final state and every tile's
+    window against the oracle's per-tile queues."""
+    import oracle
+    R = args.tile
+    lib = fb.load()
+    ctx = fb.Context(W, H, stream=stream, region=R)
+    steps = max(1, min(args.steps, 5))
+    for _ in range(max(1, min(args.warmup, 2))):
+        assert ctx.reset() == 0 and lib.fibar_submit(ctx.handle, ops, n_ops) == 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        assert ctx.reset() == 0 and lib.fibar_submit(ctx.handle, ops, n_ops) == 0
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    assert ctx.synchronize() == 0
+    st = ctx.stats()
+    g = ctx.readout_host(int(ev.t[-1]))
+    gt = ctx.tile_stats()
+    ctx.close()
+    res = {"tile": R, "tiles": int(gt["q"].shape[0]), "age_max": W * H,
+           "mev_s": round(n / el / 1e6, 2), "ms_per_step": round(1e3 * el, 3), "steps": steps}
+    if not args.no_cpu_baseline:
+        orc = oracle.Oracle(W, H, region=R)
+        t0 = time.perf_counter()
+        for it in sched:
+            if it[0] == "push":
+                assert orc.push(ev.x[it[1]:it[2]], ev.y[it[1]:it[2]], ev.p[it[1]:it[2]]) == 0
+        res["oracle_mev_s"] = round(n / (time.perf_counter() - t0) / 1e6, 3)
+        par = final_parity(g, orc.readout(int(ev.t[-1])), True)
+        ot = orc.region_stats()
+        par["tile_windows_equal"] = all(np.array_equal(gt[k], ot[k]) for k in gt)
+        par["scalars_equal"] = all(st[f] == orc.stats()[f] for f in ("k", "q", "Q", "P", "T"))
+        orc.close()
+        res["parity"] = par
+        res["total_stale"] = st["total_stale"]
+    log("hd720 per-tile queues (tiles of %d): %.1f Mev/s, %s" % (R, res["mev_s"], res.get("parity")))
+    return res
+
+
 def thresholds_leg(args, torch, dev, fb, eventsim, oracle, W, H, ev, sched, ops, stream, n):
     """Relative contrast thresholds on the 640x480 sensor: a calibration
     recording (uniform triangle wave, per-pixel thresholds 0.2 +- 0.02)
@@ -799,6 +841,9 @@ def main():
     ap.add_argument("--no-multi", action="store_true", help="skip the batched-streams measurement")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the 64x48 and 640x480 configurations")
+    ap.add_argument("--no-tiles", action="store_true",
+                    help="skip the per-tile-queue measurement")
+    ap.add_argument("--tile", type=int, default=32, help="tile side of the per-tile-queue leg")
     ap.add_argument("--only-configs", action="store_true",
                     help="run only the 64x48 and 640x480 configurations")
     ap.add_argument("--only-multi", action="store_true",
@@ -1018,6 +1063,10 @@ def main():
                 parity["blur_off"] = final_parity(final_off, orc.readout(int(ev.t[-1])), False)
             orc.close()
 
+    tiles = None
+    if not args.no_tiles:
+        tiles = tiles_leg(args, torch, dev, fb, W, H, ev, sched, ops, n_ops, stream, n)
+
     configs = None
     if not args.no_configs:
         configs = {name: run_config(args, torch, dev, fb, eventsim, name)
@@ -1056,6 +1105,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": parity,
+        "per_tile_queues": tiles,
         "configs": configs,
         "batched_streams": batched,
         "learned_fill": learned_fill,

@@ -82,6 +82,22 @@ typedef enum {
  *   max_packet     largest packet accepted by fibar_push_events (events),
  *                  1 .. 1048576; sizes device buffers.  Default 65536.
  *   stream         hipStream_t all work is ordered on; NULL = the null stream.
+ *   region         per-tile event queues (Limitations: event queues operated
+ *                  separately for each tile of the image): 0 (the default)
+ *                  keeps the paper's single queue; an even value 2 .. 32
+ *                  gives every tile of region x region pixels (edge tiles cut
+ *                  by the image) its own window, active pixel and 2x2-cell
+ *                  counts and target of Eq. (20), clamped to
+ *                  [min(q_min, n), n] for a tile of n pixels (q_max does not
+ *                  apply).  Needs spatial_filter = 1, FIBAR_REG_PACKET and at
+ *                  most 16384 tiles; device memory grows by 8 bytes x tiles x
+ *                  the power of two >= region^2 + max_packet (each tile's
+ *                  window ring).  Telemetry and groups are not available for
+ *                  such contexts (FIBAR_E_UNSUPPORTED).
+ *   age_max        with per-tile queues, an event also leaves its tile's
+ *                  window once age_max newer events have arrived anywhere on
+ *                  the sensor, so that tiles without new events still advance
+ *                  (the paper leaves this open); 0 = width*height.
  */
 typedef struct {
     double   t_cut;
@@ -92,6 +108,8 @@ typedef struct {
     uint32_t regulation;
     uint32_t max_packet;
     void*    stream;
+    uint32_t region;
+    uint64_t age_max;
 } fibar_params;
 
 void fibar_default_params(fibar_params* p);
@@ -333,6 +351,19 @@ int fibar_relative_thresholds(const uint32_t* n_on, const uint32_t* n_off, uint3
                               uint32_t height, float* c_rel, float* c_on_rel, float* c_off_rel,
                               void* stream);
 int fibar_set_pixel_gain(fibar_ctx* c, const float* gain);
+
+/*
+ * Per-tile queues: each tile's scalars after the last regulation step, into
+ * host arrays of tiles_x * tiles_y entries (row-major; tiles_x =
+ * ceil(width / region), tiles_y = ceil(height / region)); any pointer may be
+ * NULL.  q: window length, Q: target, P: active pixels, T: active 2x2 cells,
+ * front: global index of the tile's oldest window event (k + 1 when the
+ * window is empty).  Synchronises the stream.  FIBAR_E_UNSUPPORTED for a
+ * context with one queue.  fibar_get_stats reports q, Q, P and T summed over
+ * the tiles and h = k + 1 - q for such contexts.
+ */
+int fibar_tile_stats(fibar_ctx* c, uint64_t* q, uint64_t* Q, uint64_t* P, uint64_t* T,
+                     uint64_t* front);
 
 /*
  * Several independent streams advanced together.  A group holds 1..64

@@ -46,7 +46,8 @@ class fibar_params(ctypes.Structure):
                 ("fill_den", ctypes.c_uint32), ("q_min", ctypes.c_uint32),
                 ("q_max", ctypes.c_uint32), ("spatial_filter", ctypes.c_uint32),
                 ("regulation", ctypes.c_uint32), ("max_packet", ctypes.c_uint32),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("region", ctypes.c_uint32),
+                ("age_max", ctypes.c_uint64)]
 
 
 class fibar_packet(ctypes.Structure):
@@ -104,6 +105,8 @@ _SIGNATURES = {
                                                  ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
                                                  ctypes.c_void_p, ctypes.c_void_p]),
     "fibar_set_pixel_gain": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "fibar_tile_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 _SIGNATURES.update({
@@ -253,6 +256,15 @@ def fibar_relative_thresholds(n_on, n_off, width, height, c_rel, c_on_rel=None, 
                                             stream)
 
 
+def fibar_tile_stats(handle, n_tiles):
+    """Per-tile scalars of a per-tile-queue context: (status, dict of q, Q, P,
+    T, front arrays)."""
+    out = {k: np.empty(int(n_tiles), np.uint64) for k in ("q", "Q", "P", "T", "front")}
+    rc = load().fibar_tile_stats(handle, *(out[k].ctypes.data for k in ("q", "Q", "P", "T",
+                                                                          "front")))
+    return rc, out
+
+
 def fibar_set_pixel_gain(handle, gain) -> int:
     """gain: a device float buffer of width*height values, or None."""
     return load().fibar_set_pixel_gain(handle, _addr(gain))
@@ -350,8 +362,11 @@ class Context:
     """One reconstruction context (owns its device state)."""
 
     def __init__(self, width, height, t_cut=40.0, fill=(1, 2), q_min=64, q_max=0,
-                 spatial_filter=True, max_packet=65536, stream=None, regulation="packet"):
+                 spatial_filter=True, max_packet=65536, stream=None, regulation="packet",
+                 region=0, age_max=0):
         prm = fibar_default_params()
+        prm.region = int(region)
+        prm.age_max = int(age_max)
         prm.regulation = FIBAR_REG_EVENT if regulation == "event" else FIBAR_REG_PACKET
         prm.t_cut = float(t_cut)
         prm.fill_num, prm.fill_den = int(fill[0]), int(fill[1])
@@ -367,6 +382,17 @@ class Context:
         self.width, self.height = int(width), int(height)
         self.tiles = ((self.width + 1) // 2) * ((self.height + 1) // 2)
         self.spatial_filter = bool(spatial_filter)
+        self.region = int(region)
+        if self.region:
+            self.tiles_x = -(-self.width // self.region)
+            self.tiles_y = -(-self.height // self.region)
+
+    def tile_stats(self):
+        """Per-tile q, Q, P, T and window fronts (per-tile queues)."""
+        rc, out = fibar_tile_stats(self.handle, self.tiles_x * self.tiles_y)
+        if rc != FIBAR_OK:
+            raise FibarError(rc, "fibar_tile_stats")
+        return out
 
     def close(self):
         if getattr(self, "handle", None):

@@ -7,7 +7,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfibar.so")
 SOURCES = ["fibar_api.hip", "fibar_kernels.hip", "fibar_region.hip", "fibar_multi.hip",
-           "fibar_fill.hip", "fibar_event.hip", "fibar_thresholds.hip"]
+           "fibar_fill.hip", "fibar_event.hip", "fibar_thresholds.hip", "fibar_tiles.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

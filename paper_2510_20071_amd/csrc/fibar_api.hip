@@ -259,6 +259,10 @@ void free_ctx(fibar_ctx* c)
     (void)hipFree(c->s.pp);
     (void)hipFree(c->s.ring);
     (void)hipFree(c->gain);
+    (void)hipFree(c->tq_tiles);
+    (void)hipFree(c->tq_front);
+    (void)hipFree(c->tq_ring);
+    (void)hipFree(c->tq_stale);
     (void)hipFree(c->s.sc);
     (void)hipFree(c->d_chunks);
     (void)hipFree(c->seg);
@@ -313,6 +317,9 @@ int do_readout_kernel(fibar_ctx* c, const fibar_readout_buf& ro, const StepScrat
     const int sp = (int)c->prm.spatial_filter;
     const int slot = c->cur_slot;
     if (ro.on_device) {
+        if (c->tq)
+            return map_err(tq_readout(c, ro.brightness, ro.pbar, ro.stale_mask, ro.active_count,
+                                      ro.last_index, ro.log_age, ro.tile_count, ro.total_count));
         HIP_TRY(timed_launch(c, 4, [&](const LaunchTiming& tm) {
             return launch_readout(c->s, sp, pend, pend_n, slot, ro.brightness, ro.pbar,
                                   ro.stale_mask, ro.active_count, ro.last_index, ro.log_age,
@@ -343,8 +350,9 @@ int do_readout_kernel(fibar_ctx* c, const fibar_readout_buf& ro, const StepScrat
     float* dA = ro.log_age ? (float*)take(npx * 4) : nullptr;
     uint32_t* dT = ro.tile_count ? (uint32_t*)take(c->ntiles * 4) : nullptr;
     uint64_t* dN = ro.total_count ? (uint64_t*)take(npx * 8) : nullptr;
-    hipError_t e = launch_readout(c->s, sp, pend, pend_n, slot, dL, dP, dS, dC, dLi, dA, dT, dN,
-                                  c->st);
+    hipError_t e = c->tq ? tq_readout(c, dL, dP, dS, dC, dLi, dA, dT, dN)
+                         : launch_readout(c->s, sp, pend, pend_n, slot, dL, dP, dS, dC, dLi, dA,
+                                          dT, dN, c->st);
     if (e == hipSuccess) e = hipMemcpyAsync(ro.brightness, dL, npx * 4, hipMemcpyDeviceToHost, c->st);
     if (e == hipSuccess && dP) e = hipMemcpyAsync(ro.pbar, dP, npx * 4, hipMemcpyDeviceToHost, c->st);
     if (e == hipSuccess && dS) e = hipMemcpyAsync(ro.stale_mask, dS, npx, hipMemcpyDeviceToHost, c->st);
@@ -420,12 +428,54 @@ int run_event_batch(fibar_ctx* c, const Op* ops, size_t n)
     return FIBAR_OK;
 }
 
+// Per-tile queues: the batch's events bucketed by tile, then per packet
+// the tiles' steps and the blur; readouts between them.
+int run_tq_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, uint32_t n_steps)
+{
+    if (n_chunks > 0) {
+        HIP_TRY(hipEventSynchronize(c->chunks_free));
+        uint32_t ci = 0, step = 0;
+        for (size_t i = 0; i < n; ++i) {
+            if (ops[i].kind != 0) continue;
+            for (uint32_t off = 0; off < ops[i].n; off += kChunk) {
+                ChunkDesc& d = c->h_chunks[ci++];
+                const uint32_t m = ops[i].n - off < (uint32_t)kChunk ? ops[i].n - off : (uint32_t)kChunk;
+                d.x = ops[i].x + off;
+                d.y = ops[i].y + off;
+                d.p = ops[i].p + off;
+                d.n = m;
+                d.pkt = step;
+            }
+            ++step;
+        }
+        HIP_TRY(hipMemcpyAsync(c->d_chunks, c->h_chunks, (size_t)n_chunks * sizeof(ChunkDesc),
+                               hipMemcpyHostToDevice, c->st));
+        HIP_TRY(hipEventRecord(c->chunks_free, c->st));
+        HIP_TRY(hipMemsetAsync(c->scratch, 0, (size_t)n_steps * sizeof(StepScratch), c->st));
+        HIP_TRY(tq_bulk(c, n_chunks));
+    }
+    uint32_t ci = 0, step = 0;
+    for (size_t i = 0; i < n; ++i) {
+        if (ops[i].kind == 1) {
+            int rc = do_readout_kernel(c, ops[i].ro, nullptr, 0);
+            if (rc) return rc;
+            continue;
+        }
+        const uint32_t nc = (ops[i].n + kChunk - 1) / kChunk;
+        HIP_TRY(tq_step(c, ci, ci + nc, n_chunks, step));
+        ci += nc;
+        ++step;
+    }
+    return FIBAR_OK;
+}
+
 // Execute ops[0..n): bulk sort for all pushes, then the in-order steps.
 int run_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, uint32_t n_steps)
 {
     if (n == 0) return FIBAR_OK;
     if (c->region_path) return run_region_batch(c, ops, n, n_chunks, n_steps);
     if (c->event_mode) return run_event_batch(c, ops, n);
+    if (c->tq) return run_tq_batch(c, ops, n, n_chunks, n_steps);
     // graph mode replays the batch's kernels as one graph; a readout into
     // host memory (copies and a wait between the kernels) keeps the batch on
     // direct launches
@@ -635,6 +685,7 @@ hipError_t init_state(fibar_ctx* c)
     c->h_sc->stepped = 0;
     c->cur_slot = 0;
     hipError_t e = launch_init_state(c->s, c->st);
+    if (e == hipSuccess && c->tq) e = tq_init(c);
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->s.sc + c->cur_slot, c->h_sc, sizeof(DevScalars), hipMemcpyHostToDevice,
                            c->st);
@@ -681,6 +732,8 @@ void fibar_default_params(fibar_params* p)
     p->regulation = FIBAR_REG_PACKET;
     p->max_packet = 65536;
     p->stream = nullptr;
+    p->region = 0;
+    p->age_max = 0;
 }
 
 int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar_ctx** out)
@@ -706,6 +759,19 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
     // per-event regulation with the spatial filter on keeps a packet's state
     // in one workgroup's LDS (without the filter there is nothing to regulate)
     const bool event_mode = p.regulation == FIBAR_REG_EVENT && p.spatial_filter;
+    // per-tile queues: tiles of whole 2x2 cells that fit one 1024-thread
+    // workgroup, packet regulation
+    const bool tq = p.region != 0;
+    uint32_t tq_RW = 0, tq_RH = 0, tq_cap = 1;
+    if (tq) {
+        if ((p.region & 1u) || p.region > 32 || !p.spatial_filter ||
+            p.regulation != FIBAR_REG_PACKET)
+            return FIBAR_E_INVALID_ARG;
+        tq_RW = (width + p.region - 1) / p.region;
+        tq_RH = (height + p.region - 1) / p.region;
+        if ((uint64_t)tq_RW * tq_RH > kMaxRegions) return FIBAR_E_INVALID_ARG;
+        while (tq_cap < p.region * p.region + p.max_packet) tq_cap <<= 1;
+    }
     uint32_t ev_cap = 1;
     if (event_mode) {
         if (npx > kEventMaxPixels || p.q_max > kEventMaxRing - 2) return FIBAR_E_INVALID_ARG;
@@ -740,6 +806,14 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
     const uint64_t n_regions = (npx + kRegion - 1) / kRegion;
     c->region_path = !p.spatial_filter && n_regions <= kMaxRegions;
     c->event_mode = event_mode;
+    c->tq = tq;
+    if (tq) {
+        c->tq_R = p.region;
+        c->tq_RW = tq_RW;
+        c->tq_RH = tq_RH;
+        c->tq_cap = tq_cap;
+        c->tq_age = p.age_max ? p.age_max : npx;
+    }
     if (event_mode) {
         c->ev_cap = ev_cap;
         c->ev_lds = event_lds_bytes(width, height, c->TW, ev_cap);
@@ -761,6 +835,19 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
     alloc((void**)&c->stg_x, stg * 2);
     alloc((void**)&c->stg_y, stg * 2);
     alloc((void**)&c->stg_p, stg);
+    if (tq) {
+        const uint64_t nt = (uint64_t)tq_RW * tq_RH;
+        c->rb.n_regions = (uint32_t)nt;
+        alloc((void**)&c->rb.cnt, (size_t)kMaxBatchChunks * nt * 4);
+        alloc((void**)&c->rb.base, (nt + 1) * 8);
+        alloc((void**)&c->rb.total, nt * 4);
+        alloc((void**)&c->rb.chunk_k, (kMaxBatchChunks + 1) * 8);
+        alloc((void**)&c->rb.payload, (size_t)kMaxBatchChunks * kChunk * 8);
+        alloc((void**)&c->tq_tiles, nt * sizeof(TQTile));
+        alloc((void**)&c->tq_front, 2 * nt * 8);
+        alloc((void**)&c->tq_ring, nt * tq_cap * sizeof(uint2));
+        alloc((void**)&c->tq_stale, npx * 4);
+    }
     if (c->region_path) {
         c->rb.n_regions = (uint32_t)n_regions;
         alloc((void**)&c->rb.cnt, (size_t)kMaxBatchChunks * n_regions * 4);
@@ -850,6 +937,24 @@ int fibar_get_stats(fibar_ctx* c, fibar_stats* s)
     s->Q = d.Q;
     s->P = d.P;
     s->T = d.T;
+    if (c->tq) {
+        // sums over the tiles
+        const size_t nt = (size_t)c->tq_RW * c->tq_RH;
+        std::vector<TQTile> t(nt);
+        HIP_TRY(hipMemcpy(t.data(), c->tq_tiles, nt * sizeof(TQTile), hipMemcpyDeviceToHost));
+        uint64_t q = 0, Q = 0, P = 0, T = 0;
+        for (const TQTile& x : t) {
+            q += x.tail - x.head;
+            Q += x.Q;
+            P += x.P;
+            T += x.T;
+        }
+        s->q = q;
+        s->h = (uint64_t)(d.k + 1) - q;
+        s->Q = Q;
+        s->P = P;
+        s->T = T;
+    }
     s->n_regulations = d.n_reg;
     s->last_stale = d.last_stale;
     s->total_stale = d.total_stale;
@@ -879,10 +984,33 @@ int fibar_set_kernel_timing(fibar_ctx* c, uint32_t kernel_mask, uint32_t every)
     return FIBAR_OK;
 }
 
+int fibar_tile_stats(fibar_ctx* c, uint64_t* q, uint64_t* Q, uint64_t* P, uint64_t* T,
+                     uint64_t* front)
+{
+    if (!c) return FIBAR_E_INVALID_ARG;
+    if (!c->tq) return FIBAR_E_UNSUPPORTED;
+    int rc = fetch_scalars(c);
+    if (rc) return rc;
+    const size_t nt = (size_t)c->tq_RW * c->tq_RH;
+    std::vector<TQTile> t(nt);
+    std::vector<uint64_t> f(nt);
+    HIP_TRY(hipMemcpy(t.data(), c->tq_tiles, nt * sizeof(TQTile), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(f.data(), c->tq_front + (size_t)c->tq_parity * nt, nt * 8,
+                      hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < nt; ++i) {
+        if (q) q[i] = t[i].tail - t[i].head;
+        if (Q) Q[i] = t[i].Q;
+        if (P) P[i] = t[i].P;
+        if (T) T[i] = t[i].T;
+        if (front) front[i] = f[i];
+    }
+    return take_device_error(c);
+}
+
 int fibar_set_telemetry(fibar_ctx* c, fibar_step_record* records, uint64_t capacity)
 {
     if (!c || (!records && capacity)) return FIBAR_E_INVALID_ARG;
-    if ((!c->prm.spatial_filter || c->event_mode) && records) return FIBAR_E_UNSUPPORTED;
+    if ((!c->prm.spatial_filter || c->event_mode || c->tq) && records) return FIBAR_E_UNSUPPORTED;
     // launches already queued keep the buffer they were given
     c->s.tel = capacity ? reinterpret_cast<StepRecord*>(records) : nullptr;
     c->s.tel_cap = capacity;

@@ -35,6 +35,16 @@ struct fibar_ctx {
     // per-event regulation: packets run in one LDS-resident workgroup
     bool event_mode = false;
     float* gain = nullptr;              // relative thresholds, once set
+    // per-tile event queues (region > 0): tiles of tq_R x tq_R pixels
+    bool tq = false;
+    uint32_t tq_R = 0, tq_RW = 0, tq_RH = 0;
+    uint32_t tq_cap = 0;                // ring entries per tile (a power of two)
+    uint64_t tq_age = 0;                // events older than this leave
+    fibar::TQTile* tq_tiles = nullptr;
+    uint64_t* tq_front = nullptr;       // [2][tiles]: oldest window event, two steps
+    uint2* tq_ring = nullptr;           // [tiles][tq_cap]: (global index low 32 bits, local pixel)
+    uint32_t* tq_stale = nullptr;       // pixels going stale in the current step
+    int tq_parity = 0;                  // which front row is current
     uint32_t ev_cap = 0;                // LDS ring entries (a power of two)
     size_t ev_lds = 0;                  // dynamic LDS bytes of the event kernel
     fibar::RegionBuffers rb{};
@@ -58,6 +68,13 @@ struct fibar_ctx {
 
 
 namespace fibar {
+
+// Per-tile event queues (fibar_tiles.hip).
+hipError_t tq_init(fibar_ctx* c);
+hipError_t tq_bulk(fibar_ctx* c, uint32_t n_chunks);
+hipError_t tq_step(fibar_ctx* c, uint32_t c0, uint32_t c1, uint32_t n_chunks, uint32_t pkt);
+hipError_t tq_readout(fibar_ctx* c, float* L, float* pbar, uint8_t* stale, uint32_t* cnt,
+                      int64_t* last, float* log_age, uint32_t* tcnt, uint64_t* tot);
 
 inline int map_err(hipError_t e)
 {

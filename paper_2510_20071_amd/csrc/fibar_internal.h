@@ -230,6 +230,21 @@ struct RegionBuffers {
     uint32_t n_regions;
 };
 
+// Scan of the per-(chunk, region) counts and the region bases / chunk
+// indices of a batch (the first two stages of launch_region_batch); with
+// set_k the newest event index of the batch is stored in the scalars.
+hipError_t launch_region_scan_bases(const State& s, int slot, const ChunkDesc* d_chunks,
+                                    uint32_t n_chunks, StepScratch* scratch,
+                                    const RegionBuffers& rb, bool set_k, hipStream_t st);
+
+// Per-tile event queues (fibar_tiles.hip): one tile's window and counts.
+struct TQTile {
+    uint32_t head, tail;   // ring positions of the window [head, tail)
+    uint32_t Q, P, T;      // target, active pixels, active 2x2 cells
+    uint32_t npix;         // pixels of the tile
+    uint32_t pad[2];
+};
+
 hipError_t launch_region_batch(const State& s, int slot, const ChunkDesc* d_chunks,
                                uint32_t n_chunks, StepScratch* scratch, const RegionBuffers& rb,
                                uint32_t n_readouts, int key_bits, Coef coef, hipStream_t st,

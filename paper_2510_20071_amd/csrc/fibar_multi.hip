@@ -780,7 +780,8 @@ int fibar_multi_create(fibar_ctx* const* ctxs, uint32_t n, void* stream, fibar_m
     if (!ctxs || n == 0 || n > kMultiMaxStreams) return FIBAR_E_INVALID_ARG;
     for (uint32_t i = 0; i < n; ++i) {
         if (!ctxs[i]) return FIBAR_E_INVALID_ARG;
-        if (!ctxs[i]->prm.spatial_filter || ctxs[i]->event_mode) return FIBAR_E_UNSUPPORTED;
+        if (!ctxs[i]->prm.spatial_filter || ctxs[i]->event_mode || ctxs[i]->tq)
+            return FIBAR_E_UNSUPPORTED;
         for (uint32_t j = 0; j < i; ++j)
             if (ctxs[j] == ctxs[i]) return FIBAR_E_INVALID_ARG;
     }

@@ -136,7 +136,7 @@ __global__ __launch_bounds__(1024) void k_region_bases(State s, int slot,
                                                        const ChunkDesc* __restrict__ chunks,
                                                        uint32_t n_chunks,
                                                        const StepScratch* __restrict__ scratch,
-                                                       RegionBuffers rb)
+                                                       RegionBuffers rb, int set_k)
 {
     __shared__ uint32_t scan1[kWaves + 1];
     const uint32_t per = (rb.n_regions + blockDim.x - 1) / blockDim.x;
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(1024) void k_region_bases(State s, int slot,
         rb.base[rb.n_regions] = all;
         rb.chunk_k[n_chunks] = k0 + 1 + nvalid;
         DevScalars& c = s.sc[slot];
-        c.k = k0 + nvalid;
+        if (set_k) c.k = k0 + nvalid;
         if (first_bad && c.err == 0) {
             const uint32_t st0 = scratch[chunks[kMaxBatchChunks - first_bad].pkt].status;
             c.err = (st0 & 1u) ? -2 : -3;   // FIBAR_E_RANGE / FIBAR_E_POLARITY
@@ -372,6 +372,17 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
 
 }  // namespace
 
+hipError_t launch_region_scan_bases(const State& s, int slot, const ChunkDesc* d_chunks,
+                                    uint32_t n_chunks, StepScratch* scratch,
+                                    const RegionBuffers& rb, bool set_k, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_region_scan, dim3(rb.n_regions), dim3(256), 0, st, rb.cnt, n_chunks,
+                       rb.n_regions, rb.total);
+    hipLaunchKernelGGL(k_region_bases, dim3(1), dim3(1024), 0, st, s, slot, d_chunks, n_chunks,
+                       scratch, rb, set_k ? 1 : 0);
+    return hipGetLastError();
+}
+
 hipError_t launch_region_batch(const State& s, int slot, const ChunkDesc* d_chunks,
                                uint32_t n_chunks, StepScratch* scratch, const RegionBuffers& rb,
                                uint32_t n_readouts, int key_bits, Coef coef, hipStream_t st,
@@ -385,7 +396,7 @@ hipError_t launch_region_batch(const State& s, int slot, const ChunkDesc* d_chun
         hipLaunchKernelGGL(k_region_scan, dim3(rb.n_regions), dim3(256), 0, st, rb.cnt, n_chunks,
                            rb.n_regions, rb.total);
         hipLaunchKernelGGL(k_region_bases, dim3(1), dim3(1024), 0, st, s, slot, d_chunks, n_chunks,
-                           scratch, rb);
+                           scratch, rb, 1);
         int region_bits = 1;
         while ((1u << region_bits) < rb.n_regions) ++region_bits;
         hipLaunchKernelGGL(k_region_scatter, dim3(n_chunks), dim3(kSortThreads), 0, st, d_chunks,
@@ -397,7 +408,7 @@ hipError_t launch_region_batch(const State& s, int slot, const ChunkDesc* d_chun
                                           tm.start, nullptr, rb.cnt, 0u, rb.n_regions, rb.total);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_region_bases, dim3(1), dim3(1024), 0, st, s, slot, d_chunks, 0u,
-                           scratch, rb);
+                           scratch, rb, 1);
     }
     return launch_timed(k_region_apply, dim3(rb.n_regions), dim3(kSortThreads), st, nullptr,
                         tm.stop, s, rb, n_chunks, n_readouts, coef);

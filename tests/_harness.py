@@ -35,7 +35,8 @@ def make_ctx(W, H, **kw):
 
 def oracle_kw(kw):
     keep = {k: v for k, v in kw.items() if k in ("t_cut", "fill", "q_min", "q_max",
-                                                  "spatial_filter", "regulation")}
+                                                  "spatial_filter", "regulation", "region",
+                                                  "age_max")}
     return keep
 
 
@@ -62,6 +63,13 @@ def compare_state(g, r, spatial, where=""):
 def compare_stats(gs, os_, where=""):
     for f in ("k", "h", "Q", "P", "T", "n_regulations", "last_stale", "total_stale"):
         assert gs[f] == os_[f], "%s %s: gpu %d oracle %d" % (f, where, gs[f], os_[f])
+
+
+def compare_tiles(ctx, orc, where=""):
+    """Per-tile scalars of a per-tile-queue context against the oracle's."""
+    g, r = ctx.tile_stats(), orc.region_stats()
+    for key in ("q", "Q", "P", "T", "front"):
+        assert np.array_equal(g[key], r[key]), "tile %s %s" % (key, where)
 
 
 def oracle_step_record(st, n):
@@ -127,6 +135,8 @@ def run_pair(ev, W, H, sched, check_every_read=1, check_stats=True, telemetry=Tr
             compare_state(g, r, spatial, "at event %d" % k)
             if check_stats and spatial:
                 compare_stats(ctx.stats(), orc.stats(), "at event %d" % k)
+            if kw.get("region"):
+                compare_tiles(ctx, orc, "at event %d" % k)
     g = ctx.readout_host(0)
     r = orc.readout(0)
     compare_state(g, r, spatial, "final")

@@ -45,7 +45,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_binding_structs_match_header_sizes():
     # x86-64 SysV layout of the public structs
-    assert ctypes.sizeof(fb.fibar_params) == 8 + 7 * 4 + 4 + 8
+    assert ctypes.sizeof(fb.fibar_params) == 8 + 7 * 4 + 4 + 8 + 4 + 4 + 8
     assert ctypes.sizeof(fb.fibar_packet) == 4 * 8 + 8 + 8
     assert ctypes.sizeof(fb.fibar_readout_buf) == 8 * 8 + 8
     assert fb.STEP_RECORD_WORDS * 8 == 64   # fibar_step_record: one int64 and seven uint64
@@ -123,3 +123,24 @@ def test_threshold_entry_points_reject_bad_arguments_without_gpu():
     assert lib.fibar_relative_thresholds(None, None, 4, 4, None, None, None, None) == \
         fb.FIBAR_E_INVALID_ARG
     assert lib.fibar_set_pixel_gain(None, None) == fb.FIBAR_E_INVALID_ARG
+
+
+def test_per_tile_queue_parameters_without_gpu():
+    p = fb.fibar_default_params()
+    assert p.region == 0 and p.age_max == 0
+    for bad in (3, 34, 64):                 # odd, or more than 32
+        p = fb.fibar_default_params()
+        p.region = bad
+        assert fb.fibar_create(64, 48, p)[0] == fb.FIBAR_E_INVALID_ARG
+    p = fb.fibar_default_params()
+    p.region = 8
+    p.spatial_filter = 0
+    assert fb.fibar_create(64, 48, p)[0] == fb.FIBAR_E_INVALID_ARG
+    p = fb.fibar_default_params()
+    p.region = 8
+    p.regulation = fb.FIBAR_REG_EVENT
+    assert fb.fibar_create(64, 48, p)[0] == fb.FIBAR_E_INVALID_ARG
+    p = fb.fibar_default_params()
+    p.region = 2                             # 640 x 360 = 230400 tiles > 16384
+    assert fb.fibar_create(1280, 720, p)[0] == fb.FIBAR_E_INVALID_ARG
+    assert fb.load().fibar_tile_stats(None, None, None, None, None, None) == fb.FIBAR_E_INVALID_ARG
