@@ -271,6 +271,10 @@ void free_ctx(fibar_ctx* c)
     (void)hipFree(c->stg_x);
     (void)hipFree(c->stg_y);
     (void)hipFree(c->stg_p);
+    if (c->hs_x) (void)hipHostFree(c->hs_x);
+    if (c->hs_y) (void)hipHostFree(c->hs_y);
+    if (c->hs_p) (void)hipHostFree(c->hs_p);
+    if (c->hs_done) (void)hipEventDestroy(c->hs_done);
     (void)hipFree(c->rb.cnt);
     (void)hipFree(c->rb.base);
     (void)hipFree(c->rb.total);
@@ -580,7 +584,6 @@ int execute(fibar_ctx* c, const fibar_op* ops, size_t n_ops)
     std::vector<Op> batch;
     batch.reserve(n_ops < 4096 ? n_ops : 4096);
     uint32_t n_chunks = 0, n_steps = 0, n_readouts = 0;
-    size_t stg_used = 0;
     for (size_t i = 0; i < n_ops; ++i) {
         const fibar_op& op = ops[i];
         if (op.kind == FIBAR_OP_PUSH) {
@@ -592,13 +595,18 @@ int execute(fibar_ctx* c, const fibar_op* ops, size_t n_ops)
             }
             const uint32_t need = (uint32_t)((pk.n + kChunk - 1) / kChunk);
             const bool host = !pk.on_device;
-            if (n_chunks + need > kMaxBatchChunks || (host && stg_used + pk.n > c->stg_cap)) {
+            const bool wrap = host && c->hs_pos + pk.n > c->stg_cap;
+            if (n_chunks + need > kMaxBatchChunks || wrap) {
                 int rc = run_batch(c, batch.data(), batch.size(), n_chunks, n_steps);
                 if (rc) return rc;
                 batch.clear();
                 n_chunks = n_steps = 0;
-                stg_used = 0;
                 n_readouts = 0;
+            }
+            if (wrap) {
+                // the pinned ring starts over once every copy from it has run
+                HIP_TRY(hipEventSynchronize(c->hs_done));
+                c->hs_pos = 0;
             }
             Op o{};
             o.kind = 0;
@@ -609,15 +617,24 @@ int execute(fibar_ctx* c, const fibar_op* ops, size_t n_ops)
                     int rc2 = run_batch(c, batch.data(), batch.size(), n_chunks, n_steps);
                     return rc2 ? rc2 : rc;
                 }
-                // the staging area is reused by the next batch: copy synchronously
-                HIP_TRY(hipStreamSynchronize(c->st));
-                HIP_TRY(hipMemcpy(c->stg_x + stg_used, pk.x, pk.n * 2, hipMemcpyHostToDevice));
-                HIP_TRY(hipMemcpy(c->stg_y + stg_used, pk.y, pk.n * 2, hipMemcpyHostToDevice));
-                HIP_TRY(hipMemcpy(c->stg_p + stg_used, pk.p, pk.n, hipMemcpyHostToDevice));
-                o.x = c->stg_x + stg_used;
-                o.y = c->stg_y + stg_used;
-                o.p = c->stg_p + stg_used;
-                stg_used += pk.n;
+                // the caller's arrays are free when the call returns: copy
+                // them into the pinned ring, then to the device in stream
+                // order (the device staging is reused in stream order too)
+                const size_t at = c->hs_pos;
+                memcpy(c->hs_x + at, pk.x, pk.n * 2);
+                memcpy(c->hs_y + at, pk.y, pk.n * 2);
+                memcpy(c->hs_p + at, pk.p, pk.n);
+                HIP_TRY(hipMemcpyAsync(c->stg_x + at, c->hs_x + at, pk.n * 2, hipMemcpyHostToDevice,
+                                       c->st));
+                HIP_TRY(hipMemcpyAsync(c->stg_y + at, c->hs_y + at, pk.n * 2, hipMemcpyHostToDevice,
+                                       c->st));
+                HIP_TRY(hipMemcpyAsync(c->stg_p + at, c->hs_p + at, pk.n, hipMemcpyHostToDevice,
+                                       c->st));
+                HIP_TRY(hipEventRecord(c->hs_done, c->st));
+                o.x = c->stg_x + at;
+                o.y = c->stg_y + at;
+                o.p = c->stg_p + at;
+                c->hs_pos = at + pk.n;
                 if (pk.t && pk.t[pk.n - 1] > c->t_hi) c->t_hi = pk.t[pk.n - 1];
             } else {
                 o.x = pk.x;
@@ -649,7 +666,6 @@ int execute(fibar_ctx* c, const fibar_op* ops, size_t n_ops)
                     if (rc2) return rc2;
                     batch.clear();
                     n_chunks = n_steps = 0;
-                    stg_used = 0;
                     rc2 = do_readout_kernel(c, ro, nullptr, 0);
                     if (rc2) return rc2;
                     continue;
@@ -659,7 +675,6 @@ int execute(fibar_ctx* c, const fibar_op* ops, size_t n_ops)
                     if (rc2) return rc2;
                     batch.clear();
                     n_chunks = n_steps = 0;
-                    stg_used = 0;
                     n_readouts = 0;
                 }
                 ++n_readouts;
@@ -860,6 +875,10 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ro_free, hipEventDisableTiming);
     }
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_chunks, kMaxBatchChunks * sizeof(ChunkDesc), 0);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->hs_x, stg * 2, 0);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->hs_y, stg * 2, 0);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->hs_p, stg, 0);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->hs_done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_sc, sizeof(DevScalars), 0);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->chunks_free, hipEventDisableTiming);
     if (e != hipSuccess) {
@@ -880,6 +899,7 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
     if (event_mode) e = prepare_event_kernel(c->ev_lds);
     if (e == hipSuccess) e = init_state(c);
     if (e == hipSuccess) e = hipEventRecord(c->chunks_free, c->st);
+    if (e == hipSuccess) e = hipEventRecord(c->hs_done, c->st);
     if (e == hipSuccess && c->ro_free) e = hipEventRecord(c->ro_free, c->st);
     if (e == hipSuccess) e = hipStreamSynchronize(c->st);
     if (e != hipSuccess) {

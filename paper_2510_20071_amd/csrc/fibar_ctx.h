@@ -27,6 +27,14 @@ struct fibar_ctx {
     uint16_t* stg_y = nullptr;
     uint8_t* stg_p = nullptr;
     size_t stg_cap = 0;
+    // host packets go through a pinned ring of the same size: copied there on
+    // the host, then to the device staging with asynchronous copies; the
+    // cursor runs across calls, and only a wrap waits for the copies so far
+    uint16_t* hs_x = nullptr;
+    uint16_t* hs_y = nullptr;
+    uint8_t* hs_p = nullptr;
+    size_t hs_pos = 0;
+    hipEvent_t hs_done = nullptr;       // after the latest host-packet copy
     fibar::DevScalars* h_sc = nullptr;         // pinned copy for stats
     int cur_slot = 0;                   // scalar slot holding the committed state
     uint64_t t_hi = 0;

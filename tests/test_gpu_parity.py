@@ -649,3 +649,46 @@ def test_total_count_blur_off_region_path():
     g, r = run_pair(ev, 640, 480, sched, spatial_filter=False)
     assert np.array_equal(g["tot"], r["tot"])
     assert int(g["tot"].sum()) == len(ev)
+
+
+def test_host_packets_through_the_pinned_ring():
+    """Host packets are copied into a pinned ring and on to the device without
+    waiting for the stream; the ring (4M events) wraps here.  The result is
+    bit-identical to the same packets given as device arrays, with host
+    readouts and device packets interleaved."""
+    torch, dev = torch_dev()
+    W, H = 346, 260
+    sc = eventsim.Scene(W, H, 5_000_000, 71, n_blobs=150, checker_cell=16.0,
+                        checker_contrast=0.5, speed_px_s=200.0, noise_frac=0.01)
+    ev = eventsim.generate(sc)
+    n = len(ev)
+    gx, gy, gp = to_device(ev)
+    flush("346x260, %d events, host packets through the pinned ring" % n)
+    a_ctx = make_ctx(W, H, max_packet=131072)
+    b_ctx = make_ctx(W, H, max_packet=131072)
+    sizes = [100_000, 3, 77_777, 131_072, 12_345]
+    a, r, reads = 0, 0, []
+    while a < n:
+        b = min(n, a + sizes[r % len(sizes)])
+        if r % 7 == 3:   # a device packet among the host ones
+            assert a_ctx.push(gx[a:b], gy[a:b], gp[a:b]) == 0
+        else:
+            assert a_ctx.push(ev.x[a:b], ev.y[a:b], ev.p[a:b]) == 0
+        assert b_ctx.push(gx[a:b], gy[a:b], gp[a:b]) == 0
+        if r % 11 == 10:
+            reads.append((a_ctx.readout_host(0), b_ctx.readout_host(0)))
+        a, r = b, r + 1
+    reads.append((a_ctx.readout_host(0), b_ctx.readout_host(0)))
+    for ga, gb in reads:
+        for key in ga:
+            assert np.array_equal(ga[key], gb[key]), key
+    assert a_ctx.stats() == b_ctx.stats()
+    orc = oracle.Oracle(W, H)
+    a, r = 0, 0
+    while a < n:
+        b = min(n, a + sizes[r % len(sizes)])
+        assert orc.push(ev.x[a:b], ev.y[a:b], ev.p[a:b]) == 0
+        a, r = b, r + 1
+    compare_state(reads[-1][0], orc.readout(0), True, "after the host packets")
+    a_ctx.close()
+    b_ctx.close()
