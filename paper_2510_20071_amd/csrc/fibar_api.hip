@@ -263,6 +263,7 @@ void free_ctx(fibar_ctx* c)
     (void)hipFree(c->tq_front);
     (void)hipFree(c->tq_ring);
     (void)hipFree(c->tq_stale);
+    (void)hipFree(c->tq_nstale);
     (void)hipFree(c->s.sc);
     (void)hipFree(c->d_chunks);
     (void)hipFree(c->seg);
@@ -861,7 +862,8 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
         alloc((void**)&c->tq_tiles, nt * sizeof(TQTile));
         alloc((void**)&c->tq_front, 2 * nt * 8);
         alloc((void**)&c->tq_ring, nt * tq_cap * sizeof(uint2));
-        alloc((void**)&c->tq_stale, npx * 4);
+        alloc((void**)&c->tq_stale, nt * p.region * p.region * 4);
+        alloc((void**)&c->tq_nstale, nt * 4);
     }
     if (c->region_path) {
         c->rb.n_regions = (uint32_t)n_regions;

@@ -51,7 +51,8 @@ struct fibar_ctx {
     fibar::TQTile* tq_tiles = nullptr;
     uint64_t* tq_front = nullptr;       // [2][tiles]: oldest window event, two steps
     uint2* tq_ring = nullptr;           // [tiles][tq_cap]: (global index low 32 bits, local pixel)
-    uint32_t* tq_stale = nullptr;       // pixels going stale in the current step
+    uint32_t* tq_stale = nullptr;       // [tiles][region^2]: pixels going stale in the step
+    uint32_t* tq_nstale = nullptr;      // [tiles]: how many
     int tq_parity = 0;                  // which front row is current
     uint32_t ev_cap = 0;                // LDS ring entries (a power of two)
     size_t ev_lds = 0;                  // dynamic LDS bytes of the event kernel

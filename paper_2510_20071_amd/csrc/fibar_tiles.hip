@@ -13,12 +13,12 @@
 // chunk's events per tile, the blur-off scan and base kernels place the
 // tiles' slices, and k_tq_scatter moves every event into its tile's slice
 // (chunk order, then arrival order).  Per packet, two launches:
-//   k_tq_step  one 1024-thread workgroup per tile, a thread per pixel: the
-//              tile's events of the packet are applied in time order per
-//              pixel, pushed to the tile's ring, then the tile pops (target
-//              and age), finds its stale pixels (a pixel goes stale when its
-//              newest event leaves), updates its counts and target, and
-//              lists the stale pixels;
+//   k_tq_step  one wave per tile: the tile's events of the packet are
+//              pushed to its ring, the tile pops (target and age), the 2x2
+//              cells touched by an event or a pop apply their pixels' events
+//              in time order and find their stale pixels (a pixel goes stale
+//              when its newest event leaves), and the tile updates its
+//              counts and target and lists the stale pixels;
 //   k_tq_blur  every listed pixel gets its one-time 3x3 blur into Lb, from
 //              the image before the step's blurs.
 // A pixel's current brightness is Lb when its newest event is older than
@@ -189,215 +189,362 @@ struct TQStep {
     int slot;
 };
 
-// Work grows with the tile's events and pops, not with its pixels: only the
-// 2x2 cells that an event or a pop touches load and store their state.
-// Events are taken in pieces of up to 1024 (time order); each owner thread
-// scans a piece for its own pixel and applies those events in order.
-constexpr uint32_t kPiece = 1024;
+// One workgroup per tile, one thread per 2x2 cell (R <= 32: at most 256
+// cells), and work that grows with the tile's events and pops, not with its
+// pixels: only the cells that an event or a pop touches load and store their
+// state.  The dependent memory round trips are few: the tile's scalars; then
+// its new events, the oldest part of its window (the likely pops, into LDS)
+// and the step's chunk indices together; then the touched cells' state.
+// Events are bucketed by cell in pieces of kPiece (a count per cell, a scan,
+// a scatter), so a thread reads only its own cell's events and applies them
+// by increasing index.
+constexpr uint32_t kTqThreads = 256;
+constexpr uint32_t kPiece = 512;
+constexpr uint32_t kPre = 512;   // window entries prefetched into LDS
+constexpr uint32_t kPer = kPiece / kTqThreads;
 
-__global__ __launch_bounds__(1024) void k_tq_step(State s, TQGeom g, TQTile* __restrict__ tiles,
-                                                  uint64_t* __restrict__ front,
-                                                  uint2* __restrict__ ring, uint32_t ring_mask,
-                                                  uint32_t* __restrict__ stale_list,
-                                                  RegionBuffers rb, StepScratch* __restrict__ scratch,
-                                                  TQStep st, uint64_t age_max, Coef coef)
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
 {
-    __shared__ uint32_t ent_key[kPiece];     // local pixel << 1 | polarity
-    __shared__ uint32_t ent_gi[kPiece];      // global index, low 32 bits
-    __shared__ uint32_t pop_cnt[1024];
-    __shared__ uint8_t touched[1024];        // an event or a pop of this pixel
-    __shared__ uint8_t act_b[1024], act_a[1024], act_p[1024];
-    __shared__ uint32_t counts[6];           // dP, dT, old events, stale, cells gone, any work
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
 
-    const uint32_t t = blockIdx.x, n_tiles = gridDim.x;
-    const uint32_t tid = threadIdx.x;
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, uint32_t lane)
+{
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(v, o, 64);
+        if ((int)lane >= o) v += u;
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(kTqThreads, 4) void k_tq_step(
+    State s, TQGeom g, uint32_t n_tiles, TQTile* __restrict__ tiles, uint64_t* __restrict__ front,
+    uint2* __restrict__ ring, uint32_t ring_mask, uint32_t* __restrict__ stale_list,
+    uint32_t* __restrict__ nstale, RegionBuffers rb, StepScratch* __restrict__ scratch, TQStep st,
+    uint64_t age_max, Coef coef)
+{
+    __shared__ uint32_t touched_w[256];           // a byte per pixel: event or pop
+    __shared__ uint32_t popc[1024];               // pops per pixel
+    __shared__ uint32_t keys[kPiece];             // bucketed events: pixel << 1 | polarity
+    __shared__ uint32_t gis[kPiece];              // global index, low 32 bits
+    __shared__ uint32_t ccnt[kTqThreads];         // a piece's events per cell
+    __shared__ uint32_t cstart[kTqThreads];       // and where each cell's begin
+    __shared__ int64_t ck[kTqThreads];            // first global index of the step's chunks
+    __shared__ uint2 pre[kPre];                   // the window's oldest entries
+    __shared__ uint32_t wtot[kTqThreads / 64];
+    __shared__ uint32_t sh_first, sh_nstale, sh_red[3];
+
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const uint32_t t = blockIdx.x;
+    uint8_t* touched = reinterpret_cast<uint8_t*>(touched_w);
     const uint64_t* front_old = front + (size_t)st.parity * n_tiles;
     uint64_t* front_new = front + (size_t)(st.parity ^ 1) * n_tiles;
+    // the tile's scalars, all loaded together
     const uint64_t f_old = front_old[t];
-    if (scratch[st.pkt].status != 0u) {   // a rejected packet changes nothing
-        if (tid == 0) front_new[t] = f_old;
-        return;
-    }
+    const uint32_t status = scratch[st.pkt].status;
     const TQTile tl = tiles[t];
-    const uint32_t tx0 = (t % g.RW) * g.R, ty0 = (t / g.RW) * g.R;
-    const uint32_t tw = min(g.R, g.W - tx0), th = min(g.R, g.H - ty0);
-    const uint32_t lx = tid % g.R, ly = tid / g.R;
-    const bool own = ly < th && lx < tw && tid < g.R * g.R;
-    const uint64_t gp = own ? (uint64_t)(ty0 + ly) * g.W + tx0 + lx : 0u;
     const int64_t k_after = rb.chunk_k[st.c1] - 1;
-
-    // the tile's events of this packet: [lo, hi) of its slice
     const uint64_t bt = rb.base[t];
     const uint64_t lo = bt + rb.cnt[(size_t)st.c0 * n_tiles + t];
     const uint64_t hi = st.c1 < st.n_chunks ? bt + rb.cnt[(size_t)st.c1 * n_tiles + t]
                                              : bt + rb.total[t];
+    if (status != 0u) {   // a rejected packet changes nothing
+        if (tid == 0) {
+            front_new[t] = f_old;
+            nstale[t] = 0u;
+        }
+        return;
+    }
+    const uint32_t tx0 = (t % g.RW) * g.R, ty0 = (t / g.RW) * g.R;
+    const uint32_t tw = min(g.R, g.W - tx0), th = min(g.R, g.H - ty0);
+    // this tile's stale pixels of the step go to its own part of the list
+    uint32_t* my_stale = stale_list + (size_t)t * g.R * g.R;
     const uint32_t n_new = (uint32_t)(hi - lo);
+    const uint32_t q_old = tl.tail - tl.head;
     const uint32_t tail = tl.tail + n_new;
     const uint32_t q = tail - tl.head;
     const size_t rbase = (size_t)t * (ring_mask + 1);
     auto global_of = [&](uint32_t lo32) {   // a window event is < 2^32 events old
         return (uint64_t)k_after - (uint32_t)((uint32_t)k_after - lo32);
     };
+    const bool can_age = (uint64_t)k_after + 1 > age_max;
+    const uint64_t lim = can_age ? (uint64_t)k_after - age_max : 0u;   // at or below: leave
 
     // a tile without new events, within its target and whose oldest event
-    // is young enough, does nothing but move an empty window's front
+    // is young enough, only moves an empty window's front
     if (n_new == 0 && q <= tl.Q) {
         bool idle = true;
-        if (q > 0) {
-            const uint64_t e0 = global_of(ring[rbase + (tl.head & ring_mask)].x);
-            idle = (uint64_t)k_after - e0 < age_max;
-        }
+        if (q > 0 && can_age) idle = global_of(ring[rbase + (tl.head & ring_mask)].x) > lim;
         if (idle) {
-            if (tid == 0) front_new[t] = q > 0 ? f_old : (uint64_t)k_after + 1;
+            if (tid == 0) {
+                front_new[t] = q > 0 ? f_old : (uint64_t)k_after + 1;
+                nstale[t] = 0u;
+            }
             return;
         }
     }
 
-    touched[tid] = 0u;
-    pop_cnt[tid] = 0u;
-    if (tid < 6) counts[tid] = 0u;
+    const uint32_t n_len = q > tl.Q ? q - tl.Q : 0u;   // pops by target
+    uint32_t npre = n_len + 64u;
+    npre = npre < q_old ? npre : q_old;
+    npre = npre < kPre ? npre : kPre;
+    touched_w[tid] = 0u;
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) popc[tid + kTqThreads * j] = 0u;
+    if (tid < st.c1 - st.c0) ck[tid] = rb.chunk_k[st.c0 + tid];
+    for (uint32_t i = tid; i < npre; i += kTqThreads) pre[i] = ring[rbase + ((tl.head + i) & ring_mask)];
+    if (tid == 0) {
+        sh_first = q;
+        sh_nstale = 0u;
+        sh_red[0] = sh_red[1] = sh_red[2] = 0u;
+    }
+    // the step's first piece of events, kept in registers for the bucketing
+    uint64_t pl0[kPer];
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j) {
+        const uint32_t i = tid + kTqThreads * j;
+        pl0[j] = i < n_new ? rb.payload[lo + i] : 0ull;
+    }
     __syncthreads();
 
-    // events: into the ring (time order) and marked
-    for (uint64_t cur = lo; cur < hi; cur += 1024) {
-        const uint64_t e = cur + tid;
-        if (e < hi) {
-            const uint64_t pl = rb.payload[e];
-            const uint32_t pix = (uint32_t)(pl >> 32);
-            const uint32_t py = pix / g.W, px = pix - py * g.W;
-            const uint32_t lk = (py - ty0) * g.R + (px - tx0);
-            const uint32_t ch = (uint32_t)(pl >> 15) & 0xffu;
-            const uint64_t ge = (uint64_t)(rb.chunk_k[ch] + (int64_t)((pl >> 1) & 0x3fffu));
-            ring[rbase + ((tl.tail + (uint32_t)(e - lo)) & ring_mask)] = make_uint2((uint32_t)ge, lk);
+    // an event's local pixel and global index (low 32 bits) from its payload
+    auto decode = [&](uint64_t pl, uint32_t& lk, uint32_t& gi) {
+        const uint32_t pix = (uint32_t)(pl >> 32);
+        const uint32_t py = pix / g.W, px = pix - py * g.W;
+        lk = (py - ty0) * g.R + (px - tx0);
+        const uint32_t ch = (uint32_t)(pl >> 15) & 0xffu;
+        const int64_t kc = ch - st.c0 < kTqThreads ? ck[ch - st.c0] : rb.chunk_k[ch];
+        gi = (uint32_t)(uint64_t)(kc + (int64_t)((pl >> 1) & 0x3fffu));
+    };
+
+    // the packet's events join the back of the window
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j) {
+        const uint32_t i = tid + kTqThreads * j;
+        if (i < n_new) {
+            uint32_t lk, gi;
+            decode(pl0[j], lk, gi);
+            ring[rbase + ((tl.tail + i) & ring_mask)] = make_uint2(gi, lk);
             touched[lk] = 1u;
         }
     }
-    __syncthreads();   // the pushed entries are read back below
-    // pops: while the window is longer than the target, or its oldest event
-    // is age_max or more events old (both hold for a prefix of the window)
-    uint32_t my_old = 0u;
-    if ((uint64_t)k_after + 1 > age_max) {
-        const uint64_t lim = (uint64_t)k_after - age_max;   // events at or below leave
-        for (uint32_t i = tid; i < q; i += 1024) {
-            const uint2 en = ring[rbase + ((tl.head + i) & ring_mask)];
-            my_old += global_of(en.x) <= lim ? 1u : 0u;
+    for (uint32_t i = tid + kPiece; i < n_new; i += kTqThreads) {
+        uint32_t lk, gi;
+        decode(rb.payload[lo + i], lk, gi);
+        ring[rbase + ((tl.tail + i) & ring_mask)] = make_uint2(gi, lk);
+        touched[lk] = 1u;
+    }
+    // window entry i (0 = oldest): prefetched, else from the ring (the
+    // entries pushed above included)
+    auto entry = [&](uint32_t i) {
+        return i < npre ? pre[i] : ring[rbase + ((tl.head + i) & ring_mask)];
+    };
+    __threadfence_block();
+    __syncthreads();
+
+    // events that leave: a prefix of the window, by target and by age
+    uint32_t n_old = 0;
+    if (can_age) {
+        for (uint32_t b = 0; b < q; b += kTqThreads) {
+            const uint32_t i = b + tid;
+            if (i < q && global_of(entry(i).x) > lim) atomicMin(&sh_first, i);
+            __syncthreads();
+            n_old = sh_first;
+            __syncthreads();   // read by all before the next chunk's updates
+            if (n_old < q) break;
         }
     }
-    if (my_old) atomicAdd(&counts[2], my_old);
-    __syncthreads();
-    const uint32_t n_len = q > tl.Q ? q - tl.Q : 0u;
-    const uint32_t n_pop = counts[2] > n_len ? counts[2] : n_len;
-    for (uint32_t i = tid; i < n_pop; i += 1024) {
-        const uint2 en = ring[rbase + ((tl.head + i) & ring_mask)];
-        atomicAdd(&pop_cnt[en.y], 1u);
-        touched[en.y] = 1u;
+    const uint32_t n_pop = n_old > n_len ? n_old : n_len;
+    for (uint32_t i = tid; i < n_pop; i += kTqThreads) {
+        const uint32_t lk = entry(i).y;
+        atomicAdd(&popc[lk], 1u);
+        touched[lk] = 1u;
     }
-    __syncthreads();
     const uint32_t head1 = tl.head + n_pop;
     uint64_t f_new = (uint64_t)k_after + 1;
-    if (n_pop < q) f_new = global_of(ring[rbase + (head1 & ring_mask)].x);
+    if (n_pop < q) f_new = global_of(entry(n_pop).x);
+    __syncthreads();
 
-    // the pixels of touched 2x2 cells load their state
-    const uint32_t cx = lx & ~1u, cy = ly & ~1u;
-    const uint32_t c0 = cy * g.R + cx;
-    const bool cell_touched = own && (touched[c0] | (cx + 1 < tw ? touched[c0 + 1] : 0u) |
-                                      (cy + 1 < th ? touched[c0 + g.R] : 0u) |
-                                      (cx + 1 < tw && cy + 1 < th ? touched[c0 + g.R + 1] : 0u));
-    float pb = 0.f, l = 0.f, lb = 0.f, gain = 1.f;
-    int64_t last = -1;
-    uint32_t cnt = 0u;
-    uint64_t tot = 0u;
-    if (cell_touched) {
-        const PixL v = s.px[gp];
-        last = v.last;
-        lb = v.Lb;
-        l = v.last < (int64_t)f_old ? v.Lb : v.L;
-        if (touched[tid]) {
-            const PixP w = s.pp[gp];
-            pb = w.pbar;
-            cnt = w.cnt;
-            tot = w.tot;
-            if (s.gain) gain = s.gain[gp];
-        }
+    // this thread's cell: pixels q = 0..3 at (cx + (q & 1), cy + (q >> 1))
+    const uint32_t CR = g.R / 2;
+    const uint32_t cell = tid;
+    const uint32_t cx = (cell % CR) * 2, cy = (cell / CR) * 2;
+    const bool inc = cell < CR * CR;
+    const float cgain = 0.5f + 0.5f * coef.beta;
+    // pixel q's local and global indices, recomputed where needed
+    auto lk_of = [&](int qq) { return (cy + (qq >> 1)) * g.R + cx + (qq & 1); };
+    auto gp_of = [&](int qq) {
+        return (uint64_t)(ty0 + cy + (qq >> 1)) * g.W + tx0 + cx + (qq & 1);
+    };
+    bool in[4], tch[4];
+    float pb[4], l[4], c[4];
+    int64_t last[4];
+    uint32_t cnt[4], got[4];
+    uint64_t tot[4];
+    bool was[4];
+    bool has = false;
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+        const uint32_t lx = cx + (qq & 1), ly = cy + (qq >> 1);
+        in[qq] = inc && lx < tw && ly < th;
+        tch[qq] = in[qq] && touched[lk_of(qq)];
+        has |= tch[qq];
     }
-    const bool was_active = cell_touched && last >= (int64_t)f_old;
-
-    // the owner applies its pixel's events in time order (Eq. (7), then
-    // Eq. (6) and (10)), a piece of up to 1024 events at a time
-    const float c = (0.5f + 0.5f * coef.beta) * gain;
-    uint32_t got = 0u;
-    for (uint64_t cur = lo; cur < hi; cur += kPiece) {
-        const uint32_t m = (uint32_t)(hi - cur < kPiece ? hi - cur : kPiece);
-        __syncthreads();
-        if (tid < m) {
-            const uint2 en = ring[rbase + ((tl.tail + (uint32_t)(cur - lo) + tid) & ring_mask)];
-            const uint64_t pl = rb.payload[cur + tid];
-            ent_key[tid] = (en.y << 1) | (uint32_t)(pl & 1u);
-            ent_gi[tid] = en.x;
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+        in[qq] = in[qq] && has;
+        pb[qq] = l[qq] = 0.f;
+        c[qq] = cgain;
+        last[qq] = -1;
+        cnt[qq] = got[qq] = 0u;
+        tot[qq] = 0u;
+        if (in[qq]) {
+            const PixL v = s.px[gp_of(qq)];
+            last[qq] = v.last;
+            l[qq] = v.last < (int64_t)f_old ? v.Lb : v.L;
         }
+        if (tch[qq]) {
+            const PixP w = s.pp[gp_of(qq)];
+            pb[qq] = w.pbar;
+            cnt[qq] = w.cnt;
+            tot[qq] = w.tot;
+            if (s.gain) c[qq] = cgain * s.gain[gp_of(qq)];
+        }
+        was[qq] = in[qq] && last[qq] >= (int64_t)f_old;
+    }
+
+    // the cell's events in time order (Eq. (7), then Eq. (6) and (10))
+    for (uint32_t p0 = 0; p0 < n_new; p0 += kPiece) {
+        const uint32_t m = n_new - p0 < kPiece ? n_new - p0 : kPiece;
+        ccnt[tid] = 0u;
         __syncthreads();
-        if (own && touched[tid]) {
-            for (uint32_t e = 0; e < m; ++e) {
-                const uint32_t kp = ent_key[e];
-                if ((kp >> 1) != tid) continue;
-                const float p = (kp & 1u) ? 1.f : -1.f;
-                pb = fmaf(coef.alpha, pb, coef.one_m_alpha * p);
-                l = fmaf(coef.beta, l, c * (p - pb));
-                ++got;
-                last = (int64_t)global_of(ent_gi[e]);
+        uint32_t ek[kPer], eg[kPer], ec[kPer], es[kPer];
+#pragma unroll
+        for (uint32_t j = 0; j < kPer; ++j) {
+            const uint32_t i = tid + kTqThreads * j;
+            ec[j] = 0xffffffffu;
+            if (i < m) {
+                const uint64_t pl = p0 == 0 ? pl0[j] : rb.payload[lo + p0 + i];
+                uint32_t k2, gi;
+                decode(pl, k2, gi);
+                ek[j] = (k2 << 1) | (uint32_t)(pl & 1u);
+                eg[j] = gi;
+                ec[j] = (k2 / g.R / 2) * CR + (k2 % g.R) / 2;
+                es[j] = atomicAdd(&ccnt[ec[j]], 1u);
             }
         }
-    }
-    tot += got;
-    const bool active_a = was_active || got > 0u;
-    // a pixel goes stale when its newest event leaves: its last index is
-    // below the new front while it was active
-    const bool stale_now = own && active_a && last < (int64_t)f_new;
-    act_b[tid] = was_active ? 1u : 0u;
-    act_a[tid] = active_a ? 1u : 0u;
-    act_p[tid] = (active_a && !stale_now) ? 1u : 0u;
-    __syncthreads();
-    const bool cell_head = cell_touched && (lx & 1u) == 0u && (ly & 1u) == 0u;
-    auto cell_any = [&](const uint8_t* a) {
-        uint32_t v = a[tid];
-        if (lx + 1 < tw) v |= a[tid + 1];
-        if (ly + 1 < th) v |= a[tid + g.R];
-        if (lx + 1 < tw && ly + 1 < th) v |= a[tid + g.R + 1];
-        return v != 0u;
-    };
-    if (own && !was_active && active_a) atomicAdd(&counts[0], 1u);
-    if (cell_head) {
-        const bool b = cell_any(act_b), a_ = cell_any(act_a), p_ = cell_any(act_p);
-        if (!b && a_) atomicAdd(&counts[1], 1u);
-        if (a_ && !p_) atomicAdd(&counts[4], 1u);
-    }
-    if (stale_now) {
-        atomicAdd(&counts[3], 1u);
-        const uint32_t at = atomicAdd(&scratch[st.pkt].part[0][0], 1u);
-        stale_list[at] = (uint32_t)gp;
-    }
-    if (own && touched[tid]) {
-        cnt = cnt + got - pop_cnt[tid];
-        if (got) {
-            PixL v;
-            v.L = l;
-            v.Lb = lb;
-            v.last = last;
-            s.px[gp] = v;
+        __syncthreads();
+        const uint32_t nk = ccnt[tid];
+        const uint32_t incl = wave_incl_scan(nk, lane);
+        if (lane == 63) wtot[wv] = incl;
+        __syncthreads();
+        uint32_t b0 = incl - nk;
+        for (uint32_t w = 0; w < wv; ++w) b0 += wtot[w];
+        cstart[tid] = b0;
+        __syncthreads();
+#pragma unroll
+        for (uint32_t j = 0; j < kPer; ++j) {
+            if (ec[j] != 0xffffffffu) {
+                const uint32_t pos = cstart[ec[j]] + es[j];
+                keys[pos] = ek[j];
+                gis[pos] = eg[j];
+            }
         }
-        PixP w;
-        w.pbar = pb;
-        w.cnt = cnt;
-        w.tot = tot;
-        s.pp[gp] = w;
+        __syncthreads();
+        if (has && nk) {
+            // order the bucket by index: insertion sort, close to linear as
+            // the scatter leaves it nearly ordered
+            for (uint32_t a = 1; a < nk; ++a) {
+                const uint32_t kg = gis[b0 + a], kk = keys[b0 + a];
+                const uint64_t gv = global_of(kg);
+                uint32_t b = a;
+                while (b > 0 && global_of(gis[b0 + b - 1]) > gv) {
+                    gis[b0 + b] = gis[b0 + b - 1];
+                    keys[b0 + b] = keys[b0 + b - 1];
+                    --b;
+                }
+                gis[b0 + b] = kg;
+                keys[b0 + b] = kk;
+            }
+            for (uint32_t e = 0; e < nk; ++e) {
+                const uint32_t kp = keys[b0 + e];
+                const uint32_t pk = kp >> 1;
+                const int qq = (int)((pk & 1u) | (((pk / g.R) & 1u) << 1));
+                const float p = (kp & 1u) ? 1.f : -1.f;
+                const int64_t ge = (int64_t)global_of(gis[b0 + e]);
+                // fixed register indices: a run-time index would move the
+                // arrays to scratch
+#pragma unroll
+                for (int z = 0; z < 4; ++z) {
+                    if (z != qq) continue;
+                    pb[z] = fmaf(coef.alpha, pb[z], coef.one_m_alpha * p);
+                    l[z] = fmaf(coef.beta, l[z], c[z] * (p - pb[z]));
+                    ++got[z];
+                    last[z] = ge;
+                }
+            }
+        }
+        __syncthreads();   // the next piece reuses the buckets
+    }
+
+    bool b_any = false, a_any = false, p_any = false;
+    bool stale[4];
+    uint32_t my_n = 0, dP = 0;
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+        const bool act = was[qq] || got[qq] > 0u;
+        // a pixel goes stale when its newest event leaves: its last index
+        // is below the new front while it was active
+        stale[qq] = in[qq] && act && last[qq] < (int64_t)f_new;
+        b_any |= was[qq];
+        a_any |= act;
+        p_any |= act && !stale[qq];
+        dP += (!was[qq] && act) ? 1u : 0u;
+        my_n += stale[qq] ? 1u : 0u;
+    }
+    // places in the tile's list: a scan over the wave, one LDS atomic per wave
+    const uint32_t incl = wave_incl_scan(my_n, lane);
+    uint32_t wbase = 0;
+    if (lane == 63 && incl) wbase = atomicAdd(&sh_nstale, incl);
+    wbase = __shfl(wbase, 63, 64);
+    uint32_t at = wbase + incl - my_n;
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq)
+        if (stale[qq]) my_stale[at++] = (uint32_t)gp_of(qq);
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+        if (tch[qq]) {
+            PixL* pl = s.px + gp_of(qq);
+            if (got[qq]) {   // Lb stays
+                pl->L = l[qq];
+                pl->last = last[qq];
+            }
+            PixP w;
+            w.pbar = pb[qq];
+            w.cnt = cnt[qq] + got[qq] - popc[lk_of(qq)];
+            w.tot = tot[qq] + got[qq];
+            s.pp[gp_of(qq)] = w;
+        }
+    }
+    const uint32_t dT = wave_sum((has && !b_any && a_any) ? 1u : 0u);
+    const uint32_t n_gone = wave_sum((has && a_any && !p_any) ? 1u : 0u);
+    dP = wave_sum(dP);
+    if (lane == 0) {
+        if (dP) atomicAdd(&sh_red[0], dP);
+        if (dT) atomicAdd(&sh_red[1], dT);
+        if (n_gone) atomicAdd(&sh_red[2], n_gone);
     }
     __syncthreads();
     if (tid == 0) {
+        const uint32_t n_stale = sh_nstale;
         TQTile o = tl;
         o.head = head1;
         o.tail = tail;
-        o.P = tl.P + counts[0] - counts[3];
-        o.T = tl.T + counts[1] - counts[4];
+        o.P = tl.P + sh_red[0] - n_stale;
+        o.T = tl.T + sh_red[1] - sh_red[2];
         const uint32_t q1 = tail - head1;
         if (o.P > 0) {
             // Eq. (20): floor(q num 4 T / (den P)) from a double quotient
@@ -412,6 +559,8 @@ __global__ __launch_bounds__(1024) void k_tq_step(State s, TQGeom g, TQTile* __r
         }
         tiles[t] = o;
         front_new[t] = f_new;
+        nstale[t] = n_stale;
+        if (n_stale) atomicAdd(&scratch[st.pkt].part[0][0], n_stale);
     }
 }
 
@@ -422,13 +571,19 @@ __global__ __launch_bounds__(1024) void k_tq_step(State s, TQGeom g, TQTile* __r
 // stale pixels.
 __global__ __launch_bounds__(256) void k_tq_blur(State s, TQGeom g, const uint64_t* __restrict__ front,
                                                  uint32_t n_tiles, const uint32_t* __restrict__ stale_list,
+                                                 const uint32_t* __restrict__ nstale,
                                                  StepScratch* __restrict__ scratch,
                                                  const int64_t* __restrict__ chunk_k, TQStep st)
 {
     const uint64_t* front_old = front + (size_t)st.parity * n_tiles;
     const uint32_t n = scratch[st.pkt].status ? 0u : scratch[st.pkt].part[0][0];
-    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-        const uint32_t j = stale_list[i];
+    // a wave per tile, over the tile's own list
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t t = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint32_t nt = t < n_tiles ? nstale[t] : 0u;
+    const uint32_t* list = stale_list + (size_t)t * g.R * g.R;
+    for (uint32_t i = lane; i < nt; i += 64) {
+        const uint32_t j = list[i];
         const uint32_t y = j / g.W, x = j - y * g.W;
         const uint32_t xs[3] = {x > 0 ? x - 1 : 0, x, x + 1 < g.W ? x + 1 : g.W - 1};
         const uint32_t ys[3] = {y > 0 ? y - 1 : 0, y, y + 1 < g.H ? y + 1 : g.H - 1};
@@ -545,14 +700,14 @@ hipError_t tq_step(fibar_ctx* c, uint32_t c0, uint32_t c1, uint32_t n_chunks, ui
     st.pkt = pkt;
     st.parity = c->tq_parity;
     st.slot = c->cur_slot;
-    hipLaunchKernelGGL(k_tq_step, dim3(n), dim3(1024), 0, c->st, c->s, g, c->tq_tiles,
-                       c->tq_front, c->tq_ring, c->tq_cap - 1, c->tq_stale, c->rb, c->scratch, st,
-                       c->tq_age, c->coef);
+    hipLaunchKernelGGL(k_tq_step, dim3(n), dim3(kTqThreads), 0,
+                       c->st, c->s, g, n, c->tq_tiles, c->tq_front, c->tq_ring, c->tq_cap - 1,
+                       c->tq_stale, c->tq_nstale, c->rb, c->scratch, st, c->tq_age, c->coef);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tq_blur, dim3(64), dim3(256), 0, c->st, c->s, g,
-                       (const uint64_t*)c->tq_front, n, (const uint32_t*)c->tq_stale, c->scratch,
-                       (const int64_t*)c->rb.chunk_k, st);
+    hipLaunchKernelGGL(k_tq_blur, dim3((n + 3) / 4), dim3(256), 0, c->st, c->s, g,
+                       (const uint64_t*)c->tq_front, n, (const uint32_t*)c->tq_stale,
+                       (const uint32_t*)c->tq_nstale, c->scratch, (const int64_t*)c->rb.chunk_k, st);
     c->tq_parity ^= 1;
     return hipGetLastError();
 }
