@@ -32,6 +32,10 @@ namespace {
 using namespace tile;
 
 constexpr uint64_t kSentinelPix = 0xffffffffull;
+// Up to this many events of one pixel in a tile, k_region_apply orders a
+// pixel's events by insertion sort in its own bucket; above, the whole tile
+// takes the radix sort.
+constexpr uint32_t kInsertMax = 128;
 
 // Exclusive max-scan of u32 over a 1024-thread workgroup.
 __device__ uint32_t block_exscan_max(uint32_t x, uint32_t* lds)
@@ -261,6 +265,9 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
     __shared__ uint32_t scan1[kWaves + 1];
     __shared__ uint32_t run_cnt[kRegion + 1];
     __shared__ uint32_t ro_pos[kMaxBatchReadouts];    // readout position in the slice
+    __shared__ uint32_t ro_ce[kMaxBatchReadouts];     // chunk end, bit 31: optional outputs
+    __shared__ float* ro_L[kMaxBatchReadouts];        // brightness output
+    __shared__ uint32_t hot;                          // a pixel above kInsertMax events
 
     const uint32_t r = blockIdx.x;
     const uint32_t t = threadIdx.x;
@@ -283,9 +290,16 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
         if (s.gain) c *= s.gain[gp];
     }
     const uint64_t lo = rb.base[r], hi = rb.base[r + 1];
+    // the batch's readout descriptors, loaded once by all threads together
+    // (a descriptor load per readout inside the uniform loop below would be
+    // a dependent round trip each)
     for (uint32_t i = t; i < n_readouts; i += kSortThreads) {
-        const uint32_t ce = rb.ro[i].chunk_end;
+        const RegionReadout d = rb.ro[i];
+        const uint32_t ce = d.chunk_end;
         ro_pos[i] = ce < n_chunks ? rb.cnt[(size_t)ce * rb.n_regions + r] : (uint32_t)(hi - lo);
+        const bool opt = d.pbar || d.tot || d.last || d.log_age;
+        ro_ce[i] = ce | (opt ? 0x80000000u : 0u);
+        ro_L[i] = d.L;
     }
     __syncthreads();
     uint32_t next_ro = 0;   // first readout not written yet (uniform)
@@ -318,6 +332,10 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
         }
     };
     auto write_readout = [&](uint32_t i) {
+        if (!(ro_ce[i] >> 31)) {   // brightness only
+            if (own) ro_L[i][gp] = l;
+            return;
+        }
         const RegionReadout d = rb.ro[i];
         if (d.last || d.log_age) resolve_last();
         if (own) {
@@ -333,26 +351,55 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
         const uint32_t cn = (uint32_t)(hi - cursor < kChunk ? hi - cursor : kChunk);
         const uint32_t rel1 = (uint32_t)(cursor - lo) + cn;
         for (uint32_t k = t; k <= kRegion; k += kSortThreads) run_cnt[k] = 0u;
+        if (t == 0) hot = 0u;
         __syncthreads();
+        // each event's slot among its pixel's events of the tile (in whatever
+        // order the LDS atomics return them) goes to idxB
         for (uint32_t e = t; e < cn; e += kSortThreads) {
             const uint64_t pl = rb.payload[cursor + e];
             const uint64_t pix = pl >> 32;
             const uint32_t lk = pix == kSentinelPix ? kRegion : (uint32_t)(pix - p0);
             const uint32_t ch = (uint32_t)(pl >> 15) & 0xffu;
             keypol[e] = (ch << 24) | (lk << 1) | (uint32_t)(pl & 1u);
-            idxA[e] = (uint16_t)e;
-            atomicAdd(&run_cnt[lk], 1u);
+            idxB[e] = (uint16_t)atomicAdd(&run_cnt[lk], 1u);
         }
         __syncthreads();
+        const uint32_t my_cnt = run_cnt[t];
+        if (my_cnt > kInsertMax) hot = 1u;
         uint32_t total;
-        run_at = block_exscan_u32(run_cnt[t], scan1, &total);
-        run_end = run_at + run_cnt[t];
-        sorted = tile_sort(keypol, idxA, idxB, cn, 11, scan4);
+        run_at = block_exscan_u32(my_cnt, scan1, &total);   // ends with a barrier
+        run_end = run_at + my_cnt;
+        if (!hot) {
+            // counting sort by pixel: every event to its pixel's bucket, then
+            // each owner puts its bucket back in slice (= time) order
+            run_cnt[t] = run_at;
+            __syncthreads();
+            for (uint32_t e = t; e < cn; e += kSortThreads) {
+                const uint32_t lk = (keypol[e] >> 1) & 0x7ffu;
+                if (lk < kRegion) idxA[run_cnt[lk] + idxB[e]] = (uint16_t)e;
+            }
+            __syncthreads();
+            for (uint32_t a = run_at + 1; a < run_end; ++a) {
+                const uint16_t v = idxA[a];
+                uint32_t b = a;
+                while (b > run_at && idxA[b - 1] > v) {
+                    idxA[b] = idxA[b - 1];
+                    --b;
+                }
+                idxA[b] = v;
+            }
+            sorted = idxA;   // an owner reads only its own bucket from here on
+        } else {
+            // a pixel with many events in the tile: stable LDS radix sort
+            for (uint32_t e = t; e < cn; e += kSortThreads) idxA[e] = (uint16_t)e;
+            __syncthreads();
+            sorted = tile_sort(keypol, idxA, idxB, cn, 11, scan4);
+        }
         tile0 = cursor;
         if (!own) run_end = run_at;
         // readouts that fall inside this tile
         while (next_ro < n_readouts && ro_pos[next_ro] < rel1) {
-            advance(rb.ro[next_ro].chunk_end);
+            advance(ro_ce[next_ro] & 0x7fffffffu);
             write_readout(next_ro);
             ++next_ro;
         }
