@@ -36,6 +36,9 @@ constexpr uint64_t kSentinelPix = 0xffffffffull;
 // pixel's events by insertion sort in its own bucket; above, the whole tile
 // takes the radix sort.
 constexpr uint32_t kInsertMax = 128;
+// k_region_scatter counts per region in LDS up to this many regions (two per
+// thread); above, it takes the radix sort by region.
+constexpr uint32_t kScatterFastRegions = 2 * kSortThreads;
 
 // Exclusive max-scan of u32 over a 1024-thread workgroup.
 __device__ uint32_t block_exscan_max(uint32_t x, uint32_t* lds)
@@ -194,8 +197,15 @@ __global__ __launch_bounds__(kSortThreads) void k_region_scatter(
     __shared__ __align__(16) uint16_t idxB[kChunk];
     __shared__ uint64_t scan4[kWaves + 1][4];
     __shared__ uint32_t scan1[kWaves + 1];
+    __shared__ uint32_t rcnt[kScatterFastRegions];   // per region: count, then bucket start
+    __shared__ uint32_t hot;
     const ChunkDesc cd = chunks[blockIdx.x];
     const uint32_t cn = cd.n;
+    const uint32_t t = threadIdx.x;
+    const bool fast = n_regions <= kScatterFastRegions;
+    if (fast)
+        for (uint32_t r = t; r < n_regions; r += kSortThreads) rcnt[r] = 0u;
+    if (t == 0) hot = 0u;
     uint32_t bad = 0u;
     for (uint32_t e = threadIdx.x; e < cn; e += kSortThreads) {
         uint32_t pol;
@@ -204,10 +214,63 @@ __global__ __launch_bounds__(kSortThreads) void k_region_scatter(
         idxA[e] = (uint16_t)e;
     }
     __syncthreads();
-    // group by region only (stable, so arrival order is kept inside a region)
-    const uint16_t* sorted = tile_sort(keypol, idxA, idxB, cn, region_bits, scan4, 10);
     const bool valid = scratch[cd.pkt].status == 0u;
     const uint32_t* off_row = offs + (size_t)blockIdx.x * n_regions;
+    if (fast) {
+        // counting sort by region: each event's slot in its region's bucket
+        // (the workgroup takes the events in arrival order, 1024 at a time,
+        // so slots are close to arrival order), bucket starts by a scan, then
+        // every region's owner restores arrival order inside its bucket by
+        // insertion sort
+        for (uint32_t e = t; e < cn; e += kSortThreads)
+            idxB[e] = (uint16_t)atomicAdd(&rcnt[(keypol[e] >> 1) / kRegion], 1u);
+        __syncthreads();
+        const uint32_t per = (n_regions + kSortThreads - 1) / kSortThreads;   // <= 2
+        const uint32_t r0 = t * per;
+        uint32_t c0 = 0u, c1 = 0u;
+        if (r0 < n_regions) c0 = rcnt[r0];
+        if (per > 1 && r0 + 1 < n_regions) c1 = rcnt[r0 + 1];
+        if (c0 > kInsertMax || c1 > kInsertMax) hot = 1u;
+        uint32_t all;
+        const uint32_t s0 = block_exscan_u32(c0 + c1, scan1, &all);   // ends with a barrier
+        if (!hot) {
+            if (r0 < n_regions) rcnt[r0] = s0;
+            if (per > 1 && r0 + 1 < n_regions) rcnt[r0 + 1] = s0 + c0;
+            __syncthreads();
+            for (uint32_t e = t; e < cn; e += kSortThreads)
+                idxA[rcnt[(keypol[e] >> 1) / kRegion] + idxB[e]] = (uint16_t)e;
+            __syncthreads();
+            auto order = [&](uint32_t lo, uint32_t n) {
+                for (uint32_t a = lo + 1; a < lo + n; ++a) {
+                    const uint16_t v = idxA[a];
+                    uint32_t b = a;
+                    while (b > lo && idxA[b - 1] > v) {
+                        idxA[b] = idxA[b - 1];
+                        --b;
+                    }
+                    idxA[b] = v;
+                }
+            };
+            order(s0, c0);
+            order(s0 + c0, c1);
+            __syncthreads();
+            for (uint32_t sidx = t; sidx < cn; sidx += kSortThreads) {
+                const uint32_t oid = idxA[sidx];
+                const uint32_t kp = keypol[oid];
+                const uint32_t pix = kp >> 1;
+                const uint32_t reg = pix / kRegion;
+                const uint64_t dest = base[reg] + off_row[reg] + (sidx - rcnt[reg]);
+                const uint64_t pixf = valid ? (uint64_t)pix : kSentinelPix;
+                payload[dest] = (pixf << 32) | ((uint64_t)blockIdx.x << 15) |
+                                ((uint64_t)oid << 1) | (uint64_t)(kp & 1u);
+            }
+            return;
+        }
+        // a region with many of the chunk's events: the radix sort below
+        // (idxA still holds the arrival order)
+    }
+    // group by region only (stable, so arrival order is kept inside a region)
+    const uint16_t* sorted = tile_sort(keypol, idxA, idxB, cn, region_bits, scan4, 10);
 
     // rank of each item among the chunk's items of its region: position
     // minus the position of the region's first item (last head at or before)
