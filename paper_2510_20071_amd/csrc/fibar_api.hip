@@ -379,6 +379,7 @@ int run_region_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, u
     HIP_TRY(hipEventSynchronize(c->chunks_free));
     HIP_TRY(hipEventSynchronize(c->ro_free));
     uint32_t ci = 0, step = 0, nr = 0;
+    bool any_opt = false;   // a readout asks for more than the brightness
     for (size_t i = 0; i < n; ++i) {
         if (ops[i].kind == 1) {
             RegionReadout& d = c->h_ro[nr++];
@@ -389,6 +390,7 @@ int run_region_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, u
             d.last = ops[i].ro.last_index;
             d.log_age = ops[i].ro.log_age;
             d.tot = ops[i].ro.total_count;
+            any_opt = any_opt || d.pbar || d.last || d.log_age || d.tot;
             continue;
         }
         for (uint32_t off = 0; off < ops[i].n; off += kChunk) {
@@ -413,6 +415,7 @@ int run_region_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, u
     if (n_steps) HIP_TRY(hipMemsetAsync(c->scratch, 0, (size_t)n_steps * sizeof(StepScratch), c->st));
     HIP_TRY(timed_launch(c, 0, [&](const LaunchTiming& tm) {
         return launch_region_batch(c->s, c->cur_slot, c->d_chunks, n_chunks, c->scratch, c->rb, nr,
+                                   any_opt,
                                    c->key_bits, c->coef, c->st, tm);
     }));
     return FIBAR_OK;

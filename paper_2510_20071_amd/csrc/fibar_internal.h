@@ -245,10 +245,11 @@ struct TQTile {
     uint32_t pad[2];
 };
 
+// any_opt: some readout of the batch asks for more than the brightness.
 hipError_t launch_region_batch(const State& s, int slot, const ChunkDesc* d_chunks,
                                uint32_t n_chunks, StepScratch* scratch, const RegionBuffers& rb,
-                               uint32_t n_readouts, int key_bits, Coef coef, hipStream_t st,
-                               const LaunchTiming& tm = LaunchTiming());
+                               uint32_t n_readouts, bool any_opt, int key_bits, Coef coef,
+                               hipStream_t st, const LaunchTiming& tm = LaunchTiming());
 
 // ---- in-order path (fibar_kernels.hip) -----------------------------------
 // Workgroup sizes of the in-order kernels (on the 1280x720 stream with

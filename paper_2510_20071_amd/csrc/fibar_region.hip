@@ -32,6 +32,17 @@ namespace {
 using namespace tile;
 
 constexpr uint64_t kSentinelPix = 0xffffffffull;
+
+// A readout of a blur-off batch as k_region_apply keeps it in LDS: its
+// position in the region's slice, its chunk end (bit 31: outputs beyond the
+// brightness), and the brightness output.
+typedef __attribute__((address_space(1))) float GlobalF32;
+
+struct RoLds {
+    uint32_t pos;
+    uint32_t ce;
+    float* L;
+};
 // Up to this many events of one pixel in a tile, k_region_apply orders a
 // pixel's events by insertion sort in its own bucket; above, the whole tile
 // takes the radix sort.
@@ -315,6 +326,10 @@ __global__ __launch_bounds__(kSortThreads) void k_region_scatter(
 // readouts of the batch are visited in order by the whole workgroup: every
 // owner first applies its events that precede the readout, then all write
 // the readout together (coalesced).
+// kOpt: the batch has readouts with outputs beyond the brightness; without,
+// the kernel has no code path that loads while readouts are written (such a
+// path makes the compiler wait for every store in flight at each readout).
+template <bool kOpt>
 __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBuffers rb,
                                                                uint32_t n_chunks,
                                                                uint32_t n_readouts, Coef coef)
@@ -327,9 +342,7 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
     __shared__ uint64_t scan4[kWaves + 1][4];
     __shared__ uint32_t scan1[kWaves + 1];
     __shared__ uint32_t run_cnt[kRegion + 1];
-    __shared__ uint32_t ro_pos[kMaxBatchReadouts];    // readout position in the slice
-    __shared__ uint32_t ro_ce[kMaxBatchReadouts];     // chunk end, bit 31: optional outputs
-    __shared__ float* ro_L[kMaxBatchReadouts];        // brightness output
+    __shared__ RoLds ro_s[kMaxBatchReadouts];
     __shared__ uint32_t hot;                          // a pixel above kInsertMax events
 
     const uint32_t r = blockIdx.x;
@@ -359,12 +372,18 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
     for (uint32_t i = t; i < n_readouts; i += kSortThreads) {
         const RegionReadout d = rb.ro[i];
         const uint32_t ce = d.chunk_end;
-        ro_pos[i] = ce < n_chunks ? rb.cnt[(size_t)ce * rb.n_regions + r] : (uint32_t)(hi - lo);
         const bool opt = d.pbar || d.tot || d.last || d.log_age;
-        ro_ce[i] = ce | (opt ? 0x80000000u : 0u);
-        ro_L[i] = d.L;
+        RoLds q;
+        q.pos = ce < n_chunks ? rb.cnt[(size_t)ce * rb.n_regions + r] : (uint32_t)(hi - lo);
+        q.ce = ce | (opt ? 0x80000000u : 0u);
+        q.L = d.L;
+        ro_s[i] = q;
     }
     __syncthreads();
+    // the pixel's state is in registers from here on: a first use inside the
+    // loops below would wait there for every memory access in flight, and
+    // stores (the readouts) count among them
+    asm volatile("" ::"v"(pb), "v"(l), "v"(c), "v"(last), "v"(tot));
     uint32_t next_ro = 0;   // first readout not written yet (uniform)
 
     // own events of the current tile: sorted positions [run_at, run_end)
@@ -381,11 +400,14 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
             last_pos = 0xffffffffu;
         }
     };
+    // the owner's next event of the tile (key), loaded one event ahead
+    uint32_t nkp = 0u;
     // apply own events of the tile whose chunk is below `chunk_limit`
     auto advance = [&](uint32_t chunk_limit) {
         while (run_at < run_end) {
-            const uint32_t kp = keypol[sorted[run_at]];
+            const uint32_t kp = nkp;
             if ((kp >> 24) >= chunk_limit) break;
+            if (run_at + 1 < run_end) nkp = keypol[sorted[run_at + 1]];
             const float p = (kp & 1u) ? 1.f : -1.f;
             pb = fmaf(coef.alpha, pb, coef.one_m_alpha * p);    // Eq. (7)
             l = fmaf(coef.beta, l, c * (p - pb));                 // Eq. (6), (10)
@@ -394,9 +416,11 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
             ++run_at;
         }
     };
-    auto write_readout = [&](uint32_t i) {
-        if (!(ro_ce[i] >> 31)) {   // brightness only
-            if (own) ro_L[i][gp] = l;
+    auto write_readout = [&](uint32_t i, const RoLds& q) {
+        if (!kOpt || !(q.ce >> 31)) {   // brightness only
+            // a global (not flat) store: a flat store would also count as an
+            // LDS access and make every later LDS read wait for it
+            if (own) ((GlobalF32*)q.L)[gp] = l;
             return;
         }
         const RegionReadout d = rb.ro[i];
@@ -416,17 +440,22 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
         for (uint32_t k = t; k <= kRegion; k += kSortThreads) run_cnt[k] = 0u;
         if (t == 0) hot = 0u;
         __syncthreads();
-        // each event's slot among its pixel's events of the tile (in whatever
-        // order the LDS atomics return them) goes to idxB
-        for (uint32_t e = t; e < cn; e += kSortThreads) {
-            const uint64_t pl = rb.payload[cursor + e];
-            const uint64_t pix = pl >> 32;
-            const uint32_t lk = pix == kSentinelPix ? kRegion : (uint32_t)(pix - p0);
-            const uint32_t ch = (uint32_t)(pl >> 15) & 0xffu;
-            keypol[e] = (ch << 24) | (lk << 1) | (uint32_t)(pl & 1u);
-            idxB[e] = (uint16_t)atomicAdd(&run_cnt[lk], 1u);
+        // each event's slot among its pixel's events of the tile goes to
+        // idxB; a barrier between rounds of 1024 events keeps the slots of a
+        // round after those of the rounds before (only events of one pixel
+        // in the same round can come out of order)
+        for (uint32_t e0 = 0; e0 < cn; e0 += kSortThreads) {
+            const uint32_t e = e0 + t;
+            if (e < cn) {
+                const uint64_t pl = rb.payload[cursor + e];
+                const uint64_t pix = pl >> 32;
+                const uint32_t lk = pix == kSentinelPix ? kRegion : (uint32_t)(pix - p0);
+                const uint32_t ch = (uint32_t)(pl >> 15) & 0xffu;
+                keypol[e] = (ch << 24) | (lk << 1) | (uint32_t)(pl & 1u);
+                idxB[e] = (uint16_t)atomicAdd(&run_cnt[lk], 1u);
+            }
+            __syncthreads();
         }
-        __syncthreads();
         const uint32_t my_cnt = run_cnt[t];
         if (my_cnt > kInsertMax) hot = 1u;
         uint32_t total;
@@ -442,7 +471,10 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
                 if (lk < kRegion) idxA[run_cnt[lk] + idxB[e]] = (uint16_t)e;
             }
             __syncthreads();
-            for (uint32_t a = run_at + 1; a < run_end; ++a) {
+            // already in order? (independent loads, no stores)
+            bool ordered = true;
+            for (uint32_t a = run_at + 1; a < run_end; ++a) ordered &= idxA[a - 1] < idxA[a];
+            for (uint32_t a = ordered ? run_end : run_at + 1; a < run_end; ++a) {
                 const uint16_t v = idxA[a];
                 uint32_t b = a;
                 while (b > run_at && idxA[b - 1] > v) {
@@ -460,18 +492,26 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
         }
         tile0 = cursor;
         if (!own) run_end = run_at;
-        // readouts that fall inside this tile
-        while (next_ro < n_readouts && ro_pos[next_ro] < rel1) {
-            advance(ro_ce[next_ro] & 0x7fffffffu);
-            write_readout(next_ro);
-            ++next_ro;
+        if (run_at < run_end) nkp = keypol[sorted[run_at]];
+        // readouts that fall inside this tile (the next descriptor is loaded
+        // while the current one is written)
+        if (next_ro < n_readouts) {
+            RoLds q = ro_s[next_ro];
+            while (q.pos < rel1) {
+                const RoLds qn = ro_s[next_ro + 1 < n_readouts ? next_ro + 1 : next_ro];
+                advance(q.ce & 0x7fffffffu);
+                write_readout(next_ro, q);
+                ++next_ro;
+                if (next_ro >= n_readouts) break;
+                q = qn;
+            }
         }
         advance(0xffffffffu);
         resolve_last();
         __syncthreads();
         cursor += cn;
     }
-    while (next_ro < n_readouts) write_readout(next_ro++);
+    for (; next_ro < n_readouts; ++next_ro) write_readout(next_ro, ro_s[next_ro]);
     if (own) {
         s.pp[gp].pbar = pb;
         s.pp[gp].tot = tot;
@@ -495,8 +535,8 @@ hipError_t launch_region_scan_bases(const State& s, int slot, const ChunkDesc* d
 
 hipError_t launch_region_batch(const State& s, int slot, const ChunkDesc* d_chunks,
                                uint32_t n_chunks, StepScratch* scratch, const RegionBuffers& rb,
-                               uint32_t n_readouts, int key_bits, Coef coef, hipStream_t st,
-                               const LaunchTiming& tm)
+                               uint32_t n_readouts, bool any_opt, int key_bits, Coef coef,
+                               hipStream_t st, const LaunchTiming& tm)
 {
     if (n_chunks > 0) {
         const hipError_t e = launch_timed(k_region_count, dim3(n_chunks), dim3(1024), st,
@@ -520,8 +560,11 @@ hipError_t launch_region_batch(const State& s, int slot, const ChunkDesc* d_chun
         hipLaunchKernelGGL(k_region_bases, dim3(1), dim3(1024), 0, st, s, slot, d_chunks, 0u,
                            scratch, rb, 1);
     }
-    return launch_timed(k_region_apply, dim3(rb.n_regions), dim3(kSortThreads), st, nullptr,
-                        tm.stop, s, rb, n_chunks, n_readouts, coef);
+    if (any_opt)
+        return launch_timed(k_region_apply<true>, dim3(rb.n_regions), dim3(kSortThreads), st,
+                            nullptr, tm.stop, s, rb, n_chunks, n_readouts, coef);
+    return launch_timed(k_region_apply<false>, dim3(rb.n_regions), dim3(kSortThreads), st,
+                        nullptr, tm.stop, s, rb, n_chunks, n_readouts, coef);
 }
 
 }  // namespace fibar
