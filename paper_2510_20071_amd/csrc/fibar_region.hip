@@ -338,12 +338,9 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
     // packets (bits 1..11) | polarity (bit 0)
     __shared__ uint32_t keypol[kChunk];
     __shared__ __align__(16) uint16_t idxA[kChunk];
-    __shared__ __align__(16) uint16_t idxB[kChunk];
-    __shared__ uint64_t scan4[kWaves + 1][4];
+    __shared__ __align__(16) uint16_t wcnt[kWaves * kRegion];   // per wave and pixel
     __shared__ uint32_t scan1[kWaves + 1];
-    __shared__ uint32_t run_cnt[kRegion + 1];
     __shared__ RoLds ro_s[kMaxBatchReadouts];
-    __shared__ uint32_t hot;                          // a pixel above kInsertMax events
 
     const uint32_t r = blockIdx.x;
     const uint32_t t = threadIdx.x;
@@ -437,59 +434,85 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
     for (uint64_t cursor = lo; cursor < hi;) {
         const uint32_t cn = (uint32_t)(hi - cursor < kChunk ? hi - cursor : kChunk);
         const uint32_t rel1 = (uint32_t)(cursor - lo) + cn;
-        for (uint32_t k = t; k <= kRegion; k += kSortThreads) run_cnt[k] = 0u;
-        if (t == 0) hot = 0u;
-        __syncthreads();
-        // each event's slot among its pixel's events of the tile goes to
-        // idxB; a barrier between rounds of 1024 events keeps the slots of a
-        // round after those of the rounds before (only events of one pixel
-        // in the same round can come out of order)
-        for (uint32_t e0 = 0; e0 < cn; e0 += kSortThreads) {
-            const uint32_t e = e0 + t;
-            if (e < cn) {
-                const uint64_t pl = rb.payload[cursor + e];
-                const uint64_t pix = pl >> 32;
-                const uint32_t lk = pix == kSentinelPix ? kRegion : (uint32_t)(pix - p0);
-                const uint32_t ch = (uint32_t)(pl >> 15) & 0xffu;
-                keypol[e] = (ch << 24) | (lk << 1) | (uint32_t)(pl & 1u);
-                idxB[e] = (uint16_t)atomicAdd(&run_cnt[lk], 1u);
+        // a stable counting sort by pixel: wave w takes a contiguous part of
+        // the tile in order, 64 events at a time; lanes with the same pixel
+        // are ranked by a match over the pixel bits, and wcnt[w][pixel]
+        // counts, then places, the wave's events of each pixel, so every
+        // bucket ends up in slice (= time) order
+        const uint32_t wave = t >> 6, lane = t & 63;
+        const uint64_t lt_mask = (1ull << lane) - 1ull;
+        uint16_t* wrow = wcnt + (size_t)wave * kRegion;
+#pragma unroll
+        for (uint32_t j = 0; j < kRegion / 64; ++j) wrow[lane + 64 * j] = 0u;
+        for (uint32_t e0 = 0; e0 < cn; e0 += 4 * kSortThreads) {
+            uint64_t pl[4];
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) {
+                const uint32_t e = e0 + t + j * kSortThreads;
+                pl[j] = e < cn ? rb.payload[cursor + e] : 0ull;
             }
-            __syncthreads();
+#pragma unroll
+            for (uint32_t j = 0; j < 4; ++j) {
+                const uint32_t e = e0 + t + j * kSortThreads;
+                if (e < cn) {
+                    const uint64_t pix = pl[j] >> 32;
+                    const uint32_t lk = pix == kSentinelPix ? kRegion : (uint32_t)(pix - p0);
+                    const uint32_t ch = (uint32_t)(pl[j] >> 15) & 0xffu;
+                    keypol[e] = (ch << 24) | (lk << 1) | (uint32_t)(pl[j] & 1u);
+                }
+            }
         }
-        const uint32_t my_cnt = run_cnt[t];
-        if (my_cnt > kInsertMax) hot = 1u;
+        __syncthreads();
+        const uint32_t seg = ((cn + kWaves - 1) / kWaves + 63u) & ~63u;
+        const uint32_t w0 = wave * seg, w1 = min(w0 + seg, cn);
+        // lanes of the step with the same pixel as this one (rejected
+        // packets' events take part in none)
+        auto peers = [&](uint32_t e, uint32_t& lk) {
+            lk = e < w1 ? (keypol[e] >> 1) & 0x7ffu : kRegion;
+            uint64_t m = __ballot(lk < kRegion);
+#pragma unroll
+            for (int bit = 0; bit < 10; ++bit) {
+                const uint64_t bb = __ballot((lk >> bit) & 1u);
+                m &= ((lk >> bit) & 1u) ? bb : ~bb;
+            }
+            return m;
+        };
+        for (uint32_t base = w0; base < w1; base += 64) {
+            uint32_t lk;
+            const uint64_t m = peers(base + lane, lk);
+            if (lk < kRegion && (m & lt_mask) == 0ull)
+                wrow[lk] = (uint16_t)(wrow[lk] + __popcll(m));
+        }
+        __syncthreads();
+        // the owner: its pixel's count, the bucket start, and each wave's
+        // place in the bucket
+        uint32_t my_cnt = 0;
+#pragma unroll
+        for (uint32_t w = 0; w < (uint32_t)kWaves; ++w) my_cnt += wcnt[w * kRegion + t];
         uint32_t total;
         run_at = block_exscan_u32(my_cnt, scan1, &total);   // ends with a barrier
         run_end = run_at + my_cnt;
-        if (!hot) {
-            // counting sort by pixel: every event to its pixel's bucket, then
-            // each owner puts its bucket back in slice (= time) order
-            run_cnt[t] = run_at;
-            __syncthreads();
-            for (uint32_t e = t; e < cn; e += kSortThreads) {
-                const uint32_t lk = (keypol[e] >> 1) & 0x7ffu;
-                if (lk < kRegion) idxA[run_cnt[lk] + idxB[e]] = (uint16_t)e;
+        {
+            uint32_t at = run_at;
+#pragma unroll
+            for (uint32_t w = 0; w < (uint32_t)kWaves; ++w) {
+                const uint32_t cw = wcnt[w * kRegion + t];
+                wcnt[w * kRegion + t] = (uint16_t)at;
+                at += cw;
             }
-            __syncthreads();
-            // already in order? (independent loads, no stores)
-            bool ordered = true;
-            for (uint32_t a = run_at + 1; a < run_end; ++a) ordered &= idxA[a - 1] < idxA[a];
-            for (uint32_t a = ordered ? run_end : run_at + 1; a < run_end; ++a) {
-                const uint16_t v = idxA[a];
-                uint32_t b = a;
-                while (b > run_at && idxA[b - 1] > v) {
-                    idxA[b] = idxA[b - 1];
-                    --b;
-                }
-                idxA[b] = v;
-            }
-            sorted = idxA;   // an owner reads only its own bucket from here on
-        } else {
-            // a pixel with many events in the tile: stable LDS radix sort
-            for (uint32_t e = t; e < cn; e += kSortThreads) idxA[e] = (uint16_t)e;
-            __syncthreads();
-            sorted = tile_sort(keypol, idxA, idxB, cn, 11, scan4);
         }
+        __syncthreads();
+        for (uint32_t base = w0; base < w1; base += 64) {
+            uint32_t lk;
+            const uint64_t m = peers(base + lane, lk);
+            if (lk < kRegion) {
+                const uint32_t b0 = wrow[lk];
+                idxA[b0 + __popcll(m & lt_mask)] = (uint16_t)(base + lane);
+                if ((m & lt_mask) == 0ull) wrow[lk] = (uint16_t)(b0 + __popcll(m));
+            }
+        }
+        __syncthreads();
+        sorted = idxA;   // an owner reads only its own bucket from here on
         tile0 = cursor;
         if (!own) run_end = run_at;
         if (run_at < run_end) nkp = keypol[sorted[run_at]];
