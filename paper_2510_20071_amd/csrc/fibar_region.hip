@@ -43,13 +43,6 @@ struct RoLds {
     uint32_t ce;
     float* L;
 };
-// Up to this many events of one pixel in a tile, k_region_apply orders a
-// pixel's events by insertion sort in its own bucket; above, the whole tile
-// takes the radix sort.
-constexpr uint32_t kInsertMax = 128;
-// k_region_scatter counts per region in LDS up to this many regions (two per
-// thread); above, it takes the radix sort by region.
-constexpr uint32_t kScatterFastRegions = 2 * kSortThreads;
 
 // Exclusive max-scan of u32 over a 1024-thread workgroup.
 __device__ uint32_t block_exscan_max(uint32_t x, uint32_t* lds)
@@ -102,15 +95,63 @@ __device__ uint32_t block256_exscan(uint32_t x, uint32_t* lds, uint32_t* total)
     return before + inc - x;
 }
 
-__device__ __forceinline__ uint32_t event_key(const ChunkDesc& cd, uint32_t e, uint32_t W,
-                                              uint32_t H, uint32_t* bad, uint32_t* pol)
+// Atomic add to a 16-bit LDS counter (the aligned 32-bit word that holds it;
+// counters never exceed 16384, so no carry crosses into the neighbour);
+// returns the counter's old value.
+__device__ __forceinline__ uint32_t lds_add_u16(uint16_t* base, uint32_t i, uint32_t v)
 {
-    const uint32_t x = cd.x[e], y = cd.y[e], p = cd.p[e];
-    const bool inr = x < W && y < H;
-    *bad |= inr ? 0u : 1u;
-    *bad |= p > 1u ? 2u : 0u;
-    *pol = p & 1u;
-    return inr ? y * W + x : 0u;
+    uint32_t* w = reinterpret_cast<uint32_t*>(base) + (i >> 1);
+    const uint32_t sh = (i & 1u) * 16u;
+    return (atomicAdd(w, v << sh) >> sh) & 0xffffu;
+}
+
+// Puts a bucket of event indices [at, at + n) in increasing order: a check
+// with independent loads first, insertion sort only where it finds a pair
+// out of order (the buckets come out of the counting sorts nearly sorted).
+__device__ __forceinline__ void order_bucket(uint16_t* idx, uint32_t at, uint32_t n)
+{
+    bool ordered = true;
+    for (uint32_t a = at + 1; a < at + n; ++a) ordered &= idx[a - 1] < idx[a];
+    if (ordered) return;
+    for (uint32_t a = at + 1; a < at + n; ++a) {
+        const uint16_t v = idx[a];
+        uint32_t b = a;
+        while (b > at && idx[b - 1] > v) {
+            idx[b] = idx[b - 1];
+            --b;
+        }
+        idx[b] = v;
+    }
+}
+
+// f(e, key, pol) for every event of the chunk, e = threadIdx.x + k * 1024;
+// the coordinates of eight events are loaded before any is used, so that
+// a thread has eight loads in flight rather than one.
+template <class F>
+__device__ __forceinline__ void for_chunk_events(const ChunkDesc& cd, uint32_t W, uint32_t H,
+                                                 uint32_t* bad, F&& f)
+{
+    constexpr uint32_t kU = 8;
+    for (uint32_t e0 = threadIdx.x; e0 < cd.n; e0 += kU * kSortThreads) {
+        uint32_t x[kU], y[kU], p[kU];
+#pragma unroll
+        for (uint32_t j = 0; j < kU; ++j) {
+            const uint32_t e = e0 + j * kSortThreads;
+            x[j] = e < cd.n ? cd.x[e] : 0u;
+            y[j] = e < cd.n ? cd.y[e] : 0u;
+            p[j] = e < cd.n ? cd.p[e] : 0u;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kU; ++j) {
+            const uint32_t e = e0 + j * kSortThreads;
+            if (e < cd.n) {
+                const bool inr = x[j] < W && y[j] < H;
+                *bad |= inr ? 0u : 1u;
+                *bad |= p[j] > 1u ? 2u : 0u;
+                f(e, inr ? y[j] * W + x[j] : 0u, p[j] & 1u);
+            }
+        }
+    }
 }
 
 __global__ __launch_bounds__(1024) void k_region_count(const ChunkDesc* __restrict__ chunks,
@@ -125,11 +166,9 @@ __global__ __launch_bounds__(1024) void k_region_count(const ChunkDesc* __restri
     if (threadIdx.x == 0) bad_sh = 0u;
     __syncthreads();
     uint32_t bad = 0u;
-    for (uint32_t e = threadIdx.x; e < cd.n; e += blockDim.x) {
-        uint32_t pol;
-        const uint32_t key = event_key(cd, e, W, H, &bad, &pol);
+    for_chunk_events(cd, W, H, &bad, [&](uint32_t, uint32_t key, uint32_t) {
         atomicAdd(&hist[key / kRegion], 1u);
-    }
+    });
     if (bad) atomicOr(&bad_sh, bad);
     __syncthreads();
     if (threadIdx.x == 0 && bad_sh) atomicOr(&scratch[cd.pkt].status, bad_sh);
@@ -208,77 +247,74 @@ __global__ __launch_bounds__(kSortThreads) void k_region_scatter(
     __shared__ __align__(16) uint16_t idxB[kChunk];
     __shared__ uint64_t scan4[kWaves + 1][4];
     __shared__ uint32_t scan1[kWaves + 1];
-    __shared__ uint32_t rcnt[kScatterFastRegions];   // per region: count, then bucket start
-    __shared__ uint32_t hot;
+    __shared__ uint32_t rcnt[kRegion];   // per region: bucket start
     const ChunkDesc cd = chunks[blockIdx.x];
     const uint32_t cn = cd.n;
     const uint32_t t = threadIdx.x;
-    const bool fast = n_regions <= kScatterFastRegions;
-    if (fast)
-        for (uint32_t r = t; r < n_regions; r += kSortThreads) rcnt[r] = 0u;
-    if (t == 0) hot = 0u;
+    // up to kRegion regions: a counting sort (per-wave counters in idxB)
+    const bool fast = n_regions <= kRegion;
+    if (fast) {
+        uint16_t* wrow = idxB + (size_t)(t >> 6) * kRegion;
+#pragma unroll
+        for (uint32_t j = 0; j < kRegion / 64; ++j) wrow[(t & 63) + 64 * j] = 0u;
+    }
     uint32_t bad = 0u;
-    for (uint32_t e = threadIdx.x; e < cn; e += kSortThreads) {
-        uint32_t pol;
-        const uint32_t key = event_key(cd, e, W, H, &bad, &pol);
+    for_chunk_events(cd, W, H, &bad, [&](uint32_t e, uint32_t key, uint32_t pol) {
         keypol[e] = (key << 1) | pol;
         idxA[e] = (uint16_t)e;
-    }
+    });
     __syncthreads();
     const bool valid = scratch[cd.pkt].status == 0u;
     const uint32_t* off_row = offs + (size_t)blockIdx.x * n_regions;
     if (fast) {
-        // counting sort by region: each event's slot in its region's bucket
-        // (the workgroup takes the events in arrival order, 1024 at a time,
-        // so slots are close to arrival order), bucket starts by a scan, then
-        // every region's owner restores arrival order inside its bucket by
-        // insertion sort
-        for (uint32_t e = t; e < cn; e += kSortThreads)
-            idxB[e] = (uint16_t)atomicAdd(&rcnt[(keypol[e] >> 1) / kRegion], 1u);
+        // counting sort by region: wave w takes a contiguous part of the
+        // chunk in order, 64 events at a time, and row w of idxB counts, then
+        // places, the wave's events of each region (LDS atomics); a
+        // region's bucket is then in arrival order except where one step of
+        // a wave had several of its events, which the region's owner puts
+        // right by insertion sort
+        const uint32_t wave = t >> 6, lane = t & 63;
+        uint16_t* wrow = idxB + (size_t)wave * kRegion;
+        const uint32_t seg = ((cn + kWaves - 1) / kWaves + 63u) & ~63u;
+        const uint32_t w0 = wave * seg, w1 = min(w0 + seg, cn);
+        for (uint32_t s0e = w0 + lane; s0e < w1; s0e += 64)
+            lds_add_u16(wrow, (keypol[s0e] >> 1) / kRegion, 1u);
         __syncthreads();
-        const uint32_t per = (n_regions + kSortThreads - 1) / kSortThreads;   // <= 2
-        const uint32_t r0 = t * per;
-        uint32_t c0 = 0u, c1 = 0u;
-        if (r0 < n_regions) c0 = rcnt[r0];
-        if (per > 1 && r0 + 1 < n_regions) c1 = rcnt[r0 + 1];
-        if (c0 > kInsertMax || c1 > kInsertMax) hot = 1u;
-        uint32_t all;
-        const uint32_t s0 = block_exscan_u32(c0 + c1, scan1, &all);   // ends with a barrier
-        if (!hot) {
-            if (r0 < n_regions) rcnt[r0] = s0;
-            if (per > 1 && r0 + 1 < n_regions) rcnt[r0 + 1] = s0 + c0;
-            __syncthreads();
-            for (uint32_t e = t; e < cn; e += kSortThreads)
-                idxA[rcnt[(keypol[e] >> 1) / kRegion] + idxB[e]] = (uint16_t)e;
-            __syncthreads();
-            auto order = [&](uint32_t lo, uint32_t n) {
-                for (uint32_t a = lo + 1; a < lo + n; ++a) {
-                    const uint16_t v = idxA[a];
-                    uint32_t b = a;
-                    while (b > lo && idxA[b - 1] > v) {
-                        idxA[b] = idxA[b - 1];
-                        --b;
-                    }
-                    idxA[b] = v;
-                }
-            };
-            order(s0, c0);
-            order(s0 + c0, c1);
-            __syncthreads();
-            for (uint32_t sidx = t; sidx < cn; sidx += kSortThreads) {
-                const uint32_t oid = idxA[sidx];
-                const uint32_t kp = keypol[oid];
-                const uint32_t pix = kp >> 1;
-                const uint32_t reg = pix / kRegion;
-                const uint64_t dest = base[reg] + off_row[reg] + (sidx - rcnt[reg]);
-                const uint64_t pixf = valid ? (uint64_t)pix : kSentinelPix;
-                payload[dest] = (pixf << 32) | ((uint64_t)blockIdx.x << 15) |
-                                ((uint64_t)oid << 1) | (uint64_t)(kp & 1u);
-            }
-            return;
+        // region t's owner: its count, the bucket start, each wave's place
+        uint32_t cr = 0;
+        if (t < n_regions) {
+#pragma unroll
+            for (uint32_t w = 0; w < (uint32_t)kWaves; ++w) cr += idxB[w * kRegion + t];
         }
-        // a region with many of the chunk's events: the radix sort below
-        // (idxA still holds the arrival order)
+        uint32_t all;
+        const uint32_t s0 = block_exscan_u32(cr, scan1, &all);   // ends with a barrier
+        if (t < n_regions) {
+            rcnt[t] = s0;
+            uint32_t at = s0;
+#pragma unroll
+            for (uint32_t w = 0; w < (uint32_t)kWaves; ++w) {
+                const uint32_t cw = idxB[w * kRegion + t];
+                idxB[w * kRegion + t] = (uint16_t)at;
+                at += cw;
+            }
+        }
+        __syncthreads();
+        for (uint32_t s0e = w0 + lane; s0e < w1; s0e += 64)
+            idxA[lds_add_u16(wrow, (keypol[s0e] >> 1) / kRegion, 1u)] = (uint16_t)s0e;
+        __syncthreads();
+        if (t < n_regions) order_bucket(idxA, rcnt[t], cr);
+        __syncthreads();
+        for (uint32_t sidx = t; sidx < cn; sidx += kSortThreads) {
+            const uint32_t oid = idxA[sidx];
+            const uint32_t kp = keypol[oid];
+            const uint32_t pix = kp >> 1;
+            const uint32_t reg = pix / kRegion;
+            const uint64_t dest = base[reg] + off_row[reg] + (sidx - rcnt[reg]);
+            const uint64_t pixf = valid ? (uint64_t)pix : kSentinelPix;
+            payload[dest] = (pixf << 32) | ((uint64_t)blockIdx.x << 15) |
+                            ((uint64_t)oid << 1) | (uint64_t)(kp & 1u);
+        }
+        return;
     }
     // group by region only (stable, so arrival order is kept inside a region)
     const uint16_t* sorted = tile_sort(keypol, idxA, idxB, cn, region_bits, scan4, 10);
@@ -434,13 +470,13 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
     for (uint64_t cursor = lo; cursor < hi;) {
         const uint32_t cn = (uint32_t)(hi - cursor < kChunk ? hi - cursor : kChunk);
         const uint32_t rel1 = (uint32_t)(cursor - lo) + cn;
-        // a stable counting sort by pixel: wave w takes a contiguous part of
-        // the tile in order, 64 events at a time; lanes with the same pixel
-        // are ranked by a match over the pixel bits, and wcnt[w][pixel]
-        // counts, then places, the wave's events of each pixel, so every
-        // bucket ends up in slice (= time) order
+        // counting sort by pixel: wave w takes a contiguous part of the tile
+        // in order, 64 events at a time, and wcnt[w][pixel] counts, then
+        // places, the wave's events of each pixel (LDS atomics); a pixel's
+        // bucket is then in slice (= time) order except where one step of a
+        // wave had several of its events, which the owner puts right by
+        // insertion sort
         const uint32_t wave = t >> 6, lane = t & 63;
-        const uint64_t lt_mask = (1ull << lane) - 1ull;
         uint16_t* wrow = wcnt + (size_t)wave * kRegion;
 #pragma unroll
         for (uint32_t j = 0; j < kRegion / 64; ++j) wrow[lane + 64 * j] = 0u;
@@ -465,23 +501,10 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
         __syncthreads();
         const uint32_t seg = ((cn + kWaves - 1) / kWaves + 63u) & ~63u;
         const uint32_t w0 = wave * seg, w1 = min(w0 + seg, cn);
-        // lanes of the step with the same pixel as this one (rejected
-        // packets' events take part in none)
-        auto peers = [&](uint32_t e, uint32_t& lk) {
-            lk = e < w1 ? (keypol[e] >> 1) & 0x7ffu : kRegion;
-            uint64_t m = __ballot(lk < kRegion);
-#pragma unroll
-            for (int bit = 0; bit < 10; ++bit) {
-                const uint64_t bb = __ballot((lk >> bit) & 1u);
-                m &= ((lk >> bit) & 1u) ? bb : ~bb;
-            }
-            return m;
-        };
-        for (uint32_t base = w0; base < w1; base += 64) {
-            uint32_t lk;
-            const uint64_t m = peers(base + lane, lk);
-            if (lk < kRegion && (m & lt_mask) == 0ull)
-                wrow[lk] = (uint16_t)(wrow[lk] + __popcll(m));
+        // rejected packets' events (pixel kRegion) take part in none
+        for (uint32_t e = w0 + lane; e < w1; e += 64) {
+            const uint32_t lk = (keypol[e] >> 1) & 0x7ffu;
+            if (lk < kRegion) lds_add_u16(wrow, lk, 1u);
         }
         __syncthreads();
         // the owner: its pixel's count, the bucket start, and each wave's
@@ -502,16 +525,12 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
             }
         }
         __syncthreads();
-        for (uint32_t base = w0; base < w1; base += 64) {
-            uint32_t lk;
-            const uint64_t m = peers(base + lane, lk);
-            if (lk < kRegion) {
-                const uint32_t b0 = wrow[lk];
-                idxA[b0 + __popcll(m & lt_mask)] = (uint16_t)(base + lane);
-                if ((m & lt_mask) == 0ull) wrow[lk] = (uint16_t)(b0 + __popcll(m));
-            }
+        for (uint32_t e = w0 + lane; e < w1; e += 64) {
+            const uint32_t lk = (keypol[e] >> 1) & 0x7ffu;
+            if (lk < kRegion) idxA[lds_add_u16(wrow, lk, 1u)] = (uint16_t)e;
         }
         __syncthreads();
+        order_bucket(idxA, run_at, my_cnt);
         sorted = idxA;   // an owner reads only its own bucket from here on
         tile0 = cursor;
         if (!own) run_end = run_at;
