@@ -105,22 +105,33 @@ __device__ __forceinline__ uint32_t lds_add_u16(uint16_t* base, uint32_t i, uint
     return (atomicAdd(w, v << sh) >> sh) & 0xffffu;
 }
 
-// Puts a bucket of event indices [at, at + n) in increasing order: a check
-// with independent loads first, insertion sort only where it finds a pair
-// out of order (the buckets come out of the counting sorts nearly sorted).
+// Puts a bucket of event indices [at, at + n) in increasing order.  The
+// counting sorts below leave a bucket as a run of step groups: the events of
+// one key in one 64-event step of a wave (indices step * 64 + 0..63) take
+// consecutive slots in whatever order one LDS atomic returned them, and the
+// groups follow one another by step.  A check with independent loads comes
+// first; a bucket out of order has each group rewritten from a 64-bit mask of
+// its indices, which is linear in the bucket's size.
 __device__ __forceinline__ void order_bucket(uint16_t* idx, uint32_t at, uint32_t n)
 {
     bool ordered = true;
     for (uint32_t a = at + 1; a < at + n; ++a) ordered &= idx[a - 1] < idx[a];
     if (ordered) return;
-    for (uint32_t a = at + 1; a < at + n; ++a) {
-        const uint16_t v = idx[a];
-        uint32_t b = a;
-        while (b > at && idx[b - 1] > v) {
-            idx[b] = idx[b - 1];
-            --b;
+    const uint32_t end = at + n;
+    uint32_t a = at;
+    while (a < end) {
+        const uint32_t g0 = a;
+        const uint32_t step = idx[a] >> 6;
+        uint64_t mask = 0;
+        for (; a < end; ++a) {
+            const uint32_t v = idx[a];
+            if ((v >> 6) != step) break;
+            mask |= 1ull << (v & 63u);
         }
-        idx[b] = v;
+        for (uint32_t p = g0; mask; ++p) {
+            idx[p] = (uint16_t)(step * 64u + (uint32_t)__builtin_ctzll(mask));
+            mask &= mask - 1ull;
+        }
     }
 }
 
@@ -474,8 +485,8 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
         // in order, 64 events at a time, and wcnt[w][pixel] counts, then
         // places, the wave's events of each pixel (LDS atomics); a pixel's
         // bucket is then in slice (= time) order except where one step of a
-        // wave had several of its events, which the owner puts right by
-        // insertion sort
+        // wave had several of its events, which the owner puts right
+        // (order_bucket)
         const uint32_t wave = t >> 6, lane = t & 63;
         uint16_t* wrow = wcnt + (size_t)wave * kRegion;
 #pragma unroll

@@ -581,6 +581,53 @@ def test_nsf_batched_readouts_match_oracle():
     ctx.close()
 
 
+def _hot_pixel_stream(W, H, n, share, seed):
+    """Uniform events with random polarity, of which about `share` go to one
+    pixel: the blur-off counting sorts then hold buckets of thousands of one
+    key's events, and an event out of time order would change that pixel's
+    brightness and last index."""
+    rng = np.random.default_rng(seed)
+    x = rng.integers(0, W, n).astype(np.uint16)
+    y = rng.integers(0, H, n).astype(np.uint16)
+    hot = rng.random(n) < share
+    x[hot] = W // 3
+    y[hot] = (2 * H) // 3
+    p = rng.integers(0, 2, n).astype(np.uint8)
+    return eventsim.Events(x, y, p, np.arange(n, dtype=np.uint64))
+
+
+@pytest.mark.parametrize("W,H,n,extras", [(64, 48, 600_000, False), (64, 48, 600_000, True),
+                                          (1280, 1024, 400_000, False)])
+def test_nsf_hot_pixel_batched(W, H, n, extras):
+    """Blur off, one submit of 16384-event packets and device readouts, half of
+    the events on one pixel; 1280x1024 has 1280 regions, beyond the scatter's
+    counting sort (its radix sort runs).  Brightness-only readouts and readouts
+    with every output take the two variants of the apply kernel."""
+    ev = _hot_pixel_stream(W, H, n, 0.5, seed=W + n)
+    sched = eventsim.schedule(n, 16384, [50_000, 333_333, n])
+    gx, gy, gp = to_device(ev)
+    flush("blur off, hot pixel, %dx%d, %d events, extras=%s" % (W, H, n, extras))
+    ctx = make_ctx(W, H, spatial_filter=False)
+    bufs = _submit_with_device_readouts(ctx, ev, sched, gx, gy, gp, W * H, with_extras=extras)
+    orc = oracle.Oracle(W, H, spatial_filter=False)
+    done = 0
+    for b in bufs:
+        k = b["k"]
+        orc.push(ev.x[done:k], ev.y[done:k], ev.p[done:k])
+        done = k
+        r = orc.readout(0)
+        if extras:
+            g = {"L": b["L"].cpu().numpy(), "pbar": b["pbar"].cpu().numpy(),
+                 "last": b["last"].cpu().numpy()}
+            compare_state(g, r, False, "readout at %d" % k)
+        else:
+            d = np.abs(b["L"].cpu().numpy().astype(np.float64) - r["L"])
+            assert d.max() <= REL * max(np.abs(r["L"]).max(), 1.0), "L at %d" % k
+    compare_state(ctx.readout_host(0), orc.readout(0), False, "final")
+    ctx.close()
+    orc.close()
+
+
 def test_nsf_many_batches_and_host_readouts():
     """More events than one batch holds, host readouts in between."""
     w = eventsim.preset("hd720", n_events=9_000_000, seed=5)
