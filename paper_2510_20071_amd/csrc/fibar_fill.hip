@@ -22,6 +22,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -211,67 +212,135 @@ __global__ __launch_bounds__(256) void k_fill_conv(const uint16_t* __restrict__ 
 
 // ---------------------------------------------------------------------------
 // Weight gradient of one layer: g[t][o][c] = sum_p gz[p][o] in[p + off(t)][c]
-// and gb[o] = sum_p gz[p][o], as one partial sum per workgroup.  Each wave
-// takes 16-pixel segments; per segment and tap one MFMA with A = gz^T
-// (16 channels x 16 pixels) and B = the shifted input (16 pixels x 16
-// channels).  Grid: kGradBlocks x 256 threads.
+// and gb[o] = sum_p gz[p][o], as one partial sum per workgroup.
+//
+// With q = x + dx the input column, a tap (dy, dx) of output row y is
+// sum_q gz[y][q - dx][o] in[y + dy][q][c]: a GEMM over the columns q of the
+// row with both operands at q.  A workgroup takes units of kWgRowsPer rows of
+// one image and one strip of kWgStrip columns; the three input rows y - 1,
+// y, y + 1 (a ring) and the gradient row shifted by dx = -1, 0, +1 sit in LDS
+// channel-major, so a lane's eight consecutive columns of one channel are
+// one aligned 16-byte read.  Wave w takes columns 32 w .. + 31 of the strip:
+// per row and tap one v_mfma_f32_16x16x32_bf16 with A = the shifted gradient
+// (16 channels o x 32 columns) and B = the input row (32 columns x 16
+// channels c).  The next row's loads are issued before the products.
+// Zero padding: columns and rows outside the image are stored as zero.  The
+// units a workgroup takes, and every sum's order, are fixed, so the result
+// does not depend on timing.  Grid: min(units, kGradBlocks) x 256 threads.
 // ---------------------------------------------------------------------------
+constexpr int kWgStrip = 128;                   // columns per unit (4 waves x 32)
+constexpr int kWgPitch = kWgStrip + 8;          // LDS row pitch, elements (spreads the 16 channels over banks)
+constexpr int kWgRowsPer = 8;                   // output rows per unit
+
+__host__ __device__ inline uint32_t wgrad_units(uint32_t n, uint32_t H, uint32_t W)
+{
+    return n * ((H + kWgRowsPer - 1) / kWgRowsPer) * ((W + kWgStrip - 1) / kWgStrip);
+}
+
 __global__ __launch_bounds__(256) void k_fill_wgrad(const uint16_t* __restrict__ in,
                                                     const uint16_t* __restrict__ gz, uint32_t n,
                                                     uint32_t H, uint32_t W,
                                                     float* __restrict__ partial)
 {
-    __shared__ float red[4][kWgEntries];
-    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const uint32_t sw = (W + 15) / 16;
-    const size_t nseg = (size_t)n * H * sw;
-    const uint32_t ch = lane & 15, kq = (lane >> 4) * 4;
+    __shared__ __align__(16) uint16_t inb[3][kC][kWgPitch];    // input rows, a ring of three
+    __shared__ __align__(16) uint16_t gzb[3][kC][kWgPitch];    // gradient row at q - dx, dx = -1, 0, 1
+    __shared__ float red[4][kTaps * kC * kC];
+    __shared__ float bsh[256][8];
+    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const uint32_t qq = t >> 1, h = t & 1;           // the column and channel half a thread stages
+    const uint32_t ch = lane & 15, g = lane >> 4;
+    const uint32_t ry = (H + kWgRowsPer - 1) / kWgRowsPer, sx = (W + kWgStrip - 1) / kWgStrip;
+    const uint32_t units = n * ry * sx;
     f32x4 acc[kTaps];
 #pragma unroll
-    for (int t = 0; t < kTaps; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float bsum = 0.f;
-    for (size_t seg = (size_t)blockIdx.x * 4 + wv; seg < nseg; seg += (size_t)gridDim.x * 4) {
-        const size_t row = seg / sw;
-        const uint32_t y = (uint32_t)(row % H);
-        const size_t img0 = row - y;
-        const uint32_t x0 = (uint32_t)(seg % sw) * 16;
-        bf16x4 ga;
+    for (int k = 0; k < kTaps; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bs[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) bs[j] = 0.f;
+
+    // 16 bytes (8 channels) of pixel (row, x) of an image, zero outside it
+    auto ld = [&](const uint16_t* a, size_t img_row0, int row, int x) {
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (row >= 0 && row < (int)H && x >= 0 && x < (int)W)
+            v = *reinterpret_cast<const uint4*>(a + ((img_row0 + (size_t)row) * W + (size_t)x) * kC +
+                                                8 * h);
+        return v;
+    };
+    auto put = [&](uint16_t (*buf)[kWgPitch], uint4 v) {
+        const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const uint32_t xo = x0 + kq + j;
-            const uint16_t g = xo < W ? gz[(row * W + xo) * kC + ch] : (uint16_t)0;
-            ga[j] = (short)g;
-            bsum += from_bf16(g);
+            buf[8 * h + 2 * j][qq] = (uint16_t)(w4[j] & 0xffffu);
+            buf[8 * h + 2 * j + 1][qq] = (uint16_t)(w4[j] >> 16);
         }
-        bf16x4 bb[kTaps];
+    };
+
+    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const uint32_t img = u / (ry * sx), rem = u % (ry * sx);
+        const int y0 = (int)((rem / sx) * kWgRowsPer);
+        const int y1 = min(y0 + kWgRowsPer, (int)H);
+        const int x0 = (int)((rem % sx) * kWgStrip);
+        const size_t r0 = (size_t)img * H;
+        const int xq = x0 + (int)qq;
+        // the ring holds row r at slot (r - y0 + 1) % 3
+        put(inb[0], ld(in, r0, y0 - 1, xq));
+        put(inb[1], ld(in, r0, y0, xq));
+        uint4 vin = ld(in, r0, y0 + 1, xq);
+        uint4 vg[3];
 #pragma unroll
-        for (int t = 0; t < kTaps; ++t) {
-            const int yy = (int)y + t / 3 - 1;
+        for (int d = 0; d < 3; ++d) vg[d] = ld(gz, r0, y0, xq - (d - 1));
+        for (int y = y0; y < y1; ++y) {
+            put(inb[(y - y0 + 2) % 3], vin);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int xx = (int)(x0 + kq + j) + t % 3 - 1;
-                uint16_t v = 0;
-                if (yy >= 0 && yy < (int)H && xx >= 0 && xx < (int)W && x0 + kq + j < W)
-                    v = in[((img0 + yy) * W + xx) * kC + ch];
-                bb[t][j] = (short)v;
+            for (int d = 0; d < 3; ++d) put(gzb[d], vg[d]);
+            {   // the bias: the unshifted gradient, each column of the strip once
+                const uint32_t w4[4] = {vg[1].x, vg[1].y, vg[1].z, vg[1].w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    bs[2 * j] += from_bf16((uint16_t)(w4[j] & 0xffffu));
+                    bs[2 * j + 1] += from_bf16((uint16_t)(w4[j] >> 16));
+                }
             }
-        }
+            __syncthreads();
+            if (y + 1 < y1) {
+                vin = ld(in, r0, y + 2, xq);
 #pragma unroll
-        for (int t = 0; t < kTaps; ++t)
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ga, bb[t], acc[t], 0, 0, 0);
+                for (int d = 0; d < 3; ++d) vg[d] = ld(gz, r0, y + 1, xq - (d - 1));
+            }
+            const uint32_t q0 = 32 * wv + 8 * g;
+            bf16x8 a3[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) a3[d] = *reinterpret_cast<const bf16x8*>(&gzb[d][ch][q0]);
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy) {
+                if (y + dy - 1 < 0 || y + dy - 1 >= (int)H) continue;   // a zero row
+                const bf16x8 bv =
+                    *reinterpret_cast<const bf16x8*>(&inb[(y - y0 + dy) % 3][ch][q0]);
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx)
+                    acc[dy * 3 + dx] =
+                        __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3[dx], bv, acc[dy * 3 + dx], 0, 0, 0);
+            }
+            __syncthreads();
+        }
     }
     // D[m = o][n = c]: lane holds o = 4 (lane / 16) + j, c = lane % 16
 #pragma unroll
-    for (int t = 0; t < kTaps; ++t)
+    for (int k = 0; k < kTaps; ++k)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) red[wv][t * kC * kC + (kq + j) * kC + ch] = acc[t][j];
-    // bias: the four lane groups of a channel, then the waves
-    bsum += __shfl_xor(bsum, 16);
-    bsum += __shfl_xor(bsum, 32);
-    if (lane < 16) red[wv][kTaps * kC * kC + lane] = bsum;
+        for (int j = 0; j < 4; ++j) red[wv][k * kC * kC + (4 * g + j) * kC + ch] = acc[k][j];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) bsh[t][j] = bs[j];
     __syncthreads();
-    for (int e = threadIdx.x; e < kWgEntries; e += blockDim.x)
-        partial[(size_t)blockIdx.x * kWgEntries + e] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+    float* out = partial + (size_t)blockIdx.x * kWgEntries;
+    for (int e = (int)t; e < kTaps * kC * kC; e += 256)
+        out[e] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+    if (t < kC) {
+        // channel t: the threads of its half, in thread order
+        float sb = 0.f;
+        for (uint32_t i = t >> 3; i < 256; i += 2) sb += bsh[i][t & 7];
+        out[kTaps * kC * kC + t] = sb;
+    }
 }
 
 // Sum the partials of layer l into the canonical gradient: one wave per
@@ -963,10 +1032,11 @@ int loss_grad(fibar_fill* f, const float* L, const uint8_t* stale, const float* 
     // gated by the ReLU of the layer below
     int cur = 0;
     for (int l = kLayers - 1; l >= 0; --l) {
-        hipLaunchKernelGGL(k_fill_wgrad, dim3(kGradBlocks), dim3(256), 0, f->st, f->act[l], f->g[cur],
+        const uint32_t gblocks = std::min<uint32_t>(wgrad_units(n, H, W), kGradBlocks);
+        hipLaunchKernelGGL(k_fill_wgrad, dim3(gblocks), dim3(256), 0, f->st, f->act[l], f->g[cur],
                            n, H, W, f->partial);
         hipLaunchKernelGGL(k_fill_wgrad_reduce, dim3((kWgEntries + 63) / 64), dim3(512), 0, f->st,
-                           f->partial, (uint32_t)kGradBlocks, l, f->grad);
+                           f->partial, gblocks, l, f->grad);
         FILL_TRY(hipGetLastError());
         if (l > 0) {
             const int nxt = cur == 1 ? 2 : 1;

@@ -330,12 +330,14 @@ def test_full_frame_forward_matches_reference_on_bands():
         worst = max(worst, err)
 
 
-def test_gradient_where_every_wave_loops():
-    """8 x 96 x 250: 12288 16-pixel segments (the last of each row ragged)
-    over the weight-gradient kernel's 4096 waves, so every wave accumulates
-    three segments before the partial sums are reduced."""
-    n, H, W = 8, 96, 250
-    assert n * H * ((W + 15) // 16) == 3 * 4096
+def test_gradient_where_workgroups_take_several_units():
+    """24 x 203 x 130: the weight-gradient kernel's units are 8 rows of one
+    image by a strip of 128 columns, 24 x 26 x 2 = 1248 of them (the last rows
+    of an image and the second strip ragged: 3 rows, 2 columns) over 1024
+    workgroups, so some workgroups accumulate two units before the partial
+    sums are reduced."""
+    n, H, W = 24, 203, 130
+    assert n * ((H + 7) // 8) * ((W + 127) // 128) == 1248
     prm = bf16_values(params_with_biases(23))
     L, stale, age, target = make_batch(24, n, H, W)
     L, age = bf16_values(L), bf16_values(age)
