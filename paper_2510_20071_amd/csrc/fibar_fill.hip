@@ -72,7 +72,9 @@ __global__ __launch_bounds__(64) void k_fill_pack_weights(const float* __restric
                                                           bf16x4* __restrict__ wf,
                                                           bf16x4* __restrict__ wb,
                                                           float* __restrict__ bias,
-                                                          uint4* __restrict__ wk)
+                                                          uint4* __restrict__ wk,
+                                                          uint4* __restrict__ wpf,
+                                                          uint4* __restrict__ wpb)
 {
     const int l = blockIdx.x / kTaps, t = blockIdx.x % kTaps, lane = threadIdx.x;
     const int ci = cin_of(l), co = cout_of(l);
@@ -88,6 +90,28 @@ __global__ __launch_bounds__(64) void k_fill_pack_weights(const float* __restric
     wf[(l * kTaps + t) * 64 + lane] = f;
     wb[(l * kTaps + t) * 64 + lane] = b;
     if (t == 0 && lane < kC) bias[l * kC + lane] = lane < co ? prm[b_off(l) + lane] : 0.f;
+    // K = 32 operands of tap pairs for the layer-by-layer kernel, every layer:
+    // pair q = t < 5, lane group g: tap 2q + g / 2 (a tenth tap is zero),
+    // channels 8 (g % 2) + j of the operand's K side.
+    //   wpf: A[m = o][k] = w[o][c = 8 (g % 2) + j][tap]                (forward)
+    //   wpb: A[m = c][k] = w[o = 8 (g % 2) + j][c][8 - tap]            (input gradient)
+    if (t < kPairs) {
+        const int g = lane >> 4, m = lane & 15, tap = 2 * t + (g >> 1);
+        uint16_t hf[8], hb[8];
+        for (int j = 0; j < 8; ++j) {
+            const int kc = 8 * (g & 1) + j;
+            hf[j] = (tap < kTaps && m < co && kc < ci) ? to_bf16(w[(m * ci + kc) * kTaps + tap]) : 0;
+            hb[j] = (tap < kTaps && kc < co && m < ci)
+                        ? to_bf16(w[(kc * ci + m) * kTaps + (kTaps - 1 - tap)])
+                        : 0;
+        }
+        wpf[(l * kPairs + t) * 64 + lane] =
+            make_uint4(hf[0] | (uint32_t)hf[1] << 16, hf[2] | (uint32_t)hf[3] << 16,
+                       hf[4] | (uint32_t)hf[5] << 16, hf[6] | (uint32_t)hf[7] << 16);
+        wpb[(l * kPairs + t) * 64 + lane] =
+            make_uint4(hb[0] | (uint32_t)hb[1] << 16, hb[2] | (uint32_t)hb[3] << 16,
+                       hb[4] | (uint32_t)hb[5] << 16, hb[6] | (uint32_t)hb[7] << 16);
+    }
     // K = 32 operands of tap pairs (2q, 2q + 1), q = t < 5: lane group g takes
     // tap 2q + g / 2, input channels 8 (g % 2) + j, j = 0..7; tap 9 is zero.
     // The first layer (3 input channels) instead packs 4 channels per tap:
@@ -144,14 +168,36 @@ __global__ __launch_bounds__(256) void k_fill_pack_input(const float* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// One 3x3 layer (or its input gradient), one wave per 16-pixel row segment.
+// One 3x3 layer (or its input gradient).
 // out[p][o] = bias[o] + sum_t sum_c in[p + off(t)][c] w_t[c][o], then ReLU if
 // `relu`, then zero where gate[p][o] == 0 if `gate` (the ReLU of the layer
 // below, for gradients).  Writes BF16 (out16) and/or channel 0 plus skip[p]
 // as FP32 (out32: the prediction, L plus the network's correction).
+//
+// A workgroup takes units of kCvRowsPer rows of one image and a strip of
+// kCvStrip columns; the input rows y - 1, y, y + 1 of the strip (plus one
+// column each side) sit in LDS pixel-major, a ring of three, the next row's
+// loads issued before the products.  Wave w takes the strip's 16-pixel
+// segments 2w and 2w + 1: per segment five v_mfma_f32_16x16x32_bf16, the
+// weights of a tap pair as A (output channels x 32) and the pixels' shifted
+// inputs as B, a lane's eight channels of one pixel being one 16-byte LDS
+// read; the result is channels x pixels, lane l holding output channels
+// 4 (l / 16) .. + 3 of pixel l % 16 (one 8-byte gate load and store).  A tenth
+// tap (zero weights) reads the ninth tap's input.  Outside the image the
+// staged input is zero (the layer's zero padding).
 // ---------------------------------------------------------------------------
+constexpr int kCvStrip = 128;                   // output columns per unit (8 segments)
+constexpr int kCvCols = kCvStrip + 2;           // staged columns x0 - 1 .. x0 + kCvStrip
+constexpr int kCvRowsPer = 8;                   // output rows per unit
+constexpr uint32_t kCvMaxGrid = 65535;
+
+__host__ __device__ inline uint32_t conv_units(uint32_t n, uint32_t H, uint32_t W)
+{
+    return n * ((H + kCvRowsPer - 1) / kCvRowsPer) * ((W + kCvStrip - 1) / kCvStrip);
+}
+
 __global__ __launch_bounds__(256) void k_fill_conv(const uint16_t* __restrict__ in,
-                                                   const bf16x4* __restrict__ w,
+                                                   const uint4* __restrict__ w,
                                                    const float* __restrict__ bias, int relu,
                                                    const uint16_t* __restrict__ gate,
                                                    uint16_t* __restrict__ out16,
@@ -159,55 +205,93 @@ __global__ __launch_bounds__(256) void k_fill_conv(const uint16_t* __restrict__ 
                                                    const float* __restrict__ skip, uint32_t n,
                                                    uint32_t H, uint32_t W)
 {
-    const uint32_t sw = (W + 15) / 16;
-    const size_t seg = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (seg >= (size_t)n * H * sw) return;   // whole wave; no barriers below
-    const uint32_t lane = threadIdx.x & 63;
-    const size_t row = seg / sw;             // img * H + y
-    const uint32_t y = (uint32_t)(row % H);
-    const size_t img0 = row - y;             // img * H
-    const uint32_t x0 = (uint32_t)(seg % sw) * 16;
-    const int px = (int)(x0 + (lane & 15));
-    const uint32_t cq = (lane >> 4) * 4;
-
-    // every tap's operands are loaded before the products
-    bf16x4 a[kTaps], b[kTaps];
+    __shared__ __align__(16) uint16_t rowb[3][kCvCols][kC];
+    const uint32_t t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const uint32_t g = lane >> 4, pxl = lane & 15;
+    bf16x8 wa[kPairs];
+    int dyq[kPairs], colq[kPairs];
 #pragma unroll
-    for (int t = 0; t < kTaps; ++t) {
-        const int yy = (int)y + t / 3 - 1, xx = px + t % 3 - 1;
-        bf16x4 v = {0, 0, 0, 0};
-        if (yy >= 0 && yy < (int)H && xx >= 0 && xx < (int)W)
-            v = *reinterpret_cast<const bf16x4*>(in + ((img0 + yy) * W + xx) * kC + cq);
-        a[t] = v;
-        b[t] = w[t * 64 + lane];
+    for (int q = 0; q < kPairs; ++q) {
+        const uint4 v = w[q * 64 + lane];
+        wa[q] = *reinterpret_cast<const bf16x8*>(&v);
+        const int tap = min(2 * q + (int)(g >> 1), kTaps - 1);
+        dyq[q] = tap / 3;                          // ring row: y - 1 + dy
+        colq[q] = (int)pxl + tap % 3;              // staged column of segment column 0
     }
-    // weights as the A operand, activations as B: the result is channels x
-    // pixels, lane l holding output channels 4 (l / 16) .. + 3 of pixel
-    // x0 + l % 16 (one bounds check, one 8-byte gate load and store per lane)
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    float bv[4];
 #pragma unroll
-    for (int t = 0; t < kTaps; ++t)
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b[t], a[t], acc, 0, 0, 0);
+    for (int j = 0; j < 4; ++j) bv[j] = bias ? bias[4 * g + j] : 0.f;
+    const uint32_t ry = (H + kCvRowsPer - 1) / kCvRowsPer, sx = (W + kCvStrip - 1) / kCvStrip;
+    const uint32_t units = n * ry * sx;
 
-    if (px >= (int)W) return;
-    const size_t p = row * W + (uint32_t)px;
-    uint2 g = make_uint2(0xffffffffu, 0xffffffffu);
-    if (gate) g = *reinterpret_cast<const uint2*>(gate + p * kC + cq);
-    const uint32_t gh[4] = {g.x & 0xffffu, g.x >> 16, g.y & 0xffffu, g.y >> 16};
-    uint16_t h[4];
-    float v0 = 0.f;
+    // 16-byte chunk k (column k / 2, channel half k % 2) of a staged row
+    auto ld = [&](size_t r0, int row, int x0, uint32_t k) {
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        const int x = x0 - 1 + (int)(k >> 1);
+        if (k < 2u * kCvCols && row >= 0 && row < (int)H && x >= 0 && x < (int)W)
+            v = *reinterpret_cast<const uint4*>(in + ((r0 + (size_t)row) * W + (size_t)x) * kC +
+                                                8 * (k & 1));
+        return v;
+    };
+    auto put = [&](int slot, uint32_t k, uint4 v) {
+        if (k < 2u * kCvCols) *reinterpret_cast<uint4*>(&rowb[slot][k >> 1][8 * (k & 1)]) = v;
+    };
+
+    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const uint32_t img = u / (ry * sx), rem = u % (ry * sx);
+        const int y0 = (int)((rem / sx) * kCvRowsPer);
+        const int y1 = min(y0 + kCvRowsPer, (int)H);
+        const int x0 = (int)((rem % sx) * kCvStrip);
+        const size_t r0 = (size_t)img * H;
+        // the ring holds row r at slot (r - y0 + 1) % 3
+        put(0, t, ld(r0, y0 - 1, x0, t));
+        put(0, t + 256, ld(r0, y0 - 1, x0, t + 256));
+        put(1, t, ld(r0, y0, x0, t));
+        put(1, t + 256, ld(r0, y0, x0, t + 256));
+        uint4 n0 = ld(r0, y0 + 1, x0, t), n1 = ld(r0, y0 + 1, x0, t + 256);
+        for (int y = y0; y < y1; ++y) {
+            const int sl = (y - y0 + 2) % 3;
+            put(sl, t, n0);
+            put(sl, t + 256, n1);
+            __syncthreads();
+            if (y + 1 < y1) {
+                n0 = ld(r0, y + 2, x0, t);
+                n1 = ld(r0, y + 2, x0, t + 256);
+            }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        float v = acc[j] + (bias ? bias[cq + j] : 0.f);
-        if (relu) v = v > 0.f ? v : 0.f;
-        if ((gh[j] & 0x7fffu) == 0) v = 0.f;
-        h[j] = to_bf16(v);
-        if (j == 0) v0 = v;
+            for (int sg = 0; sg < 2; ++sg) {
+                const int seg = 2 * (int)wv + sg;
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int q = 0; q < kPairs; ++q) {
+                    const bf16x8 bq = *reinterpret_cast<const bf16x8*>(
+                        &rowb[(y - y0 + dyq[q]) % 3][16 * seg + colq[q]][8 * (g & 1)]);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[q], bq, acc, 0, 0, 0);
+                }
+                const int px = x0 + 16 * seg + (int)pxl;
+                if (px >= (int)W) continue;
+                const size_t p = (r0 + (size_t)y) * W + (size_t)px;
+                uint2 gg = make_uint2(0xffffffffu, 0xffffffffu);
+                if (gate) gg = *reinterpret_cast<const uint2*>(gate + p * kC + 4 * g);
+                const uint32_t gh[4] = {gg.x & 0xffffu, gg.x >> 16, gg.y & 0xffffu, gg.y >> 16};
+                uint16_t hh[4];
+                float v0 = 0.f;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    float v = acc[j] + bv[j];
+                    if (relu) v = v > 0.f ? v : 0.f;
+                    if ((gh[j] & 0x7fffu) == 0) v = 0.f;
+                    hh[j] = to_bf16(v);
+                    if (j == 0) v0 = v;
+                }
+                if (out16)
+                    *reinterpret_cast<uint2*>(out16 + p * kC + 4 * g) =
+                        make_uint2(hh[0] | (uint32_t)hh[1] << 16, hh[2] | (uint32_t)hh[3] << 16);
+                if (out32 && g == 0) out32[p] = v0 + skip[p];
+            }
+            __syncthreads();
+        }
     }
-    if (out16)
-        *reinterpret_cast<uint2*>(out16 + p * kC + cq) =
-            make_uint2(h[0] | (uint32_t)h[1] << 16, h[2] | (uint32_t)h[3] << 16);
-    if (out32 && cq == 0) out32[p] = v0 + skip[p];
 }
 
 // ---------------------------------------------------------------------------
@@ -849,6 +933,8 @@ struct fibar_fill {
     bf16x4* wf = nullptr;        // [4][9][64]
     bf16x4* wb = nullptr;
     uint4* wk = nullptr;         // [4][5][64] K = 32 operands (8 BF16 each)
+    uint4* wpf = nullptr;        // [4][5][64] tap-pair operands, forward
+    uint4* wpb = nullptr;        // [4][5][64] tap-pair operands, input gradient
     float* bias = nullptr;       // [4][16]
     float* partial = nullptr;    // [kGradBlocks][kWgEntries]
     float2* lpart = nullptr;     // [kLossBlocks]
@@ -949,13 +1035,13 @@ int check_images(const fibar_fill* f, const void* L, const void* stale, const vo
     return FIBAR_OK;
 }
 
-hipError_t launch_conv(fibar_fill* f, const uint16_t* in, const bf16x4* w, const float* bias,
+hipError_t launch_conv(fibar_fill* f, const uint16_t* in, const uint4* w, const float* bias,
                        int relu, const uint16_t* gate, uint16_t* out16, float* out32,
                        const float* skip, uint32_t n, uint32_t H, uint32_t W)
 {
-    const size_t nseg = (size_t)n * H * ((W + 15) / 16);
-    hipLaunchKernelGGL(k_fill_conv, dim3((uint32_t)((nseg + 3) / 4)), dim3(256), 0, f->st, in, w,
-                       bias, relu, gate, out16, out32, skip, n, H, W);
+    const uint32_t grid = std::min<uint32_t>(conv_units(n, H, W), kCvMaxGrid);
+    hipLaunchKernelGGL(k_fill_conv, dim3(grid), dim3(256), 0, f->st, in, w, bias, relu, gate,
+                       out16, out32, skip, n, H, W);
     return hipGetLastError();
 }
 
@@ -1007,7 +1093,7 @@ int forward(fibar_fill* f, const float* L, const uint8_t* stale, const float* ag
     FILL_TRY(hipGetLastError());
     for (int l = 0; l < kLayers; ++l) {
         const bool last = l == kLayers - 1;
-        FILL_TRY(launch_conv(f, f->act[l], f->wf + l * kTaps * 64, f->bias + l * kC, last ? 0 : 1,
+        FILL_TRY(launch_conv(f, f->act[l], f->wpf + l * kPairs * 64, f->bias + l * kC, last ? 0 : 1,
                              nullptr, last ? nullptr : f->act[l + 1], last ? f->pred : nullptr,
                              last ? L : nullptr, n, H, W));
     }
@@ -1040,7 +1126,7 @@ int loss_grad(fibar_fill* f, const float* L, const uint8_t* stale, const float* 
         FILL_TRY(hipGetLastError());
         if (l > 0) {
             const int nxt = cur == 1 ? 2 : 1;
-            FILL_TRY(launch_conv(f, f->g[cur], f->wb + l * kTaps * 64, nullptr, 0, f->act[l],
+            FILL_TRY(launch_conv(f, f->g[cur], f->wpb + l * kPairs * 64, nullptr, 0, f->act[l],
                                  f->g[nxt], nullptr, nullptr, n, H, W));
             cur = nxt;
         }
@@ -1051,7 +1137,7 @@ int loss_grad(fibar_fill* f, const float* L, const uint8_t* stale, const float* 
 hipError_t pack_weights(fibar_fill* f)
 {
     hipLaunchKernelGGL(k_fill_pack_weights, dim3(kLayers * kTaps), dim3(64), 0, f->st, f->prm,
-                       f->wf, f->wb, f->bias, f->wk);
+                       f->wf, f->wb, f->bias, f->wk, f->wpf, f->wpb);
     return hipGetLastError();
 }
 
@@ -1061,8 +1147,8 @@ void free_fill(fibar_fill* f)
     if (f->st) (void)hipStreamSynchronize(f->st);
     free_ws(f);
     (void)hipFree(f->apply_pred);
-    void* p[] = {f->prm, f->m, f->v, f->grad, f->wf, f->wb, f->wk, f->bias, f->partial,
-                 f->lpart, f->loss2, f->fallbacks};
+    void* p[] = {f->prm, f->m, f->v, f->grad, f->wf, f->wb, f->wk, f->wpf, f->wpb, f->bias,
+                 f->partial, f->lpart, f->loss2, f->fallbacks};
     for (void* q : p) (void)hipFree(q);
     delete f;
 }
@@ -1090,6 +1176,8 @@ int fibar_fill_create(void* stream, fibar_fill** out)
     alloc((void**)&f->wf, kLayers * kTaps * 64 * sizeof(bf16x4));
     alloc((void**)&f->wb, kLayers * kTaps * 64 * sizeof(bf16x4));
     alloc((void**)&f->wk, kLayers * kPairs * 64 * sizeof(uint4));
+    alloc((void**)&f->wpf, kLayers * kPairs * 64 * sizeof(uint4));
+    alloc((void**)&f->wpb, kLayers * kPairs * 64 * sizeof(uint4));
     alloc((void**)&f->bias, kLayers * kC * sizeof(float));
     alloc((void**)&f->partial, (size_t)kGradBlocks * kWgEntries * sizeof(float));
     alloc((void**)&f->lpart, kLossBlocks * sizeof(float2));
