@@ -188,7 +188,7 @@ __global__ __launch_bounds__(256) void k_fill_pack_input(const float* __restrict
 // ---------------------------------------------------------------------------
 constexpr int kCvStrip = 128;                   // output columns per unit (8 segments)
 constexpr int kCvCols = kCvStrip + 2;           // staged columns x0 - 1 .. x0 + kCvStrip
-constexpr int kCvRowsPer = 8;                   // output rows per unit
+constexpr int kCvRowsPer = 4;                   // output rows per unit
 constexpr uint32_t kCvMaxGrid = 65535;
 
 __host__ __device__ inline uint32_t conv_units(uint32_t n, uint32_t H, uint32_t W)
@@ -258,6 +258,17 @@ __global__ __launch_bounds__(256) void k_fill_conv(const uint16_t* __restrict__ 
                 n0 = ld(r0, y + 2, x0, t);
                 n1 = ld(r0, y + 2, x0, t + 256);
             }
+            // the gate and skip values of the row, loaded before the products
+            uint2 gg2[2];
+            float sk2[2];
+#pragma unroll
+            for (int sg = 0; sg < 2; ++sg) {
+                const int px = x0 + 16 * (2 * (int)wv + sg) + (int)pxl;
+                const size_t p = (r0 + (size_t)y) * W + (size_t)(px < (int)W ? px : 0);
+                gg2[sg] = make_uint2(0xffffffffu, 0xffffffffu);
+                if (gate && px < (int)W) gg2[sg] = *reinterpret_cast<const uint2*>(gate + p * kC + 4 * g);
+                sk2[sg] = (out32 && g == 0 && px < (int)W) ? skip[p] : 0.f;
+            }
 #pragma unroll
             for (int sg = 0; sg < 2; ++sg) {
                 const int seg = 2 * (int)wv + sg;
@@ -271,8 +282,7 @@ __global__ __launch_bounds__(256) void k_fill_conv(const uint16_t* __restrict__ 
                 const int px = x0 + 16 * seg + (int)pxl;
                 if (px >= (int)W) continue;
                 const size_t p = (r0 + (size_t)y) * W + (size_t)px;
-                uint2 gg = make_uint2(0xffffffffu, 0xffffffffu);
-                if (gate) gg = *reinterpret_cast<const uint2*>(gate + p * kC + 4 * g);
+                const uint2 gg = gg2[sg];
                 const uint32_t gh[4] = {gg.x & 0xffffu, gg.x >> 16, gg.y & 0xffffu, gg.y >> 16};
                 uint16_t hh[4];
                 float v0 = 0.f;
@@ -287,7 +297,7 @@ __global__ __launch_bounds__(256) void k_fill_conv(const uint16_t* __restrict__ 
                 if (out16)
                     *reinterpret_cast<uint2*>(out16 + p * kC + 4 * g) =
                         make_uint2(hh[0] | (uint32_t)hh[1] << 16, hh[2] | (uint32_t)hh[3] << 16);
-                if (out32 && g == 0) out32[p] = v0 + skip[p];
+                if (out32 && g == 0) out32[p] = v0 + sk2[sg];
             }
             __syncthreads();
         }
