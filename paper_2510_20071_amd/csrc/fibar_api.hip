@@ -281,8 +281,7 @@ void free_ctx(fibar_ctx* c)
     (void)hipFree(c->rb.total);
     (void)hipFree(c->rb.chunk_k);
     (void)hipFree(c->rb.payload);
-    (void)hipFree(c->rb.ro);
-    if (c->h_ro) (void)hipHostFree(c->h_ro);
+    // rb.ro and h_ro (blur off) are parts of d_chunks and h_chunks
     if (c->ro_free) (void)hipEventDestroy(c->ro_free);
     if (c->h_chunks) (void)hipHostFree(c->h_chunks);
     if (c->h_sc) (void)hipHostFree(c->h_sc);
@@ -404,13 +403,12 @@ int run_region_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, u
         }
         ++step;
     }
-    if (n_chunks)
-        HIP_TRY(hipMemcpyAsync(c->d_chunks, c->h_chunks, (size_t)n_chunks * sizeof(ChunkDesc),
-                               hipMemcpyHostToDevice, c->st));
+    // one copy: the chunk descriptors, and the readout descriptors after all
+    // kMaxBatchChunks chunk slots when there are readouts
+    const size_t bytes = nr ? kMaxBatchChunks * sizeof(ChunkDesc) + (size_t)nr * sizeof(RegionReadout)
+                            : (size_t)n_chunks * sizeof(ChunkDesc);
+    if (bytes) HIP_TRY(hipMemcpyAsync(c->d_chunks, c->h_chunks, bytes, hipMemcpyHostToDevice, c->st));
     HIP_TRY(hipEventRecord(c->chunks_free, c->st));
-    if (nr)
-        HIP_TRY(hipMemcpyAsync(c->rb.ro, c->h_ro, (size_t)nr * sizeof(RegionReadout),
-                               hipMemcpyHostToDevice, c->st));
     HIP_TRY(hipEventRecord(c->ro_free, c->st));
     if (n_steps) HIP_TRY(hipMemsetAsync(c->scratch, 0, (size_t)n_steps * sizeof(StepScratch), c->st));
     HIP_TRY(timed_launch(c, 0, [&](const LaunchTiming& tm) {
@@ -846,7 +844,11 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
     alloc((void**)&c->s.pp, npx * sizeof(PixP));
     alloc((void**)&c->s.ring, ring * 4);
     alloc((void**)&c->s.sc, 2 * sizeof(DevScalars));
-    alloc((void**)&c->d_chunks, kMaxBatchChunks * sizeof(ChunkDesc));
+    // blur off: the readout descriptors of a batch follow its chunk
+    // descriptors in the same buffers, so that one copy carries both
+    const size_t desc_bytes = kMaxBatchChunks * sizeof(ChunkDesc) +
+                              (c->region_path ? kMaxBatchReadouts * sizeof(RegionReadout) : 0);
+    alloc((void**)&c->d_chunks, desc_bytes);
     // 4 spare records: an item reads records up to i + 3 of its chunk
     alloc((void**)&c->seg, ((size_t)kMaxBatchChunks * kChunk + 4) * sizeof(SegRec));
     alloc((void**)&c->seg_count, kMaxBatchChunks * 4);
@@ -875,11 +877,13 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
         alloc((void**)&c->rb.total, n_regions * 4);
         alloc((void**)&c->rb.chunk_k, (kMaxBatchChunks + 1) * 8);
         alloc((void**)&c->rb.payload, (size_t)kMaxBatchChunks * kChunk * 8);
-        alloc((void**)&c->rb.ro, kMaxBatchReadouts * sizeof(RegionReadout));
-        if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_ro, kMaxBatchReadouts * sizeof(RegionReadout), 0);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ro_free, hipEventDisableTiming);
     }
-    if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_chunks, kMaxBatchChunks * sizeof(ChunkDesc), 0);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_chunks, desc_bytes, 0);
+    if (e == hipSuccess && c->region_path) {
+        c->rb.ro = reinterpret_cast<RegionReadout*>(c->d_chunks + kMaxBatchChunks);
+        c->h_ro = reinterpret_cast<RegionReadout*>(c->h_chunks + kMaxBatchChunks);
+    }
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->hs_x, stg * 2, 0);
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->hs_y, stg * 2, 0);
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->hs_p, stg, 0);
