@@ -410,7 +410,9 @@ int run_region_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, u
     if (bytes) HIP_TRY(hipMemcpyAsync(c->d_chunks, c->h_chunks, bytes, hipMemcpyHostToDevice, c->st));
     HIP_TRY(hipEventRecord(c->chunks_free, c->st));
     HIP_TRY(hipEventRecord(c->ro_free, c->st));
-    if (n_steps) HIP_TRY(hipMemsetAsync(c->scratch, 0, (size_t)n_steps * sizeof(StepScratch), c->st));
+    // no clearing of the step scratch: the kernels write each chunk's and
+    // each packet's validation bits whole
+    (void)n_steps;
     HIP_TRY(timed_launch(c, 0, [&](const LaunchTiming& tm) {
         return launch_region_batch(c->s, c->cur_slot, c->d_chunks, n_chunks, c->scratch, c->rb, nr,
                                    any_opt,

@@ -182,7 +182,9 @@ __global__ __launch_bounds__(1024) void k_region_count(const ChunkDesc* __restri
     });
     if (bad) atomicOr(&bad_sh, bad);
     __syncthreads();
-    if (threadIdx.x == 0 && bad_sh) atomicOr(&scratch[cd.pkt].status, bad_sh);
+    // the chunk's validation bits, in its own slot (k_region_bases gathers
+    // them per packet, so no slot needs clearing first)
+    if (threadIdx.x == 0) scratch[blockIdx.x].pad[0] = bad_sh;
     uint32_t* row = cnt + (size_t)blockIdx.x * n_regions;
     for (uint32_t r = threadIdx.x; r < n_regions; r += blockDim.x) row[r] = hist[r];
 }
@@ -203,10 +205,24 @@ __global__ __launch_bounds__(256) void k_region_scan(uint32_t* __restrict__ cnt,
 __global__ __launch_bounds__(1024) void k_region_bases(State s, int slot,
                                                        const ChunkDesc* __restrict__ chunks,
                                                        uint32_t n_chunks,
-                                                       const StepScratch* __restrict__ scratch,
+                                                       StepScratch* __restrict__ scratch,
                                                        RegionBuffers rb, int set_k)
 {
     __shared__ uint32_t scan1[kWaves + 1];
+    __shared__ uint32_t pst[kMaxBatchChunks];   // validation bits per packet
+    // a packet's status: the validation bits of its chunks, written for every
+    // packet of the batch (the per-chunk bits are in each chunk's own slot)
+    for (uint32_t i = threadIdx.x; i < kMaxBatchChunks; i += blockDim.x) pst[i] = 0u;
+    __syncthreads();
+    if (threadIdx.x < n_chunks) {
+        const uint32_t b = scratch[threadIdx.x].pad[0];
+        if (b) atomicOr(&pst[chunks[threadIdx.x].pkt], b);
+    }
+    __syncthreads();
+    if (threadIdx.x < n_chunks) {
+        const uint32_t pk = chunks[threadIdx.x].pkt;
+        scratch[pk].status = pst[pk];
+    }
     const uint32_t per = (rb.n_regions + blockDim.x - 1) / blockDim.x;
     const uint32_t r0 = threadIdx.x * per;
     uint32_t local = 0;
@@ -225,7 +241,7 @@ __global__ __launch_bounds__(1024) void k_region_bases(State s, int slot,
     const uint32_t ci = threadIdx.x;
     uint32_t st = 0u, sz = 0u;
     if (ci < n_chunks) {
-        st = scratch[chunks[ci].pkt].status;
+        st = pst[chunks[ci].pkt];
         sz = st == 0u ? chunks[ci].n : 0u;
     }
     uint32_t nvalid;
@@ -242,7 +258,7 @@ __global__ __launch_bounds__(1024) void k_region_bases(State s, int slot,
         DevScalars& c = s.sc[slot];
         if (set_k) c.k = k0 + nvalid;
         if (first_bad && c.err == 0) {
-            const uint32_t st0 = scratch[chunks[kMaxBatchChunks - first_bad].pkt].status;
+            const uint32_t st0 = pst[chunks[kMaxBatchChunks - first_bad].pkt];
             c.err = (st0 & 1u) ? -2 : -3;   // FIBAR_E_RANGE / FIBAR_E_POLARITY
         }
     }

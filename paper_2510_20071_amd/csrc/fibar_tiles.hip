@@ -75,7 +75,9 @@ __global__ __launch_bounds__(1024) void k_tq_count(const ChunkDesc* __restrict__
     }
     if (bad) atomicOr(&bad_sh, bad);
     __syncthreads();
-    if (threadIdx.x == 0 && bad_sh) atomicOr(&scratch[cd.pkt].status, bad_sh);
+    // the chunk's validation bits, in its own slot (the base kernel gathers
+    // them per packet)
+    if (threadIdx.x == 0) scratch[blockIdx.x].pad[0] = bad_sh;
     uint32_t* row = cnt + (size_t)blockIdx.x * n_tiles;
     for (uint32_t r = threadIdx.x; r < n_tiles; r += blockDim.x) row[r] = hist[r];
 }
