@@ -238,6 +238,8 @@ def run_config(args, torch, dev, fb, eventsim, name):
         log("%s %s: %.1f Mev/s (oracle %.2f Mev/s), parity %s"
             % (name, key, mev, m / secs / 1e6, par))
     res["distinct_pixels_per_event"] = round(u, 4)
+    res["event_vs_packet"] = event_vs_packet(oracle, eventsim, wl, ev, sched)
+    log("%s per-event against per-packet regulation (oracle): %s" % (name, res["event_vs_packet"]))
     if name == "vga":
         res["relative_thresholds"] = thresholds_leg(args, torch, dev, fb, eventsim, oracle, W, H,
                                                     ev, sched, ops, stream, n)
@@ -267,6 +269,41 @@ def run_config(args, torch, dev, fb, eventsim, name):
         log("%s per-event regulation: %.1f Mev/s (oracle %.2f Mev/s), parity %s"
             % (name, n / el / 1e6, m / secs / 1e6, par))
     return res
+
+
+def event_vs_packet(oracle, eventsim, wl, ev, sched):
+    """How far per-packet regulation (the GPU contract) is from the paper's
+    per-event regulation, both from the FP64 oracle at every readout: the
+    Jaccard index of the two stale sets, and each mode's PSNR against the
+    simulator's ground truth (its log intensity mapped affinely onto the
+    brightness over the active pixels, the whole frame scored)."""
+    W, H = wl.scene.width, wl.scene.height
+    reads = [it[1] for it in sched if it[0] == "read"]
+    gt = eventsim.render_frames(wl.scene, [int(ev.t[k - 1]) for k in reads])
+    orcs = {m: oracle.Oracle(W, H, regulation=m) for m in ("packet", "event")}
+    jac, psnr = [], {m: [] for m in orcs}
+    i = 0
+    for it in sched:
+        if it[0] == "push":
+            a, b = it[1], it[2]
+            for o in orcs.values():
+                assert o.push(ev.x[a:b], ev.y[a:b], ev.p[a:b]) == 0
+            continue
+        r = {m: o.readout(0) for m, o in orcs.items()}
+        se, sp = r["event"]["stale"] != 0, r["packet"]["stale"] != 0
+        union = int(np.count_nonzero(se | sp))
+        jac.append(int(np.count_nonzero(se & sp)) / union if union else 1.0)
+        for m in orcs:
+            L = r[m]["L"].reshape(H, W)
+            target = eventsim.fill_target(gt[i], L, (r[m]["cnt"] > 0).reshape(H, W))
+            psnr[m].append(eventsim.fill_psnr(L, target, np.ones((H, W), bool)))
+        i += 1
+    for o in orcs.values():
+        o.close()
+    return {"readouts": len(jac), "stale_jaccard_mean": round(float(np.mean(jac)), 4),
+            "stale_jaccard_min": round(float(np.min(jac)), 4),
+            "psnr_db_packet": round(float(np.mean(psnr["packet"])), 3),
+            "psnr_db_event": round(float(np.mean(psnr["event"])), 3)}
 
 
 def tiles_leg(args, torch, dev, fb, W, H, ev, sched, ops, n_ops, stream, n):
