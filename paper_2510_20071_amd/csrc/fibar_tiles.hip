@@ -236,6 +236,7 @@ __global__ __launch_bounds__(kTqThreads, 4) void k_tq_step(
     __shared__ uint32_t cstart[kTqThreads];       // and where each cell's begin
     __shared__ int64_t ck[kTqThreads];            // first global index of the step's chunks
     __shared__ uint2 pre[kPre];                   // the window's oldest entries
+    __shared__ uint2 newe[kPiece];                // and its entries pushed by the step
     __shared__ uint32_t wtot[kTqThreads / 64];
     __shared__ uint32_t sh_first, sh_nstale, sh_red[3];
 
@@ -330,6 +331,7 @@ __global__ __launch_bounds__(kTqThreads, 4) void k_tq_step(
             uint32_t lk, gi;
             decode(pl0[j], lk, gi);
             ring[rbase + ((tl.tail + i) & ring_mask)] = make_uint2(gi, lk);
+            newe[i] = make_uint2(gi, lk);
             touched[lk] = 1u;
         }
     }
@@ -339,24 +341,37 @@ __global__ __launch_bounds__(kTqThreads, 4) void k_tq_step(
         ring[rbase + ((tl.tail + i) & ring_mask)] = make_uint2(gi, lk);
         touched[lk] = 1u;
     }
-    // window entry i (0 = oldest): prefetched, else from the ring (the
-    // entries pushed above included)
+    // window entry i (0 = oldest): prefetched, pushed by this step (the
+    // first kPiece), else from the ring
     auto entry = [&](uint32_t i) {
-        return i < npre ? pre[i] : ring[rbase + ((tl.head + i) & ring_mask)];
+        if (i < npre) return pre[i];
+        if (i >= q_old && i - q_old < kPiece) return newe[i - q_old];
+        return ring[rbase + ((tl.head + i) & ring_mask)];
     };
-    __threadfence_block();
+    // the ring stores above need to be visible to the workgroup only when a
+    // pushed entry beyond the first kPiece may be read back
+    if (n_new > kPiece) __threadfence_block();
     __syncthreads();
 
-    // events that leave: a prefix of the window, by target and by age
+    // events that leave: a prefix of the window, by target and by age.  The
+    // oldest entries are in LDS; the ring is read only when all of them are
+    // too old (the first young entry is nearly always among the first few)
     uint32_t n_old = 0;
     if (can_age) {
-        for (uint32_t b = 0; b < q; b += kTqThreads) {
-            const uint32_t i = b + tid;
-            if (i < q && global_of(entry(i).x) > lim) atomicMin(&sh_first, i);
-            __syncthreads();
-            n_old = sh_first;
-            __syncthreads();   // read by all before the next chunk's updates
-            if (n_old < q) break;
+        for (uint32_t i = tid; i < npre; i += kTqThreads)
+            if (global_of(pre[i].x) > lim) atomicMin(&sh_first, i);
+        __syncthreads();
+        n_old = sh_first;
+        if (n_old == q && npre < q) {
+            __syncthreads();   // read by all before the updates below
+            for (uint32_t b = npre; b < q; b += kTqThreads) {
+                const uint32_t i = b + tid;
+                if (i < q && global_of(entry(i).x) > lim) atomicMin(&sh_first, i);
+                __syncthreads();
+                n_old = sh_first;
+                __syncthreads();   // read by all before the next chunk's updates
+                if (n_old < q) break;
+            }
         }
     }
     const uint32_t n_pop = n_old > n_len ? n_old : n_len;
