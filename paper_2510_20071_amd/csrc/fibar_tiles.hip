@@ -19,7 +19,7 @@
 //              in time order and find their stale pixels (a pixel goes stale
 //              when its newest event leaves), and the tile updates its
 //              counts and target and lists the stale pixels;
-//   k_tq_blur  every listed pixel gets its one-time 3x3 blur into Lb, from
+//   k_tq_blur  (a workgroup per tile) every listed pixel gets its one-time 3x3 blur into Lb, from
 //              the image before the step's blurs.
 // A pixel's current brightness is Lb when its newest event is older than
 // its tile's window front (the global index of the tile's oldest window
@@ -594,12 +594,11 @@ __global__ __launch_bounds__(256) void k_tq_blur(State s, TQGeom g, const uint64
 {
     const uint64_t* front_old = front + (size_t)st.parity * n_tiles;
     const uint32_t n = scratch[st.pkt].status ? 0u : scratch[st.pkt].part[0][0];
-    // a wave per tile, over the tile's own list
-    const uint32_t lane = threadIdx.x & 63;
-    const uint32_t t = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const uint32_t nt = t < n_tiles ? nstale[t] : 0u;
+    // a workgroup per tile, over the tile's own list
+    const uint32_t t = blockIdx.x;
+    const uint32_t nt = nstale[t];
     const uint32_t* list = stale_list + (size_t)t * g.R * g.R;
-    for (uint32_t i = lane; i < nt; i += 64) {
+    for (uint32_t i = threadIdx.x; i < nt; i += 256) {
         const uint32_t j = list[i];
         const uint32_t y = j / g.W, x = j - y * g.W;
         const uint32_t xs[3] = {x > 0 ? x - 1 : 0, x, x + 1 < g.W ? x + 1 : g.W - 1};
@@ -722,7 +721,7 @@ hipError_t tq_step(fibar_ctx* c, uint32_t c0, uint32_t c1, uint32_t n_chunks, ui
                        c->tq_stale, c->tq_nstale, c->rb, c->scratch, st, c->tq_age, c->coef);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tq_blur, dim3((n + 3) / 4), dim3(256), 0, c->st, c->s, g,
+    hipLaunchKernelGGL(k_tq_blur, dim3(n), dim3(256), 0, c->st, c->s, g,
                        (const uint64_t*)c->tq_front, n, (const uint32_t*)c->tq_stale,
                        (const uint32_t*)c->tq_nstale, c->scratch, (const int64_t*)c->rb.chunk_k, st);
     c->tq_parity ^= 1;
