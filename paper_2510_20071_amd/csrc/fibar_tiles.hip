@@ -19,8 +19,8 @@
 //              in time order and find their stale pixels (a pixel goes stale
 //              when its newest event leaves), and the tile updates its
 //              counts and target and lists the stale pixels;
-//   k_tq_blur  (a workgroup per tile) every listed pixel gets its one-time 3x3 blur into Lb, from
-//              the image before the step's blurs.
+//   k_tq_blur  a workgroup per tile: every listed pixel gets its one-time
+//              3x3 blur into Lb, from the image before the step's blurs.
 // A pixel's current brightness is Lb when its newest event is older than
 // its tile's window front (the global index of the tile's oldest window
 // event), else L.  Fronts are kept for two consecutive steps, so that the
