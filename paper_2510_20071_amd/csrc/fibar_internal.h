@@ -206,7 +206,9 @@ inline hipError_t launch_timed(void (*kernel)(P...), dim3 grid, dim3 block, hipS
 // applies them in time order with the region's state held in LDS.
 constexpr uint32_t kRegion = 1024;
 constexpr uint32_t kMaxRegions = 16384;
-constexpr uint32_t kMaxBatchReadouts = 1024;
+constexpr uint32_t kMaxBatchReadouts = 256;
+// Events of a region's slice that the blur-off apply kernel orders at a time.
+constexpr uint32_t kApplyTile = 8192;
 
 // A readout placed inside a blur-off batch: it sees the events of chunks
 // [0, chunk_end).

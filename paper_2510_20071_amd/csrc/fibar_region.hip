@@ -393,14 +393,14 @@ __global__ __launch_bounds__(kSortThreads) void k_region_scatter(
 // the kernel has no code path that loads while readouts are written (such a
 // path makes the compiler wait for every store in flight at each readout).
 template <bool kOpt>
-__global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBuffers rb,
+__global__ __launch_bounds__(kSortThreads, 8) void k_region_apply(State s, RegionBuffers rb,
                                                                uint32_t n_chunks,
                                                                uint32_t n_readouts, Coef coef)
 {
-    // keypol: chunk (bits 24..31) | local pixel, kRegion for rejected
-    // packets (bits 1..11) | polarity (bit 0)
-    __shared__ uint32_t keypol[kChunk];
-    __shared__ __align__(16) uint16_t idxA[kChunk];
+    // keypol: local pixel, kRegion for rejected packets (bits 1..11) |
+    // polarity (bit 0)
+    __shared__ uint16_t keypol[kApplyTile];
+    __shared__ __align__(16) uint16_t idxA[kApplyTile];
     __shared__ __align__(16) uint16_t wcnt[kWaves * kRegion];   // per wave and pixel
     __shared__ uint32_t scan1[kWaves + 1];
     __shared__ RoLds ro_s[kMaxBatchReadouts];
@@ -460,14 +460,21 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
             last_pos = 0xffffffffu;
         }
     };
-    // the owner's next event of the tile (key), loaded one event ahead
-    uint32_t nkp = 0u;
-    // apply own events of the tile whose chunk is below `chunk_limit`
-    auto advance = [&](uint32_t chunk_limit) {
+    // the owner's next event of the tile: its position in the region's
+    // slice << 1 | polarity, loaded one event ahead (trel: the tile's first
+    // position).  The slice is in chunk order, so the events before a
+    // readout are those at positions below the readout's.
+    uint32_t nkp = 0u, trel = 0u;
+    auto key_at = [&](uint32_t a) {
+        const uint32_t e = sorted[a];
+        return ((trel + e) << 1) | (uint32_t)(keypol[e] & 1u);
+    };
+    // apply own events of the tile at slice positions below `pos_limit`
+    auto advance = [&](uint32_t pos_limit) {
         while (run_at < run_end) {
             const uint32_t kp = nkp;
-            if ((kp >> 24) >= chunk_limit) break;
-            if (run_at + 1 < run_end) nkp = keypol[sorted[run_at + 1]];
+            if ((kp >> 1) >= pos_limit) break;
+            if (run_at + 1 < run_end) nkp = key_at(run_at + 1);
             const float p = (kp & 1u) ? 1.f : -1.f;
             pb = fmaf(coef.alpha, pb, coef.one_m_alpha * p);    // Eq. (7)
             l = fmaf(coef.beta, l, c * (p - pb));                 // Eq. (6), (10)
@@ -495,7 +502,7 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
     };
 
     for (uint64_t cursor = lo; cursor < hi;) {
-        const uint32_t cn = (uint32_t)(hi - cursor < kChunk ? hi - cursor : kChunk);
+        const uint32_t cn = (uint32_t)(hi - cursor < kApplyTile ? hi - cursor : kApplyTile);
         const uint32_t rel1 = (uint32_t)(cursor - lo) + cn;
         // counting sort by pixel: wave w takes a contiguous part of the tile
         // in order, 64 events at a time, and wcnt[w][pixel] counts, then
@@ -507,21 +514,20 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
         uint16_t* wrow = wcnt + (size_t)wave * kRegion;
 #pragma unroll
         for (uint32_t j = 0; j < kRegion / 64; ++j) wrow[lane + 64 * j] = 0u;
-        for (uint32_t e0 = 0; e0 < cn; e0 += 4 * kSortThreads) {
-            uint64_t pl[4];
+        for (uint32_t e0 = 0; e0 < cn; e0 += 2 * kSortThreads) {
+            uint64_t pl[2];
 #pragma unroll
-            for (uint32_t j = 0; j < 4; ++j) {
+            for (uint32_t j = 0; j < 2; ++j) {
                 const uint32_t e = e0 + t + j * kSortThreads;
                 pl[j] = e < cn ? rb.payload[cursor + e] : 0ull;
             }
 #pragma unroll
-            for (uint32_t j = 0; j < 4; ++j) {
+            for (uint32_t j = 0; j < 2; ++j) {
                 const uint32_t e = e0 + t + j * kSortThreads;
                 if (e < cn) {
                     const uint64_t pix = pl[j] >> 32;
                     const uint32_t lk = pix == kSentinelPix ? kRegion : (uint32_t)(pix - p0);
-                    const uint32_t ch = (uint32_t)(pl[j] >> 15) & 0xffu;
-                    keypol[e] = (ch << 24) | (lk << 1) | (uint32_t)(pl[j] & 1u);
+                    keypol[e] = (uint16_t)((lk << 1) | (uint32_t)(pl[j] & 1u));
                 }
             }
         }
@@ -561,14 +567,15 @@ __global__ __launch_bounds__(kSortThreads) void k_region_apply(State s, RegionBu
         sorted = idxA;   // an owner reads only its own bucket from here on
         tile0 = cursor;
         if (!own) run_end = run_at;
-        if (run_at < run_end) nkp = keypol[sorted[run_at]];
+        trel = (uint32_t)(cursor - lo);
+        if (run_at < run_end) nkp = key_at(run_at);
         // readouts that fall inside this tile (the next descriptor is loaded
         // while the current one is written)
         if (next_ro < n_readouts) {
             RoLds q = ro_s[next_ro];
             while (q.pos < rel1) {
                 const RoLds qn = ro_s[next_ro + 1 < n_readouts ? next_ro + 1 : next_ro];
-                advance(q.ce & 0x7fffffffu);
+                advance(q.pos);
                 write_readout(next_ro, q);
                 ++next_ro;
                 if (next_ro >= n_readouts) break;
