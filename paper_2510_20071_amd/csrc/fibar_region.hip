@@ -410,7 +410,7 @@ __global__ __launch_bounds__(kSortThreads, 8) void k_region_apply(State s, Regio
     const uint64_t npx = (uint64_t)s.W * s.H;
     const uint64_t p0 = (uint64_t)r * kRegion;
     const bool own = p0 + t < npx;
-    const uint64_t gp = p0 + t;
+    const uint32_t gp = (uint32_t)(p0 + t);   // W x H < 2^31
     // the increment's factor, times the pixel's relative threshold if any
     float c = 0.5f + 0.5f * coef.beta;
     float pb = 0.f, l = 0.f;
@@ -425,7 +425,8 @@ __global__ __launch_bounds__(kSortThreads, 8) void k_region_apply(State s, Regio
         last = v.last;
         if (s.gain) c *= s.gain[gp];
     }
-    const uint64_t lo = rb.base[r], hi = rb.base[r + 1];
+    // slice offsets of a batch stay below kMaxBatchChunks x kChunk (2^22)
+    const uint32_t lo = (uint32_t)rb.base[r], hi = (uint32_t)rb.base[r + 1];
     // the batch's readout descriptors, loaded once by all threads together
     // (a descriptor load per readout inside the uniform loop below would be
     // a dependent round trip each)
@@ -450,7 +451,7 @@ __global__ __launch_bounds__(kSortThreads, 8) void k_region_apply(State s, Regio
     uint32_t run_at = 0, run_end = 0;
     uint32_t last_pos = 0xffffffffu;   // sorted position of the newest applied event
     const uint16_t* sorted = idxA;
-    uint64_t tile0 = lo;
+    uint32_t tile0 = lo;
 
     auto resolve_last = [&]() {
         if (last_pos != 0xffffffffu) {
@@ -501,7 +502,7 @@ __global__ __launch_bounds__(kSortThreads, 8) void k_region_apply(State s, Regio
         }
     };
 
-    for (uint64_t cursor = lo; cursor < hi;) {
+    for (uint32_t cursor = lo; cursor < hi;) {
         const uint32_t cn = (uint32_t)(hi - cursor < kApplyTile ? hi - cursor : kApplyTile);
         const uint32_t rel1 = (uint32_t)(cursor - lo) + cn;
         // counting sort by pixel: wave w takes a contiguous part of the tile
