@@ -54,6 +54,26 @@ struct ChunkDesc {
     uint32_t pkt;      // packet slot in the current batch
 };
 
+// A pointer that a kernel loads from memory (a descriptor, a record) is a
+// generic pointer to the compiler, and its accesses become flat
+// instructions, which also count as LDS accesses: every later LDS wait then
+// waits for them as well.  Passed through an integer into the global address
+// space, the compiler emits global instructions (all such pointers here are
+// device or pinned host allocations).
+template <class T>
+__device__ __forceinline__ T* as_global(T* p)
+{
+    return (T*)(__attribute__((address_space(1))) T*)(uintptr_t)p;
+}
+
+__device__ __forceinline__ ChunkDesc global_chunk(ChunkDesc cd)
+{
+    cd.x = as_global(cd.x);
+    cd.y = as_global(cd.y);
+    cd.p = as_global(cd.p);
+    return cd;
+}
+
 // Window scalars of one context after a regulation step (device resident).
 struct DevScalars {
     int64_t k;             // index of the newest applied event (-1: none)
@@ -127,6 +147,18 @@ struct State {
     uint64_t tel_cap;
     const float* gain; // per-pixel multiplier of Eq. (6)'s increment (null: none)
 };
+
+// A State loaded from memory (a record), with its pointers global (as_global).
+__device__ __forceinline__ State global_state(State s)
+{
+    s.px = as_global(s.px);
+    s.pp = as_global(s.pp);
+    s.ring = as_global(s.ring);
+    s.sc = as_global(s.sc);
+    s.tel = as_global(s.tel);
+    s.gain = as_global(s.gain);
+    return s;
+}
 
 // Optional HIP events attached to a launch's dispatch (hipExtLaunchKernel):
 // the runtime stamps them with the dispatch's own start and end, as a

@@ -47,7 +47,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_compose(
     __shared__ uint32_t scan1[kWaves + 1];
     __shared__ uint32_t bad_sh;
 
-    const ChunkDesc cd = chunks[blockIdx.x];
+    const ChunkDesc cd = global_chunk(chunks[blockIdx.x]);
     const uint32_t cn = cd.n;
     const int tid = threadIdx.x;
     if (tid == 0) bad_sh = 0u;

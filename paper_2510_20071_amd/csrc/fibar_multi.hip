@@ -142,7 +142,7 @@ __device__ __forceinline__ P* bcast_ptr(P* p, uint32_t k)
 {
     const uint64_t v = reinterpret_cast<uint64_t>(p);
     const uint64_t r = (uint64_t)bcast32((uint32_t)v, k) | ((uint64_t)bcast32((uint32_t)(v >> 32), k) << 32);
-    return reinterpret_cast<P*>(r);
+    return as_global(reinterpret_cast<P*>(r));   // every record pointer is device memory
 }
 __device__ __forceinline__ uint64_t bcast64(uint64_t v, uint32_t k)
 {
@@ -308,15 +308,16 @@ __global__ __launch_bounds__(256) void k_multi_readout(const StreamStep* rr, Mul
         const RoTask task = a.rot[off + t];
         const MultiReadout ro = a.ros[task.ro];
         const StreamStep* e = rr + task.rec;
-        const State s = e->s;
+        const State s = global_state(e->s);
         int64_t k;
         uint64_t h;
         current_head(s, e->pop_slot, e->step, e->events, 1, &k, &h);
         const uint64_t npx = (uint64_t)s.W * s.H;
         const uint64_t p0 = (uint64_t)task.blk * kReadoutBlock;
         for (uint64_t i = p0 + threadIdx.x; i < npx && i < p0 + kReadoutBlock; i += blockDim.x)
-            readout_pixel(s, 1, k, (int64_t)h, i, ro.L, ro.pbar, ro.stale, ro.cnt, ro.last,
-                          ro.log_age, ro.tot);
+            readout_pixel(s, 1, k, (int64_t)h, i, as_global(ro.L), as_global(ro.pbar),
+                          as_global(ro.stale), as_global(ro.cnt), as_global(ro.last),
+                          as_global(ro.log_age), as_global(ro.tot));
     }
 }
 
@@ -342,7 +343,9 @@ __global__ void k_multi_advance(uint32_t* base, uint32_t rounds)
 __global__ __launch_bounds__(64) void k_multi_commit(const CommitDesc* __restrict__ cd, uint32_t n)
 {
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
-        const CommitDesc c = cd[i];
+        CommitDesc c = cd[i];
+        c.s = global_state(c.s);
+        c.prev = as_global(c.prev);
         const DevScalars r = commit_by_wave(c.s.sc + c.slot_in, c.prev, c.prev_events, c.s, 1);
         if (threadIdx.x == 0) store_commit(c.s, c.s.sc + c.slot_out, r, c.prev_events);
     }

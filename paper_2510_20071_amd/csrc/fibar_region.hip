@@ -172,7 +172,7 @@ __global__ __launch_bounds__(1024) void k_region_count(const ChunkDesc* __restri
 {
     __shared__ uint32_t hist[kMaxRegions];
     __shared__ uint32_t bad_sh;
-    const ChunkDesc cd = chunks[blockIdx.x];
+    const ChunkDesc cd = global_chunk(chunks[blockIdx.x]);
     for (uint32_t r = threadIdx.x; r < n_regions; r += blockDim.x) hist[r] = 0u;
     if (threadIdx.x == 0) bad_sh = 0u;
     __syncthreads();
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(kSortThreads) void k_region_scatter(
     __shared__ uint64_t scan4[kWaves + 1][4];
     __shared__ uint32_t scan1[kWaves + 1];
     __shared__ uint32_t rcnt[kRegion];   // per region: bucket start
-    const ChunkDesc cd = chunks[blockIdx.x];
+    const ChunkDesc cd = global_chunk(chunks[blockIdx.x]);
     const uint32_t cn = cd.n;
     const uint32_t t = threadIdx.x;
     // up to kRegion regions: a counting sort (per-wave counters in idxB)

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(1024) void k_tq_count(const ChunkDesc* __restrict__
 {
     __shared__ uint32_t hist[kMaxRegions];
     __shared__ uint32_t bad_sh;
-    const ChunkDesc cd = chunks[blockIdx.x];
+    const ChunkDesc cd = global_chunk(chunks[blockIdx.x]);
     for (uint32_t r = threadIdx.x; r < n_tiles; r += blockDim.x) hist[r] = 0u;
     if (threadIdx.x == 0) bad_sh = 0u;
     __syncthreads();
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(kSortThreads) void k_tq_scatter(
     __shared__ __align__(16) uint16_t idxB[kChunk];
     __shared__ uint64_t scan4[kWaves + 1][4];
     __shared__ uint32_t scan1[kWaves + 1];
-    const ChunkDesc cd = chunks[blockIdx.x];
+    const ChunkDesc cd = global_chunk(chunks[blockIdx.x]);
     const uint32_t cn = cd.n;
     for (uint32_t e = threadIdx.x; e < cn; e += kSortThreads) {
         const uint32_t x = cd.x[e], y = cd.y[e], p = cd.p[e];
@@ -204,6 +204,7 @@ constexpr uint32_t kTqThreads = 256;
 constexpr uint32_t kPiece = 512;
 constexpr uint32_t kPre = 512;   // window entries prefetched into LDS
 constexpr uint32_t kPer = kPiece / kTqThreads;
+static_assert(kMaxBatchChunks <= kTqThreads, "a step's chunk indices are staged one per thread");
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
 {
@@ -319,7 +320,9 @@ __global__ __launch_bounds__(kTqThreads, 4) void k_tq_step(
         const uint32_t py = pix / g.W, px = pix - py * g.W;
         lk = (py - ty0) * g.R + (px - tx0);
         const uint32_t ch = (uint32_t)(pl >> 15) & 0xffu;
-        const int64_t kc = ch - st.c0 < kTqThreads ? ck[ch - st.c0] : rb.chunk_k[ch];
+        // a step's chunks are chunks of one batch (at most kMaxBatchChunks =
+        // kTqThreads), all staged in ck
+        const int64_t kc = ck[ch - st.c0];
         gi = (uint32_t)(uint64_t)(kc + (int64_t)((pl >> 1) & 0x3fffu));
     };
 
