@@ -5,21 +5,24 @@
 // and a whole batch of packets -- with the readouts placed between them --
 // can be processed at once:
 //
-//   k_region_count   per chunk: validate, histogram of events per region
+//   k_region_count   per chunk: validate (the chunk's bits to its own
+//                    scratch slot), histogram of events per region
 //   k_region_scan    per region: offsets of each chunk's events in the
 //                    region's slice (exclusive scan over chunks)
-//   k_region_bases   one workgroup: region slice bases, first global event
-//                    index of every chunk (rejected packets do not count),
-//                    new newest-event index
-//   k_region_scatter per chunk: stable LDS sort by region, then every event
-//                    goes to its region's slice (chunk order, then arrival
-//                    order)
+//   k_region_bases   one workgroup: each packet's status from its chunks'
+//                    bits, region slice bases, first global event index of
+//                    every chunk (rejected packets do not count), new
+//                    newest-event index
+//   k_region_scatter per chunk: stable counting sort by region (up to
+//                    kRegion regions, else a stable LDS radix sort), then
+//                    every event goes to its region's slice (chunk order,
+//                    then arrival order)
 //   k_region_apply   per region, one thread per pixel holding that pixel's
 //                    pbar, L and last index in registers; the slice is
-//                    consumed in tiles (stable LDS sort by pixel), each
-//                    owner applies its pixel's events in time order and
-//                    writes the pixel into every readout of the batch as it
-//                    passes the readout's position.
+//                    consumed in tiles of kApplyTile events (stable counting
+//                    sort by pixel), each owner applies its pixel's events in
+//                    time order and writes the pixel into every readout of
+//                    the batch as it passes the readout's position.
 //
 // HBM traffic per event: the packet (5 B) is read twice, an 8-byte bucket
 // entry is written and read once; the state is read and written once per
@@ -382,13 +385,14 @@ __global__ __launch_bounds__(kSortThreads) void k_region_scatter(
 }
 
 // One workgroup per region, thread t owns pixel p0 + t.  The region's slice
-// (chunk order, then arrival order) is consumed
-// in tiles of up to kChunk events: a stable LDS sort by local pixel puts
-// each pixel's events of the tile together, in time order, and the owner
-// thread applies them one by one (Eq. (7), then Eq. (6) and (10)).  The
-// readouts of the batch are visited in order by the whole workgroup: every
-// owner first applies its events that precede the readout, then all write
-// the readout together (coalesced).
+// (chunk order, then arrival order) is consumed in tiles of up to kApplyTile
+// events: a stable counting sort by local pixel puts each pixel's events of
+// the tile together, in time order, and the owner thread applies them one by
+// one (Eq. (7), then Eq. (6) and (10)).  The readouts of the batch are
+// visited in order by the whole workgroup: every owner first applies its
+// events that precede the readout (those at lower slice positions), then all
+// write the readout together (coalesced).  70 KB of LDS and at most 64 VGPRs
+// keep two workgroups on a CU.
 // kOpt: the batch has readouts with outputs beyond the brightness; without,
 // the kernel has no code path that loads while readouts are written (such a
 // path makes the compiler wait for every store in flight at each readout).
