@@ -13,9 +13,10 @@
 // chunk's events per tile, the blur-off scan and base kernels place the
 // tiles' slices, and k_tq_scatter moves every event into its tile's slice
 // (chunk order, then arrival order).  Per packet, two launches:
-//   k_tq_step  one wave per tile: the tile's events of the packet are
-//              pushed to its ring, the tile pops (target and age), the 2x2
-//              cells touched by an event or a pop apply their pixels' events
+//   k_tq_step  a workgroup per tile, a thread per 2x2 cell: the tile's
+//              events of the packet are pushed to its ring, the tile pops
+//              (target and age), the cells touched by an event or a pop
+//              apply their pixels' events
 //              in time order and find their stale pixels (a pixel goes stale
 //              when its newest event leaves), and the tile updates its
 //              counts and target and lists the stale pixels;
