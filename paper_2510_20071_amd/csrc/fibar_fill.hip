@@ -2,18 +2,20 @@
 //
 // Activations are NHWC with 16 BF16 channels per pixel (32 bytes; the 3 input
 // channels are zero-padded to 16, the 1 output channel is channel 0 of 16).
-// A 3x3 layer is an implicit GEMM per 16-pixel row segment: for each of the 9
-// taps one v_mfma_f32_16x16x16_bf16 multiplies the segment's shifted input
-// (16 pixels x 16 input channels) by the tap's weights (16 x 16), FP32
-// accumulation.  Operand lane layout (checked on the device): lane l holds
-// A[l % 16][4 (l / 16) + j], B[4 (l / 16) + j][l % 16] and D[4 (l / 16) + j][l % 16],
-// j = 0..3.  The weights of every tap are stored per lane in that order, so
-// a lane loads its B operand with one 8-byte read.
+// A 3x3 layer is an implicit GEMM per 16-pixel row segment: the weights of
+// two taps (output channels x 32) times the segment's shifted inputs (32 x 16
+// pixels) in one v_mfma_f32_16x16x32_bf16, five per segment, FP32
+// accumulation.  Operand lane layouts (checked on the device): for the
+// 16x16x16 product lane l holds A[l % 16][4 (l / 16) + j], B[4 (l / 16) + j][l % 16]
+// and D[4 (l / 16) + j][l % 16], j = 0..3; for 16x16x32, A[l % 16][8 (l / 16) + j]
+// and B[8 (l / 16) + j][l % 16], j = 0..7, with the same D.  Weights are stored
+// per lane in operand order, so a lane loads an operand with one read.
 //
 // The input gradient of a layer is the same kernel with the tap-flipped,
-// channel-transposed weights; the weight gradient is a GEMM over pixels
-// (gradient^T x shifted input) per tap, summed per workgroup and then over
-// workgroups in a fixed order, so training is deterministic.
+// channel-transposed weights; the weight gradient is a GEMM over the columns
+// of a row per tap (gradient x shifted input), summed per workgroup and then
+// over workgroups in a fixed order, so training is deterministic.  Inference
+// runs all four layers of a tile in one fused kernel.
 #include "fibar.h"
 #include "fibar_fill.h"
 
