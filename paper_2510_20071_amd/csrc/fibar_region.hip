@@ -396,15 +396,19 @@ __global__ __launch_bounds__(kSortThreads) void k_region_scatter(
 // kOpt: the batch has readouts with outputs beyond the brightness; without,
 // the kernel has no code path that loads while readouts are written (such a
 // path makes the compiler wait for every store in flight at each readout).
-template <bool kOpt>
-__global__ __launch_bounds__(kSortThreads, 8) void k_region_apply(State s, RegionBuffers rb,
+// kTile: events ordered at a time.  kApplyTile (8192) with at most 64 VGPRs
+// fits two workgroups on a CU; sensors of few regions, whose workgroups run
+// in one round anyway, take twice that (fewer rounds of the tile loop).
+template <bool kOpt, uint32_t kTile>
+__global__ __launch_bounds__(kSortThreads, kTile == kApplyTile ? 8 : 4) void k_region_apply(
+    State s, RegionBuffers rb,
                                                                uint32_t n_chunks,
                                                                uint32_t n_readouts, Coef coef)
 {
     // keypol: local pixel, kRegion for rejected packets (bits 1..11) |
     // polarity (bit 0)
-    __shared__ uint16_t keypol[kApplyTile];
-    __shared__ __align__(16) uint16_t idxA[kApplyTile];
+    __shared__ uint16_t keypol[kTile];
+    __shared__ __align__(16) uint16_t idxA[kTile];
     __shared__ __align__(16) uint16_t wcnt[kWaves * kRegion];   // per wave and pixel
     __shared__ uint32_t scan1[kWaves + 1];
     __shared__ RoLds ro_s[kMaxBatchReadouts];
@@ -507,7 +511,7 @@ __global__ __launch_bounds__(kSortThreads, 8) void k_region_apply(State s, Regio
     };
 
     for (uint32_t cursor = lo; cursor < hi;) {
-        const uint32_t cn = (uint32_t)(hi - cursor < kApplyTile ? hi - cursor : kApplyTile);
+        const uint32_t cn = (uint32_t)(hi - cursor < kTile ? hi - cursor : kTile);
         const uint32_t rel1 = (uint32_t)(cursor - lo) + cn;
         // counting sort by pixel: wave w takes a contiguous part of the tile
         // in order, 64 events at a time, and wcnt[w][pixel] counts, then
@@ -641,11 +645,22 @@ hipError_t launch_region_batch(const State& s, int slot, const ChunkDesc* d_chun
         hipLaunchKernelGGL(k_region_bases, dim3(1), dim3(1024), 0, st, s, slot, d_chunks, 0u,
                            scratch, rb, 1);
     }
+    // up to 256 regions: one round of workgroups in any case, the larger tile
+    const bool big = rb.n_regions <= 256;
+    if (any_opt && big)
+        return launch_timed(k_region_apply<true, 2 * kApplyTile>, dim3(rb.n_regions),
+                            dim3(kSortThreads), st, nullptr, tm.stop, s, rb, n_chunks, n_readouts,
+                            coef);
     if (any_opt)
-        return launch_timed(k_region_apply<true>, dim3(rb.n_regions), dim3(kSortThreads), st,
-                            nullptr, tm.stop, s, rb, n_chunks, n_readouts, coef);
-    return launch_timed(k_region_apply<false>, dim3(rb.n_regions), dim3(kSortThreads), st,
-                        nullptr, tm.stop, s, rb, n_chunks, n_readouts, coef);
+        return launch_timed(k_region_apply<true, kApplyTile>, dim3(rb.n_regions),
+                            dim3(kSortThreads), st, nullptr, tm.stop, s, rb, n_chunks, n_readouts,
+                            coef);
+    if (big)
+        return launch_timed(k_region_apply<false, 2 * kApplyTile>, dim3(rb.n_regions),
+                            dim3(kSortThreads), st, nullptr, tm.stop, s, rb, n_chunks, n_readouts,
+                            coef);
+    return launch_timed(k_region_apply<false, kApplyTile>, dim3(rb.n_regions), dim3(kSortThreads),
+                        st, nullptr, tm.stop, s, rb, n_chunks, n_readouts, coef);
 }
 
 }  // namespace fibar
