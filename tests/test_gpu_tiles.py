@@ -57,6 +57,27 @@ def test_vga_packets_of_several_chunks_with_tiles():
     run_pair(ev, 640, 480, sched, telemetry=False, region=32)
 
 
+@pytest.mark.parametrize("R", [8, 32])
+def test_hot_tile_with_thousands_of_events_per_packet(R):
+    """About half of every 8192-event packet on one pixel, random polarity:
+    its tile takes ~4000 of a packet's events (the step kernel's pieces of 512
+    events) and, with a window of at most R^2 events, pops nearly all of them
+    in the same step (entries past those the kernel keeps in LDS are read back
+    from the ring)."""
+    W, H, n = 64, 48, 300_000
+    rng = np.random.default_rng(31 + R)
+    x = rng.integers(0, W, n).astype(np.uint16)
+    y = rng.integers(0, H, n).astype(np.uint16)
+    hot = rng.random(n) < 0.5
+    x[hot] = 20
+    y[hot] = 13
+    p = rng.integers(0, 2, n).astype(np.uint8)
+    ev = eventsim.Events(x, y, p, np.arange(n, dtype=np.uint64))
+    sched = eventsim.schedule(n, 8192, list(range(20_000, n, 40_000)) + [n])
+    flush("64x48, hot tile, tiles of %d" % R)
+    run_pair(ev, W, H, sched, telemetry=False, region=R, q_min=16)
+
+
 def test_rejected_packet_changes_nothing_with_tiles():
     W, H = 64, 48
     w = eventsim.preset("sensor64x48", n_events=30000)
