@@ -362,15 +362,23 @@ __global__ __launch_bounds__(kTqThreads, 4) void k_tq_step(
     // too old (the first young entry is nearly always among the first few)
     uint32_t n_old = 0;
     if (can_age) {
-        for (uint32_t i = tid; i < npre; i += kTqThreads)
-            if (global_of(pre[i].x) > lim) atomicMin(&sh_first, i);
+        // a wave's young entries have ascending indices, so only its first
+        // young lane takes the LDS minimum: one atomic per wave, not one per
+        // lane (a uniform-address atomic is serialised over active lanes)
+        for (uint32_t i = tid; i < npre; i += kTqThreads) {
+            const bool young = global_of(pre[i].x) > lim;
+            const uint64_t m = __ballot(young);
+            if (young && lane == (uint32_t)__builtin_ctzll(m)) atomicMin(&sh_first, i);
+        }
         __syncthreads();
         n_old = sh_first;
         if (n_old == q && npre < q) {
             __syncthreads();   // read by all before the updates below
             for (uint32_t b = npre; b < q; b += kTqThreads) {
                 const uint32_t i = b + tid;
-                if (i < q && global_of(entry(i).x) > lim) atomicMin(&sh_first, i);
+                const bool young = i < q && global_of(entry(i).x) > lim;
+                const uint64_t m = __ballot(young);
+                if (young && lane == (uint32_t)__builtin_ctzll(m)) atomicMin(&sh_first, i);
                 __syncthreads();
                 n_old = sh_first;
                 __syncthreads();   // read by all before the next chunk's updates
