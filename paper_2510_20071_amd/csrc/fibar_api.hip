@@ -403,20 +403,26 @@ int run_region_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, u
         }
         ++step;
     }
-    // one copy: the chunk descriptors, and the readout descriptors after all
-    // kMaxBatchChunks chunk slots when there are readouts
-    const size_t bytes = nr ? kMaxBatchChunks * sizeof(ChunkDesc) + (size_t)nr * sizeof(RegionReadout)
-                            : (size_t)n_chunks * sizeof(ChunkDesc);
-    if (bytes) HIP_TRY(hipMemcpyAsync(c->d_chunks, c->h_chunks, bytes, hipMemcpyHostToDevice, c->st));
-    HIP_TRY(hipEventRecord(c->chunks_free, c->st));
-    HIP_TRY(hipEventRecord(c->ro_free, c->st));
+    // the first kernel reads the descriptors from host memory and keeps the
+    // device copy (no copy in the stream), and its end fires chunks_free
+    // (ro_free guards the same buffer and keeps an older, earlier record); a
+    // batch of readouts only has no such kernel and takes one copy: the chunk
+    // descriptors, and the readout descriptors after all kMaxBatchChunks slots
+    const bool direct = n_chunks > 0 && c->h_chunks_dev;
+    if (!direct) {
+        const size_t bytes = nr ? kMaxBatchChunks * sizeof(ChunkDesc) + (size_t)nr * sizeof(RegionReadout)
+                                : (size_t)n_chunks * sizeof(ChunkDesc);
+        if (bytes) HIP_TRY(hipMemcpyAsync(c->d_chunks, c->h_chunks, bytes, hipMemcpyHostToDevice, c->st));
+        HIP_TRY(hipEventRecord(c->chunks_free, c->st));
+        HIP_TRY(hipEventRecord(c->ro_free, c->st));
+    }
     // no clearing of the step scratch: the kernels write each chunk's and
     // each packet's validation bits whole
     (void)n_steps;
     HIP_TRY(timed_launch(c, 0, [&](const LaunchTiming& tm) {
         return launch_region_batch(c->s, c->cur_slot, c->d_chunks, n_chunks, c->scratch, c->rb, nr,
-                                   any_opt,
-                                   c->key_bits, c->coef, c->st, tm);
+                                   any_opt, c->key_bits, c->coef, c->st, tm,
+                                   direct ? c->h_chunks_dev : nullptr, c->chunks_free);
     }));
     return FIBAR_OK;
 }
@@ -881,10 +887,19 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
         alloc((void**)&c->rb.payload, (size_t)kMaxBatchChunks * kChunk * 8);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ro_free, hipEventDisableTiming);
     }
-    if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_chunks, desc_bytes, 0);
+    // blur off: the descriptors are read by a kernel where the host wrote
+    // them (mapped and coherent, so a kernel sees the host's latest writes)
+    if (e == hipSuccess)
+        e = hipHostMalloc((void**)&c->h_chunks, desc_bytes,
+                          c->region_path ? hipHostMallocMapped | hipHostMallocCoherent : 0u);
     if (e == hipSuccess && c->region_path) {
         c->rb.ro = reinterpret_cast<RegionReadout*>(c->d_chunks + kMaxBatchChunks);
         c->h_ro = reinterpret_cast<RegionReadout*>(c->h_chunks + kMaxBatchChunks);
+        void* dev = nullptr;
+        if (hipHostGetDevicePointer(&dev, c->h_chunks, 0) == hipSuccess && dev)
+            c->h_chunks_dev = static_cast<const ChunkDesc*>(dev);
+        else
+            (void)hipGetLastError();   // no device view: each batch copies its descriptors
     }
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->hs_x, stg * 2, 0);
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->hs_y, stg * 2, 0);

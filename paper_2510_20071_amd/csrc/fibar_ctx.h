@@ -19,6 +19,7 @@ struct fibar_ctx {
     // batch resources
     fibar::ChunkDesc* d_chunks = nullptr;
     fibar::ChunkDesc* h_chunks = nullptr;      // pinned
+    const fibar::ChunkDesc* h_chunks_dev = nullptr;   // blur off: h_chunks as kernels see it
     hipEvent_t chunks_free = nullptr;   // h_chunks may be rewritten once this fired
     fibar::SegRec* seg = nullptr;
     uint32_t* seg_count = nullptr;

@@ -6,7 +6,10 @@
 // can be processed at once:
 //
 //   k_region_count   per chunk: validate (the chunk's bits to its own
-//                    scratch slot), histogram of events per region
+//                    scratch slot), histogram of events per region; it
+//                    reads the batch's chunk and readout descriptors where
+//                    the host wrote them (mapped host memory) and keeps the
+//                    device copy the later launches read
 //   k_region_scan    per region: offsets of each chunk's events in the
 //                    region's slice (exclusive scan over chunks)
 //   k_region_bases   one workgroup: each packet's status from its chunks'
@@ -168,15 +171,28 @@ __device__ __forceinline__ void for_chunk_events(const ChunkDesc& cd, uint32_t W
     }
 }
 
-__global__ __launch_bounds__(1024) void k_region_count(const ChunkDesc* __restrict__ chunks,
-                                                       uint32_t W, uint32_t H, uint32_t n_regions,
-                                                       uint32_t* __restrict__ cnt,
-                                                       StepScratch* __restrict__ scratch)
+// What the first loads and the descriptor copy need leads the argument list
+// (the leading arguments arrive preloaded in scalar registers; a loaded one
+// would wait together with the descriptor's load from host memory).
+__global__ __launch_bounds__(1024) void k_region_count(
+    const ChunkDesc* __restrict__ chunks, ChunkDesc* __restrict__ chunks_out,
+    const RegionReadout* __restrict__ ro_in, RegionReadout* __restrict__ ro_out,
+    uint32_t n_chunks, uint32_t n_readouts, uint32_t W, uint32_t H, uint32_t n_regions,
+    uint32_t* __restrict__ cnt, StepScratch* __restrict__ scratch)
 {
     __shared__ uint32_t hist[kMaxRegions];
     __shared__ uint32_t bad_sh;
-    const ChunkDesc cd = global_chunk(chunks[blockIdx.x]);
-    for (uint32_t r = threadIdx.x; r < n_regions; r += blockDim.x) hist[r] = 0u;
+    const ChunkDesc raw = chunks[blockIdx.x];
+    const ChunkDesc cd = global_chunk(raw);
+    // descriptors read from host memory: the device copy for the batch's
+    // later launches (workgroup b takes chunk b and readouts b, b + n_chunks,
+    // ...; the readouts' loads first, so that they travel with the chunk's)
+    if (chunks_out) {
+        const uint32_t r = blockIdx.x + n_chunks * threadIdx.x;
+        if (r < n_readouts) ro_out[r] = ro_in[r];
+        if (threadIdx.x == 0) chunks_out[blockIdx.x] = raw;
+    }
+    for (uint32_t r = threadIdx.x; r < n_regions; r += 1024u) hist[r] = 0u;
     if (threadIdx.x == 0) bad_sh = 0u;
     __syncthreads();
     uint32_t bad = 0u;
@@ -189,7 +205,7 @@ __global__ __launch_bounds__(1024) void k_region_count(const ChunkDesc* __restri
     // them per packet, so no slot needs clearing first)
     if (threadIdx.x == 0) scratch[blockIdx.x].pad[0] = bad_sh;
     uint32_t* row = cnt + (size_t)blockIdx.x * n_regions;
-    for (uint32_t r = threadIdx.x; r < n_regions; r += blockDim.x) row[r] = hist[r];
+    for (uint32_t r = threadIdx.x; r < n_regions; r += 1024u) row[r] = hist[r];
 }
 
 __global__ __launch_bounds__(256) void k_region_scan(uint32_t* __restrict__ cnt, uint32_t n_chunks,
@@ -621,12 +637,19 @@ hipError_t launch_region_scan_bases(const State& s, int slot, const ChunkDesc* d
 hipError_t launch_region_batch(const State& s, int slot, const ChunkDesc* d_chunks,
                                uint32_t n_chunks, StepScratch* scratch, const RegionBuffers& rb,
                                uint32_t n_readouts, bool any_opt, int key_bits, Coef coef,
-                               hipStream_t st, const LaunchTiming& tm)
+                               hipStream_t st, const LaunchTiming& tm, const ChunkDesc* src,
+                               hipEvent_t src_read)
 {
     if (n_chunks > 0) {
-        const hipError_t e = launch_timed(k_region_count, dim3(n_chunks), dim3(1024), st,
-                                          tm.start, nullptr, d_chunks, s.W, s.H, rb.n_regions,
-                                          rb.cnt, scratch);
+        const RegionReadout* ro_src =
+            src ? reinterpret_cast<const RegionReadout*>(src + kMaxBatchChunks) : nullptr;
+        // the event that frees src is the count launch's own end (an event
+        // recorded apart from a launch put a ~10 us gap into the stream)
+        const hipError_t e = launch_timed(
+            k_region_count, dim3(n_chunks), dim3(1024), st, tm.start, src ? src_read : nullptr,
+            src ? src : d_chunks, src ? const_cast<ChunkDesc*>(d_chunks) : nullptr, ro_src,
+            src ? rb.ro : nullptr, n_chunks, src ? n_readouts : 0u, s.W, s.H, rb.n_regions, rb.cnt,
+            scratch);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_region_scan, dim3(rb.n_regions), dim3(256), 0, st, rb.cnt, n_chunks,
                            rb.n_regions, rb.total);
