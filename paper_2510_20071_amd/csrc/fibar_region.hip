@@ -171,6 +171,42 @@ __device__ __forceinline__ void for_chunk_events(const ChunkDesc& cd, uint32_t W
     }
 }
 
+// Exclusive scan of u32 over a 1024-thread workgroup (as block_exscan_u32)
+// for k_region_apply, whose tile loop calls it once per tile: the lane index
+// passes through an empty asm statement at each call and the wave index is
+// scalar, so that the shuffle and LDS addresses are made at the call rather
+// than hoisted out of the loop into registers (at 64 VGPRs they spilled).
+__device__ __forceinline__ uint32_t block_exscan_u32_at_call(uint32_t x, uint32_t* lds,
+                                                              uint32_t* total)
+{
+    uint32_t lane = threadIdx.x & 63u;
+    asm volatile("" : "+v"(lane));
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint32_t inc = x;
+#pragma unroll
+    for (uint32_t off = 1; off < 64; off <<= 1) {
+        const uint32_t src = lane >= off ? lane - off : lane;
+        const uint32_t o = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(src << 2), (int)inc);
+        if (lane >= off) inc += o;
+    }
+    if (lane == 63u) lds[wave] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t v = lds[w];
+            lds[w] = run;
+            run += v;
+        }
+        lds[kWaves] = run;
+    }
+    __syncthreads();
+    const uint32_t res = lds[wave] + inc - x;
+    *total = lds[kWaves];
+    __syncthreads();
+    return res;
+}
+
 // What the first loads and the descriptor copy need leads the argument list
 // (the leading arguments arrive preloaded in scalar registers; a loaded one
 // would wait together with the descriptor's load from host memory).
@@ -438,6 +474,9 @@ __global__ __launch_bounds__(kSortThreads, kTile == kApplyTile ? 8 : 4) void k_r
     // the increment's factor, times the pixel's relative threshold if any
     float c = 0.5f + 0.5f * coef.beta;
     float pb = 0.f, l = 0.f;
+    // with readouts of the brightness only, the last index does not stay in
+    // registers (no spill at 64 VGPRs: a kernel with scratch memory waits
+    // ~5 us longer to start): it is stored when it is resolved
     int64_t last = -1;
     uint64_t tot = 0u;
     if (own) {
@@ -446,7 +485,7 @@ __global__ __launch_bounds__(kSortThreads, kTile == kApplyTile ? 8 : 4) void k_r
         pb = w.pbar;
         tot = w.tot;
         l = v.L;
-        last = v.last;
+        if constexpr (kOpt) last = v.last;
         if (s.gain) c *= s.gain[gp];
     }
     // slice offsets of a batch stay below kMaxBatchChunks x kChunk (2^22)
@@ -468,7 +507,8 @@ __global__ __launch_bounds__(kSortThreads, kTile == kApplyTile ? 8 : 4) void k_r
     // the pixel's state is in registers from here on: a first use inside the
     // loops below would wait there for every memory access in flight, and
     // stores (the readouts) count among them
-    asm volatile("" ::"v"(pb), "v"(l), "v"(c), "v"(last), "v"(tot));
+    if constexpr (kOpt) asm volatile("" ::"v"(pb), "v"(l), "v"(c), "v"(last), "v"(tot));
+    else asm volatile("" ::"v"(pb), "v"(l), "v"(c), "v"(tot));
     uint32_t next_ro = 0;   // first readout not written yet (uniform)
 
     // own events of the current tile: sorted positions [run_at, run_end)
@@ -481,7 +521,15 @@ __global__ __launch_bounds__(kSortThreads, kTile == kApplyTile ? 8 : 4) void k_r
         if (last_pos != 0xffffffffu) {
             const uint32_t oid = sorted[last_pos];
             const uint64_t pl = rb.payload[tile0 + oid];
-            last = rb.chunk_k[(uint32_t)(pl >> 15) & 0x1ffffu] + (int64_t)((pl >> 1) & 0x3fffu);
+            const int64_t lv =
+                rb.chunk_k[(uint32_t)(pl >> 15) & 0x1ffffu] + (int64_t)((pl >> 1) & 0x3fffu);
+            if constexpr (kOpt) {
+                last = lv;
+            } else {   // an owner's (events were applied); the address made here
+                uint32_t g = gp;
+                asm volatile("" : "+v"(g));
+                *as_global(&s.px[g].last) = lv;
+            }
             last_pos = 0xffffffffu;
         }
     };
@@ -571,7 +619,7 @@ __global__ __launch_bounds__(kSortThreads, kTile == kApplyTile ? 8 : 4) void k_r
 #pragma unroll
         for (uint32_t w = 0; w < (uint32_t)kWaves; ++w) my_cnt += wcnt[w * kRegion + t];
         uint32_t total;
-        run_at = block_exscan_u32(my_cnt, scan1, &total);   // ends with a barrier
+        run_at = block_exscan_u32_at_call(my_cnt, scan1, &total);   // ends with a barrier
         run_end = run_at + my_cnt;
         {
             uint32_t at = run_at;
@@ -614,10 +662,13 @@ __global__ __launch_bounds__(kSortThreads, kTile == kApplyTile ? 8 : 4) void k_r
     }
     for (; next_ro < n_readouts; ++next_ro) write_readout(next_ro, ro_s[next_ro]);
     if (own) {
-        s.pp[gp].pbar = pb;
-        s.pp[gp].tot = tot;
-        s.px[gp].L = l;
-        s.px[gp].last = last;
+        // the records' addresses from here, not kept from the loads above
+        uint32_t g = gp;
+        asm volatile("" : "+v"(g));
+        s.pp[g].pbar = pb;
+        s.pp[g].tot = tot;
+        s.px[g].L = l;
+        if constexpr (kOpt) s.px[g].last = last;
     }
 }
 
