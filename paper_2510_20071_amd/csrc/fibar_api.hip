@@ -15,6 +15,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <new>
 #include <vector>
 
@@ -372,9 +373,29 @@ int do_readout_kernel(fibar_ctx* c, const fibar_readout_buf& ro, const StepScrat
     return map_err(e);
 }
 
+// Wait until the latest blur-off batch that read its descriptors in place
+// has read them (its base launch stored its number).  The stream is queried
+// only after a millisecond of waiting (a query can put a marker into the
+// stream, which costs as much as an event); if it has gone idle without the
+// number, the launch did not run.
+hipError_t wait_descriptors_read(fibar_ctx* c)
+{
+    if (!c->h_done) return hipSuccess;
+    auto next_query = std::chrono::steady_clock::now() + std::chrono::milliseconds(1);
+    while (*c->h_done < c->done_seq) {
+        if (std::chrono::steady_clock::now() < next_query) continue;
+        const hipError_t q = hipStreamQuery(c->st);
+        if (q == hipSuccess && *c->h_done < c->done_seq) return hipErrorLaunchFailure;
+        if (q != hipSuccess && q != hipErrorNotReady) return q;
+        next_query = std::chrono::steady_clock::now() + std::chrono::milliseconds(1);
+    }
+    return hipSuccess;
+}
+
 // Blur-off batch: pushes and device readouts in one region-path pass.
 int run_region_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, uint32_t n_steps)
 {
+    HIP_TRY(wait_descriptors_read(c));
     HIP_TRY(hipEventSynchronize(c->chunks_free));
     HIP_TRY(hipEventSynchronize(c->ro_free));
     uint32_t ci = 0, step = 0, nr = 0;
@@ -404,10 +425,10 @@ int run_region_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, u
         ++step;
     }
     // the first kernel reads the descriptors from host memory and keeps the
-    // device copy (no copy in the stream), and its end fires chunks_free
-    // (ro_free guards the same buffer and keeps an older, earlier record); a
-    // batch of readouts only has no such kernel and takes one copy: the chunk
-    // descriptors, and the readout descriptors after all kMaxBatchChunks slots
+    // device copy (no copy in the stream), and a later one then stores the
+    // batch's number into h_done; a batch of readouts only has no such kernel
+    // and takes one copy: the chunk descriptors, and the readout descriptors
+    // after all kMaxBatchChunks slots
     const bool direct = n_chunks > 0 && c->h_chunks_dev;
     if (!direct) {
         const size_t bytes = nr ? kMaxBatchChunks * sizeof(ChunkDesc) + (size_t)nr * sizeof(RegionReadout)
@@ -419,11 +440,13 @@ int run_region_batch(fibar_ctx* c, const Op* ops, size_t n, uint32_t n_chunks, u
     // no clearing of the step scratch: the kernels write each chunk's and
     // each packet's validation bits whole
     (void)n_steps;
+    const uint64_t seq = direct ? c->done_seq + 1 : 0;
     HIP_TRY(timed_launch(c, 0, [&](const LaunchTiming& tm) {
         return launch_region_batch(c->s, c->cur_slot, c->d_chunks, n_chunks, c->scratch, c->rb, nr,
                                    any_opt, c->key_bits, c->coef, c->st, tm,
-                                   direct ? c->h_chunks_dev : nullptr, c->chunks_free);
+                                   direct ? c->h_chunks_dev : nullptr, c->d_done, seq);
     }));
+    if (direct) c->done_seq = seq;
     return FIBAR_OK;
 }
 
@@ -889,17 +912,23 @@ int fibar_create(uint32_t width, uint32_t height, const fibar_params* prm, fibar
     }
     // blur off: the descriptors are read by a kernel where the host wrote
     // them (mapped and coherent, so a kernel sees the host's latest writes)
+    // (and the word after them that says a batch's descriptors were read)
     if (e == hipSuccess)
-        e = hipHostMalloc((void**)&c->h_chunks, desc_bytes,
+        e = hipHostMalloc((void**)&c->h_chunks, desc_bytes + (c->region_path ? 64 : 0),
                           c->region_path ? hipHostMallocMapped | hipHostMallocCoherent : 0u);
     if (e == hipSuccess && c->region_path) {
         c->rb.ro = reinterpret_cast<RegionReadout*>(c->d_chunks + kMaxBatchChunks);
         c->h_ro = reinterpret_cast<RegionReadout*>(c->h_chunks + kMaxBatchChunks);
         void* dev = nullptr;
-        if (hipHostGetDevicePointer(&dev, c->h_chunks, 0) == hipSuccess && dev)
+        if (hipHostGetDevicePointer(&dev, c->h_chunks, 0) == hipSuccess && dev) {
             c->h_chunks_dev = static_cast<const ChunkDesc*>(dev);
-        else
+            c->h_done = reinterpret_cast<volatile uint64_t*>(
+                reinterpret_cast<char*>(c->h_chunks) + desc_bytes);
+            *c->h_done = 0;
+            c->d_done = reinterpret_cast<uint64_t*>(static_cast<char*>(dev) + desc_bytes);
+        } else {
             (void)hipGetLastError();   // no device view: each batch copies its descriptors
+        }
     }
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->hs_x, stg * 2, 0);
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->hs_y, stg * 2, 0);

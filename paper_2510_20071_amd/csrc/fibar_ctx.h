@@ -20,6 +20,11 @@ struct fibar_ctx {
     fibar::ChunkDesc* d_chunks = nullptr;
     fibar::ChunkDesc* h_chunks = nullptr;      // pinned
     const fibar::ChunkDesc* h_chunks_dev = nullptr;   // blur off: h_chunks as kernels see it
+    // blur off: the word after the descriptors in h_chunks, where a launch of
+    // the batch that read them in place stores its number once they are read
+    volatile uint64_t* h_done = nullptr;
+    uint64_t* d_done = nullptr;          // the same word as kernels see it
+    uint64_t done_seq = 0;               // number of the latest such batch
     hipEvent_t chunks_free = nullptr;   // h_chunks may be rewritten once this fired
     fibar::SegRec* seg = nullptr;
     uint32_t* seg_count = nullptr;

@@ -283,14 +283,16 @@ struct TQTile {
 // src (may be null): the batch's descriptors in mapped, coherent host memory,
 // laid out as in d_chunks (chunk descriptors, readout descriptors after
 // kMaxBatchChunks slots); the first launch reads them there and keeps the
-// device copy that the later launches read, and src_read (may be null) fires
-// when that launch ends, so that the host rewrites src only after it ran.
-// Null src: the descriptors are in d_chunks already.
+// device copy that the later launches read, and a later launch stores src_seq
+// into src_done (host memory, as the device sees it) once that launch has
+// ended, so that the host rewrites src only after it ran.  Null src: the
+// descriptors are in d_chunks already.
 hipError_t launch_region_batch(const State& s, int slot, const ChunkDesc* d_chunks,
                                uint32_t n_chunks, StepScratch* scratch, const RegionBuffers& rb,
                                uint32_t n_readouts, bool any_opt, int key_bits, Coef coef,
                                hipStream_t st, const LaunchTiming& tm = LaunchTiming(),
-                               const ChunkDesc* src = nullptr, hipEvent_t src_read = nullptr);
+                               const ChunkDesc* src = nullptr, uint64_t* src_done = nullptr,
+                               uint64_t src_seq = 0);
 
 // ---- in-order path (fibar_kernels.hip) -----------------------------------
 // Workgroup sizes of the in-order kernels (on the 1280x720 stream with

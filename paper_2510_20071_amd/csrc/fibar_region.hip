@@ -257,14 +257,20 @@ __global__ __launch_bounds__(256) void k_region_scan(uint32_t* __restrict__ cnt,
     if (c == 0) total[r] = tot;
 }
 
+// done (may be null): a word of host memory that gets done_seq, telling the
+// host that the launch before this one (k_region_count, which reads the
+// batch's descriptors in host memory) has ended.
 __global__ __launch_bounds__(1024) void k_region_bases(State s, int slot,
                                                        const ChunkDesc* __restrict__ chunks,
                                                        uint32_t n_chunks,
                                                        StepScratch* __restrict__ scratch,
-                                                       RegionBuffers rb, int set_k)
+                                                       RegionBuffers rb, int set_k,
+                                                       uint64_t* done, uint64_t done_seq)
 {
     __shared__ uint32_t scan1[kWaves + 1];
     __shared__ uint32_t pst[kMaxBatchChunks];   // validation bits per packet
+    if (done && threadIdx.x == 0)
+        __hip_atomic_store(done, done_seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     // a packet's status: the validation bits of its chunks, written for every
     // packet of the batch (the per-chunk bits are in each chunk's own slot)
     for (uint32_t i = threadIdx.x; i < kMaxBatchChunks; i += blockDim.x) pst[i] = 0u;
@@ -681,7 +687,7 @@ hipError_t launch_region_scan_bases(const State& s, int slot, const ChunkDesc* d
     hipLaunchKernelGGL(k_region_scan, dim3(rb.n_regions), dim3(256), 0, st, rb.cnt, n_chunks,
                        rb.n_regions, rb.total);
     hipLaunchKernelGGL(k_region_bases, dim3(1), dim3(1024), 0, st, s, slot, d_chunks, n_chunks,
-                       scratch, rb, set_k ? 1 : 0);
+                       scratch, rb, set_k ? 1 : 0, (uint64_t*)nullptr, (uint64_t)0);
     return hipGetLastError();
 }
 
@@ -689,23 +695,24 @@ hipError_t launch_region_batch(const State& s, int slot, const ChunkDesc* d_chun
                                uint32_t n_chunks, StepScratch* scratch, const RegionBuffers& rb,
                                uint32_t n_readouts, bool any_opt, int key_bits, Coef coef,
                                hipStream_t st, const LaunchTiming& tm, const ChunkDesc* src,
-                               hipEvent_t src_read)
+                               uint64_t* src_done, uint64_t src_seq)
 {
     if (n_chunks > 0) {
         const RegionReadout* ro_src =
             src ? reinterpret_cast<const RegionReadout*>(src + kMaxBatchChunks) : nullptr;
-        // the event that frees src is the count launch's own end (an event
-        // recorded apart from a launch put a ~10 us gap into the stream)
         const hipError_t e = launch_timed(
-            k_region_count, dim3(n_chunks), dim3(1024), st, tm.start, src ? src_read : nullptr,
+            k_region_count, dim3(n_chunks), dim3(1024), st, tm.start, nullptr,
             src ? src : d_chunks, src ? const_cast<ChunkDesc*>(d_chunks) : nullptr, ro_src,
             src ? rb.ro : nullptr, n_chunks, src ? n_readouts : 0u, s.W, s.H, rb.n_regions, rb.cnt,
             scratch);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_region_scan, dim3(rb.n_regions), dim3(256), 0, st, rb.cnt, n_chunks,
                            rb.n_regions, rb.total);
+        // src is free once the count launch has ended: the base launch says
+        // so in host memory (an event fired by a launch's end put ~5 us into
+        // the stream, one recorded apart from it ~10 us)
         hipLaunchKernelGGL(k_region_bases, dim3(1), dim3(1024), 0, st, s, slot, d_chunks, n_chunks,
-                           scratch, rb, 1);
+                           scratch, rb, 1, src ? src_done : (uint64_t*)nullptr, src_seq);
         int region_bits = 1;
         while ((1u << region_bits) < rb.n_regions) ++region_bits;
         hipLaunchKernelGGL(k_region_scatter, dim3(n_chunks), dim3(kSortThreads), 0, st, d_chunks,
@@ -717,7 +724,7 @@ hipError_t launch_region_batch(const State& s, int slot, const ChunkDesc* d_chun
                                           tm.start, nullptr, rb.cnt, 0u, rb.n_regions, rb.total);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_region_bases, dim3(1), dim3(1024), 0, st, s, slot, d_chunks, 0u,
-                           scratch, rb, 1);
+                           scratch, rb, 1, (uint64_t*)nullptr, (uint64_t)0);
     }
     // up to 256 regions: one round of workgroups in any case, the larger tile
     const bool big = rb.n_regions <= 256;
