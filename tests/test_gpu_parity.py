@@ -637,6 +637,59 @@ def test_nsf_many_batches_and_host_readouts():
     run_pair(ev, 1280, 720, sched, spatial_filter=False)
 
 
+def test_nsf_back_to_back_submits_reuse_the_descriptor_buffer():
+    """Blur off, ~40 submits in a row with no wait between them.  Each submit
+    is one batch whose chunk and readout descriptors the host writes into the
+    one host buffer that the batch's first kernel reads in place, so the host
+    has to wait until the batch before has read it; every fifth submit is a
+    readout alone (its descriptors go by copy instead).  Every readout must see
+    exactly the events submitted before it."""
+    W, H = 640, 480
+    w = eventsim.preset("vga", n_events=600_000, seed=21)
+    ev = eventsim.generate(w.scene)
+    n = len(ev)
+    gx, gy, gp = to_device(ev)
+    torch, dev = torch_dev()
+    rng = np.random.default_rng(3)
+    flush("blur off, back-to-back submits, 640x480, %d events" % n)
+    ctx = make_ctx(W, H, spatial_filter=False)
+    bufs, k, sub = [], 0, 0
+
+    def readout(ops):
+        b = dict(k=k, L=torch.empty(W * H, dtype=torch.float32, device=dev))
+        bufs.append(b)
+        ops.append(fb.readout_op(0, b["L"]))
+
+    while k < n:
+        ops = []
+        if sub % 5 == 4:
+            readout(ops)
+        else:
+            for _ in range(int(rng.integers(1, 4))):
+                m = int(min(n - k, rng.integers(1, 16385)))
+                ops.append(fb.push_op(gx[k:k + m], gy[k:k + m], gp[k:k + m]))
+                k += m
+                if rng.random() < 0.5 or k == n:
+                    readout(ops)
+                if k == n:
+                    break
+        assert ctx.submit(ops) == 0
+        sub += 1
+    torch.cuda.synchronize()
+    assert sub >= 30 and len(bufs) >= 30
+    orc = oracle.Oracle(W, H, spatial_filter=False)
+    done = 0
+    for b in bufs:
+        orc.push(ev.x[done:b["k"]], ev.y[done:b["k"]], ev.p[done:b["k"]])
+        done = b["k"]
+        r = orc.readout(0)
+        d = np.abs(b["L"].cpu().numpy().astype(np.float64) - r["L"])
+        assert d.max() <= REL * max(np.abs(r["L"]).max(), 1.0), "L at %d" % b["k"]
+    compare_state(ctx.readout_host(0), orc.readout(0), False, "final")
+    ctx.close()
+    orc.close()
+
+
 def test_nsf_device_packet_rejection():
     w = eventsim.preset("sensor64x48", n_events=20000)
     ev = eventsim.generate(w.scene)
