@@ -224,11 +224,18 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, uint32_t lane)
     return v;
 }
 
+// The pointers the first loads need lead the argument list (16 dwords, which
+// arrive preloaded in scalar registers): the fronts before and after the
+// step, the packet's scratch record, the tiles, the step's end index
+// (chunk_k of its end chunk), the region bases and the count rows of the
+// step's first and end chunk (the totals when the step ends the batch).
 __global__ __launch_bounds__(kTqThreads, 4) void k_tq_step(
-    State s, TQGeom g, uint32_t n_tiles, TQTile* __restrict__ tiles, uint64_t* __restrict__ front,
+    const uint64_t* __restrict__ front_old, StepScratch* __restrict__ pkt_scratch,
+    TQTile* __restrict__ tiles, const int64_t* __restrict__ k_end,
+    const uint64_t* __restrict__ base, const uint32_t* __restrict__ cnt_lo,
+    const uint32_t* __restrict__ cnt_hi, uint64_t* __restrict__ front_new, State s, TQGeom g,
     uint2* __restrict__ ring, uint32_t ring_mask, uint32_t* __restrict__ stale_list,
-    uint32_t* __restrict__ nstale, RegionBuffers rb, StepScratch* __restrict__ scratch, TQStep st,
-    uint64_t age_max, Coef coef)
+    uint32_t* __restrict__ nstale, RegionBuffers rb, TQStep st, uint64_t age_max, Coef coef)
 {
     __shared__ uint32_t touched_w[256];           // a byte per pixel: event or pop
     __shared__ uint32_t popc[1024];               // pops per pixel
@@ -245,17 +252,21 @@ __global__ __launch_bounds__(kTqThreads, 4) void k_tq_step(
     const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const uint32_t t = blockIdx.x;
     uint8_t* touched = reinterpret_cast<uint8_t*>(touched_w);
-    const uint64_t* front_old = front + (size_t)st.parity * n_tiles;
-    uint64_t* front_new = front + (size_t)(st.parity ^ 1) * n_tiles;
-    // the tile's scalars, all loaded together
+    // the tile's scalars, all loaded together: the empty asm statement takes
+    // the loaded values as they are, so that all loads are issued before one
+    // wait (else the loads that only the full path needs would follow the
+    // status test's wait, and arithmetic on one value would wait for it alone)
     const uint64_t f_old = front_old[t];
-    const uint32_t status = scratch[st.pkt].status;
+    const uint32_t status = pkt_scratch->status;
     const TQTile tl = tiles[t];
-    const int64_t k_after = rb.chunk_k[st.c1] - 1;
-    const uint64_t bt = rb.base[t];
-    const uint64_t lo = bt + rb.cnt[(size_t)st.c0 * n_tiles + t];
-    const uint64_t hi = st.c1 < st.n_chunks ? bt + rb.cnt[(size_t)st.c1 * n_tiles + t]
-                                             : bt + rb.total[t];
+    const int64_t k_end_v = *k_end;
+    const uint64_t bt = base[t];
+    const uint32_t c_lo = cnt_lo[t], c_hi = cnt_hi[t];
+    asm volatile("" ::"s"(f_old), "s"(status), "s"(tl.head), "s"(tl.tail), "s"(tl.Q), "s"(tl.P),
+                 "s"(tl.T), "s"(k_end_v), "s"(bt), "s"(c_lo), "s"(c_hi));
+    const int64_t k_after = k_end_v - 1;
+    const uint64_t lo = bt + c_lo;
+    const uint64_t hi = bt + c_hi;
     if (status != 0u) {   // a rejected packet changes nothing
         if (tid == 0) {
             front_new[t] = f_old;
@@ -589,7 +600,7 @@ __global__ __launch_bounds__(kTqThreads, 4) void k_tq_step(
         tiles[t] = o;
         front_new[t] = f_new;
         nstale[t] = n_stale;
-        if (n_stale) atomicAdd(&scratch[st.pkt].part[0][0], n_stale);
+        if (n_stale) atomicAdd(&pkt_scratch->part[0][0], n_stale);
     }
 }
 
@@ -728,9 +739,14 @@ hipError_t tq_step(fibar_ctx* c, uint32_t c0, uint32_t c1, uint32_t n_chunks, ui
     st.pkt = pkt;
     st.parity = c->tq_parity;
     st.slot = c->cur_slot;
-    hipLaunchKernelGGL(k_tq_step, dim3(n), dim3(kTqThreads), 0,
-                       c->st, c->s, g, n, c->tq_tiles, c->tq_front, c->tq_ring, c->tq_cap - 1,
-                       c->tq_stale, c->tq_nstale, c->rb, c->scratch, st, c->tq_age, c->coef);
+    const uint64_t* f_old = c->tq_front + (size_t)c->tq_parity * n;
+    uint64_t* f_new = c->tq_front + (size_t)(c->tq_parity ^ 1) * n;
+    const uint32_t* cnt_lo = c->rb.cnt + (size_t)c0 * n;
+    const uint32_t* cnt_hi = c1 < n_chunks ? c->rb.cnt + (size_t)c1 * n : c->rb.total;
+    hipLaunchKernelGGL(k_tq_step, dim3(n), dim3(kTqThreads), 0, c->st, f_old, c->scratch + pkt,
+                       c->tq_tiles, (const int64_t*)c->rb.chunk_k + c1,
+                       (const uint64_t*)c->rb.base, cnt_lo, cnt_hi, f_new, c->s, g, c->tq_ring,
+                       c->tq_cap - 1, c->tq_stale, c->tq_nstale, c->rb, st, c->tq_age, c->coef);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_tq_blur, dim3(n), dim3(256), 0, c->st, c->s, g,
