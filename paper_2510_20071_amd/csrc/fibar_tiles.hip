@@ -441,20 +441,38 @@ __global__ __launch_bounds__(kTqThreads, 4) void k_tq_step(
         last[qq] = -1;
         cnt[qq] = got[qq] = 0u;
         tot[qq] = 0u;
-        if (in[qq]) {
-            const PixL v = s.px[gp_of(qq)];
-            last[qq] = v.last;
-            l[qq] = v.last < (int64_t)f_old ? v.Lb : v.L;
-        }
-        if (tch[qq]) {
-            const PixP w = s.pp[gp_of(qq)];
-            pb[qq] = w.pbar;
-            cnt[qq] = w.cnt;
-            tot[qq] = w.tot;
-            if (s.gain) c[qq] = cgain * s.gain[gp_of(qq)];
-        }
-        was[qq] = in[qq] && last[qq] >= (int64_t)f_old;
     }
+    // a touched cell loads all four pixels' records before it waits for any
+    // (one round trip, not one per pixel: loads under per-pixel conditions
+    // were each followed by their own wait), pixels outside the tile from
+    // the cell's first pixel, which is inside it, and keeps what it needs
+    if (has) {
+        PixL v[4];
+        PixP w[4];
+        float gn[4];
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+            const uint64_t gq = gp_of(in[qq] ? qq : 0);
+            v[qq] = s.px[gq];
+            w[qq] = s.pp[gq];
+            gn[qq] = s.gain ? s.gain[gq] : 1.f;
+        }
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+            if (in[qq]) {
+                last[qq] = v[qq].last;
+                l[qq] = v[qq].last < (int64_t)f_old ? v[qq].Lb : v[qq].L;
+            }
+            if (tch[qq]) {
+                pb[qq] = w[qq].pbar;
+                cnt[qq] = w[qq].cnt;
+                tot[qq] = w[qq].tot;
+                if (s.gain) c[qq] = cgain * gn[qq];
+            }
+        }
+    }
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) was[qq] = in[qq] && last[qq] >= (int64_t)f_old;
 
     // the cell's events in time order (Eq. (7), then Eq. (6) and (10))
     for (uint32_t p0 = 0; p0 < n_new; p0 += kPiece) {
