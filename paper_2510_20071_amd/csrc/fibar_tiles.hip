@@ -204,6 +204,7 @@ struct TQStep {
 constexpr uint32_t kTqThreads = 256;
 constexpr uint32_t kPiece = 512;
 constexpr uint32_t kPre = 512;   // window entries prefetched into LDS
+static_assert(kPre % kTqThreads == 0, "the prefetch takes kPre / kTqThreads entries per thread");
 constexpr uint32_t kPer = kPiece / kTqThreads;
 static_assert(kMaxBatchChunks <= kTqThreads, "a step's chunk indices are staged one per thread");
 
@@ -310,19 +311,37 @@ __global__ __launch_bounds__(kTqThreads, 4) void k_tq_step(
     touched_w[tid] = 0u;
 #pragma unroll
     for (uint32_t j = 0; j < 4; ++j) popc[tid + kTqThreads * j] = 0u;
-    if (tid < st.c1 - st.c0) ck[tid] = rb.chunk_k[st.c0 + tid];
-    for (uint32_t i = tid; i < npre; i += kTqThreads) pre[i] = ring[rbase + ((tl.head + i) & ring_mask)];
-    if (tid == 0) {
-        sh_first = q;
-        sh_nstale = 0u;
-        sh_red[0] = sh_red[1] = sh_red[2] = 0u;
+    // the step's chunk indices and the window's oldest entries: every load
+    // issued (from clamped, valid indices) before any is stored to LDS, so
+    // that they travel together (a load stored at once waits for itself)
+    const bool has_ck = tid < st.c1 - st.c0;
+    const int64_t ckv = rb.chunk_k[st.c0 + (has_ck ? tid : 0u)];
+    uint2 prv[kPre / kTqThreads];
+#pragma unroll
+    for (uint32_t j = 0; j < kPre / kTqThreads; ++j) {
+        const uint32_t i = tid + kTqThreads * j;
+        prv[j] = ring[rbase + ((tl.head + (i < npre ? i : 0u)) & ring_mask)];
     }
     // the step's first piece of events, kept in registers for the bucketing
+    // (loaded from entry 0 where a thread has none, then zeroed)
     uint64_t pl0[kPer];
 #pragma unroll
     for (uint32_t j = 0; j < kPer; ++j) {
         const uint32_t i = tid + kTqThreads * j;
-        pl0[j] = i < n_new ? rb.payload[lo + i] : 0ull;
+        pl0[j] = rb.payload[i < n_new ? lo + i : 0u];
+    }
+    if (has_ck) ck[tid] = ckv;
+#pragma unroll
+    for (uint32_t j = 0; j < kPre / kTqThreads; ++j) {
+        const uint32_t i = tid + kTqThreads * j;
+        if (i < npre) pre[i] = prv[j];
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j) pl0[j] = tid + kTqThreads * j < n_new ? pl0[j] : 0ull;
+    if (tid == 0) {
+        sh_first = q;
+        sh_nstale = 0u;
+        sh_red[0] = sh_red[1] = sh_red[2] = 0u;
     }
     __syncthreads();
 
